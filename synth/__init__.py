@@ -1,0 +1,247 @@
+"""Seeded synthetic inputs shared by the GPU path, the oracle and the tests.
+
+This module holds only inputs: system parameters, phantoms (activity and
+attenuation maps) and a generic list-mode event generator.  It contains none of
+the reconstruction method's arithmetic (no attenuation line integrals, no
+Klein-Nishina weights, no collimator or energy-acceptance model): the events it
+makes have the structure of the paper's workloads (angles over 360 degrees,
+bins concentrated on the object's projection, energies clustered on the
+emission lines inside the windows) and serve as inputs whose exact values do
+not matter.  Events drawn from the exact model itself come from the oracle's
+sampler, which only the tests use.
+
+Workloads follow the paper's simulation (Sec. 3.1): a 2-D phantom with an
+elliptical water body and circular or elliptical hot regions, 120 angles over
+360 degrees, the Ra-223-like lines at 85/154/270 keV and the windows
+68-102, 123-184 and 243-297 keV.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+EW1 = (68.0, 102.0)
+EW2 = (123.0, 184.0)
+EW3 = (243.0, 297.0)
+SW = (184.0, 243.0)
+
+
+@dataclass(frozen=True)
+class SysParams:
+    n: int                 # pixels per side
+    pix: float             # pixel size, mm
+    ns: int                # scatter points per side
+    nb: int                # detector bins
+    na: int                # angles over 360 degrees
+    fwhm0: float = 2.0     # collimator-detector FWHM at depth 0, mm
+    fwhm_slope: float = 0.03
+    dtheta: float = 0.03   # collimator angular acceptance, rad
+    lines: tuple = (85.0, 154.0, 270.0)
+    yields: tuple = (0.25, 0.06, 0.14)
+    windows: tuple = (EW1, EW2)
+    eres_frac: float = 0.10
+    eres_ref: float = 140.0
+    mu_ref: float = 85.0
+    mu_pow: float = 1.0 / 3.0
+    T: float = 1.0
+    me: float = 510.99895  # electron rest energy, keV
+
+    @property
+    def fov(self):
+        return self.n * self.pix
+
+    @property
+    def R(self):
+        return 0.5 * self.n * self.pix
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    params: SysParams
+    n_events: int
+    n_subsets: int
+    n_iters: int
+    phantom: str
+    seed_phantom: int
+    seed_events: int
+    poisson: bool = False
+    n_cases: int = 1
+    case_min: int = 0
+    case_max: int = 0
+    seed_cases: int = 0
+
+
+CONFIGS = {
+    # 16x16 at 4 mm, 8x8 scatter grid, 16 bins x 32 angles, EW1+EW2, 2000 events.
+    "c1": Workload("c1", SysParams(16, 4.0, 8, 16, 32, windows=(EW1, EW2)),
+                   2000, 4, 10, "disk2", 11, 12),
+    # 64x64 at 4 mm, 32x32 scatter grid, 64 bins x 120 angles, EW1-3, ~50k events.
+    "c2": Workload("c2", SysParams(64, 4.0, 32, 64, 120, windows=(EW1, EW2, EW3)),
+                   50000, 8, 20, "ellipse3", 21, 22, poisson=True),
+    # 64 cases of the c2 geometry, per-case means uniform in [20k, 200k].
+    "c3": Workload("c3", SysParams(64, 4.0, 32, 64, 120, windows=(EW1, EW2, EW3)),
+                   0, 8, 20, "ellipse3", 21, 3100, poisson=True, n_cases=64,
+                   case_min=20000, case_max=200000, seed_cases=31),
+    # 128x128 at 2 mm, 64x64 scatter grid, 128 bins x 120 angles, EW1-3 + SW,
+    # 1M events over 16 uneven cases.
+    "c5": Workload("c5", SysParams(128, 2.0, 64, 128, 120, windows=(EW1, EW2, SW, EW3)),
+                   1000000, 16, 20, "ellipse3", 5200, 5300, poisson=False, n_cases=16,
+                   case_min=20000, case_max=200000, seed_cases=51),
+}
+
+
+def pixel_centres(p: SysParams):
+    c = (np.arange(p.n) + 0.5) * p.pix - p.R
+    x, y = np.meshgrid(c, c)          # x varies along columns (ix), y along rows (iy)
+    return x.ravel(), y.ravel()
+
+
+def fov_support(p: SysParams):
+    x, y = pixel_centres(p)
+    return (x * x + y * y <= p.R * p.R)
+
+
+def phantom_disk2(p: SysParams, mu85=0.018, body_r=28.0, hot_r=6.0, hot_x=14.0,
+                  ratio=4.0):
+    """Water disk with two hot disks on the x axis (activity ratio `ratio`:1)."""
+    x, y = pixel_centres(p)
+    body = x * x + y * y <= body_r * body_r
+    mu = np.where(body, mu85, 0.0)
+    act = np.where(body, 1.0, 0.0)
+    rois = []
+    for cx in (-hot_x, hot_x):
+        roi = (x - cx) ** 2 + y ** 2 <= hot_r * hot_r
+        act = np.where(roi, ratio, act)
+        rois.append(roi)
+    return mu, act, rois
+
+
+def _in_ellipse(x, y, cx, cy, a, b, th):
+    c, s = np.cos(th), np.sin(th)
+    u = (x - cx) * c + (y - cy) * s
+    v = -(x - cx) * s + (y - cy) * c
+    return (u / a) ** 2 + (v / b) ** 2 <= 1.0
+
+
+def phantom_ellipse3(p: SysParams, seed: int, body=(110.0, 90.0), rim=8.0,
+                     mu_rim=0.021, mu_inner=0.018):
+    """Elliptical water body (rim and inner attenuation of Sec. 3.1.1, given
+    there in 1/cm) with three random non-overlapping elliptical hot regions
+    (semi-axes U[7,20] mm, random orientation, ratios drawn from {2,4,6}:1)
+    on a uniform background."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x, y = pixel_centres(p)
+    A, B = body
+    scale = min(1.0, 0.9 * p.R / A)       # keep the body inside smaller fields of view
+    A, B, rim = A * scale, B * scale, rim * scale
+    outer = _in_ellipse(x, y, 0, 0, A, B, 0.0)
+    inner = _in_ellipse(x, y, 0, 0, A - rim, B - rim, 0.0)
+    mu = np.where(inner, mu_inner, np.where(outer, mu_rim, 0.0))
+    act = np.where(outer, 1.0, 0.0)
+    rois, placed = [], []
+    tries = 0
+    while len(rois) < 3 and tries < 10000:
+        tries += 1
+        a_ = rng.uniform(7.0, 20.0) * scale
+        b_ = rng.uniform(7.0, 20.0) * scale
+        th = rng.uniform(0, np.pi)
+        r = max(a_, b_)
+        cx = rng.uniform(-(A - rim - r), A - rim - r)
+        cy = rng.uniform(-(B - rim - r), B - rim - r)
+        if not _in_ellipse(np.array([cx]), np.array([cy]), 0, 0, A - rim - r, B - rim - r, 0)[0]:
+            continue
+        if any(np.hypot(cx - px, cy - py) < r + pr + 2 * p.pix for px, py, pr in placed):
+            continue
+        roi = _in_ellipse(x, y, cx, cy, a_, b_, th)
+        if roi.sum() == 0:
+            continue
+        ratio = float(rng.choice([2.0, 4.0, 6.0]))
+        act = np.where(roi, ratio, act)
+        rois.append(roi)
+        placed.append((cx, cy, r))
+    return mu, act, rois
+
+
+def phantom(w: Workload, case: int = 0):
+    if w.phantom == "disk2":
+        return phantom_disk2(w.params)
+    seed = w.seed_phantom + (case if w.name == "c5" else 0)
+    return phantom_ellipse3(w.params, seed)
+
+
+def case_counts(w: Workload):
+    """Per-case event counts for batched workloads."""
+    rng = np.random.Generator(np.random.PCG64(w.seed_cases))
+    means = rng.uniform(w.case_min, w.case_max, size=w.n_cases)
+    if w.n_events > 0:                       # fixed total split in proportion
+        cnt = np.floor(means / means.sum() * w.n_events).astype(np.int64)
+        cnt[: w.n_events - cnt.sum()] += 1
+        return cnt
+    return np.array([np.random.Generator(np.random.PCG64(w.seed_events + 1000 + c)).poisson(m)
+                     for c, m in enumerate(means)], dtype=np.int64)
+
+
+def generic_events(p: SysParams, activity, n_events: int, seed: int, poisson=False,
+                   blur_mm=3.0, peak_frac=0.7, peak_sigma=5.0):
+    """List-mode events with the structure of a SPECT acquisition.
+
+    Emission pixel drawn in proportion to `activity`, angle uniform over the
+    `na` angles, lateral detector position = projection of the pixel centre
+    plus a fixed Gaussian blur (`blur_mm`), energy either near an emission line
+    (line chosen by yield, fixed Gaussian spread `peak_sigma`) or uniform below
+    it (a stand-in for the scatter continuum), kept only inside the windows.
+    None of these draws uses the reconstruction model."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    J = int(rng.poisson(n_events)) if poisson else int(n_events)
+    act = np.asarray(activity, dtype=np.float64).ravel()
+    cdf = np.cumsum(act)
+    cdf /= cdf[-1]
+    x, y = pixel_centres(p)
+    lines = np.asarray(p.lines)
+    yields = np.asarray(p.yields) / np.sum(p.yields)
+    wins = np.asarray(p.windows)
+    bins = np.empty(J, np.int16)
+    angs = np.empty(J, np.int16)
+    ener = np.empty(J, np.float32)
+    db = p.fov / p.nb
+    filled = 0
+    while filled < J:
+        m = max(1024, 2 * (J - filled))
+        q = np.minimum(np.searchsorted(cdf, rng.random(m), side="right"), act.size - 1)
+        a = rng.integers(0, p.na, m)
+        th = 2 * np.pi * a / p.na
+        u = -x[q] * np.sin(th) + y[q] * np.cos(th) + rng.normal(0, blur_mm, m)
+        b = np.floor((u + p.R) / db).astype(np.int64)
+        w = rng.choice(len(lines), size=m, p=yields)
+        peak = rng.random(m) < peak_frac
+        e = np.where(peak, rng.normal(lines[w], peak_sigma), rng.uniform(0.4 * lines[w], lines[w]))
+        inwin = np.zeros(m, bool)
+        for lo, hi in wins:
+            inwin |= (e >= lo) & (e <= hi)
+        ok = (b >= 0) & (b < p.nb) & inwin
+        k = min(int(ok.sum()), J - filled)
+        idx = np.flatnonzero(ok)[:k]
+        bins[filled:filled + k] = b[idx]
+        angs[filled:filled + k] = a[idx]
+        ener[filled:filled + k] = e[idx]
+        filled += k
+    return {"bin": bins, "angle": angs, "energy": ener}
+
+
+def workload_inputs(name: str, case: int = 0, n_events=None):
+    """(params, mu85 [Q], activity [Q], rois, events) for one case of a workload,
+    with generic events."""
+    w = CONFIGS[name]
+    mu, act, rois = phantom(w, case)
+    if n_events is None:
+        n_events = int(case_counts(w)[case]) if w.n_cases > 1 else w.n_events
+    ev = generic_events(w.params, act, n_events, w.seed_events + case,
+                        poisson=(w.poisson and w.n_cases == 1))
+    return w.params, mu, act, rois, ev
+
+
+__all__ = ["SysParams", "Workload", "CONFIGS", "EW1", "EW2", "EW3", "SW", "pixel_centres",
+           "fov_support", "phantom_disk2", "phantom_ellipse3", "phantom", "case_counts",
+           "generic_events", "workload_inputs", "replace", "field"]
