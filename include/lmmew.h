@@ -1,0 +1,222 @@
+/*
+ * lmmew: list-mode multi-energy-window OSEM SPECT on one MI355X (gfx950).
+ *
+ * Method: Rahman, Li, Yu, Laforest, Thorek, Jha, "A list-mode multi-energy
+ * window low-count SPECT reconstruction method for isotopes with multiple
+ * emission peaks", arXiv 2305.17111.
+ *
+ * The library evaluates, for every detected photon (detector bin, angle,
+ * measured energy), the path mixture of Eq. (3): the unscattered path from
+ * each object pixel plus every once-scattered path through a grid of scatter
+ * points, each weighted by attenuation (Eq. (6)), the depth-dependent
+ * collimator-detector response, the planar Klein-Nishina density and the
+ * Gaussian energy resolution evaluated at the photon's true energy.  Those
+ * per-event densities a_jq drive the list-mode forward projection
+ * p_j = sum_q a_jq lambda_q, the backprojection, the ordered-subsets EM
+ * update of Eq. (18)-(20) and the sensitivity image (denominator of
+ * Eq. (18), Eq. (7) per pixel).
+ *
+ * Conventions shared by every entry point
+ *   - Image arrays are float32 over the full n x n grid, row-major,
+ *     q = iy*n + ix, pixel centre ((ix+1/2)pix - R, (iy+1/2)pix - R),
+ *     R = n*pix/2.  Pixels outside the support (centre outside the circular
+ *     field of view of radius R, or cleared in the caller's mask) hold 0 in
+ *     every output and are never updated.
+ *   - Angle a points the detector normal along (cos t, sin t), t = 2 pi a /
+ *     n_angles (exact at multiples of 90 degrees); bin b covers the lateral
+ *     coordinate u = -x sin t + y cos t in [-R + b*db, -R + (b+1)*db),
+ *     db = 2R / n_bins; the detector plane is x.n = R.
+ *   - Subset s of an n_subsets partition holds the angles a with
+ *     a mod n_subsets == s; subsets are visited in order 0..n_subsets-1.
+ *   - Every pointer argument documented as "device" is memory the caller
+ *     allocated on the current HIP device and keeps ownership of.  The
+ *     library owns only what it allocates behind a context or plan handle.
+ *   - Work is enqueued on the caller's stream.  Calls that synchronise that
+ *     stream say so.  A context (and its plans) must be used by one host
+ *     thread at a time.
+ *   - Every function returns an lmmew status code; on failure the context's
+ *     last error text says why (lmmew_last_error).  No exception, abort or
+ *     exit crosses this interface.
+ */
+#ifndef LMMEW_H
+#define LMMEW_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LMMEW_OK         0
+#define LMMEW_EINVAL    -1   /* NULL pointer, bad size, event out of range, non-finite input */
+#define LMMEW_ENOMEM    -2   /* device or host allocation failed */
+#define LMMEW_EDEVICE   -3   /* a HIP runtime call failed */
+#define LMMEW_ENUMERIC  -4   /* a non-finite value appeared in a result */
+
+#define LMMEW_MAX_LINES   8
+#define LMMEW_MAX_WINDOWS 8
+
+/* System parameters (the sysParam and T inputs of Algorithm 1). */
+typedef struct lmmew_system {
+    int32_t n;                 /* pixels per side of the square grid */
+    int32_t ns;                /* scatter points per side; n/ns must be an even integer */
+    int32_t n_bins;            /* detector bins across the field of view */
+    int32_t n_angles;          /* angles evenly spaced over 360 degrees */
+    int32_t n_lines;           /* emission lines, 1..LMMEW_MAX_LINES */
+    int32_t n_windows;         /* energy windows, 1..LMMEW_MAX_WINDOWS */
+    double pixel_mm;           /* pixel size */
+    double psf_fwhm0_mm;       /* collimator-detector FWHM at depth 0 */
+    double psf_fwhm_slope;     /* FWHM growth per mm of depth below the detector plane */
+    double coll_dtheta;        /* collimator angular acceptance, radians */
+    double line_keV[LMMEW_MAX_LINES];    /* emission energies E_w */
+    double line_yield[LMMEW_MAX_LINES];  /* photons per decay alpha_w (Sec. 2.1) */
+    double win_lo_keV[LMMEW_MAX_WINDOWS];
+    double win_hi_keV[LMMEW_MAX_WINDOWS];
+    double eres_frac;          /* energy FWHM as a fraction of eres_ref_keV at that energy */
+    double eres_ref_keV;       /* absolute FWHM scales as sqrt(E) (Sec. 3.1.2) */
+    double mu_ref_keV;         /* energy at which the attenuation map is given */
+    double mu_power;           /* mu(E) = mu(mu_ref) * (E / mu_ref)^(-mu_power) */
+    double T;                  /* acquisition time (Eq. (2)) */
+    double electron_keV;       /* electron rest energy used by Klein-Nishina */
+} lmmew_system;
+
+/* List-mode data (lmData of Algorithm 1): one entry per detected photon.
+ * All three arrays are device arrays of n entries.  An event is valid when
+ * 0 <= bin < n_bins, 0 <= angle < n_angles and energy_keV is finite and lies
+ * in some window [lo, hi]. */
+typedef struct lmmew_events {
+    int64_t n;
+    const int16_t *bin;
+    const int16_t *angle;
+    const float *energy_keV;
+} lmmew_events;
+
+/* Optional statistics of an OSEM call (host memory owned by the caller). */
+typedef struct lmmew_stats {
+    int64_t skipped_total;   /* out: events with p_j = 0 over all sub-iterations */
+    int64_t *skipped;        /* in: NULL or host [n_iters*n_subsets]; out: per sub-iteration */
+    double *subset_loglik;   /* in: NULL or host [n_iters*n_subsets]; out: sum over the
+                                subset's events of log p_j minus sum_q sens_s[q] lambda_q,
+                                before the update, summed over cases; with one subset
+                                this is Eq. (8) up to a constant */
+} lmmew_stats;
+
+typedef struct lmmew_ctx lmmew_ctx;
+typedef struct lmmew_plan lmmew_plan;
+
+/* Text for a status code. */
+const char *lmmew_status_string(int status);
+
+/* Text of the last failure on this context ("" if none). */
+const char *lmmew_last_error(const lmmew_ctx *ctx);
+
+/* Builds a context for one attenuation map: the attenuation line integrals
+ * of Eq. (6) from every support pixel to every scatter point and to the
+ * detector plane at every angle, and from every scatter point to the
+ * detector plane (the precomputation of Algorithm 1).
+ *   sys      host; copied.
+ *   mu85     device [n*n] float, attenuation at mu_ref_keV in 1/mm, >= 0.
+ *   support  device [n*n] uint8 or NULL: pixels allowed to carry activity
+ *            (intersected with the circular field of view).
+ *   stream   the tables are built on this stream; the call synchronises it
+ *            once to read mu85 and support.
+ *   out      receives the context; NULL on failure.
+ * Errors: EINVAL (bad parameters, NULL pointers, negative or non-finite
+ * mu85), ENOMEM, EDEVICE. */
+int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *support,
+                 hipStream_t stream, lmmew_ctx **out);
+
+/* Releases the context and everything it owns (waits for its work). */
+int lmmew_destroy(lmmew_ctx *ctx);
+
+/* Sensitivity image per subset: sens[s][q] = T * sum over the subset's
+ * angles of the probability that a decay in pixel q is recorded (on the
+ * detector and inside a window), unscattered or once scattered: the
+ * denominator of Eq. (18) with the window acceptance of every path.
+ *   sens     device [n_subsets][n*n] float, written.
+ * Errors: EINVAL (n_subsets < 1 or > n_angles, NULL), EDEVICE. */
+int lmmew_sensitivity(lmmew_ctx *ctx, int n_subsets, float *sens, hipStream_t stream);
+
+/* List-mode forward projection: p[j] = sum_q a_jq lambda[q] (the
+ * denominator of Eq. (19)) for arbitrary events in any order.
+ *   ev       events (device arrays); validated.
+ *   lambda   device [n*n] float.
+ *   p        device [ev->n] float, written in input order.
+ * Synchronises the stream once to validate and sort the events.
+ * Errors: EINVAL (invalid event: the message names its index), ENOMEM,
+ * EDEVICE. */
+int lmmew_forward(lmmew_ctx *ctx, const lmmew_events *ev, const float *lambda, float *p,
+                  hipStream_t stream);
+
+/* Adjoint: out[q] = sum_j a_jq w[j] (events with w[j] = 0 contribute
+ * nothing).
+ *   w        device [ev->n] float, input order.
+ *   out      device [n*n] float, written.
+ * Synchronises the stream once.  Errors as lmmew_forward. */
+int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, float *out,
+                      hipStream_t stream);
+
+/* Prepares list-mode data for OSEM: validates every event, sorts each
+ * subset's events by (case, angle, bin, energy) (stable) and lays out the
+ * work tiles and the per-subset scratch.  A plan holds one or more
+ * independent cases (noise realisations or patients) that share the context's
+ * attenuation map and sensitivity.
+ *   ev            events of all cases, concatenated (device arrays).
+ *   case_offsets  host int64 [n_cases+1] or NULL (one case): events of case
+ *                 c are [case_offsets[c], case_offsets[c+1]).
+ *   n_subsets     angle subsets, 1..n_angles.
+ * The plan copies what it needs; the event arrays may be freed afterwards.
+ * Synchronises the stream once.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int lmmew_plan_create(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets,
+                      int n_cases, int n_subsets, hipStream_t stream, lmmew_plan **out);
+
+int lmmew_plan_destroy(lmmew_plan *plan);
+
+/* Runs n_iters iterations of list-mode OSEM (Eq. (18)-(20)): for every
+ * subset s in order and every case c,
+ *   p_j = sum_q a_jq lambda_c[q]                  (events j of case c in s)
+ *   B_q = sum_{j, p_j > 0} a_jq / p_j
+ *   lambda_c[q] <- lambda_c[q] * B_q / sens[s][q]  where sens[s][q] > 0.
+ * The system model is evaluated afresh in every sub-iteration.
+ *   sens     device [n_subsets][n*n] from lmmew_sensitivity (same n_subsets).
+ *   lambda   device [n_cases][n*n], in: the current image, out: the image
+ *            after n_iters iterations.  Initial values must be >= 0.
+ *   stats    NULL, or host statistics; requesting them synchronises the
+ *            stream at the end of the call.
+ * Without stats the call only enqueues work.  Errors: EINVAL, EDEVICE,
+ * ENUMERIC (a non-finite image value, reported only when stats are
+ * requested). */
+int lmmew_osem_iter(lmmew_ctx *ctx, lmmew_plan *plan, int n_iters, const float *sens,
+                    float *lambda, lmmew_stats *stats, hipStream_t stream);
+
+/* One sub-iteration of Eq. (18)-(20) for subset `subset` (0..n_subsets-1):
+ * the same update as lmmew_osem_iter restricted to that subset.  Calling it
+ * for subsets 0..n_subsets-1 in order is exactly one iteration, so a run can
+ * stop after any sub-iteration and resume from (lambda, iteration, subset)
+ * with a bitwise-identical result.  stats (optional) then holds one entry. */
+int lmmew_osem_subiter(lmmew_ctx *ctx, lmmew_plan *plan, int subset, const float *sens,
+                       float *lambda, lmmew_stats *stats, hipStream_t stream);
+
+/* Tuning knobs of the per-event system-model kernel for a plan (chosen by
+ * lmmew_autotune or set by hand).  event_tile: events per work tile, one of
+ * 16, 32, 64.  Changing it rebuilds the plan's tiles (synchronises). */
+int lmmew_plan_set_event_tile(lmmew_ctx *ctx, lmmew_plan *plan, int event_tile,
+                              hipStream_t stream);
+int lmmew_plan_get_event_tile(const lmmew_plan *plan);
+
+/* Number of algorithmic terms one OSEM iteration of the plan evaluates in
+ * the per-event system-model kernel: for every (event, support pixel) pair,
+ * one term per line for the unscattered path and one per (line, scatter
+ * point) whose collimator-response factor is not dropped (a scatter point
+ * whose Gaussian response puts the event's bin beyond 7 standard
+ * deviations contributes below 1.3e-12 of its peak and is skipped).
+ *   out_terms      host: terms evaluated per iteration.
+ *   out_full_terms host: terms of the unpruned model per iteration. */
+int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full_terms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMMEW_H */

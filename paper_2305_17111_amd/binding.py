@@ -1,0 +1,285 @@
+"""ctypes binding of liblmmew.so: argument marshalling only.
+
+Every entry point of ``include/lmmew.h`` is exposed under the same name through
+``Context`` and ``Plan``.  Device arrays are torch tensors on the current HIP
+device; work goes to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liblmmew.so")
+
+MAX_LINES = 8
+MAX_WIN = 8
+
+
+class LmmewError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lmmew status {status}: {msg}")
+        self.status = status
+
+
+class _System(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("ns", C.c_int32), ("n_bins", C.c_int32), ("n_angles", C.c_int32),
+        ("n_lines", C.c_int32), ("n_windows", C.c_int32),
+        ("pixel_mm", C.c_double), ("psf_fwhm0_mm", C.c_double), ("psf_fwhm_slope", C.c_double),
+        ("coll_dtheta", C.c_double),
+        ("line_keV", C.c_double * MAX_LINES), ("line_yield", C.c_double * MAX_LINES),
+        ("win_lo_keV", C.c_double * MAX_WIN), ("win_hi_keV", C.c_double * MAX_WIN),
+        ("eres_frac", C.c_double), ("eres_ref_keV", C.c_double),
+        ("mu_ref_keV", C.c_double), ("mu_power", C.c_double),
+        ("T", C.c_double), ("electron_keV", C.c_double),
+    ]
+
+
+class _Events(C.Structure):
+    _fields_ = [("n", C.c_int64), ("bin", C.c_void_p), ("angle", C.c_void_p),
+                ("energy_keV", C.c_void_p)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("skipped_total", C.c_int64), ("skipped", C.POINTER(C.c_int64)),
+                ("subset_loglik", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def library_path():
+    return _LIBPATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise ImportError(f"{_LIBPATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(_LIBPATH)
+    vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
+    sig = {
+        "lmmew_status_string": (C.c_char_p, [i32]),
+        "lmmew_last_error": (C.c_char_p, [vp]),
+        "lmmew_create": (i32, [C.POINTER(_System), vp, vp, vp, C.POINTER(vp)]),
+        "lmmew_destroy": (i32, [vp]),
+        "lmmew_sensitivity": (i32, [vp, i32, vp, vp]),
+        "lmmew_forward": (i32, [vp, C.POINTER(_Events), vp, vp, vp]),
+        "lmmew_backproject": (i32, [vp, C.POINTER(_Events), vp, vp, vp]),
+        "lmmew_plan_create": (i32, [vp, C.POINTER(_Events), vp, i32, i32, vp, C.POINTER(vp)]),
+        "lmmew_plan_destroy": (i32, [vp]),
+        "lmmew_osem_iter": (i32, [vp, vp, i32, vp, vp, C.POINTER(_Stats), vp]),
+        "lmmew_osem_subiter": (i32, [vp, vp, i32, vp, vp, C.POINTER(_Stats), vp]),
+        "lmmew_plan_set_event_tile": (i32, [vp, vp, i32, vp]),
+        "lmmew_plan_get_event_tile": (i32, [vp]),
+        "lmmew_plan_terms": (i32, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def system_from_params(p) -> _System:
+    """Fill lmmew_system from any object with the system attributes (n, pix, ns, nb,
+    na, fwhm0, fwhm_slope, dtheta, lines, yields, windows, eres_frac, eres_ref,
+    mu_ref, mu_pow, T, me)."""
+    s = _System()
+    s.n, s.ns, s.n_bins, s.n_angles = int(p.n), int(p.ns), int(p.nb), int(p.na)
+    s.n_lines, s.n_windows = len(p.lines), len(p.windows)
+    s.pixel_mm, s.psf_fwhm0_mm, s.psf_fwhm_slope = float(p.pix), float(p.fwhm0), float(p.fwhm_slope)
+    s.coll_dtheta = float(p.dtheta)
+    for i, (e, y) in enumerate(zip(p.lines, p.yields)):
+        s.line_keV[i], s.line_yield[i] = float(e), float(y)
+    for i, (lo, hi) in enumerate(p.windows):
+        s.win_lo_keV[i], s.win_hi_keV[i] = float(lo), float(hi)
+    s.eres_frac, s.eres_ref_keV = float(p.eres_frac), float(p.eres_ref)
+    s.mu_ref_keV, s.mu_power = float(p.mu_ref), float(p.mu_pow)
+    s.T, s.electron_keV = float(p.T), float(p.me)
+    return s
+
+
+def events_to_device(ev, device="cuda"):
+    """dict(bin, angle, energy) of arrays -> dict of device tensors (int16, int16, float32)."""
+    return {
+        "bin": torch.as_tensor(ev["bin"]).to(device=device, dtype=torch.int16).contiguous(),
+        "angle": torch.as_tensor(ev["angle"]).to(device=device, dtype=torch.int16).contiguous(),
+        "energy": torch.as_tensor(ev["energy"]).to(device=device, dtype=torch.float32).contiguous(),
+    }
+
+
+def _events(ev):
+    b, a, e = ev["bin"], ev["angle"], ev["energy"]
+    for t, dt in ((b, torch.int16), (a, torch.int16), (e, torch.float32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("events must be contiguous device tensors (int16, int16, float32)")
+    n = b.numel()
+    if a.numel() != n or e.numel() != n:
+        raise ValueError("event arrays differ in length")
+    return _Events(n, b.data_ptr(), a.data_ptr(), e.data_ptr())
+
+
+class Context:
+    """lmmew_create / lmmew_destroy and the per-map entry points."""
+
+    def __init__(self, params, mu85, support=None):
+        L = _load()
+        self.params = params
+        self.sys = system_from_params(params)
+        self.n = int(params.n)
+        self.Q = self.n * self.n
+        self.mu85 = torch.as_tensor(mu85).to("cuda", torch.float32).contiguous().view(-1)
+        if self.mu85.numel() != self.Q:
+            raise ValueError("mu85 must have n*n entries")
+        self.support = None
+        if support is not None:
+            self.support = torch.as_tensor(support).to("cuda", torch.uint8).contiguous().view(-1)
+        h = C.c_void_p()
+        rc = L.lmmew_create(C.byref(self.sys), _ptr(self.mu85), _ptr(self.support), _stream(),
+                            C.byref(h))
+        if rc != 0:
+            raise LmmewError(rc, L.lmmew_status_string(rc).decode())
+        self._h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            L = _load()
+            raise LmmewError(rc, L.lmmew_last_error(self._h).decode() or
+                             L.lmmew_status_string(rc).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().lmmew_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def lmmew_sensitivity(self, n_subsets, out=None):
+        if out is None:
+            out = torch.empty((n_subsets, self.Q), device="cuda", dtype=torch.float32)
+        self._check(_load().lmmew_sensitivity(self._h, int(n_subsets), _ptr(out), _stream()))
+        return out
+
+    def lmmew_forward(self, ev, lam, out=None):
+        e = _events(ev)
+        lam = lam.contiguous()
+        if out is None:
+            out = torch.empty(e.n, device="cuda", dtype=torch.float32)
+        self._check(_load().lmmew_forward(self._h, C.byref(e), _ptr(lam), _ptr(out), _stream()))
+        return out
+
+    def lmmew_backproject(self, ev, w, out=None):
+        e = _events(ev)
+        w = w.contiguous()
+        if out is None:
+            out = torch.empty(self.Q, device="cuda", dtype=torch.float32)
+        self._check(_load().lmmew_backproject(self._h, C.byref(e), _ptr(w), _ptr(out), _stream()))
+        return out
+
+    def lmmew_plan_create(self, ev, n_subsets, case_offsets=None):
+        return Plan(self, ev, n_subsets, case_offsets)
+
+    # short aliases
+    sensitivity = lmmew_sensitivity
+    forward = lmmew_forward
+    backproject = lmmew_backproject
+    plan = lmmew_plan_create
+
+
+class Plan:
+    """lmmew_plan_create / lmmew_osem_iter / lmmew_plan_destroy."""
+
+    def __init__(self, ctx: Context, ev, n_subsets, case_offsets=None):
+        L = _load()
+        self.ctx = ctx
+        e = _events(ev)
+        self.n_subsets = int(n_subsets)
+        if case_offsets is None:
+            self.n_cases = 1
+            offs = None
+        else:
+            arr = (C.c_int64 * len(case_offsets))(*[int(x) for x in case_offsets])
+            self.n_cases = len(case_offsets) - 1
+            offs = C.cast(arr, C.c_void_p)
+        h = C.c_void_p()
+        ctx._check(L.lmmew_plan_create(ctx._h, C.byref(e), offs, self.n_cases, self.n_subsets,
+                                       _stream(), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().lmmew_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def lmmew_osem_iter(self, n_iters, sens, lam, stats=False):
+        """Runs n_iters OSEM iterations in place on lam ([n_cases, Q] or [Q]).
+        With stats=True returns (skipped per sub-iteration, subset log-likelihoods)."""
+        L = _load()
+        st = None
+        if stats:
+            K = int(n_iters) * self.n_subsets
+            sk = (C.c_int64 * max(K, 1))()
+            ll = (C.c_double * max(K, 1))()
+            st = _Stats(0, C.cast(sk, C.POINTER(C.c_int64)), C.cast(ll, C.POINTER(C.c_double)))
+        self.ctx._check(L.lmmew_osem_iter(self.ctx._h, self._h, int(n_iters), _ptr(sens), _ptr(lam),
+                                          C.byref(st) if st is not None else None, _stream()))
+        if stats:
+            return list(sk)[:K], list(ll)[:K]
+        return None
+
+    def lmmew_osem_subiter(self, subset, sens, lam, stats=False):
+        """One sub-iteration for `subset` in place on lam.  With stats=True returns
+        (skipped, subset log-likelihood)."""
+        L = _load()
+        st = None
+        if stats:
+            sk = (C.c_int64 * 1)()
+            ll = (C.c_double * 1)()
+            st = _Stats(0, C.cast(sk, C.POINTER(C.c_int64)), C.cast(ll, C.POINTER(C.c_double)))
+        self.ctx._check(L.lmmew_osem_subiter(self.ctx._h, self._h, int(subset), _ptr(sens),
+                                             _ptr(lam), C.byref(st) if st is not None else None,
+                                             _stream()))
+        if stats:
+            return sk[0], ll[0]
+        return None
+
+    def set_event_tile(self, jt):
+        self.ctx._check(_load().lmmew_plan_set_event_tile(self.ctx._h, self._h, int(jt), _stream()))
+
+    @property
+    def event_tile(self):
+        return _load().lmmew_plan_get_event_tile(self._h)
+
+    def terms(self):
+        t, f = C.c_double(), C.c_double()
+        self.ctx._check(_load().lmmew_plan_terms(self._h, C.byref(t), C.byref(f)))
+        return t.value, f.value
+
+    osem_iter = lmmew_osem_iter
+    osem_subiter = lmmew_osem_subiter

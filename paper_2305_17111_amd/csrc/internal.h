@@ -1,0 +1,152 @@
+// Internal structures shared by the host code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lmmew.h"
+
+namespace lmmew {
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kPi = 3.14159265358979323846;
+constexpr float kPsfCut = 7.0f;    // collimator-response Gaussian dropped beyond 7 sigma
+
+// Per-run constants passed by value to the kernels.
+struct DevSys {
+    int n, ns, nb, na, nw, nwin;
+    int Qm, Qp, nsc;
+    float pix, R, hs, db;
+    float fwhm0, fslope;            // PSF FWHM = fwhm0 + fslope * depth
+    float inv_fwhm_to_sigma;        // 1 / (2 sqrt(2 ln 2))
+    float T;
+    float eres_k;                   // sigma_E^2 = eres_k * E
+    float mu_pow;
+    float rmin;                     // hs / (2 sqrt(pi))
+    // per line
+    float E[LMMEW_MAX_LINES];
+    float eps[LMMEW_MAX_LINES];     // E / m_e c^2
+    float f[LMMEW_MAX_LINES];       // mu(E_w)/mu_ref
+    float pp[LMMEW_MAX_LINES];      // alpha_w * dtheta / (2 pi)
+    float lsc[LMMEW_MAX_LINES];     // log2(alpha_w * f_w * dtheta / Z_w)
+    float c0[LMMEW_MAX_LINES];      // log2(e) / (2 eres_k E_w)
+    float sqc0[LMMEW_MAX_LINES];    // sqrt(c0)
+    float nc[LMMEW_MAX_LINES];      // -0.5 log2(2 pi eres_k E_w)
+    float gnorm[LMMEW_MAX_LINES];   // 1 / sqrt(2 pi eres_k E_w)
+    float wlo[LMMEW_MAX_WINDOWS], whi[LMMEW_MAX_WINDOWS];
+};
+
+// Scatter point as seen from one angle (array [na][nsc], sorted by u).
+struct ScatA {
+    float x, y;         // position (mm)
+    float u;            // lateral detector coordinate
+    float isig;         // 1 / PSF sigma at its depth
+    float gsa;          // attenuation integral at mu_ref to the detector plane
+    float lc;           // log2(hs^2 * mu_s / (2 pi))
+    float D;            // probability of landing on the detector
+    int sidx;           // index into the [nsc][Qp] pixel->scatter table
+};
+
+// Work tile of the per-event kernel: events [e0, e0+cnt) of one angle and
+// one case, and the range [k0, k1) of that angle's u-sorted scatter points
+// whose response can reach the tile's bins.
+struct Tile {
+    int e0, cnt;
+    int angle, ncase;
+    int k0, k1;
+    int pad0, pad1;
+};
+
+// Chunk of consecutive rows of one case for the deterministic backprojection.
+struct Chunk {
+    int r0, r1, ncase, pad;
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+// Attenuation tables, computed in double precision.
+hipError_t launch_tables_d(const DevSys &S, const double *mu, const double2 *pix,
+                           const double2 *dirs, const double2 *sc, float *g_qa, float *g_qs,
+                           ScatA *sa, double pixmm, double R, hipStream_t st);
+
+struct RowArgs {
+    const float2 *pix_xy;
+    const float2 *dirs;
+    const float *g_qa;
+    const float *g_qs;
+    const ScatA *sa;
+    const Tile *tiles;
+    int ntiles;
+    const int *ev_bin;       // sorted rows of this subset
+    const float *ev_E;
+    float *A;                // [rows][Qp]
+};
+hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st);
+
+struct FwdArgs {
+    const float *A;          // [rows][Qp]
+    int rows;
+    const int *row_case;     // [rows]
+    const int *pixq;         // [Qp] full-grid index or -1
+    const float *lambda;     // [ncases][Q]
+    int Q;
+    float *p;                // [rows]
+    float *wt;               // [rows] 1/p (0 if p <= 0)
+    double *logp;            // [rows] log p (0 if p <= 0), may be NULL
+    unsigned long long *nskip;   // may be NULL
+};
+hipError_t launch_forward(const DevSys &S, const FwdArgs &f, hipStream_t st);
+
+struct BackArgs {
+    const float *A;
+    const float *wt;         // [rows]
+    const Chunk *chunks;
+    int nchunks;
+    float *part;             // [nchunks][Qp]
+    float *comp;             // [nchunks][Qp]
+};
+hipError_t launch_back(const DevSys &S, const BackArgs &b, hipStream_t st);
+
+struct UpdArgs {
+    const float *part, *comp;
+    const int *case_chunk;   // [ncases+1] chunk ranges per case
+    int ncases;
+    const int *pixq;
+    int Q;
+    const float *sens;       // [Q] of this subset, or NULL (plain backprojection)
+    float *lambda;           // [ncases][Q] in/out (update) or out (backprojection)
+};
+hipError_t launch_update(const DevSys &S, const UpdArgs &u, hipStream_t st);
+
+struct SensArgs {
+    const float2 *pix_xy;
+    const float2 *dirs;
+    const float *g_qa;
+    const float *g_qs;
+    const ScatA *sa;
+    const int *pixq;
+    float *Sqa;              // [na][Qp]
+    float *sens;             // [nsub][Q]
+    int nsub, Q;
+};
+hipError_t launch_sens(const DevSys &S, const SensArgs &a, hipStream_t st);
+
+struct ReduceArgs {          // deterministic sums for statistics
+    const double *logp;
+    int rows;
+    const float *sens;       // [Q]
+    const float *lambda;     // [ncases][Q]
+    int ncases, Q;
+    double *out;             // [1]: sum logp - sum sens*lambda
+};
+hipError_t launch_loglik(const ReduceArgs &r, hipStream_t st);
+
+hipError_t launch_scatter_out(const float *src, const int64_t *perm, int64_t n, float *dst,
+                              hipStream_t st);
+hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float *dst,
+                           hipStream_t st);
+
+}  // namespace lmmew

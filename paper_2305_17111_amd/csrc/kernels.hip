@@ -1,0 +1,630 @@
+// gfx950 kernels of the list-mode multi-energy-window OSEM (arXiv 2305.17111).
+//
+// Layout in HBM (all float32 unless noted):
+//   pix_xy  [Qp]          support pixels (compacted, padded to a multiple of 64)
+//   g_qa    [na][Qp]      attenuation integral pixel -> detector plane at mu_ref
+//   g_qs    [nsc][Qp]     attenuation integral pixel -> scatter point at mu_ref
+//   sa      [na][nsc]     scatter points as seen from each angle, sorted by u
+//   A       [rows][Qp]    per-subset scratch: a_jq for the subset's sorted events
+//   part/comp [chunks][Qp] compensated partial backprojections
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace lmmew {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Phi(zhi) - Phi(zlo) for the standard normal CDF, using erfc on the side of
+// the distribution where the difference does not cancel.
+__device__ __forceinline__ float phi_diff(float zhi, float zlo)
+{
+    const float r2 = 0.70710678118654752f;
+    if (zlo >= 0.f) return 0.5f * (erfcf(zlo * r2) - erfcf(zhi * r2));
+    if (zhi <= 0.f) return 0.5f * (erfcf(-zhi * r2) - erfcf(-zlo * r2));
+    return 1.f - 0.5f * erfcf(zhi * r2) - 0.5f * erfcf(-zlo * r2);
+}
+
+// Collimator-response probability of a bin whose edges are zhi, zlo standard
+// deviations from the projected point; exactly 0 when the whole bin lies
+// beyond kPsfCut standard deviations.
+__device__ __forceinline__ float psf_cut(float zhi, float zlo)
+{
+    if (zlo >= kPsfCut || zhi <= -kPsfCut) return 0.f;
+    return phi_diff(zhi, zlo);
+}
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+__device__ __forceinline__ float uniform_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// ---------------------------------------------------------------------------
+// attenuation line integrals (Eq. (6)), double precision, Amanatides-Woo walk
+// ---------------------------------------------------------------------------
+
+// Integral of the pixel map over the segment (x0,y0)->(x1,y1), walking the
+// cells the segment crosses in order.
+__device__ double walk_segment(const double *mu, int n, double pix, double R, double x0,
+                               double y0, double x1, double y1)
+{
+    const double dx = x1 - x0, dy = y1 - y0;
+    const double L = sqrt(dx * dx + dy * dy);
+    if (L == 0.0) return 0.0;
+    double tmin = 0.0, tmax = 1.0;
+    if (dx != 0.0) {
+        double ta = (-R - x0) / dx, tb = (R - x0) / dx;
+        tmin = fmax(tmin, fmin(ta, tb));
+        tmax = fmin(tmax, fmax(ta, tb));
+    } else if (x0 < -R || x0 > R) {
+        return 0.0;
+    }
+    if (dy != 0.0) {
+        double ta = (-R - y0) / dy, tb = (R - y0) / dy;
+        tmin = fmax(tmin, fmin(ta, tb));
+        tmax = fmin(tmax, fmax(ta, tb));
+    } else if (y0 < -R || y0 > R) {
+        return 0.0;
+    }
+    if (!(tmax > tmin)) return 0.0;
+    const double xs = x0 + tmin * dx, ys = y0 + tmin * dy;
+    const double fx = (xs + R) / pix, fy = (ys + R) / pix;
+    // cell entered in the direction of travel
+    int ix = (dx >= 0.0) ? (int)floor(fx) : (int)ceil(fx) - 1;
+    int iy = (dy >= 0.0) ? (int)floor(fy) : (int)ceil(fy) - 1;
+    ix = min(max(ix, 0), n - 1);
+    iy = min(max(iy, 0), n - 1);
+    const int sx = dx > 0.0 ? 1 : -1, sy = dy > 0.0 ? 1 : -1;
+    double tX = INFINITY, tY = INFINITY, dX = INFINITY, dY = INFINITY;
+    if (dx != 0.0) {
+        double xb = (dx > 0.0 ? (ix + 1) : ix) * pix - R;
+        tX = (xb - x0) / dx;
+        dX = pix / fabs(dx);
+    }
+    if (dy != 0.0) {
+        double yb = (dy > 0.0 ? (iy + 1) : iy) * pix - R;
+        tY = (yb - y0) / dy;
+        dY = pix / fabs(dy);
+    }
+    double t = tmin, sum = 0.0;
+    for (int guard = 0; guard < 4 * n + 4; ++guard) {
+        double tn = fmin(fmin(tX, tY), tmax);
+        if (tn > t) sum += mu[iy * n + ix] * (tn - t);
+        t = tn;
+        if (t >= tmax) break;
+        if (tX <= tn) { ix += sx; tX += dX; }
+        if (tY <= tn) { iy += sy; tY += dY; }
+        if (ix < 0 || iy < 0 || ix >= n || iy >= n) break;
+    }
+    return sum * L;
+}
+
+// A segment lying exactly on a grid line sees the mean of the two pixel
+// columns (rows) that share the line; the walk along each neighbouring
+// column centre gives each of them.
+__device__ double seg_integral(const double *mu, int n, double pix, double R, double x0,
+                               double y0, double x1, double y1)
+{
+    if (x0 == x1) {
+        double f = (x0 + R) / pix, k = rint(f);
+        if (fabs(f - k) < 1e-9) {
+            double h = 0.5 * pix;
+            return 0.5 * (walk_segment(mu, n, pix, R, x0 - h, y0, x1 - h, y1) +
+                          walk_segment(mu, n, pix, R, x0 + h, y0, x1 + h, y1));
+        }
+    }
+    if (y0 == y1) {
+        double f = (y0 + R) / pix, k = rint(f);
+        if (fabs(f - k) < 1e-9) {
+            double h = 0.5 * pix;
+            return 0.5 * (walk_segment(mu, n, pix, R, x0, y0 - h, x1, y1 - h) +
+                          walk_segment(mu, n, pix, R, x0, y0 + h, x1, y1 + h));
+        }
+    }
+    return walk_segment(mu, n, pix, R, x0, y0, x1, y1);
+}
+
+struct TabArgsD {
+    const double *mu;
+    const double2 *pix;     // [Qp]
+    const double2 *dirs;    // [na]
+    const double2 *sc;      // [nsc]
+    float *g_qa, *g_qs;
+    ScatA *sa;
+};
+
+__global__ __launch_bounds__(256) void k_tab_qa(const DevSys S, const TabArgsD t, double pix,
+                                                double R)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = blockIdx.y;
+    if (i >= S.Qp) return;
+    float v = 0.f;
+    if (i < S.Qm) {
+        double2 p = t.pix[i], d = t.dirs[a];
+        double depth = R - (p.x * d.x + p.y * d.y);
+        v = (float)seg_integral(t.mu, S.n, pix, R, p.x, p.y, p.x + depth * d.x, p.y + depth * d.y);
+    }
+    t.g_qa[(size_t)a * S.Qp + i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_tab_qs(const DevSys S, const TabArgsD t, double pix,
+                                                double R)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = blockIdx.y;
+    if (i >= S.Qp) return;
+    float v = 0.f;
+    if (i < S.Qm) {
+        double2 p = t.pix[i], q = t.sc[s];
+        v = (float)seg_integral(t.mu, S.n, pix, R, p.x, p.y, q.x, q.y);
+    }
+    t.g_qs[(size_t)s * S.Qp + i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_tab_sa(const DevSys S, const TabArgsD t, double pix,
+                                                double R)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = blockIdx.y;
+    if (k >= S.nsc) return;
+    ScatA &e = t.sa[(size_t)a * S.nsc + k];
+    double2 q = t.sc[e.sidx], d = t.dirs[a];
+    double depth = R - (q.x * d.x + q.y * d.y);
+    e.gsa = (float)seg_integral(t.mu, S.n, pix, R, q.x, q.y, q.x + depth * d.x, q.y + depth * d.y);
+    double u = -q.x * d.y + q.y * d.x;
+    double isig = (double)e.isig;
+    double zhi = (R - u) * isig, zlo = (-R - u) * isig;
+    const double r2 = 0.70710678118654752;
+    double D;
+    if (zlo >= 0.0) D = 0.5 * (erfc(zlo * r2) - erfc(zhi * r2));
+    else if (zhi <= 0.0) D = 0.5 * (erfc(-zhi * r2) - erfc(-zlo * r2));
+    else D = 1.0 - 0.5 * erfc(zhi * r2) - 0.5 * erfc(-zlo * r2);
+    e.D = (float)D;
+}
+
+// ---------------------------------------------------------------------------
+// scatter-path parameters of one (pixel, scatter point, angle)
+// ---------------------------------------------------------------------------
+
+// For each line w: log2 of the path weight (with or without the energy
+// Gaussian's normalisation), the scaled Compton energy sw*E' and sw =
+// sqrt(log2(e) / (2 sigma'^2)), so that the energy factor of an event with
+// measured energy E is exp2(-(sw*E - Fw)^2).
+template <int NW, bool NORM>
+__device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float dy, float c,
+                                               float s, float lc, float gqs, float gsa,
+                                               float *Aw, float *sw, float *Fw, float *Ep)
+{
+    const float r2 = dx * dx + dy * dy;
+    const float rinv = fast_rsq(r2);
+    const float r = r2 * rinv;
+    const float reff = fmaxf(r, S.rmin);
+    const float cosphi = (dx * c + dy * s) * rinv;
+    const float omc = 1.f - cosphi;
+    const float sin2 = omc * (1.f + cosphi);
+    const float base = lc - fast_log2(reff);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+        const float invP = fmaf(S.eps[w], omc, 1.f);
+        const float P = fast_rcp(invP);
+        const float l2i = fast_log2(invP);
+        const float lK = fast_log2(P + invP - sin2) - 2.f * l2i;
+        const float fE = S.f[w] * fast_exp2(S.mu_pow * l2i);
+        const float att = (S.f[w] * gqs + fE * gsa) * kLog2e;
+        float A = base + S.lsc[w] + lK - att;
+        if (NORM) A += S.nc[w] + 0.5f * l2i;
+        Aw[w] = A;
+        const float e = S.E[w] * P;
+        Ep[w] = e;
+        const float sq = S.sqc0[w] * fast_sqrt(invP);
+        sw[w] = sq;
+        Fw[w] = sq * e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-event system model (the hot path)
+//
+// One wavefront per work item: 64 support pixels (one per lane) x one tile of
+// up to JT events of a single angle.  Every lane keeps JT accumulators a_jq in
+// registers.  For every scatter point of the tile's range the lane derives the
+// path parameters of its pixel once, then adds the JT events' terms; the
+// collimator-response factors of the tile's events for a block of 64 scatter
+// points are computed cooperatively (one scatter point per lane) into LDS and
+// read back as broadcasts, and a (event, scatter point) pair whose factor is
+// zero is skipped by a uniform branch.
+// ---------------------------------------------------------------------------
+template <int JT, int NW>
+__global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
+{
+    constexpr int KC = 16;                      // scatter points per response block
+    __shared__ float2 lds_pe[KC][JT + 1];       // (response factor, energy) per (scatter, event)
+    __shared__ float lds_gq[JT][NW];            // unscattered energy factor per (event, line)
+
+    const Tile T = r.tiles[blockIdx.y];
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * kWave + lane;
+    const int a = T.angle;
+    const float2 dir = r.dirs[a];
+    const float c = dir.x, s = dir.y;
+    const bool valid = i < S.Qm;
+
+    if (lane < JT) {
+        const float E = (lane < T.cnt) ? r.ev_E[T.e0 + lane] : 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+            const float d = E - S.E[w];
+            lds_gq[lane][w] = S.gnorm[w] * __expf(-d * d / (2.f * S.eres_k * S.E[w]));
+        }
+    }
+    __syncthreads();
+
+    const float2 xy = r.pix_xy[i];
+    const float xq = xy.x, yq = xy.y;
+
+    // unscattered paths: written straight to the output rows
+    {
+        const float dq = S.R - (xq * c + yq * s);
+        const float uq = -xq * s + yq * c;
+        const float isq = 1.f / ((S.fwhm0 + S.fslope * dq) * S.inv_fwhm_to_sigma);
+        const float gqa = r.g_qa[(size_t)a * S.Qp + i];
+        float Pp[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) Pp[w] = S.pp[w] * fast_exp2(-S.f[w] * gqa * kLog2e);
+        for (int j = 0; j < T.cnt; ++j) {
+            const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
+            const float ps = psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
+            float g = 0.f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+                g = fmaf(Pp[w], lds_gq[j][w], g);
+            }
+            r.A[(size_t)(T.e0 + j) * S.Qp + i] = ps * g;
+        }
+    }
+
+    float acc[JT];
+#pragma unroll
+    for (int j = 0; j < JT; ++j) acc[j] = 0.f;
+
+    const ScatA *sa = r.sa + (size_t)a * S.nsc;
+    const int kl = lane % KC, jg = lane / KC;   // response block: lane -> (scatter, event quarter)
+    for (int kc = T.k0; kc < T.k1; kc += KC) {
+        __syncthreads();
+        {
+            const int k = kc + kl;
+            if (k < T.k1) {
+                const ScatA sp = sa[k];
+                for (int j = jg * (JT / 4); j < (jg + 1) * (JT / 4); ++j) {
+                    float ps = 0.f, E = 0.f;
+                    if (j < T.cnt) {
+                        const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
+                        ps = psf_cut((lo + S.db - sp.u) * sp.isig, (lo - sp.u) * sp.isig);
+                        E = r.ev_E[T.e0 + j];
+                    }
+                    lds_pe[kl][j] = make_float2(ps, E);
+                }
+            }
+        }
+        __syncthreads();
+        const int kn = min(KC, T.k1 - kc);
+        for (int kk = 0; kk < kn; ++kk) {
+            const ScatA sp = sa[kc + kk];
+            const float gqs = r.g_qs[(size_t)sp.sidx * S.Qp + i];
+            float Aw[NW], sw[NW], Fw[NW], Ep[NW];
+            scatter_params<NW, true>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw, sw,
+                                     Fw, Ep);
+#pragma unroll
+            for (int j = 0; j < JT; ++j) {
+                const float2 pe = lds_pe[kk][j];
+                const float ps = uniform_f(pe.x);
+                if (ps != 0.f) {
+                    float t = 0.f;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+                        const float u = fmaf(sw[w], pe.y, -Fw[w]);
+                        t += fast_exp2(fmaf(-u, u, Aw[w]));
+                    }
+                    acc[j] = fmaf(ps, t, acc[j]);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < JT; ++j) {
+        if (j < T.cnt) {
+            float *dst = r.A + (size_t)(T.e0 + j) * S.Qp + i;
+            *dst = valid ? *dst + acc[j] : 0.f;
+        }
+    }
+}
+
+template <int JT>
+static hipError_t launch_row_jt(const DevSys &S, const RowArgs &r, hipStream_t st)
+{
+    dim3 grid(S.Qp / kWave, r.ntiles);
+    switch (S.nw) {
+    case 1: hipLaunchKernelGGL((k_row<JT, 1>), grid, dim3(kWave), 0, st, S, r); break;
+    case 2: hipLaunchKernelGGL((k_row<JT, 2>), grid, dim3(kWave), 0, st, S, r); break;
+    case 3: hipLaunchKernelGGL((k_row<JT, 3>), grid, dim3(kWave), 0, st, S, r); break;
+    case 4: hipLaunchKernelGGL((k_row<JT, 4>), grid, dim3(kWave), 0, st, S, r); break;
+    default:
+        hipLaunchKernelGGL((k_row<JT, LMMEW_MAX_LINES>), grid, dim3(kWave), 0, st, S, r);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st)
+{
+    if (r.ntiles == 0) return hipSuccess;
+    switch (event_tile) {
+    case 16: return launch_row_jt<16>(S, r, st);
+    case 32: return launch_row_jt<32>(S, r, st);
+    default: return launch_row_jt<64>(S, r, st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward projection: p_j = sum_q lambda_q a_jq, one wavefront per event row
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_forward(const DevSys S, const FwdArgs f)
+{
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= f.rows) return;
+    const float *lam = f.lambda + (size_t)f.row_case[e] * f.Q;
+    const float *A = f.A + (size_t)e * S.Qp;
+    float sum = 0.f;
+    for (int i = lane; i < S.Qm; i += kWave) sum = fmaf(lam[f.pixq[i]], A[i], sum);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, kWave);
+    if (lane == 0) {
+        f.p[e] = sum;
+        f.wt[e] = sum > 0.f ? 1.f / sum : 0.f;
+        if (f.logp) f.logp[e] = sum > 0.f ? log((double)sum) : 0.0;
+        if (f.nskip && !(sum > 0.f)) atomicAdd(f.nskip, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backprojection: compensated (Neumaier) column sums over a chunk of rows
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_back(const DevSys S, const BackArgs b)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= S.Qp) return;
+    const Chunk ch = b.chunks[blockIdx.y];
+    float sum = 0.f, cmp = 0.f;
+    for (int e = ch.r0; e < ch.r1; ++e) {
+        const float w = b.wt[e];
+        if (w == 0.f) continue;
+        const float v = b.A[(size_t)e * S.Qp + i] * w;
+        const float t = sum + v;
+        cmp += (fabsf(sum) >= fabsf(v)) ? (sum - t) + v : (v - t) + sum;
+        sum = t;
+    }
+    b.part[(size_t)blockIdx.y * S.Qp + i] = sum;
+    b.comp[(size_t)blockIdx.y * S.Qp + i] = cmp;
+}
+
+// ---------------------------------------------------------------------------
+// EM update (Eq. (18)): lambda_q <- lambda_q * B_q / sens_q, or the plain
+// backprojection B_q when no sensitivity is given
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_update(const DevSys S, const UpdArgs u)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= S.Qm) return;
+    float sum = 0.f, cmp = 0.f;
+    for (int ch = u.case_chunk[c]; ch < u.case_chunk[c + 1]; ++ch) {
+        const float v = u.part[(size_t)ch * S.Qp + i];
+        cmp += u.comp[(size_t)ch * S.Qp + i];
+        const float t = sum + v;
+        cmp += (fabsf(sum) >= fabsf(v)) ? (sum - t) + v : (v - t) + sum;
+        sum = t;
+    }
+    const float B = sum + cmp;
+    const int q = u.pixq[i];
+    float *lam = u.lambda + (size_t)c * u.Q;
+    if (u.sens) {
+        const float d = u.sens[q];
+        if (d > 0.f) lam[q] = lam[q] * B / d;
+    } else {
+        lam[q] = B;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sensitivity: per (pixel, angle) detection probability, then per subset
+// ---------------------------------------------------------------------------
+template <int NW>
+__global__ __launch_bounds__(64) void k_sens(const DevSys S, const SensArgs g)
+{
+    const int i = blockIdx.x * kWave + threadIdx.x;
+    const int a = blockIdx.y;
+    const float2 dir = g.dirs[a];
+    const float c = dir.x, s = dir.y;
+    const float2 xy = g.pix_xy[i];
+    const float xq = xy.x, yq = xy.y;
+    const float dq = S.R - (xq * c + yq * s);
+    const float uq = -xq * s + yq * c;
+    const float isq = 1.f / ((S.fwhm0 + S.fslope * dq) * S.inv_fwhm_to_sigma);
+    const float Dq = phi_diff((S.R - uq) * isq, (-S.R - uq) * isq);
+    const float gqa = g.g_qa[(size_t)a * S.Qp + i];
+
+    auto acceptance = [&](float E) {
+        const float isg = fast_rsq(S.eres_k * E);
+        float acc = 0.f;
+        for (int k = 0; k < S.nwin; ++k) acc += phi_diff((S.whi[k] - E) * isg, (S.wlo[k] - E) * isg);
+        return acc;
+    };
+
+    float tot = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+        tot += S.pp[w] * expf(-S.f[w] * gqa) * Dq * acceptance(S.E[w]);
+    }
+    const ScatA *sa = g.sa + (size_t)a * S.nsc;
+    float scat = 0.f;
+    for (int k = 0; k < S.nsc; ++k) {
+        const ScatA sp = sa[k];
+        const float gqs = g.g_qs[(size_t)sp.sidx * S.Qp + i];
+        float Aw[NW], sw[NW], Fw[NW], Ep[NW];
+        scatter_params<NW, false>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw, sw, Fw,
+                                  Ep);
+        float t = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+            t = fmaf(fast_exp2(Aw[w]), acceptance(Ep[w]), t);
+        }
+        scat = fmaf(sp.D, t, scat);
+    }
+    g.Sqa[(size_t)a * S.Qp + i] = (i < S.Qm) ? tot + scat : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_sens_subsets(const DevSys S, const SensArgs g)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int sub = blockIdx.y;
+    if (i >= S.Qm) return;
+    float acc = 0.f;
+    for (int a = sub; a < S.na; a += g.nsub) acc += g.Sqa[(size_t)a * S.Qp + i];
+    g.sens[(size_t)sub * g.Q + g.pixq[i]] = S.T * acc;
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loglik(const ReduceArgs r)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < r.rows; e += 256) acc += r.logp[e];
+    for (int c = 0; c < r.ncases; ++c)
+        for (int q = threadIdx.x; q < r.Q; q += 256)
+            acc -= (double)r.sens[q] * (double)r.lambda[(size_t)c * r.Q + q];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) r.out[0] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_out(const float *src, const int64_t *perm,
+                                                     int64_t n, float *dst)
+{
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) dst[perm[e]] = src[e];
+}
+
+__global__ __launch_bounds__(256) void k_gather_w(const float *w, const int64_t *perm, int64_t n,
+                                                  float *dst)
+{
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) dst[e] = w[perm[e]];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_tables_d(const DevSys &S, const double *mu, const double2 *pix,
+                           const double2 *dirs, const double2 *sc, float *g_qa, float *g_qs,
+                           ScatA *sa, double pixmm, double R, hipStream_t st)
+{
+    TabArgsD d{mu, pix, dirs, sc, g_qa, g_qs, sa};
+    hipLaunchKernelGGL(k_tab_qa, dim3((S.Qp + 255) / 256, S.na), dim3(256), 0, st, S, d, pixmm,
+                       R);
+    if (S.nsc > 0) {
+        hipLaunchKernelGGL(k_tab_qs, dim3((S.Qp + 255) / 256, S.nsc), dim3(256), 0, st, S, d,
+                           pixmm, R);
+        hipLaunchKernelGGL(k_tab_sa, dim3((S.nsc + 255) / 256, S.na), dim3(256), 0, st, S, d,
+                           pixmm, R);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const DevSys &S, const FwdArgs &f, hipStream_t st)
+{
+    if (f.rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_forward, dim3((f.rows + 3) / 4), dim3(256), 0, st, S, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_back(const DevSys &S, const BackArgs &b, hipStream_t st)
+{
+    if (b.nchunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_back, dim3((S.Qp + 255) / 256, b.nchunks), dim3(256), 0, st, S, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const DevSys &S, const UpdArgs &u, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update, dim3((S.Qm + 255) / 256, u.ncases), dim3(256), 0, st, S, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_sens(const DevSys &S, const SensArgs &g, hipStream_t st)
+{
+    dim3 grid(S.Qp / kWave, S.na);
+    switch (S.nw) {
+    case 1: hipLaunchKernelGGL((k_sens<1>), grid, dim3(kWave), 0, st, S, g); break;
+    case 2: hipLaunchKernelGGL((k_sens<2>), grid, dim3(kWave), 0, st, S, g); break;
+    case 3: hipLaunchKernelGGL((k_sens<3>), grid, dim3(kWave), 0, st, S, g); break;
+    case 4: hipLaunchKernelGGL((k_sens<4>), grid, dim3(kWave), 0, st, S, g); break;
+    default:
+        hipLaunchKernelGGL((k_sens<LMMEW_MAX_LINES>), grid, dim3(kWave), 0, st, S, g);
+        break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sens_subsets, dim3((S.Qm + 255) / 256, g.nsub), dim3(256), 0, st, S, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_loglik(const ReduceArgs &r, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_loglik, dim3(1), dim3(256), 0, st, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_out(const float *src, const int64_t *perm, int64_t n, float *dst,
+                              hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src,
+                       perm, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float *dst,
+                           hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_w, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, perm,
+                       n, dst);
+    return hipGetLastError();
+}
+
+}  // namespace lmmew

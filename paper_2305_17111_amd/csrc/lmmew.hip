@@ -1,0 +1,935 @@
+// Host side of the lmmew C ABI: context (attenuation tables), event plans
+// (validation, sorting, work tiles) and the OSEM driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace lmmew;
+
+struct lmmew_ctx {
+    lmmew_system sys{};
+    DevSys S{};
+    std::string err;
+    int Q = 0;
+    double R = 0, hs = 0, db = 0;
+    std::vector<int> pixq;            // [Qp] full-grid index of support pixel i, -1 for padding
+    std::vector<double> dir_c, dir_s; // [na]
+    std::vector<ScatA> sa;            // [na][nsc] host copy (x, y, u, isig, lc, sidx)
+    std::vector<double> sig_max;      // [na] largest PSF sigma over the scatter points
+    // device
+    float2 *d_pix = nullptr;
+    double2 *d_pixd = nullptr;
+    int *d_pixq = nullptr;
+    float2 *d_dirs = nullptr;
+    double2 *d_dirsd = nullptr;
+    double2 *d_scd = nullptr;
+    double *d_mu = nullptr;
+    float *d_gqa = nullptr, *d_gqs = nullptr;
+    ScatA *d_sa = nullptr;
+    float *d_Sqa = nullptr;
+};
+
+struct lmmew_plan {
+    lmmew_ctx *ctx = nullptr;
+    int nsub = 1, ncases = 1, JT = 64;
+    int64_t n = 0;
+    std::vector<int> bin, ang, cas;   // sorted rows
+    std::vector<float> E;
+    std::vector<int64_t> perm;        // sorted row -> input index
+    struct Sub {
+        int row0 = 0, rows = 0;
+        int tile0 = 0, ntiles = 0;
+        int chunk0 = 0, nchunks = 0;
+    };
+    std::vector<Sub> subs;
+    std::vector<int> case_chunk;      // [nsub][ncases+1], chunk index relative to the subset
+    std::vector<Tile> tiles;
+    std::vector<Chunk> chunks;
+    int max_rows = 0, max_chunks = 0;
+    double terms = 0, full_terms = 0;
+    // device
+    int *d_bin = nullptr, *d_case = nullptr, *d_case_chunk = nullptr;
+    float *d_E = nullptr;
+    int64_t *d_perm = nullptr;
+    Tile *d_tiles = nullptr;
+    Chunk *d_chunks = nullptr;
+    float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
+    double *d_logp = nullptr, *d_ll = nullptr;
+    float *d_part = nullptr, *d_comp = nullptr;
+    unsigned long long *d_nskip = nullptr;
+    int stats_cap = 0;
+};
+
+namespace {
+
+constexpr int kChunkRows = 128;
+constexpr size_t kScratchBudget = size_t(2) << 30;   // per-call a_jq scratch for forward/adjoint
+
+int fail(lmmew_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hipfail(lmmew_ctx *ctx, hipError_t e, const char *what)
+{
+    if (ctx) ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    return (e == hipErrorOutOfMemory) ? LMMEW_ENOMEM : LMMEW_EDEVICE;
+}
+
+#define HIPCHK(ctx, call)                                        \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hipfail((ctx), e_, #call);  \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+template <class T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+double fwhm_per_sigma() { return 2.0 * std::sqrt(2.0 * std::log(2.0)); }
+
+// Planar Klein-Nishina normaliser: integral over the circle of
+// P^2 (P + 1/P - sin^2 phi), by the periodic trapezoid rule.
+double kn_norm(double E, double me)
+{
+    const int N = 2048;
+    const double eps = E / me;
+    double s = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double ph = 2.0 * kPi * (k + 0.5) / N;
+        const double cp = std::cos(ph);
+        const double P = 1.0 / (1.0 + eps * (1.0 - cp));
+        s += P * P * (P + 1.0 / P - (1.0 - cp * cp));
+    }
+    return s * 2.0 * kPi / N;
+}
+
+void angle_dir(int a, int na, double *c, double *s)
+{
+    if ((4 * a) % na == 0) {
+        const int k = ((4 * a) / na) % 4;
+        const double cs[4] = {1, 0, -1, 0}, sn[4] = {0, 1, 0, -1};
+        *c = cs[k];
+        *s = sn[k];
+        return;
+    }
+    const double th = 2.0 * kPi * a / na;
+    *c = std::cos(th);
+    *s = std::sin(th);
+}
+
+int validate_sys(lmmew_ctx *ctx, const lmmew_system *s)
+{
+    if (s->n <= 0 || s->ns <= 0 || s->n % s->ns != 0 || ((s->n / s->ns) % 2) != 0)
+        return fail(ctx, LMMEW_EINVAL, "n must be a positive multiple of ns with an even ratio");
+    if (s->n_bins <= 0 || s->n_angles <= 0 || s->n_bins > 32767 || s->n_angles > 32767)
+        return fail(ctx, LMMEW_EINVAL, "n_bins and n_angles must be in 1..32767");
+    if (s->n_lines < 1 || s->n_lines > LMMEW_MAX_LINES)
+        return fail(ctx, LMMEW_EINVAL, "n_lines must be in 1..8");
+    if (s->n_windows < 1 || s->n_windows > LMMEW_MAX_WINDOWS)
+        return fail(ctx, LMMEW_EINVAL, "n_windows must be in 1..8");
+    if (!(s->pixel_mm > 0) || !(s->psf_fwhm0_mm > 0) || !(s->psf_fwhm_slope >= 0) ||
+        !(s->coll_dtheta > 0) || !(s->eres_frac > 0) || !(s->eres_ref_keV > 0) ||
+        !(s->mu_ref_keV > 0) || !std::isfinite(s->mu_power) || !(s->T > 0) ||
+        !(s->electron_keV > 0))
+        return fail(ctx, LMMEW_EINVAL, "non-positive or non-finite system parameter");
+    for (int w = 0; w < s->n_lines; ++w)
+        if (!(s->line_keV[w] > 0) || !(s->line_yield[w] >= 0) || !std::isfinite(s->line_keV[w]))
+            return fail(ctx, LMMEW_EINVAL, "bad emission line");
+    for (int k = 0; k < s->n_windows; ++k)
+        if (!(s->win_hi_keV[k] > s->win_lo_keV[k]) || !std::isfinite(s->win_lo_keV[k]) ||
+            !std::isfinite(s->win_hi_keV[k]))
+            return fail(ctx, LMMEW_EINVAL, "bad energy window");
+    return LMMEW_OK;
+}
+
+void free_ctx(lmmew_ctx *c)
+{
+    dfree(c->d_pix); dfree(c->d_pixd); dfree(c->d_pixq); dfree(c->d_dirs); dfree(c->d_dirsd);
+    dfree(c->d_scd); dfree(c->d_mu); dfree(c->d_gqa); dfree(c->d_gqs); dfree(c->d_sa);
+    dfree(c->d_Sqa);
+}
+
+void free_plan(lmmew_plan *p)
+{
+    dfree(p->d_bin); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
+    dfree(p->d_tiles); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
+    dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
+}
+
+bool in_window(const lmmew_system &s, float e)
+{
+    if (!std::isfinite(e)) return false;
+    for (int k = 0; k < s.n_windows; ++k)
+        if (e >= (float)s.win_lo_keV[k] && e <= (float)s.win_hi_keV[k]) return true;
+    return false;
+}
+
+// Relevant (not pruned) scatter points of one event: those whose collimator
+// response reaches the event's bin within kPsfCut standard deviations.
+int relevant_scatter(const lmmew_ctx *c, int a, int b)
+{
+    const int nsc = c->S.nsc;
+    const double lo = -c->R + b * c->db, hi = lo + c->db;
+    int cnt = 0;
+    for (int k = 0; k < nsc; ++k) {
+        const ScatA &sp = c->sa[(size_t)a * nsc + k];
+        const double zhi = (hi - sp.u) * sp.isig, zlo = (lo - sp.u) * sp.isig;
+        if (!(zlo >= kPsfCut || zhi <= -kPsfCut)) ++cnt;
+    }
+    return cnt;
+}
+
+// Builds tiles and chunks of a plan for the event tile size p->JT.
+void build_tiles(lmmew_plan *p)
+{
+    const lmmew_ctx *c = p->ctx;
+    const int nsc = c->S.nsc, na = c->S.na;
+    p->tiles.clear();
+    p->chunks.clear();
+    p->case_chunk.assign((size_t)p->nsub * (p->ncases + 1), 0);
+    p->max_chunks = 0;
+    for (int s = 0; s < p->nsub; ++s) {
+        lmmew_plan::Sub &sub = p->subs[s];
+        sub.tile0 = (int)p->tiles.size();
+        sub.chunk0 = (int)p->chunks.size();
+        int r = sub.row0;
+        const int rend = sub.row0 + sub.rows;
+        int *cc = &p->case_chunk[(size_t)s * (p->ncases + 1)];
+        int cur_case = 0;
+        // tiles: runs of <= JT rows with the same (case, angle)
+        while (r < rend) {
+            int e = r;
+            const int cs = p->cas[r], a = p->ang[r];
+            while (e < rend && e - r < p->JT && p->cas[e] == cs && p->ang[e] == a) ++e;
+            int bmin = p->bin[r], bmax = p->bin[r];
+            for (int k = r; k < e; ++k) {
+                bmin = std::min(bmin, p->bin[k]);
+                bmax = std::max(bmax, p->bin[k]);
+            }
+            const double reach = kPsfCut * c->sig_max[a];
+            const float ulo = (float)(-c->R + bmin * c->db - reach);
+            const float uhi = (float)(-c->R + (bmax + 1) * c->db + reach);
+            const ScatA *sa = &c->sa[(size_t)a * nsc];
+            int k0 = 0, k1 = nsc;
+            while (k0 < nsc && sa[k0].u < ulo) ++k0;
+            while (k1 > k0 && sa[k1 - 1].u > uhi) --k1;
+            Tile t{};
+            t.e0 = r - sub.row0;
+            t.cnt = e - r;
+            t.angle = a;
+            t.ncase = cs;
+            t.k0 = k0;
+            t.k1 = k1;
+            p->tiles.push_back(t);
+            r = e;
+        }
+        sub.ntiles = (int)p->tiles.size() - sub.tile0;
+        // chunks: runs of <= kChunkRows rows of one case
+        r = sub.row0;
+        for (int cs = 0; cs < p->ncases; ++cs) {
+            cc[cs] = (int)p->chunks.size() - sub.chunk0;
+            while (r < rend && p->cas[r] == cs) {
+                int e = r;
+                while (e < rend && e - r < kChunkRows && p->cas[e] == cs) ++e;
+                Chunk ch{};
+                ch.r0 = r - sub.row0;
+                ch.r1 = e - sub.row0;
+                ch.ncase = cs;
+                p->chunks.push_back(ch);
+                r = e;
+            }
+            cur_case = cs;
+        }
+        (void)cur_case;
+        cc[p->ncases] = (int)p->chunks.size() - sub.chunk0;
+        sub.nchunks = (int)p->chunks.size() - sub.chunk0;
+        p->max_chunks = std::max(p->max_chunks, sub.nchunks);
+    }
+    (void)na;
+}
+
+int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
+{
+    dfree(p->d_tiles);
+    dfree(p->d_chunks);
+    dfree(p->d_case_chunk);
+    dfree(p->d_part);
+    dfree(p->d_comp);
+    HIPCHK(ctx, dalloc(&p->d_tiles, p->tiles.size()));
+    HIPCHK(ctx, dalloc(&p->d_chunks, p->chunks.size()));
+    HIPCHK(ctx, dalloc(&p->d_case_chunk, p->case_chunk.size()));
+    const size_t total_chunks = std::max<size_t>(p->chunks.size(), 1);
+    HIPCHK(ctx, dalloc(&p->d_part, total_chunks * ctx->S.Qp));
+    HIPCHK(ctx, dalloc(&p->d_comp, total_chunks * ctx->S.Qp));
+    if (!p->tiles.empty())
+        HIPCHK(ctx, hipMemcpyAsync(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile),
+                                   hipMemcpyHostToDevice, st));
+    if (!p->chunks.empty())
+        HIPCHK(ctx, hipMemcpyAsync(p->d_chunks, p->chunks.data(),
+                                   p->chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_case_chunk, p->case_chunk.data(),
+                               p->case_chunk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return LMMEW_OK;
+}
+
+int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets, int n_cases,
+              int n_subsets, hipStream_t st, lmmew_plan **out)
+{
+    *out = nullptr;
+    if (!ev || ev->n < 0 || (ev->n > 0 && (!ev->bin || !ev->angle || !ev->energy_keV)))
+        return fail(ctx, LMMEW_EINVAL, "events: NULL array or negative count");
+    if (n_subsets < 1 || n_subsets > ctx->S.na)
+        return fail(ctx, LMMEW_EINVAL, "n_subsets must be in 1..n_angles");
+    if (n_cases < 1) return fail(ctx, LMMEW_EINVAL, "n_cases must be >= 1");
+    const int64_t n = ev->n;
+    if (n > ((int64_t)1 << 31) - 1) return fail(ctx, LMMEW_EINVAL, "too many events");
+    std::vector<int64_t> off(n_cases + 1);
+    if (case_offsets) {
+        for (int c = 0; c <= n_cases; ++c) off[c] = case_offsets[c];
+        if (off[0] != 0 || off[n_cases] != n)
+            return fail(ctx, LMMEW_EINVAL, "case_offsets must start at 0 and end at n");
+        for (int c = 0; c < n_cases; ++c)
+            if (off[c + 1] < off[c]) return fail(ctx, LMMEW_EINVAL, "case_offsets not sorted");
+    } else {
+        if (n_cases != 1) return fail(ctx, LMMEW_EINVAL, "case_offsets required for n_cases > 1");
+        off[0] = 0;
+        off[1] = n;
+    }
+    std::vector<int16_t> hb(n), ha(n);
+    std::vector<float> he(n);
+    if (n > 0) {
+        HIPCHK(ctx, hipMemcpyAsync(hb.data(), ev->bin, n * sizeof(int16_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(ha.data(), ev->angle, n * sizeof(int16_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(he.data(), ev->energy_keV, n * sizeof(float),
+                                   hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+    }
+    const lmmew_system &s = ctx->sys;
+    for (int64_t j = 0; j < n; ++j) {
+        if (hb[j] < 0 || hb[j] >= s.n_bins || ha[j] < 0 || ha[j] >= s.n_angles ||
+            !in_window(s, he[j])) {
+            char buf[160];
+            snprintf(buf, sizeof buf,
+                     "event %lld invalid (bin %d, angle %d, energy %g keV)", (long long)j,
+                     (int)hb[j], (int)ha[j], (double)he[j]);
+            return fail(ctx, LMMEW_EINVAL, buf);
+        }
+    }
+    lmmew_plan *p = new (std::nothrow) lmmew_plan;
+    if (!p) return fail(ctx, LMMEW_ENOMEM, "host allocation");
+    p->ctx = ctx;
+    p->nsub = n_subsets;
+    p->ncases = n_cases;
+    p->n = n;
+    std::vector<int> casev(n);
+    for (int c = 0; c < n_cases; ++c)
+        for (int64_t j = off[c]; j < off[c + 1]; ++j) casev[j] = c;
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        const int sx = ha[x] % n_subsets, sy = ha[y] % n_subsets;
+        if (sx != sy) return sx < sy;
+        if (casev[x] != casev[y]) return casev[x] < casev[y];
+        if (ha[x] != ha[y]) return ha[x] < ha[y];
+        if (hb[x] != hb[y]) return hb[x] < hb[y];
+        return he[x] < he[y];
+    });
+    p->bin.resize(n);
+    p->ang.resize(n);
+    p->cas.resize(n);
+    p->E.resize(n);
+    p->perm = order;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t j = order[r];
+        p->bin[r] = hb[j];
+        p->ang[r] = ha[j];
+        p->cas[r] = casev[j];
+        p->E[r] = he[j];
+    }
+    p->subs.assign(n_subsets, {});
+    {
+        int64_t r = 0;
+        for (int sidx = 0; sidx < n_subsets; ++sidx) {
+            p->subs[sidx].row0 = (int)r;
+            while (r < n && p->ang[r] % n_subsets == sidx) ++r;
+            p->subs[sidx].rows = (int)r - p->subs[sidx].row0;
+            p->max_rows = std::max(p->max_rows, p->subs[sidx].rows);
+        }
+    }
+    // algorithmic terms per iteration
+    {
+        const double QW = (double)ctx->S.Qm * ctx->S.nw;
+        std::vector<int> rel_cache((size_t)s.n_angles * s.n_bins, -1);
+        double t = 0;
+        for (int64_t r = 0; r < n; ++r) {
+            int &rc = rel_cache[(size_t)p->ang[r] * s.n_bins + p->bin[r]];
+            if (rc < 0) rc = relevant_scatter(ctx, p->ang[r], p->bin[r]);
+            t += QW * (1.0 + rc);
+        }
+        p->terms = t;
+        p->full_terms = (double)n * QW * (1.0 + ctx->S.nsc);
+    }
+    build_tiles(p);
+    const int Qp = ctx->S.Qp;
+    auto fin = [&](int code) {
+        if (code != LMMEW_OK) {
+            free_plan(p);
+            delete p;
+        }
+        return code;
+    };
+#define PCHK(call)                                               \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return fin(hipfail(ctx, e_, #call)); \
+    } while (0)
+    PCHK(dalloc(&p->d_bin, n));
+    PCHK(dalloc(&p->d_case, n));
+    PCHK(dalloc(&p->d_E, n));
+    PCHK(dalloc(&p->d_perm, n));
+    PCHK(dalloc(&p->d_p, n));
+    PCHK(dalloc(&p->d_wt, n));
+    PCHK(dalloc(&p->d_logp, n));
+    PCHK(dalloc(&p->d_A, (size_t)std::max(p->max_rows, 1) * Qp));
+    if (n > 0) {
+        PCHK(hipMemcpyAsync(p->d_bin, p->bin.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(p->d_case, p->cas.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(p->d_E, p->E.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(p->d_perm, p->perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice,
+                            st));
+    }
+    const int rc = upload_tiles(ctx, p, st);
+    if (rc != LMMEW_OK) return fin(rc);
+#undef PCHK
+    *out = p;
+    return LMMEW_OK;
+}
+
+int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st)
+{
+    const lmmew_plan::Sub &sub = p->subs[s];
+    RowArgs r{};
+    r.pix_xy = ctx->d_pix;
+    r.dirs = ctx->d_dirs;
+    r.g_qa = ctx->d_gqa;
+    r.g_qs = ctx->d_gqs;
+    r.sa = ctx->d_sa;
+    r.tiles = p->d_tiles + sub.tile0;
+    r.ntiles = sub.ntiles;
+    r.ev_bin = p->d_bin + sub.row0;
+    r.ev_E = p->d_E + sub.row0;
+    r.A = p->d_A;
+    HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
+    return LMMEW_OK;
+}
+
+int run_forward(lmmew_ctx *ctx, lmmew_plan *p, int s, const float *lambda, bool stats, int k,
+                hipStream_t st)
+{
+    const lmmew_plan::Sub &sub = p->subs[s];
+    FwdArgs f{};
+    f.A = p->d_A;
+    f.rows = sub.rows;
+    f.row_case = p->d_case + sub.row0;
+    f.pixq = ctx->d_pixq;
+    f.lambda = lambda;
+    f.Q = ctx->Q;
+    f.p = p->d_p + sub.row0;
+    f.wt = p->d_wt + sub.row0;
+    f.logp = stats ? p->d_logp + sub.row0 : nullptr;
+    f.nskip = stats ? p->d_nskip + k : nullptr;
+    HIPCHK(ctx, launch_forward(ctx->S, f, st));
+    return LMMEW_OK;
+}
+
+int run_back(lmmew_ctx *ctx, lmmew_plan *p, int s, const float *wt_rows, float *part, float *comp,
+             hipStream_t st)
+{
+    const lmmew_plan::Sub &sub = p->subs[s];
+    BackArgs b{};
+    b.A = p->d_A;
+    b.wt = wt_rows;
+    b.chunks = p->d_chunks + sub.chunk0;
+    b.nchunks = sub.nchunks;
+    b.part = part;
+    b.comp = comp;
+    HIPCHK(ctx, launch_back(ctx->S, b, st));
+    return LMMEW_OK;
+}
+
+int ensure_stats(lmmew_ctx *ctx, lmmew_plan *p, int count)
+{
+    if (p->stats_cap >= count) return LMMEW_OK;
+    dfree(p->d_nskip);
+    dfree(p->d_ll);
+    HIPCHK(ctx, dalloc(&p->d_nskip, count));
+    HIPCHK(ctx, dalloc(&p->d_ll, count));
+    p->stats_cap = count;
+    return LMMEW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lmmew_status_string(int status)
+{
+    switch (status) {
+    case LMMEW_OK: return "ok";
+    case LMMEW_EINVAL: return "invalid argument";
+    case LMMEW_ENOMEM: return "out of memory";
+    case LMMEW_EDEVICE: return "device error";
+    case LMMEW_ENUMERIC: return "non-finite result";
+    default: return "unknown status";
+    }
+}
+
+const char *lmmew_last_error(const lmmew_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *support,
+                 hipStream_t st, lmmew_ctx **out)
+{
+    if (!out) return LMMEW_EINVAL;
+    *out = nullptr;
+    if (!sys || !mu85) return LMMEW_EINVAL;
+    lmmew_ctx *ctx = new (std::nothrow) lmmew_ctx;
+    if (!ctx) return LMMEW_ENOMEM;
+    auto bail = [&](int code) {
+        if (code != LMMEW_OK) {
+            free_ctx(ctx);
+            delete ctx;
+        }
+        return code;
+    };
+    int rc = validate_sys(ctx, sys);
+    if (rc != LMMEW_OK) return bail(rc);
+    ctx->sys = *sys;
+    const lmmew_system &s = *sys;
+    const int n = s.n, Q = n * n, na = s.n_angles, ns = s.ns, m = n / ns;
+    ctx->Q = Q;
+    const double pix = s.pixel_mm, R = 0.5 * n * pix, hs = 2.0 * R / ns, db = 2.0 * R / s.n_bins;
+    ctx->R = R;
+    ctx->hs = hs;
+    ctx->db = db;
+
+    std::vector<float> mu_f(Q);
+    std::vector<uint8_t> mask(Q, 1);
+#define CCHK(call)                                                 \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return bail(hipfail(ctx, e_, #call)); \
+    } while (0)
+    CCHK(hipMemcpyAsync(mu_f.data(), mu85, Q * sizeof(float), hipMemcpyDeviceToHost, st));
+    if (support) CCHK(hipMemcpyAsync(mask.data(), support, Q, hipMemcpyDeviceToHost, st));
+    CCHK(hipStreamSynchronize(st));
+    std::vector<double> mu(Q);
+    for (int q = 0; q < Q; ++q) {
+        if (!std::isfinite(mu_f[q]) || mu_f[q] < 0.f)
+            return bail(fail(ctx, LMMEW_EINVAL, "mu85 must be finite and >= 0"));
+        mu[q] = mu_f[q];
+    }
+    // support pixels
+    std::vector<double> px, py;
+    std::vector<int> pq;
+    for (int q = 0; q < Q; ++q) {
+        const double x = ((q % n) + 0.5) * pix - R, y = ((q / n) + 0.5) * pix - R;
+        if (x * x + y * y <= R * R && mask[q]) {
+            px.push_back(x);
+            py.push_back(y);
+            pq.push_back(q);
+        }
+    }
+    const int Qm = (int)pq.size();
+    const int Qp = std::max(kWave, (Qm + kWave - 1) / kWave * kWave);
+    std::vector<float2> pix_f(Qp);
+    std::vector<double2> pix_d(Qp);
+    ctx->pixq.assign(Qp, -1);
+    for (int i = 0; i < Qp; ++i) {
+        const double x = i < Qm ? px[i] : -10.0 * R, y = i < Qm ? py[i] : -10.0 * R;
+        pix_f[i] = make_float2((float)x, (float)y);
+        pix_d[i] = make_double2(x, y);
+        if (i < Qm) ctx->pixq[i] = pq[i];
+    }
+    // scatter points: cell centres with mean attenuation of the covered pixels
+    std::vector<double2> sc;
+    std::vector<double> smu;
+    for (int ky = 0; ky < ns; ++ky)
+        for (int kx = 0; kx < ns; ++kx) {
+            const double x = (kx + 0.5) * hs - R, y = (ky + 0.5) * hs - R;
+            double acc = 0.0;
+            for (int j = 0; j < m; ++j)
+                for (int i = 0; i < m; ++i) acc += mu[(size_t)(ky * m + j) * n + (kx * m + i)];
+            acc /= (double)(m * m);
+            if (x * x + y * y <= R * R && acc > 0.0) {
+                sc.push_back(make_double2(x, y));
+                smu.push_back(acc);
+            }
+        }
+    const int nsc = (int)sc.size();
+    // directions and per-angle scatter lists sorted by lateral coordinate
+    ctx->dir_c.resize(na);
+    ctx->dir_s.resize(na);
+    std::vector<float2> dirs_f(na);
+    std::vector<double2> dirs_d(na);
+    for (int a = 0; a < na; ++a) {
+        angle_dir(a, na, &ctx->dir_c[a], &ctx->dir_s[a]);
+        dirs_f[a] = make_float2((float)ctx->dir_c[a], (float)ctx->dir_s[a]);
+        dirs_d[a] = make_double2(ctx->dir_c[a], ctx->dir_s[a]);
+    }
+    const double fps = fwhm_per_sigma();
+    ctx->sa.resize((size_t)na * nsc);
+    ctx->sig_max.assign(na, 0.0);
+    for (int a = 0; a < na; ++a) {
+        const double c = ctx->dir_c[a], sn = ctx->dir_s[a];
+        std::vector<int> idx(nsc);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::vector<double> u(nsc);
+        for (int k = 0; k < nsc; ++k) u[k] = -sc[k].x * sn + sc[k].y * c;
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return u[x] < u[y]; });
+        for (int k = 0; k < nsc; ++k) {
+            const int si = idx[k];
+            const double depth = R - (sc[si].x * c + sc[si].y * sn);
+            const double sig = (s.psf_fwhm0_mm + s.psf_fwhm_slope * depth) / fps;
+            ctx->sig_max[a] = std::max(ctx->sig_max[a], sig);
+            ScatA e{};
+            e.x = (float)sc[si].x;
+            e.y = (float)sc[si].y;
+            e.u = (float)u[si];
+            e.isig = (float)(1.0 / sig);
+            e.gsa = 0.f;
+            e.lc = (float)std::log2(hs * hs * smu[si] / (2.0 * kPi));
+            e.D = 0.f;
+            e.sidx = si;
+            ctx->sa[(size_t)a * nsc + k] = e;
+        }
+    }
+    // constants
+    DevSys &S = ctx->S;
+    S.n = n;
+    S.ns = ns;
+    S.nb = s.n_bins;
+    S.na = na;
+    S.nw = s.n_lines;
+    S.nwin = s.n_windows;
+    S.Qm = Qm;
+    S.Qp = Qp;
+    S.nsc = nsc;
+    S.pix = (float)pix;
+    S.R = (float)R;
+    S.hs = (float)hs;
+    S.db = (float)db;
+    S.fwhm0 = (float)s.psf_fwhm0_mm;
+    S.fslope = (float)s.psf_fwhm_slope;
+    S.inv_fwhm_to_sigma = (float)(1.0 / fps);
+    S.T = (float)s.T;
+    const double k = s.eres_frac * s.eres_frac * s.eres_ref_keV / (fps * fps);
+    S.eres_k = (float)k;
+    S.mu_pow = (float)s.mu_power;
+    S.rmin = (float)(hs / (2.0 * std::sqrt(kPi)));
+    const double log2e = 1.0 / std::log(2.0);
+    for (int w = 0; w < s.n_lines; ++w) {
+        const double E = s.line_keV[w];
+        const double f = std::pow(E / s.mu_ref_keV, -s.mu_power);
+        const double Z = kn_norm(E, s.electron_keV);
+        S.E[w] = (float)E;
+        S.eps[w] = (float)(E / s.electron_keV);
+        S.f[w] = (float)f;
+        S.pp[w] = (float)(s.line_yield[w] * s.coll_dtheta / (2.0 * kPi));
+        S.lsc[w] = (float)std::log2(s.line_yield[w] * f * s.coll_dtheta / Z);
+        S.c0[w] = (float)(log2e / (2.0 * k * E));
+        S.sqc0[w] = (float)std::sqrt(log2e / (2.0 * k * E));
+        S.nc[w] = (float)(-0.5 * std::log2(2.0 * kPi * k * E));
+        S.gnorm[w] = (float)(1.0 / std::sqrt(2.0 * kPi * k * E));
+    }
+    for (int w = 0; w < s.n_windows; ++w) {
+        S.wlo[w] = (float)s.win_lo_keV[w];
+        S.whi[w] = (float)s.win_hi_keV[w];
+    }
+    // device tables
+    CCHK(dalloc(&ctx->d_pix, Qp));
+    CCHK(dalloc(&ctx->d_pixd, Qp));
+    CCHK(dalloc(&ctx->d_pixq, Qp));
+    CCHK(dalloc(&ctx->d_dirs, na));
+    CCHK(dalloc(&ctx->d_dirsd, na));
+    CCHK(dalloc(&ctx->d_scd, nsc));
+    CCHK(dalloc(&ctx->d_mu, Q));
+    CCHK(dalloc(&ctx->d_gqa, (size_t)na * Qp));
+    CCHK(dalloc(&ctx->d_gqs, (size_t)std::max(nsc, 1) * Qp));
+    CCHK(dalloc(&ctx->d_sa, (size_t)na * std::max(nsc, 1)));
+    CCHK(hipMemcpyAsync(ctx->d_pix, pix_f.data(), Qp * sizeof(float2), hipMemcpyHostToDevice, st));
+    CCHK(hipMemcpyAsync(ctx->d_pixd, pix_d.data(), Qp * sizeof(double2), hipMemcpyHostToDevice, st));
+    CCHK(hipMemcpyAsync(ctx->d_pixq, ctx->pixq.data(), Qp * sizeof(int), hipMemcpyHostToDevice, st));
+    CCHK(hipMemcpyAsync(ctx->d_dirs, dirs_f.data(), na * sizeof(float2), hipMemcpyHostToDevice, st));
+    CCHK(hipMemcpyAsync(ctx->d_dirsd, dirs_d.data(), na * sizeof(double2), hipMemcpyHostToDevice, st));
+    if (nsc > 0) {
+        CCHK(hipMemcpyAsync(ctx->d_scd, sc.data(), nsc * sizeof(double2), hipMemcpyHostToDevice, st));
+        CCHK(hipMemcpyAsync(ctx->d_sa, ctx->sa.data(), ctx->sa.size() * sizeof(ScatA),
+                            hipMemcpyHostToDevice, st));
+    }
+    CCHK(hipMemcpyAsync(ctx->d_mu, mu.data(), Q * sizeof(double), hipMemcpyHostToDevice, st));
+    CCHK(launch_tables_d(S, ctx->d_mu, ctx->d_pixd, ctx->d_dirsd, ctx->d_scd, ctx->d_gqa,
+                         ctx->d_gqs, ctx->d_sa, pix, R, st));
+    CCHK(hipStreamSynchronize(st));
+#undef CCHK
+    *out = ctx;
+    return LMMEW_OK;
+}
+
+int lmmew_destroy(lmmew_ctx *ctx)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    (void)hipDeviceSynchronize();
+    free_ctx(ctx);
+    delete ctx;
+    return LMMEW_OK;
+}
+
+int lmmew_sensitivity(lmmew_ctx *ctx, int n_subsets, float *sens, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!sens) return fail(ctx, LMMEW_EINVAL, "sens is NULL");
+    if (n_subsets < 1 || n_subsets > ctx->S.na)
+        return fail(ctx, LMMEW_EINVAL, "n_subsets must be in 1..n_angles");
+    if (!ctx->d_Sqa) HIPCHK(ctx, dalloc(&ctx->d_Sqa, (size_t)ctx->S.na * ctx->S.Qp));
+    HIPCHK(ctx, hipMemsetAsync(sens, 0, (size_t)n_subsets * ctx->Q * sizeof(float), st));
+    SensArgs g{};
+    g.pix_xy = ctx->d_pix;
+    g.dirs = ctx->d_dirs;
+    g.g_qa = ctx->d_gqa;
+    g.g_qs = ctx->d_gqs;
+    g.sa = ctx->d_sa;
+    g.pixq = ctx->d_pixq;
+    g.Sqa = ctx->d_Sqa;
+    g.sens = sens;
+    g.nsub = n_subsets;
+    g.Q = ctx->Q;
+    HIPCHK(ctx, launch_sens(ctx->S, g, st));
+    return LMMEW_OK;
+}
+
+static int subsets_for_budget(const lmmew_ctx *ctx, int64_t n)
+{
+    const size_t row = (size_t)ctx->S.Qp * sizeof(float);
+    int nsub = 1;
+    while (nsub < ctx->S.na && (size_t)(n / nsub + 64) * row > kScratchBudget) nsub *= 2;
+    return std::min(nsub, ctx->S.na);
+}
+
+int lmmew_forward(lmmew_ctx *ctx, const lmmew_events *ev, const float *lambda, float *p,
+                  hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!ev || !lambda || (!p && ev->n > 0)) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    lmmew_plan *pl = nullptr;
+    int rc = make_plan(ctx, ev, nullptr, 1, subsets_for_budget(ctx, ev->n), st, &pl);
+    if (rc != LMMEW_OK) return rc;
+    for (int s = 0; s < pl->nsub && rc == LMMEW_OK; ++s) {
+        rc = run_rows(ctx, pl, s, st);
+        if (rc == LMMEW_OK) rc = run_forward(ctx, pl, s, lambda, false, 0, st);
+    }
+    if (rc == LMMEW_OK) {
+        hipError_t e = launch_scatter_out(pl->d_p, pl->d_perm, pl->n, p, st);
+        if (e != hipSuccess) rc = hipfail(ctx, e, "scatter");
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (rc == LMMEW_OK && e != hipSuccess) rc = hipfail(ctx, e, "synchronize");
+    lmmew_plan_destroy(pl);
+    return rc;
+}
+
+int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, float *out,
+                      hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!ev || !out || (!w && ev->n > 0)) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    lmmew_plan *pl = nullptr;
+    int rc = make_plan(ctx, ev, nullptr, 1, subsets_for_budget(ctx, ev->n), st, &pl);
+    if (rc != LMMEW_OK) return rc;
+    hipError_t e = hipMemsetAsync(out, 0, (size_t)ctx->Q * sizeof(float), st);
+    if (e != hipSuccess) rc = hipfail(ctx, e, "memset");
+    if (rc == LMMEW_OK) {
+        e = launch_gather_w(w, pl->d_perm, pl->n, pl->d_wt, st);
+        if (e != hipSuccess) rc = hipfail(ctx, e, "gather");
+    }
+    for (int s = 0; s < pl->nsub && rc == LMMEW_OK; ++s) {
+        const lmmew_plan::Sub &sub = pl->subs[s];
+        rc = run_rows(ctx, pl, s, st);
+        if (rc == LMMEW_OK)
+            rc = run_back(ctx, pl, s, pl->d_wt + sub.row0, pl->d_part + (size_t)sub.chunk0 * ctx->S.Qp,
+                          pl->d_comp + (size_t)sub.chunk0 * ctx->S.Qp, st);
+    }
+    if (rc == LMMEW_OK) {
+        const int total = (int)pl->chunks.size();
+        int *d_cc = nullptr;
+        const int cc[2] = {0, total};
+        e = dalloc(&d_cc, 2);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_cc, cc, sizeof cc, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+            UpdArgs u{};
+            u.part = pl->d_part;
+            u.comp = pl->d_comp;
+            u.case_chunk = d_cc;
+            u.ncases = 1;
+            u.pixq = ctx->d_pixq;
+            u.Q = ctx->Q;
+            u.sens = nullptr;
+            u.lambda = out;
+            e = launch_update(ctx->S, u, st);
+        }
+        hipError_t e2 = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = e2;
+        dfree(d_cc);
+        if (e != hipSuccess) rc = hipfail(ctx, e, "backprojection");
+    } else {
+        (void)hipStreamSynchronize(st);
+    }
+    lmmew_plan_destroy(pl);
+    return rc;
+}
+
+int lmmew_plan_create(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets,
+                      int n_cases, int n_subsets, hipStream_t st, lmmew_plan **out)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!out) return fail(ctx, LMMEW_EINVAL, "out is NULL");
+    return make_plan(ctx, ev, case_offsets, n_cases, n_subsets, st, out);
+}
+
+int lmmew_plan_destroy(lmmew_plan *plan)
+{
+    if (!plan) return LMMEW_EINVAL;
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    delete plan;
+    return LMMEW_OK;
+}
+
+int lmmew_plan_set_event_tile(lmmew_ctx *ctx, lmmew_plan *plan, int event_tile, hipStream_t st)
+{
+    if (!ctx || !plan || plan->ctx != ctx) return LMMEW_EINVAL;
+    if (event_tile != 16 && event_tile != 32 && event_tile != 64)
+        return fail(ctx, LMMEW_EINVAL, "event_tile must be 16, 32 or 64");
+    if (event_tile == plan->JT) return LMMEW_OK;
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    plan->JT = event_tile;
+    build_tiles(plan);
+    return upload_tiles(ctx, plan, st);
+}
+
+int lmmew_plan_get_event_tile(const lmmew_plan *plan) { return plan ? plan->JT : 0; }
+
+int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full_terms)
+{
+    if (!plan) return LMMEW_EINVAL;
+    if (out_terms) *out_terms = plan->terms;
+    if (out_full_terms) *out_full_terms = plan->full_terms;
+    return LMMEW_OK;
+}
+
+static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, const float *sens,
+                    float *lambda, lmmew_stats *stats, hipStream_t st)
+{
+    const int K = count;
+    const bool want = stats != nullptr;
+    if (want) {
+        int rc = ensure_stats(ctx, p, std::max(K, 1));
+        if (rc != LMMEW_OK) return rc;
+        HIPCHK(ctx, hipMemsetAsync(p->d_nskip, 0, sizeof(unsigned long long) * std::max(K, 1), st));
+    }
+    for (int k = 0; k < K; ++k) {
+        const int s = (first_subset + k) % p->nsub;
+        const lmmew_plan::Sub &sub = p->subs[s];
+        int rc = run_rows(ctx, p, s, st);
+        if (rc == LMMEW_OK) rc = run_forward(ctx, p, s, lambda, want, k, st);
+        if (rc != LMMEW_OK) return rc;
+        if (want) {
+            ReduceArgs ra{};
+            ra.logp = p->d_logp + sub.row0;
+            ra.rows = sub.rows;
+            ra.sens = sens + (size_t)s * ctx->Q;
+            ra.lambda = lambda;
+            ra.ncases = p->ncases;
+            ra.Q = ctx->Q;
+            ra.out = p->d_ll + k;
+            HIPCHK(ctx, launch_loglik(ra, st));
+        }
+        rc = run_back(ctx, p, s, p->d_wt + sub.row0, p->d_part, p->d_comp, st);
+        if (rc != LMMEW_OK) return rc;
+        UpdArgs u{};
+        u.part = p->d_part;
+        u.comp = p->d_comp;
+        u.case_chunk = p->d_case_chunk + (size_t)s * (p->ncases + 1);
+        u.ncases = p->ncases;
+        u.pixq = ctx->d_pixq;
+        u.Q = ctx->Q;
+        u.sens = sens + (size_t)s * ctx->Q;
+        u.lambda = lambda;
+        HIPCHK(ctx, launch_update(ctx->S, u, st));
+    }
+    if (want) {
+        std::vector<unsigned long long> sk(std::max(K, 1));
+        std::vector<double> ll(std::max(K, 1));
+        std::vector<float> lam((size_t)p->ncases * ctx->Q);
+        HIPCHK(ctx, hipMemcpyAsync(sk.data(), p->d_nskip, sk.size() * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(ll.data(), p->d_ll, ll.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(lam.data(), lambda, lam.size() * sizeof(float),
+                                   hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        stats->skipped_total = 0;
+        for (int i = 0; i < K; ++i) {
+            stats->skipped_total += (int64_t)sk[i];
+            if (stats->skipped) stats->skipped[i] = (int64_t)sk[i];
+            if (stats->subset_loglik) stats->subset_loglik[i] = ll[i];
+        }
+        for (float v : lam)
+            if (!std::isfinite(v)) return fail(ctx, LMMEW_ENUMERIC, "non-finite image value");
+    }
+    return LMMEW_OK;
+}
+
+int lmmew_osem_iter(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *sens, float *lambda,
+                    lmmew_stats *stats, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!p || p->ctx != ctx) return fail(ctx, LMMEW_EINVAL, "plan does not belong to context");
+    if (!sens || !lambda) return fail(ctx, LMMEW_EINVAL, "NULL image or sensitivity");
+    if (n_iters < 0) return fail(ctx, LMMEW_EINVAL, "n_iters < 0");
+    return osem_run(ctx, p, 0, n_iters * p->nsub, sens, lambda, stats, st);
+}
+
+int lmmew_osem_subiter(lmmew_ctx *ctx, lmmew_plan *p, int subset, const float *sens,
+                       float *lambda, lmmew_stats *stats, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!p || p->ctx != ctx) return fail(ctx, LMMEW_EINVAL, "plan does not belong to context");
+    if (!sens || !lambda) return fail(ctx, LMMEW_EINVAL, "NULL image or sensitivity");
+    if (subset < 0 || subset >= p->nsub) return fail(ctx, LMMEW_EINVAL, "subset out of range");
+    return osem_run(ctx, p, subset, 1, sens, lambda, stats, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+"""Writes the oracle's expected values used by the GPU parity tests.
+
+Calls only the FP64 oracle (oracle/) and the seeded input generators (synth/).
+Every floating-point input is rounded to float32 first, exactly as the GPU path
+receives it, and the oracle then works in double precision on those values.
+
+    python tests/golden/make_oracle_golden.py c1        # ~1 min on 8 cores
+    python tests/golden/make_oracle_golden.py c2        # sampled rows + sensitivity
+    python tests/golden/make_oracle_golden.py c2iter    # one full iteration, 2000 events
+    python tests/golden/make_oracle_golden.py c5        # sampled rows at 128x128
+"""
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+OUT = os.path.dirname(os.path.abspath(__file__))
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def digest(ev):
+    h = hashlib.sha256()
+    for k in ("bin", "angle", "energy"):
+        h.update(np.ascontiguousarray(ev[k]).tobytes())
+    return h.hexdigest()
+
+
+def c1():
+    w = synth.CONFIGS["c1"]
+    p = w.params
+    mu, act, rois = synth.phantom(w)
+    mu32 = f32(mu)
+    o = oracle.Oracle(p, mu32)
+    ev = o.sample_events(act, w.n_events, seed=w.seed_events)
+    ev = {"bin": ev["bin"].astype(np.int16), "angle": ev["angle"].astype(np.int16),
+          "energy": ev["energy"].astype(np.float32)}
+    evd = {"bin": ev["bin"], "angle": ev["angle"], "energy": ev["energy"].astype(np.float64)}
+    sens = o.sensitivity(w.n_subsets)
+    lam0 = o.support.astype(np.float64)
+    sens32 = f32(sens)          # the GPU run is checked against the oracle fed the same sens
+    t = time.time()
+    lam, hist, ll, sk = o.osem(evd, w.n_subsets, w.n_iters, lam0, sens32)
+    print("c1 osem", time.time() - t, "s")
+    act32 = f32(act)
+    p_act = o.forward(evd, act32)
+    rng = np.random.default_rng(1234)
+    wts = f32(rng.uniform(0.5, 1.5, ev["bin"].size))
+    bp = o.backproject(evd, wts)
+    np.savez_compressed(os.path.join(OUT, "c1_oracle.npz"), mu=mu32, act=act32,
+                        support=o.support, bin=ev["bin"], angle=ev["angle"],
+                        energy=ev["energy"], sens=sens, lam0=lam0, hist=hist, ll=ll,
+                        skipped=sk, p_act=p_act, bp_w=wts, bp=bp)
+
+
+def c2():
+    w = synth.CONFIGS["c2"]
+    p = w.params
+    mu, act, rois = synth.phantom(w)
+    mu32, act32 = f32(mu), f32(act)
+    ev = synth.generic_events(p, act, w.n_events, w.seed_events, poisson=True)
+    o = oracle.Oracle(p, mu32)
+    rng = np.random.default_rng(2222)
+    J = ev["bin"].size
+    idx = np.sort(rng.choice(J, 12, replace=False))
+    sub = {"bin": ev["bin"][idx], "angle": ev["angle"][idx],
+           "energy": ev["energy"][idx].astype(np.float64)}
+    t = time.time()
+    p_act = o.forward(sub, act32)
+    print("c2 rows", time.time() - t, "s")
+    qs = np.flatnonzero(o.support)
+    pix = np.sort(rng.choice(qs, 16, replace=False))
+    nsub = w.n_subsets
+    sens = np.zeros((nsub, pix.size))
+    t = time.time()
+    for k, q in enumerate(pix):
+        for a in range(p.na):
+            sens[a % nsub, k] += p.T * o.sens_qa(int(q), a)
+    print("c2 sens", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "c2_oracle.npz"), digest=digest(ev), J=J, idx=idx,
+                        p_act=p_act, pix=pix, sens=sens)
+
+
+def c2iter():
+    w = synth.CONFIGS["c2"]
+    p = w.params
+    mu, act, rois = synth.phantom(w)
+    mu32 = f32(mu)
+    ev = synth.generic_events(p, act, 2000, 23)
+    evd = {"bin": ev["bin"], "angle": ev["angle"], "energy": ev["energy"].astype(np.float64)}
+    o = oracle.Oracle(p, mu32)
+    sens = o.sensitivity(w.n_subsets)
+    lam0 = o.support.astype(np.float64)
+    t = time.time()
+    lam, hist, ll, sk = o.osem(evd, w.n_subsets, 1, lam0, f32(sens))
+    print("c2 iteration", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "c2iter_oracle.npz"), digest=digest(ev), sens=sens,
+                        lam0=lam0, hist=hist, ll=ll, skipped=sk)
+
+
+def c5():
+    w = synth.CONFIGS["c5"]
+    p = w.params
+    mu, act, rois = synth.phantom(w, 0)
+    mu32, act32 = f32(mu), f32(act)
+    ev = synth.generic_events(p, act, 20000, 5300)
+    o = oracle.Oracle(p, mu32)
+    rng = np.random.default_rng(5555)
+    idx = np.sort(rng.choice(ev["bin"].size, 4, replace=False))
+    sub = {"bin": ev["bin"][idx], "angle": ev["angle"][idx],
+           "energy": ev["energy"][idx].astype(np.float64)}
+    t = time.time()
+    p_act = o.forward(sub, act32)
+    print("c5 rows", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "c5_oracle.npz"), digest=digest(ev), idx=idx,
+                        p_act=p_act)
+
+
+if __name__ == "__main__":
+    oracle.build(force=False)
+    for name in sys.argv[1:]:
+        globals()[name]()

@@ -1,0 +1,288 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Expected values come from tests/golden/make_oracle_golden.py, which calls only
+the oracle and the seeded input generators.  The bar (relative error of images
+and rows, in max-norm and L2) is 1e-4, the tolerance the method's FP32 images
+are held to against the FP64 oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def lm():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2305_17111_amd as lm
+
+    return lm
+
+
+def _rel(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = got - ref
+    return (np.abs(d).max() / np.abs(ref).max(), np.linalg.norm(d) / np.linalg.norm(ref))
+
+
+def _dev(ev):
+    from paper_2305_17111_amd import events_to_device
+
+    return events_to_device(ev)
+
+
+def _digest(ev):
+    import hashlib
+
+    h = hashlib.sha256()
+    for k in ("bin", "angle", "energy"):
+        h.update(np.ascontiguousarray(ev[k]).tobytes())
+    return h.hexdigest()
+
+
+@pytest.fixture(scope="module")
+def c1(lm):
+    import torch
+
+    g = np.load(os.path.join(GOLD, "c1_oracle.npz"))
+    p = synth.CONFIGS["c1"].params
+    ctx = lm.Context(p, torch.from_numpy(g["mu"].astype(np.float32)))
+    ev = {"bin": g["bin"], "angle": g["angle"], "energy": g["energy"]}
+    return p, g, ctx, _dev(ev)
+
+
+def test_c1_sensitivity(c1):
+    p, g, ctx, ev = c1
+    sens = ctx.sensitivity(4).cpu().numpy()
+    mx, l2 = _rel(sens, g["sens"])
+    assert mx < TOL and l2 < TOL, (mx, l2)
+
+
+def test_c1_forward_every_event(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    pj = ctx.forward(ev, torch.from_numpy(g["act"].astype(np.float32)).cuda()).cpu().numpy()
+    rel = np.abs(pj - g["p_act"]) / g["p_act"]
+    assert rel.max() < TOL, rel.max()
+
+
+def test_c1_backproject(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    out = ctx.backproject(ev, torch.from_numpy(g["bp_w"].astype(np.float32)).cuda()).cpu().numpy()
+    mx, l2 = _rel(out, g["bp"])
+    assert mx < TOL and l2 < TOL, (mx, l2)
+    assert np.all(out[~g["support"]] == 0)
+
+
+def test_c1_osem_every_subiteration(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    nsub = 4
+    sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan = ctx.plan(ev, nsub)
+    worst = 0.0
+    for k in range(g["hist"].shape[0]):
+        sk, ll = plan.osem_subiter(k % nsub, sens, lam, stats=True)
+        mx, l2 = _rel(lam.cpu().numpy(), g["hist"][k])
+        worst = max(worst, mx, l2)
+        assert mx < TOL and l2 < TOL, (k, mx, l2)
+        assert sk == g["skipped"][k]
+        assert ll == pytest.approx(g["ll"][k], rel=1e-5)
+    print("c1 worst relative error over 40 sub-iterations", worst)
+
+
+def test_c1_end_to_end_with_gpu_sensitivity(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    sens = ctx.sensitivity(4)
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan = ctx.plan(ev, 4)
+    plan.osem_iter(10, sens, lam)
+    mx, l2 = _rel(lam.cpu().numpy(), g["hist"][-1])
+    assert mx < TOL and l2 < TOL, (mx, l2)
+
+
+def test_c1_resume_is_bitwise_identical(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    sens = ctx.sensitivity(4)
+    plan = ctx.plan(ev, 4)
+    a = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    b = a.clone()
+    plan.osem_iter(3, sens, a)
+    plan.osem_iter(1, sens, b)
+    for s in range(4):                 # stop after iteration 1, resume subset by subset
+        plan.osem_subiter(s, sens, b)
+    plan.osem_iter(1, sens, b)
+    assert torch.equal(a, b)
+
+
+def test_c1_event_tiles_agree_and_runs_are_deterministic(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
+    plan = ctx.plan(ev, 4)
+    outs = {}
+    for jt in (16, 32, 64, 64):
+        plan.set_event_tile(jt)
+        lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+        plan.osem_iter(2, sens, lam)
+        if jt in outs:
+            assert torch.equal(outs[jt], lam)          # run-to-run bitwise
+        outs[jt] = lam
+    ref = g["hist"][7]
+    for jt, lam in outs.items():
+        mx, l2 = _rel(lam.cpu().numpy(), ref)
+        assert mx < TOL and l2 < TOL, (jt, mx, l2)
+    a, b = outs[16].cpu().numpy(), outs[64].cpu().numpy()
+    assert np.abs(a - b).max() / np.abs(a).max() < 1e-5
+
+
+def test_batched_cases_equal_independent_runs(c1, lm):
+    import torch
+
+    p, g, ctx, ev = c1
+    sens = ctx.sensitivity(4)
+    rng = np.random.default_rng(3)
+    n = ev["bin"].numel()
+    cuts = np.sort(rng.choice(np.arange(1, n), 2, replace=False))
+    offs = [0, int(cuts[0]), int(cuts[1]), n]
+    lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    batched = lam0.repeat(3, 1).contiguous()
+    ctx.plan(ev, 4, case_offsets=offs).osem_iter(2, sens, batched)
+    for c in range(3):
+        sub = {k: v[offs[c]:offs[c + 1]].contiguous() for k, v in ev.items()}
+        lam = lam0.clone()
+        ctx.plan(sub, 4).osem_iter(2, sens, lam)
+        assert torch.equal(lam, batched[c])
+
+
+def test_c2_sampled_rows_at_full_size(lm):
+    import torch
+
+    g = np.load(os.path.join(GOLD, "c2_oracle.npz"))
+    w = synth.CONFIGS["c2"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    ev = synth.generic_events(p, act, w.n_events, w.seed_events, poisson=True)
+    assert _digest(ev) == str(g["digest"])
+    ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+    pj = ctx.forward(_dev(ev), torch.from_numpy(act.astype(np.float32)).cuda()).cpu().numpy()
+    rel = np.abs(pj[g["idx"]] - g["p_act"]) / g["p_act"]
+    assert rel.max() < TOL, rel.max()
+    sens = ctx.sensitivity(w.n_subsets).cpu().numpy()
+    got = sens[:, g["pix"]]
+    assert np.abs(got - g["sens"]).max() / np.abs(g["sens"]).max() < TOL
+
+
+def test_c2_count_conservation_full_size(lm):
+    import torch
+
+    w = synth.CONFIGS["c2"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    ev = synth.generic_events(p, act, w.n_events, w.seed_events, poisson=True)
+    ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+    sens = ctx.sensitivity(w.n_subsets)
+    plan = ctx.plan(_dev(ev), w.n_subsets)
+    lam = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+    for s in range(w.n_subsets):
+        sk, _ = plan.osem_subiter(s, sens, lam, stats=True)
+        Js = int(np.sum(ev["angle"] % w.n_subsets == s))
+        tot = float((sens[s].double() * lam.double()).sum())
+        assert tot == pytest.approx(Js - sk, rel=TOL)
+        assert bool(torch.all(lam >= 0))
+
+
+def test_c2_one_full_iteration(lm):
+    import torch
+
+    path = os.path.join(GOLD, "c2iter_oracle.npz")
+    g = np.load(path)
+    w = synth.CONFIGS["c2"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    ev = synth.generic_events(p, act, 2000, 23)
+    assert _digest(ev) == str(g["digest"])
+    ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+    sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan = ctx.plan(_dev(ev), w.n_subsets)
+    for k in range(g["hist"].shape[0]):
+        plan.osem_subiter(k, sens, lam)
+        mx, l2 = _rel(lam.cpu().numpy(), g["hist"][k])
+        assert mx < TOL and l2 < TOL, (k, mx, l2)
+
+
+def test_c5_sampled_rows_at_128(lm):
+    import torch
+
+    g = np.load(os.path.join(GOLD, "c5_oracle.npz"))
+    w = synth.CONFIGS["c5"]
+    p = w.params
+    mu, act, _ = synth.phantom(w, 0)
+    ev = synth.generic_events(p, act, 20000, 5300)
+    assert _digest(ev) == str(g["digest"])
+    ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+    pj = ctx.forward(_dev(ev), torch.from_numpy(act.astype(np.float32)).cuda()).cpu().numpy()
+    rel = np.abs(pj[g["idx"]] - g["p_act"]) / g["p_act"]
+    assert rel.max() < TOL, rel.max()
+
+
+def test_invalid_inputs_are_rejected(c1, lm):
+    import torch
+
+    p, g, ctx, ev = c1
+    for key, val in (("bin", 16), ("angle", 32), ("energy", 110.0), ("energy", float("nan"))):
+        bad = {k: v.clone() for k, v in ev.items()}
+        bad[key][5] = val
+        with pytest.raises(lm.LmmewError) as e:
+            ctx.plan(bad, 4)
+        assert e.value.status == -1 and "event 5" in str(e.value)
+    with pytest.raises(lm.LmmewError):
+        ctx.plan(ev, 0)
+    with pytest.raises(lm.LmmewError):
+        ctx.sensitivity(33)
+    mu = torch.from_numpy(g["mu"].astype(np.float32)).clone()
+    mu[3] = float("nan")
+    with pytest.raises(lm.LmmewError):
+        lm.Context(p, mu)
+    with pytest.raises(lm.LmmewError):
+        lm.Context(synth.replace(p, ns=5), torch.from_numpy(g["mu"].astype(np.float32)))
+
+
+def test_empty_and_single_event_lists(c1, lm):
+    import torch
+
+    p, g, ctx, ev = c1
+    sens = ctx.sensitivity(4)
+    empty = {k: v[:0].contiguous() for k, v in ev.items()}
+    assert ctx.forward(empty, sens[0]).numel() == 0
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    ctx.plan(empty, 4).osem_iter(1, sens, lam)
+    # no events: every pixel the subsets can see goes to zero (Eq. (18) numerator is 0)
+    assert float(lam.abs().max()) == 0.0
+    one = {k: v[:1].contiguous() for k, v in ev.items()}
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan = ctx.plan(one, 1)
+    s1 = ctx.sensitivity(1)
+    plan.osem_iter(1, s1, lam)
+    # count conservation with a single event
+    assert float((s1[0].double() * lam.double()).sum()) == pytest.approx(1.0, rel=TOL)
