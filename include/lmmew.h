@@ -205,6 +205,14 @@ int lmmew_plan_set_event_tile(lmmew_ctx *ctx, lmmew_plan *plan, int event_tile,
                               hipStream_t stream);
 int lmmew_plan_get_event_tile(const lmmew_plan *plan);
 
+/* Timing of the per-event system-model kernel: with profiling enabled,
+ * every launch of that kernel made for this plan is bracketed by two HIP
+ * events recorded on the caller's stream.  lmmew_plan_profile_read waits for
+ * the recorded launches, returns their summed duration (ms) and count, and
+ * starts a new measurement. */
+int lmmew_plan_profile(lmmew_ctx *ctx, lmmew_plan *plan, int enable);
+int lmmew_plan_profile_read(lmmew_ctx *ctx, lmmew_plan *plan, double *row_ms, int64_t *launches);
+
 /* Number of algorithmic terms one OSEM iteration of the plan evaluates in
  * the per-event system-model kernel: for every (event, support pixel) pair,
  * one term per line for the unscattered path and one per (line, scatter

@@ -80,6 +80,7 @@ def lib():
             build(force=True)
         L = C.CDLL(_LIB)
         sig = {
+            "or_threads": (C.c_int, []),
             "or_angle_dir": (None, [C.c_int, C.c_int, _D, _D]),
             "or_segment_integral": (C.c_double, [_D, C.c_int, C.c_double, C.c_double,
                                                  C.c_double, C.c_double, C.c_double]),
@@ -143,6 +144,11 @@ def make_sys(p) -> _Sys:
 
 
 # ---- free functions ------------------------------------------------------
+
+def threads():
+    """OpenMP threads the oracle uses."""
+    return int(lib().or_threads())
+
 
 def angle_dir(a, na):
     c, s = C.c_double(), C.c_double()

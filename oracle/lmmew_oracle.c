@@ -16,6 +16,16 @@
 
 #define OR_PI 3.14159265358979323846
 
+/* Threads the OpenMP loops of this library will use. */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* FWHM of a Gaussian in units of its standard deviation: 2 sqrt(2 ln 2). */
 static double fwhm_per_sigma(void) { return 2.0 * sqrt(2.0 * log(2.0)); }
 
@@ -186,8 +196,10 @@ double or_acc(const or_sys *S, double E)
     return a;
 }
 
-/* Energy dependence of attenuation (Sec. 3.1.1 models it as a smooth
- * function of energy fitted to water): mu(E) = mu(E_ref) (E/E_ref)^(-p). */
+/* Energy dependence of attenuation.  Sec. 3.1.1 fits water's attenuation
+ * with a bilinear curve in energy but prints no coefficients; this oracle
+ * reads it as a power law mu(E) = mu(E_ref) (E/E_ref)^(-p) with the exponent
+ * a system parameter. */
 double or_mu_scale(const or_sys *S, double E)
 {
     return pow(E / S->mu_ref, -S->mu_pow);

@@ -69,6 +69,8 @@ typedef struct {
     double Zw[OR_MAX_LINES];  /* 2-D Klein-Nishina normaliser per line */
 } or_geom;
 
+int    or_threads(void);
+
 /* ---- physics and geometry primitives ---------------------------------- */
 void   or_angle_dir(int a, int na, double *c, double *s);
 double or_segment_integral(const double *mu, int n, double pix,

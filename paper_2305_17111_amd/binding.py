@@ -79,6 +79,8 @@ def _load():
         "lmmew_plan_set_event_tile": (i32, [vp, vp, i32, vp]),
         "lmmew_plan_get_event_tile": (i32, [vp]),
         "lmmew_plan_terms": (i32, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "lmmew_plan_profile": (i32, [vp, vp, i32]),
+        "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -275,6 +277,20 @@ class Plan:
     @property
     def event_tile(self):
         return _load().lmmew_plan_get_event_tile(self._h)
+
+    def lmmew_plan_profile(self, enable=True):
+        self.ctx._check(_load().lmmew_plan_profile(self.ctx._h, self._h, int(bool(enable))))
+
+    def lmmew_plan_profile_read(self):
+        """(summed duration in ms, number of launches) of the per-event kernel since the
+        last read."""
+        ms, n = C.c_double(), C.c_int64()
+        self.ctx._check(_load().lmmew_plan_profile_read(self.ctx._h, self._h, C.byref(ms),
+                                                        C.byref(n)))
+        return ms.value, n.value
+
+    profile = lmmew_plan_profile
+    profile_read = lmmew_plan_profile_read
 
     def terms(self):
         t, f = C.c_double(), C.c_double()

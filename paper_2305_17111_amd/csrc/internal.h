@@ -52,8 +52,8 @@ struct ScatA {
 };
 
 // Work tile of the per-event kernel: events [e0, e0+cnt) of one angle and
-// one case, and the range [k0, k1) of that angle's u-sorted scatter points
-// whose response can reach the tile's bins.
+// one case; entries [k0, k1) of the plan's scatter list name the angle's
+// (u-sorted) scatter points whose response reaches at least one of them.
 struct Tile {
     int e0, cnt;
     int angle, ncase;
@@ -79,6 +79,7 @@ struct RowArgs {
     const float *g_qs;
     const ScatA *sa;
     const Tile *tiles;
+    const int *slist;        // scatter list entries referenced by the tiles
     int ntiles;
     const int *ev_bin;       // sorted rows of this subset
     const float *ev_E;

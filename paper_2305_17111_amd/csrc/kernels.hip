@@ -217,8 +217,10 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+        // invP = E_w / E' = 1 + eps (1 - cos phi); rs = invP^(-1/2)
         const float invP = fmaf(S.eps[w], omc, 1.f);
-        const float P = fast_rcp(invP);
+        const float rs = fast_rsq(invP);
+        const float P = rs * rs;
         const float l2i = fast_log2(invP);
         const float lK = fast_log2(P + invP - sin2) - 2.f * l2i;
         const float fE = S.f[w] * fast_exp2(S.mu_pow * l2i);
@@ -226,11 +228,10 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
         float A = base + S.lsc[w] + lK - att;
         if (NORM) A += S.nc[w] + 0.5f * l2i;
         Aw[w] = A;
-        const float e = S.E[w] * P;
-        Ep[w] = e;
-        const float sq = S.sqc0[w] * fast_sqrt(invP);
-        sw[w] = sq;
-        Fw[w] = sq * e;
+        Ep[w] = S.E[w] * P;
+        // sqrt(c0 * invP) = sqc0 * invP * rs ;  F = sqrt(c) * E' = sqc0 * E_w * rs
+        sw[w] = S.sqc0[w] * invP * rs;
+        Fw[w] = S.sqc0[w] * S.E[w] * rs;
     }
 }
 
@@ -238,21 +239,21 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
 // per-event system model (the hot path)
 //
 // One wavefront per work item: 64 support pixels (one per lane) x one tile of
-// up to JT events of a single angle.  Every lane keeps JT accumulators a_jq in
-// registers.  For every scatter point of the tile's range the lane derives the
-// path parameters of its pixel once, then adds the JT events' terms; the
-// collimator-response factors of the tile's events for a block of 64 scatter
-// points are computed cooperatively (one scatter point per lane) into LDS and
-// read back as broadcasts, and a (event, scatter point) pair whose factor is
-// zero is skipped by a uniform branch.
+// up to JT events of a single angle, with JT accumulators a_jq per lane in
+// registers.  The tile carries the list of scatter points whose collimator
+// response reaches at least one of its events.  For each block of 16 listed
+// scatter points the wavefront computes the response factors of all
+// (scatter point, event) pairs, one group of JT/4 events per lane, and keeps
+// them in registers; in the pair loop v_readlane moves a factor into a scalar
+// register, so a zero factor skips its three exponentials with a uniform
+// branch.  For each listed scatter point every lane derives its pixel's path
+// parameters once and reuses them for all of the tile's events.
 // ---------------------------------------------------------------------------
 template <int JT, int NW>
 __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 {
-    constexpr int KC = 16;                      // scatter points per response block
-    __shared__ float2 lds_pe[KC][JT + 1];       // (response factor, energy) per (scatter, event)
-    __shared__ float lds_gq[JT][NW];            // unscattered energy factor per (event, line)
-
+    constexpr int KC = 16;               // scatter points per response block
+    constexpr int TJ = JT / 4;           // events per lane in a response block
     const Tile T = r.tiles[blockIdx.y];
     const int lane = threadIdx.x;
     const int i = blockIdx.x * kWave + lane;
@@ -260,17 +261,19 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const float2 dir = r.dirs[a];
     const float c = dir.x, s = dir.y;
     const bool valid = i < S.Qm;
+    const int last = T.cnt - 1;
 
-    if (lane < JT) {
-        const float E = (lane < T.cnt) ? r.ev_E[T.e0 + lane] : 0.f;
+    // unscattered energy factor of event `lane` for every line
+    float gq[NW];
+    {
+        const float E = r.ev_E[T.e0 + min(lane, last)];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
             const float d = E - S.E[w];
-            lds_gq[lane][w] = S.gnorm[w] * __expf(-d * d / (2.f * S.eres_k * S.E[w]));
+            gq[w] = S.gnorm[w] * __expf(-d * d / (2.f * S.eres_k * S.E[w]));
         }
     }
-    __syncthreads();
 
     const float2 xy = r.pix_xy[i];
     const float xq = xy.x, yq = xy.y;
@@ -291,53 +294,64 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                g = fmaf(Pp[w], lds_gq[j][w], g);
+                g = fmaf(Pp[w], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gq[w]), j)), g);
             }
             r.A[(size_t)(T.e0 + j) * S.Qp + i] = ps * g;
         }
     }
+
+    float Ej[JT];
+#pragma unroll
+    for (int j = 0; j < JT; ++j) Ej[j] = r.ev_E[T.e0 + min(j, last)];
 
     float acc[JT];
 #pragma unroll
     for (int j = 0; j < JT; ++j) acc[j] = 0.f;
 
     const ScatA *sa = r.sa + (size_t)a * S.nsc;
-    const int kl = lane % KC, jg = lane / KC;   // response block: lane -> (scatter, event quarter)
-    for (int kc = T.k0; kc < T.k1; kc += KC) {
-        __syncthreads();
+    const int kl = lane % KC, jg = lane / KC;
+    for (int lc0 = T.k0; lc0 < T.k1; lc0 += KC) {
+        // response factors of (listed scatter point lc0+kl, events jg*TJ .. jg*TJ+TJ-1)
+        float pv[TJ];
         {
-            const int k = kc + kl;
-            if (k < T.k1) {
-                const ScatA sp = sa[k];
-                for (int j = jg * (JT / 4); j < (jg + 1) * (JT / 4); ++j) {
-                    float ps = 0.f, E = 0.f;
-                    if (j < T.cnt) {
-                        const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
-                        ps = psf_cut((lo + S.db - sp.u) * sp.isig, (lo - sp.u) * sp.isig);
-                        E = r.ev_E[T.e0 + j];
-                    }
-                    lds_pe[kl][j] = make_float2(ps, E);
+            const int l = lc0 + kl;
+            float u = 0.f, isg = 0.f;
+            if (l < T.k1) {
+                const ScatA &sp = sa[r.slist[l]];
+                u = sp.u;
+                isg = sp.isig;
+            }
+#pragma unroll
+            for (int t = 0; t < TJ; ++t) {
+                const int j = jg * TJ + t;
+                float ps = 0.f;
+                if (l < T.k1 && j < T.cnt) {
+                    const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
+                    ps = psf_cut((lo + S.db - u) * isg, (lo - u) * isg);
                 }
+                pv[t] = ps;
             }
         }
-        __syncthreads();
-        const int kn = min(KC, T.k1 - kc);
+        const int kn = min(KC, T.k1 - lc0);
         for (int kk = 0; kk < kn; ++kk) {
-            const ScatA sp = sa[kc + kk];
+            const ScatA sp = sa[r.slist[lc0 + kk]];
             const float gqs = r.g_qs[(size_t)sp.sidx * S.Qp + i];
             float Aw[NW], sw[NW], Fw[NW], Ep[NW];
             scatter_params<NW, true>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw, sw,
                                      Fw, Ep);
 #pragma unroll
             for (int j = 0; j < JT; ++j) {
-                const float2 pe = lds_pe[kk][j];
-                const float ps = uniform_f(pe.x);
-                if (ps != 0.f) {
-                    float t = 0.f;
+                // factor bits in a scalar register: a scalar compare decides the branch
+                const int pbits =
+                    __builtin_amdgcn_readlane(__float_as_int(pv[j % TJ]), kk + KC * (j / TJ));
+                if (pbits != 0) {
+                    const float ps = __int_as_float(pbits);
+                    float u = fmaf(sw[0], Ej[j], -Fw[0]);
+                    float t = fast_exp2(fmaf(-u, u, Aw[0]));
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) {
+                    for (int w = 1; w < NW; ++w) {
                         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                        const float u = fmaf(sw[w], pe.y, -Fw[w]);
+                        u = fmaf(sw[w], Ej[j], -Fw[w]);
                         t += fast_exp2(fmaf(-u, u, Aw[w]));
                     }
                     acc[j] = fmaf(ps, t, acc[j]);

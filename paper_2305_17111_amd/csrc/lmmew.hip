@@ -25,6 +25,7 @@ struct lmmew_ctx {
     std::vector<double> dir_c, dir_s; // [na]
     std::vector<ScatA> sa;            // [na][nsc] host copy (x, y, u, isig, lc, sidx)
     std::vector<double> sig_max;      // [na] largest PSF sigma over the scatter points
+    std::vector<int> rb_lo, rb_hi;    // [na][nsc] bins reached by each scatter point's response
     // device
     float2 *d_pix = nullptr;
     double2 *d_pixd = nullptr;
@@ -53,6 +54,7 @@ struct lmmew_plan {
     std::vector<Sub> subs;
     std::vector<int> case_chunk;      // [nsub][ncases+1], chunk index relative to the subset
     std::vector<Tile> tiles;
+    std::vector<int> slist;           // scatter list entries of all tiles
     std::vector<Chunk> chunks;
     int max_rows = 0, max_chunks = 0;
     double terms = 0, full_terms = 0;
@@ -61,12 +63,17 @@ struct lmmew_plan {
     float *d_E = nullptr;
     int64_t *d_perm = nullptr;
     Tile *d_tiles = nullptr;
+    int *d_slist = nullptr;
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
     double *d_logp = nullptr, *d_ll = nullptr;
     float *d_part = nullptr, *d_comp = nullptr;
     unsigned long long *d_nskip = nullptr;
     int stats_cap = 0;
+    // optional timing of the per-event kernel launches (HIP events on the caller's stream)
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
 };
 
 namespace {
@@ -173,8 +180,10 @@ void free_ctx(lmmew_ctx *c)
 
 void free_plan(lmmew_plan *p)
 {
+    for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
+    p->prof_ev.clear();
     dfree(p->d_bin); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
-    dfree(p->d_tiles); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
+    dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
 }
 
@@ -191,12 +200,10 @@ bool in_window(const lmmew_system &s, float e)
 int relevant_scatter(const lmmew_ctx *c, int a, int b)
 {
     const int nsc = c->S.nsc;
-    const double lo = -c->R + b * c->db, hi = lo + c->db;
     int cnt = 0;
     for (int k = 0; k < nsc; ++k) {
-        const ScatA &sp = c->sa[(size_t)a * nsc + k];
-        const double zhi = (hi - sp.u) * sp.isig, zlo = (lo - sp.u) * sp.isig;
-        if (!(zlo >= kPsfCut || zhi <= -kPsfCut)) ++cnt;
+        const size_t ak = (size_t)a * nsc + k;
+        cnt += (b >= c->rb_lo[ak] && b <= c->rb_hi[ak]);
     }
     return cnt;
 }
@@ -207,6 +214,7 @@ void build_tiles(lmmew_plan *p)
     const lmmew_ctx *c = p->ctx;
     const int nsc = c->S.nsc, na = c->S.na;
     p->tiles.clear();
+    p->slist.clear();
     p->chunks.clear();
     p->case_chunk.assign((size_t)p->nsub * (p->ncases + 1), 0);
     p->max_chunks = 0;
@@ -228,13 +236,18 @@ void build_tiles(lmmew_plan *p)
                 bmin = std::min(bmin, p->bin[k]);
                 bmax = std::max(bmax, p->bin[k]);
             }
-            const double reach = kPsfCut * c->sig_max[a];
-            const float ulo = (float)(-c->R + bmin * c->db - reach);
-            const float uhi = (float)(-c->R + (bmax + 1) * c->db + reach);
-            const ScatA *sa = &c->sa[(size_t)a * nsc];
-            int k0 = 0, k1 = nsc;
-            while (k0 < nsc && sa[k0].u < ulo) ++k0;
-            while (k1 > k0 && sa[k1 - 1].u > uhi) --k1;
+            // scatter points whose response reaches some bin of the tile
+            const int k0 = (int)p->slist.size();
+            for (int k = 0; k < nsc; ++k) {
+                const size_t ak = (size_t)a * nsc + k;
+                const int lo = c->rb_lo[ak], hi = c->rb_hi[ak];
+                if (hi < bmin || lo > bmax) continue;
+                // the tile's bins are sorted: is one of them inside [lo, hi]?
+                const int *first = p->bin.data() + r, *lastp = p->bin.data() + e;
+                const int *it = std::lower_bound(first, lastp, lo);
+                if (it != lastp && *it <= hi) p->slist.push_back(k);
+            }
+            const int k1 = (int)p->slist.size();
             Tile t{};
             t.e0 = r - sub.row0;
             t.cnt = e - r;
@@ -273,11 +286,13 @@ void build_tiles(lmmew_plan *p)
 int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
 {
     dfree(p->d_tiles);
+    dfree(p->d_slist);
     dfree(p->d_chunks);
     dfree(p->d_case_chunk);
     dfree(p->d_part);
     dfree(p->d_comp);
     HIPCHK(ctx, dalloc(&p->d_tiles, p->tiles.size()));
+    HIPCHK(ctx, dalloc(&p->d_slist, p->slist.size()));
     HIPCHK(ctx, dalloc(&p->d_chunks, p->chunks.size()));
     HIPCHK(ctx, dalloc(&p->d_case_chunk, p->case_chunk.size()));
     const size_t total_chunks = std::max<size_t>(p->chunks.size(), 1);
@@ -285,6 +300,9 @@ int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
     HIPCHK(ctx, dalloc(&p->d_comp, total_chunks * ctx->S.Qp));
     if (!p->tiles.empty())
         HIPCHK(ctx, hipMemcpyAsync(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile),
+                                   hipMemcpyHostToDevice, st));
+    if (!p->slist.empty())
+        HIPCHK(ctx, hipMemcpyAsync(p->d_slist, p->slist.data(), p->slist.size() * sizeof(int),
                                    hipMemcpyHostToDevice, st));
     if (!p->chunks.empty())
         HIPCHK(ctx, hipMemcpyAsync(p->d_chunks, p->chunks.data(),
@@ -438,10 +456,23 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st)
     r.g_qs = ctx->d_gqs;
     r.sa = ctx->d_sa;
     r.tiles = p->d_tiles + sub.tile0;
+    r.slist = p->d_slist;
     r.ntiles = sub.ntiles;
     r.ev_bin = p->d_bin + sub.row0;
     r.ev_E = p->d_E + sub.row0;
     r.A = p->d_A;
+    if (p->prof && sub.ntiles > 0) {
+        while (p->prof_ev.size() < p->prof_used + 2) {
+            hipEvent_t e;
+            HIPCHK(ctx, hipEventCreate(&e));
+            p->prof_ev.push_back(e);
+        }
+        HIPCHK(ctx, hipEventRecord(p->prof_ev[p->prof_used], st));
+        HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
+        HIPCHK(ctx, hipEventRecord(p->prof_ev[p->prof_used + 1], st));
+        p->prof_used += 2;
+        return LMMEW_OK;
+    }
     HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
     return LMMEW_OK;
 }
@@ -624,6 +655,27 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
             e.D = 0.f;
             e.sidx = si;
             ctx->sa[(size_t)a * nsc + k] = e;
+        }
+    }
+    // bins reached by each scatter point's response (the kernel's 7-sigma rule,
+    // evaluated in the kernel's float arithmetic)
+    ctx->rb_lo.assign((size_t)na * nsc, 0);
+    ctx->rb_hi.assign((size_t)na * nsc, -1);
+    {
+        const float fR = (float)R, fdb = (float)db;
+        for (size_t ak = 0; ak < (size_t)na * nsc; ++ak) {
+            const ScatA &e = ctx->sa[ak];
+            int lo = s.n_bins, hi = -1;
+            for (int b = 0; b < s.n_bins; ++b) {
+                const float blo = -fR + (float)b * fdb;
+                const float zhi = (blo + fdb - e.u) * e.isig, zlo = (blo - e.u) * e.isig;
+                if (!(zlo >= kPsfCut || zhi <= -kPsfCut)) {
+                    lo = std::min(lo, b);
+                    hi = std::max(hi, b);
+                }
+            }
+            ctx->rb_lo[ak] = lo;
+            ctx->rb_hi[ak] = hi;
         }
     }
     // constants
@@ -840,6 +892,30 @@ int lmmew_plan_set_event_tile(lmmew_ctx *ctx, lmmew_plan *plan, int event_tile, 
 }
 
 int lmmew_plan_get_event_tile(const lmmew_plan *plan) { return plan ? plan->JT : 0; }
+
+int lmmew_plan_profile(lmmew_ctx *ctx, lmmew_plan *plan, int enable)
+{
+    if (!ctx || !plan || plan->ctx != ctx) return LMMEW_EINVAL;
+    plan->prof = enable != 0;
+    plan->prof_used = 0;
+    return LMMEW_OK;
+}
+
+int lmmew_plan_profile_read(lmmew_ctx *ctx, lmmew_plan *plan, double *row_ms, int64_t *launches)
+{
+    if (!ctx || !plan || plan->ctx != ctx) return LMMEW_EINVAL;
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < plan->prof_used; k += 2) {
+        HIPCHK(ctx, hipEventSynchronize(plan->prof_ev[k + 1]));
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, plan->prof_ev[k], plan->prof_ev[k + 1]));
+        tot += ms;
+    }
+    if (row_ms) *row_ms = tot;
+    if (launches) *launches = (int64_t)(plan->prof_used / 2);
+    plan->prof_used = 0;
+    return LMMEW_OK;
+}
 
 int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full_terms)
 {
