@@ -73,7 +73,11 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--event-tile", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--event-tile", type=int, default=0,
+                    help="0 = autotune over 16, 32, 64")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device with a plain copy kernel (a known "
+                         "byte count for scaling hardware traffic counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -94,7 +98,16 @@ def main():
     J = int(ev["bin"].size)
     nsub = w.n_subsets
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        # one elementwise kernel (a multiply by 1) that reads and writes exactly
+        # MIB MiB each
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     setup = {}
     t = time.perf_counter()
