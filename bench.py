@@ -65,6 +65,53 @@ def cpu_baseline(p, mu, ev, seconds):
                       f"FP64 system rows, {dt:.1f} s"}
 
 
+def batched(ctx, sens, args):
+    """64 independent cases (noise realisations of the 64x64 phantom, per-case means
+    uniform in 20k-200k events) packed in one plan; each iteration of all cases is one
+    captured hipGraph launch."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2305_17111_amd import events_to_device
+
+    w = synth.CONFIGS["c3"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    counts = synth.case_counts(w)
+    t = time.perf_counter()
+    evs = [synth.generic_events(p, act, int(n), w.seed_events + c) for c, n in enumerate(counts)]
+    cat = {k: np.concatenate([e[k] for e in evs]) for k in ("bin", "angle", "energy")}
+    offs = np.concatenate([[0], np.cumsum(counts)]).tolist()
+    gen_s = time.perf_counter() - t
+    t = time.perf_counter()
+    plan = ctx.plan(events_to_device(cat), w.n_subsets, case_offsets=offs)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t
+    t = time.perf_counter()
+    jt = plan.autotune(use_cache=False)
+    tune_s = time.perf_counter() - t
+    lam = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+    lam = lam.repeat(len(counts), 1).contiguous()
+    plan.osem_graph(1, sens, lam)                      # capture + first iteration (warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_steps):
+        plan.osem_graph(1, sens, lam)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    J = int(counts.sum())
+    terms, _ = plan.terms()
+    assert bool(torch.isfinite(lam).all())
+    return {"workload": f"c3: {len(counts)} cases of the 64x64 workload, {J} events "
+                        f"({int(counts.min())}..{int(counts.max())} per case), {w.n_subsets} subsets",
+            "value": J * args.batched_steps / el, "unit": "events*iterations/s",
+            "s_per_iteration": el / args.batched_steps, "steps": args.batched_steps,
+            "event_tile": jt, "terms_per_s": terms * args.batched_steps / el,
+            "frac_of_term_peak": terms * args.batched_steps / el / PEAK_TERMS_PER_S,
+            "setup_s": {"events": gen_s, "plan": plan_s, "autotune": tune_s}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +120,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--event-tile", type=int, default=0,
                     help="0 = autotune over 16, 32, 64")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -127,20 +176,8 @@ def main():
     t = time.perf_counter()
     if args.event_tile:
         plan.set_event_tile(args.event_tile)
-    else:                                   # pick the event tile by timing one iteration each
-        best = None
-        for jt in (16, 32, 64):
-            plan.set_event_tile(jt)
-            scratch = lam.clone()
-            plan.osem_iter(1, sens, scratch)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            plan.osem_iter(1, sens, scratch)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if best is None or dt < best[0]:
-                best = (dt, jt)
-        plan.set_event_tile(best[1])
+    else:                                   # the library's autotuner (times k_row per tile size)
+        plan.autotune(use_cache=False)
     setup["autotune_ms"] = 1e3 * (time.perf_counter() - t)
 
     for _ in range(args.warmup):
@@ -157,6 +194,15 @@ def main():
     row_ms, launches = plan.profile_read()
     plan.profile(False)
     assert bool(torch.isfinite(lam).all())
+
+    # the same iterations as one captured hipGraph launch per step
+    plan.osem_graph(1, sens, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.osem_graph(1, sens, lam)
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
 
     terms, full_terms = plan.terms()
     achieved = terms * args.steps / (row_ms * 1e-3)          # terms/s in the per-event kernel
@@ -191,9 +237,13 @@ def main():
             "avg_launch_ms": row_ms / launches,
             "kernel_share_of_step": row_ms / (1e3 * elapsed),
         },
+        "graph_ms_per_step": graph_ms,
         "model_terms_per_iteration": {"evaluated": terms, "unpruned": full_terms},
         "setup_ms": setup,
     }
+    del plan
+    if not args.no_batched:
+        out["batched"] = batched(ctx, sens, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, mu, ev, args.cpu_seconds)
     print(json.dumps(out))

@@ -198,6 +198,27 @@ int lmmew_osem_iter(lmmew_ctx *ctx, lmmew_plan *plan, int n_iters, const float *
 int lmmew_osem_subiter(lmmew_ctx *ctx, lmmew_plan *plan, int subset, const float *sens,
                        float *lambda, lmmew_stats *stats, hipStream_t stream);
 
+/* The same n_iters iterations as lmmew_osem_iter (no statistics), issued as
+ * ONE hipGraph launch: on the first call (and whenever n_iters, sens, lambda
+ * or the event tile differ from the previous call) the library captures the
+ * whole launch sequence of every sub-iteration of every case into a graph
+ * owned by the plan, then replays it.  The captured graph contains kernel
+ * launches only.  Results are bitwise identical to lmmew_osem_iter.  The
+ * arrays behind sens and lambda must stay allocated while the plan may
+ * replay the graph.  Errors: EINVAL, EDEVICE. */
+int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *plan, int n_iters, const float *sens,
+                     float *lambda, hipStream_t stream);
+
+/* Autotuner: times the per-event system-model kernel alone (it writes only
+ * the plan's scratch) on the plan's largest subset at each event tile size
+ * (16, 32, 64) with HIP events, keeps the fastest and returns it in *chosen.
+ * With use_cache, a plan whose problem shape (support pixels, scatter
+ * points, lines, angles, subsets, events per case and angle to a power of
+ * two) was tuned before in this process reuses that choice without timing.
+ * Synchronises the stream.  Errors: EINVAL, EDEVICE. */
+int lmmew_autotune(lmmew_ctx *ctx, lmmew_plan *plan, int use_cache, hipStream_t stream,
+                   int *chosen);
+
 /* Tuning knobs of the per-event system-model kernel for a plan (chosen by
  * lmmew_autotune or set by hand).  event_tile: events per work tile, one of
  * 16, 32, 64.  Changing it rebuilds the plan's tiles (synchronises). */

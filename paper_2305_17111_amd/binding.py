@@ -77,6 +77,8 @@ def _load():
         "lmmew_osem_iter": (i32, [vp, vp, i32, vp, vp, C.POINTER(_Stats), vp]),
         "lmmew_osem_subiter": (i32, [vp, vp, i32, vp, vp, C.POINTER(_Stats), vp]),
         "lmmew_plan_set_event_tile": (i32, [vp, vp, i32, vp]),
+        "lmmew_osem_graph": (i32, [vp, vp, i32, vp, vp, vp]),
+        "lmmew_autotune": (i32, [vp, vp, i32, vp, C.POINTER(C.c_int)]),
         "lmmew_plan_get_event_tile": (i32, [vp]),
         "lmmew_plan_terms": (i32, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lmmew_plan_profile": (i32, [vp, vp, i32]),
@@ -270,6 +272,22 @@ class Plan:
         if stats:
             return sk[0], ll[0]
         return None
+
+    def lmmew_osem_graph(self, n_iters, sens, lam):
+        """n_iters iterations as one captured hipGraph launch (replayed on later calls
+        with the same arguments)."""
+        self.ctx._check(_load().lmmew_osem_graph(self.ctx._h, self._h, int(n_iters), _ptr(sens),
+                                                 _ptr(lam), _stream()))
+
+    def lmmew_autotune(self, use_cache=True):
+        """Times the per-event kernel at event tiles 16/32/64 and keeps the fastest."""
+        ch = C.c_int()
+        self.ctx._check(_load().lmmew_autotune(self.ctx._h, self._h, int(bool(use_cache)),
+                                               _stream(), C.byref(ch)))
+        return ch.value
+
+    osem_graph = lmmew_osem_graph
+    autotune = lmmew_autotune
 
     def set_event_tile(self, jt):
         self.ctx._check(_load().lmmew_plan_set_event_tile(self.ctx._h, self._h, int(jt), _stream()))

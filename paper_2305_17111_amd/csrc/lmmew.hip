@@ -37,6 +37,7 @@ struct lmmew_ctx {
     float *d_gqa = nullptr, *d_gqs = nullptr;
     ScatA *d_sa = nullptr;
     float *d_Sqa = nullptr;
+    hipStream_t cap_stream = nullptr; // private stream that graph captures are recorded on
 };
 
 struct lmmew_plan {
@@ -70,6 +71,11 @@ struct lmmew_plan {
     float *d_part = nullptr, *d_comp = nullptr;
     unsigned long long *d_nskip = nullptr;
     int stats_cap = 0;
+    // captured OSEM sequence (lmmew_osem_graph) and the arguments it was captured with
+    hipGraphExec_t gexec = nullptr;
+    int g_iters = -1, g_jt = 0;
+    const float *g_sens = nullptr;
+    float *g_lambda = nullptr;
     // optional timing of the per-event kernel launches (HIP events on the caller's stream)
     bool prof = false;
     std::vector<hipEvent_t> prof_ev;
@@ -173,6 +179,8 @@ int validate_sys(lmmew_ctx *ctx, const lmmew_system *s)
 
 void free_ctx(lmmew_ctx *c)
 {
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     dfree(c->d_pix); dfree(c->d_pixd); dfree(c->d_pixq); dfree(c->d_dirs); dfree(c->d_dirsd);
     dfree(c->d_scd); dfree(c->d_mu); dfree(c->d_gqa); dfree(c->d_gqs); dfree(c->d_sa);
     dfree(c->d_Sqa);
@@ -180,6 +188,8 @@ void free_ctx(lmmew_ctx *c)
 
 void free_plan(lmmew_plan *p)
 {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
     p->prof_ev.clear();
     dfree(p->d_bin); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
@@ -285,6 +295,11 @@ void build_tiles(lmmew_plan *p)
 
 int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
 {
+    // a captured graph refers to the arrays about to be replaced
+    if (p->gexec) {
+        HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
+        p->gexec = nullptr;
+    }
     dfree(p->d_tiles);
     dfree(p->d_slist);
     dfree(p->d_chunks);
@@ -862,6 +877,56 @@ int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, fl
     return rc;
 }
 
+static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, const float *sens,
+                    float *lambda, lmmew_stats *stats, hipStream_t st);
+
+int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *sens,
+                     float *lambda, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!p || p->ctx != ctx) return fail(ctx, LMMEW_EINVAL, "plan does not belong to context");
+    if (!sens || !lambda) return fail(ctx, LMMEW_EINVAL, "NULL image or sensitivity");
+    if (n_iters < 0) return fail(ctx, LMMEW_EINVAL, "n_iters < 0");
+    if (n_iters == 0) return LMMEW_OK;
+    if (!p->gexec || p->g_iters != n_iters || p->g_sens != sens || p->g_lambda != lambda ||
+        p->g_jt != p->JT) {
+        if (p->gexec) {
+            HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
+            p->gexec = nullptr;
+        }
+        // Capture records launches without running them; it happens on a private
+        // stream (the caller's may be the null stream, which cannot be captured)
+        // and the graph is then launched on the caller's stream.
+        if (!ctx->cap_stream)
+            HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = ctx->cap_stream;
+        const bool prof_was = p->prof;
+        p->prof = false;                 // no event records inside the capture
+        HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const int rc = osem_run(ctx, p, 0, n_iters * p->nsub, sens, lambda, nullptr, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &g);
+        p->prof = prof_was;
+        if (rc != LMMEW_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ec != hipSuccess) return hipfail(ctx, ec, "hipStreamEndCapture");
+        const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            p->gexec = nullptr;
+            return hipfail(ctx, ei, "hipGraphInstantiate");
+        }
+        p->g_iters = n_iters;
+        p->g_sens = sens;
+        p->g_lambda = lambda;
+        p->g_jt = p->JT;
+    }
+    HIPCHK(ctx, hipGraphLaunch(p->gexec, st));
+    return LMMEW_OK;
+}
+
 int lmmew_plan_create(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets,
                       int n_cases, int n_subsets, hipStream_t st, lmmew_plan **out)
 {
@@ -892,6 +957,80 @@ int lmmew_plan_set_event_tile(lmmew_ctx *ctx, lmmew_plan *plan, int event_tile, 
 }
 
 int lmmew_plan_get_event_tile(const lmmew_plan *plan) { return plan ? plan->JT : 0; }
+
+namespace {
+// Autotuner cache: problem shape -> fastest event tile.
+struct TuneKey {
+    int Qm, nsc, nw, na, nsub, per_angle;
+    bool operator==(const TuneKey &o) const
+    {
+        return Qm == o.Qm && nsc == o.nsc && nw == o.nw && na == o.na && nsub == o.nsub &&
+               per_angle == o.per_angle;
+    }
+};
+std::vector<std::pair<TuneKey, int>> g_tune_cache;
+
+TuneKey tune_key(const lmmew_ctx *ctx, const lmmew_plan *p)
+{
+    // events per (case, angle), bucketed by powers of two
+    const double per = (double)p->n / std::max(1, p->ncases) / std::max(1, ctx->S.na);
+    int b = 0;
+    while ((1 << b) < per) ++b;
+    return TuneKey{ctx->S.Qm, ctx->S.nsc, ctx->S.nw, ctx->S.na, p->nsub, b};
+}
+}  // namespace
+
+int lmmew_autotune(lmmew_ctx *ctx, lmmew_plan *p, int use_cache, hipStream_t st, int *chosen)
+{
+    if (!ctx || !p || p->ctx != ctx) return LMMEW_EINVAL;
+    const TuneKey key = tune_key(ctx, p);
+    if (use_cache) {
+        for (const auto &kv : g_tune_cache)
+            if (kv.first == key) {
+                if (chosen) *chosen = kv.second;
+                return lmmew_plan_set_event_tile(ctx, p, kv.second, st);
+            }
+    }
+    int big = 0;
+    for (int s = 1; s < p->nsub; ++s)
+        if (p->subs[s].rows > p->subs[big].rows) big = s;
+    const bool prof_was = p->prof;
+    p->prof = false;
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    int best = 16;
+    float best_ms = 0.f;
+    int rc = LMMEW_OK;
+    for (int jt : {16, 32, 64}) {
+        rc = lmmew_plan_set_event_tile(ctx, p, jt, st);
+        if (rc != LMMEW_OK) break;
+        // the per-event kernel alone (it writes only the plan's scratch rows) on
+        // the largest subset: once to warm up, once timed
+        rc = run_rows(ctx, p, big, st);
+        if (rc != LMMEW_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = LMMEW_EDEVICE; break; }
+        rc = run_rows(ctx, p, big, st);
+        if (rc != LMMEW_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(ctx, LMMEW_EDEVICE, "autotune timing failed");
+            break;
+        }
+        if (jt == 16 || ms < best_ms) {
+            best = jt;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->prof = prof_was;
+    if (rc != LMMEW_OK) return rc;
+    g_tune_cache.push_back({key, best});
+    if (chosen) *chosen = best;
+    return lmmew_plan_set_event_tile(ctx, p, best, st);
+}
 
 int lmmew_plan_profile(lmmew_ctx *ctx, lmmew_plan *plan, int enable)
 {

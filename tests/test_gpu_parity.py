@@ -286,3 +286,63 @@ def test_empty_and_single_event_lists(c1, lm):
     plan.osem_iter(1, s1, lam)
     # count conservation with a single event
     assert float((s1[0].double() * lam.double()).sum()) == pytest.approx(1.0, rel=TOL)
+
+
+def test_graph_launch_equals_eager_and_replays(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    sens = ctx.sensitivity(4)
+    plan = ctx.plan(ev, 4)
+    lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    eager = lam0.clone()
+    plan.osem_iter(3, sens, eager)
+    lam = lam0.clone()
+    for rep in range(3):
+        lam.copy_(lam0)                    # eager work between replays
+        torch.cuda.synchronize()
+        plan.osem_graph(3, sens, lam)
+        torch.cuda.synchronize()
+        assert torch.equal(lam, eager), rep
+    mx, l2 = _rel(lam.cpu().numpy(), g["hist"][11])
+    assert mx < TOL and l2 < TOL
+
+
+def test_autotune_keeps_results(c1):
+    import torch
+
+    p, g, ctx, ev = c1
+    sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
+    plan = ctx.plan(ev, 4)
+    jt = plan.autotune(use_cache=False)
+    assert jt in (16, 32, 64) and plan.event_tile == jt
+    assert plan.autotune(use_cache=True) == jt
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan.osem_graph(2, sens, lam)
+    mx, l2 = _rel(lam.cpu().numpy(), g["hist"][7])
+    assert mx < TOL and l2 < TOL
+
+
+def test_batched_uneven_cases_in_one_graph(lm):
+    import torch
+
+    w = synth.CONFIGS["c2"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+    sens = ctx.sensitivity(w.n_subsets)
+    counts = [1500, 9000, 300, 4200]
+    evs = [synth.generic_events(p, act, n, 700 + c) for c, n in enumerate(counts)]
+    cat = {k: np.concatenate([e[k] for e in evs]) for k in ("bin", "angle", "energy")}
+    offs = np.concatenate([[0], np.cumsum(counts)]).tolist()
+    lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+    batched = lam0.repeat(len(counts), 1).contiguous()
+    plan = ctx.plan(_dev(cat), w.n_subsets, case_offsets=offs)
+    plan.autotune()
+    plan.osem_graph(2, sens, batched)
+    for c, e in enumerate(evs):
+        lam = lam0.clone()
+        single = ctx.plan(_dev(e), w.n_subsets)
+        single.set_event_tile(plan.event_tile)
+        single.osem_iter(2, sens, lam)
+        assert torch.equal(lam, batched[c]), c
