@@ -104,6 +104,7 @@ typedef struct lmmew_stats {
 
 typedef struct lmmew_ctx lmmew_ctx;
 typedef struct lmmew_plan lmmew_plan;
+typedef struct lmmew_mlp lmmew_mlp;
 
 /* Text for a status code. */
 const char *lmmew_status_string(int status);
@@ -243,6 +244,91 @@ int lmmew_plan_profile_read(lmmew_ctx *ctx, lmmew_plan *plan, double *row_ms, in
  *   out_terms      host: terms evaluated per iteration.
  *   out_full_terms host: terms of the unpruned model per iteration. */
 int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full_terms);
+
+/* ---------------------------------------------------------------------------
+ * Per-event rows
+ * ------------------------------------------------------------------------- */
+
+/* Full system rows for arbitrary events: rows[j][q] = a_jq over the n*n grid
+ * (zero off the support), in input order.
+ *   part  0: the context's scatter model (exact, or the surrogate when one
+ *            is set with lmmew_set_scatter_model) plus the unscattered paths;
+ *         1: exact once-scattered paths only; 2: unscattered paths only;
+ *         3: exact model (ignores a surrogate).
+ *   rows  device [ev->n][n*n] float, written.
+ * Synchronises the stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int lmmew_rows(lmmew_ctx *ctx, const lmmew_events *ev, int part, float *rows, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Scatter surrogate (an extension beyond the paper)
+ *
+ * A network that replaces the once-scattered part of a_jq (the sum over lines
+ * and scatter points in Eq. (3)) for the context's attenuation map, while the
+ * unscattered part stays exact.  Inputs of an (event, pixel) pair, in the
+ * detector frame of the event's angle: (bin centre - pixel's lateral
+ * projection)/R, pixel depth below the detector plane/R, pixel's lateral
+ * projection/R, cos(angle), sin(angle), (E - 180 keV)/120 keV.
+ * Architecture: 6 -> 128 -> 128 -> 128 -> 1, tanh-form GELU after each hidden
+ * layer; the 128x128 layers run as BF16 MFMA with FP32 accumulation, the
+ * first and last layers in FP32.  The output y is the shifted logarithm of
+ * the density: density = max(exp(y + c0) - floor, 0).
+ * Parameters (FP32 master copy, 34049 floats, in this order):
+ *   W1[6][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] w4[128] b4[1],
+ * W[i][o] mapping input unit i to output unit o.
+ * ------------------------------------------------------------------------- */
+#define LMMEW_MLP_PARAMS 34049
+
+/* Creates a network for the context with Glorot-uniform weights (zero biases)
+ * drawn from a counter-based generator seeded with seed.  Synchronises. */
+int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out);
+int lmmew_mlp_destroy(lmmew_mlp *mlp);
+
+/* Host copies of the FP32 parameters (NULL to skip) and the output shift c0
+ * and floor.  set also resets the Adam state. */
+int lmmew_mlp_get_params(const lmmew_mlp *mlp, float *params, double *c0, double *floor_);
+int lmmew_mlp_set_params(lmmew_mlp *mlp, const float *params, double c0, double floor_);
+
+/* Raw network output y for n feature rows.  feats: device [n][6] float;
+ * y: device [n] float.  Synchronises. */
+int lmmew_mlp_forward(lmmew_ctx *ctx, lmmew_mlp *mlp, const float *feats, int64_t n, float *y,
+                      hipStream_t stream);
+
+/* Gradient of the mean squared error (1/n) sum (y - target)^2 with respect to
+ * the parameters, for one batch of n rows (n a multiple of 16, <= 2^24).
+ *   grad: device [LMMEW_MLP_PARAMS] float; loss: host, may be NULL.
+ * Synchronises. */
+int lmmew_mlp_grad(lmmew_ctx *ctx, lmmew_mlp *mlp, const float *feats, const float *target,
+                   int64_t n, float *grad, double *loss, hipStream_t stream);
+
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error over
+ * epochs passes of the n rows, shuffled each epoch (seeded), in batches of
+ * `batch` rows (a multiple of 16; a trailing partial batch is dropped); the
+ * step size decays from lr to lr/10 along a half cosine over the run.
+ * epoch_loss: host [epochs] or NULL (mean loss of each epoch). */
+int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *mlp, const float *feats, const float *target,
+                    int64_t n, int batch, int epochs, double lr, uint64_t seed,
+                    double *epoch_loss, hipStream_t stream);
+
+/* Training samples from the exact model: n_events events with bin and angle
+ * uniform and energy uniform over the union of the windows (seeded), each
+ * paired with every support pixel (Qm pixels): n_events*Qm samples in the
+ * library's row order.  feats: device [n_events*Qm][6]; raw: device
+ * [n_events*Qm], the exact once-scattered density. */
+int lmmew_scatter_labels(lmmew_ctx *ctx, int64_t n_events, uint64_t seed, float *feats,
+                         float *raw, hipStream_t stream);
+
+/* Labels (lmmew_scatter_labels), floor = floor_frac x mean density, c0 =
+ * mean of log(density + floor), targets log(density + floor) - c0, then
+ * lmmew_mlp_train. */
+int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, int64_t n_label_events, int epochs, int batch,
+                  double lr, double floor_frac, uint64_t seed, double *epoch_loss,
+                  hipStream_t stream);
+
+/* Selects the scatter model that lmmew_osem_iter/_subiter/_graph,
+ * lmmew_forward and lmmew_backproject use for this context: NULL for the
+ * exact model, or a network of this context (kept by pointer: it must stay
+ * alive while selected). */
+int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *mlp);
 
 #ifdef __cplusplus
 }

@@ -99,6 +99,7 @@ def lib():
             "or_Pp": (C.c_double, [_G, C.c_int, C.c_int, C.c_int]),
             "or_Ps": (C.c_double, [_G, C.c_int, C.c_int, C.c_int, C.c_int, _D]),
             "or_event_row": (None, [_G, C.c_int, C.c_int, C.c_double, _D]),
+            "or_event_row_scatter": (None, [_G, C.c_int, C.c_int, C.c_double, _D]),
             "or_sens_qa": (C.c_double, [_G, C.c_int, C.c_int]),
             "or_sensitivity": (None, [_G, C.c_int, _D]),
             "or_sample_masses": (C.c_long, [_G, _D, _D]),
@@ -266,6 +267,11 @@ class Oracle:
     def row(self, b, a, E):
         out = np.zeros(self.Q)
         lib().or_event_row(C.byref(self._g), int(b), int(a), float(E), _dp(out))
+        return out
+
+    def row_scatter(self, b, a, E):
+        out = np.zeros(self.Q)
+        lib().or_event_row_scatter(C.byref(self._g), int(b), int(a), float(E), _dp(out))
         return out
 
     def sens_qa(self, q, a):

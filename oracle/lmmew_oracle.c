@@ -412,6 +412,27 @@ void or_event_row(const or_geom *G, int b, int a, double Ehat, double *row)
     }
 }
 
+/* The once-scattered part of or_event_row alone (the quantity the scatter
+ * surrogate learns): sum over lines and scatter points of the scattered
+ * path terms. */
+void or_event_row_scatter(const or_geom *G, int b, int a, double Ehat, double *row)
+{
+    const or_sys *S = &G->S;
+    for (int q = 0; q < G->Q; ++q) {
+        row[q] = 0.0;
+        if (!G->support[q]) continue;
+        double acc = 0.0;
+        for (int w = 0; w < S->nw; ++w)
+            for (int si = 0; si < G->nsc; ++si) {
+                double Ep;
+                double ps = or_Ps(G, q, si, a, w, &Ep);
+                acc += ps * or_psf_bin(G, b, G->sx[si], G->sy[si], a) *
+                       or_gauss(Ehat, Ep, or_sigmaE(S, Ep));
+            }
+        row[q] = acc;
+    }
+}
+
 /* Detection probability per unit activity of pixel q at angle a (Eq. (7)
  * restricted to one pixel and one angle, counting only photons that land on
  * the detector and inside an energy window). */

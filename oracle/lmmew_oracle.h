@@ -93,6 +93,7 @@ void   or_geom_free(or_geom *G);
 double or_Pp(const or_geom *G, int q, int a, int w);
 double or_Ps(const or_geom *G, int q, int si, int a, int w, double *Eprime);
 void   or_event_row(const or_geom *G, int b, int a, double Ehat, double *row);
+void   or_event_row_scatter(const or_geom *G, int b, int a, double Ehat, double *row);
 double or_sens_qa(const or_geom *G, int q, int a);
 void   or_sensitivity(const or_geom *G, int nsub, double *sens);
 long   or_sample_masses(const or_geom *G, const double *lambda, double *mass);

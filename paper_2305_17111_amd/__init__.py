@@ -10,6 +10,7 @@ from .binding import (  # noqa: F401
     LmmewError,
     Context,
     Plan,
+    Mlp,
     events_to_device,
     system_from_params,
     library_path,

@@ -82,6 +82,19 @@ def _load():
         "lmmew_plan_get_event_tile": (i32, [vp]),
         "lmmew_plan_terms": (i32, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lmmew_plan_profile": (i32, [vp, vp, i32]),
+        "lmmew_rows": (i32, [vp, C.POINTER(_Events), i32, vp, vp]),
+        "lmmew_mlp_create": (i32, [vp, C.c_uint64, C.POINTER(vp)]),
+        "lmmew_mlp_destroy": (i32, [vp]),
+        "lmmew_mlp_get_params": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "lmmew_mlp_set_params": (i32, [vp, vp, C.c_double, C.c_double]),
+        "lmmew_mlp_forward": (i32, [vp, vp, vp, i64, vp, vp]),
+        "lmmew_mlp_grad": (i32, [vp, vp, vp, vp, i64, vp, C.POINTER(C.c_double), vp]),
+        "lmmew_mlp_train": (i32, [vp, vp, vp, vp, i64, i32, i32, C.c_double, C.c_uint64,
+                                  C.POINTER(C.c_double), vp]),
+        "lmmew_scatter_labels": (i32, [vp, i64, C.c_uint64, vp, vp, vp]),
+        "lmmew_mlp_fit": (i32, [vp, vp, i64, i32, i32, C.c_double, C.c_double, C.c_uint64,
+                                C.POINTER(C.c_double), vp]),
+        "lmmew_set_scatter_model": (i32, [vp, vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -200,6 +213,34 @@ class Context:
         self._check(_load().lmmew_backproject(self._h, C.byref(e), _ptr(w), _ptr(out), _stream()))
         return out
 
+    def lmmew_rows(self, ev, part=0, out=None):
+        """Full rows a_jq [n, n*n]; part 0 context model, 1 exact scattered, 2 unscattered,
+        3 exact."""
+        e = _events(ev)
+        if out is None:
+            out = torch.empty((e.n, self.Q), device="cuda", dtype=torch.float32)
+        self._check(_load().lmmew_rows(self._h, C.byref(e), int(part), _ptr(out), _stream()))
+        return out
+
+    def lmmew_scatter_labels(self, n_events, seed, Qm):
+        feats = torch.empty((n_events * Qm, 6), device="cuda", dtype=torch.float32)
+        raw = torch.empty(n_events * Qm, device="cuda", dtype=torch.float32)
+        self._check(_load().lmmew_scatter_labels(self._h, int(n_events), C.c_uint64(seed),
+                                                 _ptr(feats), _ptr(raw), _stream()))
+        return feats, raw
+
+    def lmmew_set_scatter_model(self, mlp):
+        self._check(_load().lmmew_set_scatter_model(self._h, mlp._h if mlp is not None else None))
+        self._scatter_model = mlp
+
+    def lmmew_mlp_create(self, seed=0):
+        return Mlp(self, seed)
+
+    rows = lmmew_rows
+    scatter_labels = lmmew_scatter_labels
+    set_scatter_model = lmmew_set_scatter_model
+    mlp = lmmew_mlp_create
+
     def lmmew_plan_create(self, ev, n_subsets, case_offsets=None):
         return Plan(self, ev, n_subsets, case_offsets)
 
@@ -317,3 +358,74 @@ class Plan:
 
     osem_iter = lmmew_osem_iter
     osem_subiter = lmmew_osem_subiter
+
+
+class Mlp:
+    """lmmew_mlp_*: the scatter surrogate network of a context."""
+
+    NPARAM = 34049
+
+    def __init__(self, ctx: Context, seed=0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx._check(_load().lmmew_mlp_create(ctx._h, C.c_uint64(seed), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().lmmew_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+
+        p = np.zeros(self.NPARAM, np.float32)
+        c0, fl = C.c_double(), C.c_double()
+        self.ctx._check(_load().lmmew_mlp_get_params(self._h, C.c_void_p(p.ctypes.data),
+                                                     C.byref(c0), C.byref(fl)))
+        return p, c0.value, fl.value
+
+    def set_params(self, params, c0=0.0, floor=0.0):
+        import numpy as np
+
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == self.NPARAM
+        self.ctx._check(_load().lmmew_mlp_set_params(self._h, C.c_void_p(p.ctypes.data),
+                                                     float(c0), float(floor)))
+
+    def forward(self, feats):
+        feats = feats.contiguous()
+        y = torch.empty(feats.shape[0], device="cuda", dtype=torch.float32)
+        self.ctx._check(_load().lmmew_mlp_forward(self.ctx._h, self._h, _ptr(feats),
+                                                  feats.shape[0], _ptr(y), _stream()))
+        return y
+
+    def grad(self, feats, target):
+        feats, target = feats.contiguous(), target.contiguous()
+        g = torch.empty(self.NPARAM, device="cuda", dtype=torch.float32)
+        loss = C.c_double()
+        self.ctx._check(_load().lmmew_mlp_grad(self.ctx._h, self._h, _ptr(feats), _ptr(target),
+                                               feats.shape[0], _ptr(g), C.byref(loss), _stream()))
+        return g, loss.value
+
+    def train(self, feats, target, batch=4096, epochs=1, lr=1e-3, seed=0):
+        feats, target = feats.contiguous(), target.contiguous()
+        losses = (C.c_double * max(epochs, 1))()
+        self.ctx._check(_load().lmmew_mlp_train(self.ctx._h, self._h, _ptr(feats), _ptr(target),
+                                                feats.shape[0], int(batch), int(epochs), float(lr),
+                                                C.c_uint64(seed), losses, _stream()))
+        return list(losses)[:epochs]
+
+    def fit(self, n_label_events, epochs=4, batch=4096, lr=1e-3, floor_frac=1e-2, seed=0):
+        losses = (C.c_double * max(epochs, 1))()
+        self.ctx._check(_load().lmmew_mlp_fit(self.ctx._h, self._h, int(n_label_events),
+                                              int(epochs), int(batch), float(lr),
+                                              float(floor_frac), C.c_uint64(seed), losses,
+                                              _stream()))
+        return list(losses)[:epochs]

@@ -16,6 +16,21 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kPi = 3.14159265358979323846;
 constexpr float kPsfCut = 7.0f;    // collimator-response Gaussian dropped beyond 7 sigma
 
+// scatter surrogate network (6 -> 128 -> 128 -> 128 -> 1)
+constexpr int kMlpIn = 6;
+constexpr int kMlpHidden = 128;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpIn * kMlpHidden;
+constexpr int kOffW2 = kOffB1 + kMlpHidden;
+constexpr int kOffB2 = kOffW2 + kMlpHidden * kMlpHidden;
+constexpr int kOffW3 = kOffB2 + kMlpHidden;
+constexpr int kOffB3 = kOffW3 + kMlpHidden * kMlpHidden;
+constexpr int kOffW4 = kOffB3 + kMlpHidden;
+constexpr int kOffB4 = kOffW4 + kMlpHidden;
+constexpr int kMlpParams = kOffB4 + 1;            // 34049
+constexpr int kMlpTStride = kMlpHidden + 4;       // padded row of the transposed bf16 weights
+constexpr float kMlpEc = 180.f, kMlpEs = 120.f;   // energy feature: (E - kMlpEc) / kMlpEs
+
 // Per-run constants passed by value to the kernels.
 struct DevSys {
     int n, ns, nb, na, nw, nwin;
@@ -84,6 +99,7 @@ struct RowArgs {
     const int *ev_bin;       // sorted rows of this subset
     const float *ev_E;
     float *A;                // [rows][Qp]
+    int mode;                // 0: all paths, 1: scattered paths only, 2: unscattered only
 };
 hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st);
 
@@ -147,7 +163,44 @@ hipError_t launch_loglik(const ReduceArgs &r, hipStream_t st);
 
 hipError_t launch_scatter_out(const float *src, const int64_t *perm, int64_t n, float *dst,
                               hipStream_t st);
+hipError_t launch_rows_out(const DevSys &S, const float *A, int rows, const int64_t *perm,
+                           const int *pixq, int Q, float *out, hipStream_t st);
 hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float *dst,
                            hipStream_t st);
+
+// ---- scatter surrogate (mlp.hip) ------------------------------------------
+struct MlpWork {             // activations of one training batch
+    float *X, *Z1, *Z2, *Z3, *H3, *dZ, *dH, *y, *dy, *sq;
+    float *part, *split;               // reduction partials: [M/256][8][128], [64][128][128]
+    double *dsum;
+    unsigned short *H1b, *H2b, *dZb;
+    const unsigned short *W2b, *W3b;   // bf16 [in][out]
+};
+struct MlpRowArgs {
+    const float2 *pix_xy, *dirs;
+    const int *ev_bin, *ev_ang;
+    const float *ev_E;
+    int rows;
+    float *A;
+    const float *P;                    // fp32 parameters
+    const unsigned short *W2t, *W3t;   // bf16 [out][kMlpTStride]
+    float c0, floor_;
+};
+hipError_t mlp_gemm(const unsigned short *A, long sai, long sak, const unsigned short *B, long sbk,
+                    long sbj, float *C, long ldc, int M, int N, int K, hipStream_t st);
+hipError_t mlp_forward_batch(const MlpWork &w, const float *P, const float *feats, const int *idx,
+                             int M, const float *tgt, hipStream_t st);
+hipError_t mlp_backward_batch(const MlpWork &w, const float *P, int M, float *G, hipStream_t st);
+hipError_t mlp_loss(const MlpWork &w, int M, double *out, hipStream_t st);
+hipError_t mlp_adam(float *P, const float *G, float *m1, float *m2, float lr, int step,
+                    hipStream_t st);
+hipError_t mlp_refresh(const float *P, unsigned short *W2b, unsigned short *W3b,
+                       unsigned short *W2t, unsigned short *W3t, hipStream_t st);
+hipError_t mlp_labels(const DevSys &S, const float2 *pix_xy, const float2 *dirs, const int *ev_bin,
+                      const int *ev_ang, const float *ev_E, const float *A, int rows, float *feats,
+                      float *raw, hipStream_t st);
+hipError_t mlp_targets(const float *raw, long n, float floor_, float c0, float *tgt,
+                       hipStream_t st);
+hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st);
 
 }  // namespace lmmew

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         for (int w = 0; w < NW; ++w) Pp[w] = S.pp[w] * fast_exp2(-S.f[w] * gqa * kLog2e);
         for (int j = 0; j < T.cnt; ++j) {
             const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
-            const float ps = psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
+            const float ps = (r.mode == 1) ? 0.f : psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
             float g = 0.f;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
@@ -310,7 +310,8 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 
     const ScatA *sa = r.sa + (size_t)a * S.nsc;
     const int kl = lane % KC, jg = lane / KC;
-    for (int lc0 = T.k0; lc0 < T.k1; lc0 += KC) {
+    const int kend = (r.mode == 2) ? T.k0 : T.k1;     // unscattered only: no scatter loop
+    for (int lc0 = T.k0; lc0 < kend; lc0 += KC) {
         // response factors of (listed scatter point lc0+kl, events jg*TJ .. jg*TJ+TJ-1)
         float pv[TJ];
         {
@@ -553,6 +554,17 @@ __global__ __launch_bounds__(256) void k_scatter_out(const float *src, const int
     if (e < n) dst[perm[e]] = src[e];
 }
 
+// out[perm[e]][pixq[i]] = A[e][i] for the rows of one subset (full-grid rows)
+__global__ __launch_bounds__(256) void k_rows_out(const DevSys S, const float *A, int rows,
+                                                  const int64_t *perm, const int *pixq, int Q,
+                                                  float *out)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)rows * S.Qm) return;
+    const int e = (int)(t / S.Qm), i = (int)(t % S.Qm);
+    out[perm[e] * Q + pixq[i]] = A[(long)e * S.Qp + i];
+}
+
 __global__ __launch_bounds__(256) void k_gather_w(const float *w, const int64_t *perm, int64_t n,
                                                   float *dst)
 {
@@ -629,6 +641,16 @@ hipError_t launch_scatter_out(const float *src, const int64_t *perm, int64_t n, 
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src,
                        perm, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_out(const DevSys &S, const float *A, int rows, const int64_t *perm,
+                           const int *pixq, int Q, float *out, hipStream_t st)
+{
+    const long n = (long)rows * S.Qm;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rows_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S, A, rows,
+                       perm, pixq, Q, out);
     return hipGetLastError();
 }
 

@@ -38,6 +38,25 @@ struct lmmew_ctx {
     ScatA *d_sa = nullptr;
     float *d_Sqa = nullptr;
     hipStream_t cap_stream = nullptr; // private stream that graph captures are recorded on
+    lmmew_mlp *mlp = nullptr;         // scatter surrogate used by OSEM (NULL: exact model)
+    int model_gen = 0;                // bumped whenever the scatter model changes
+};
+
+struct lmmew_mlp {
+    lmmew_ctx *ctx = nullptr;
+    float *P = nullptr, *G = nullptr, *m1 = nullptr, *m2 = nullptr;   // [kMlpParams]
+    unsigned short *W2b = nullptr, *W3b = nullptr, *W2t = nullptr, *W3t = nullptr;
+    double c0 = 0.0, floor_ = 0.0;    // target = log(density + floor) - c0
+    int step = 0;                     // Adam step count
+    // training workspace for batches of up to cap samples
+    int cap = 0;
+    float *X = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *H3 = nullptr, *dZ = nullptr,
+          *dH = nullptr, *y = nullptr, *dy = nullptr, *sq = nullptr;
+    unsigned short *H1b = nullptr, *H2b = nullptr, *dZb = nullptr;
+    int *idx = nullptr;
+    double *dloss = nullptr;
+    float *part = nullptr, *split = nullptr;
+    double *dsum = nullptr;
 };
 
 struct lmmew_plan {
@@ -45,6 +64,7 @@ struct lmmew_plan {
     int nsub = 1, ncases = 1, JT = 64;
     int64_t n = 0;
     std::vector<int> bin, ang, cas;   // sorted rows
+    int *d_ang = nullptr;
     std::vector<float> E;
     std::vector<int64_t> perm;        // sorted row -> input index
     struct Sub {
@@ -73,7 +93,7 @@ struct lmmew_plan {
     int stats_cap = 0;
     // captured OSEM sequence (lmmew_osem_graph) and the arguments it was captured with
     hipGraphExec_t gexec = nullptr;
-    int g_iters = -1, g_jt = 0;
+    int g_iters = -1, g_jt = 0, g_gen = -1;
     const float *g_sens = nullptr;
     float *g_lambda = nullptr;
     // optional timing of the per-event kernel launches (HIP events on the caller's stream)
@@ -192,7 +212,7 @@ void free_plan(lmmew_plan *p)
     p->gexec = nullptr;
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
     p->prof_ev.clear();
-    dfree(p->d_bin); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
+    dfree(p->d_bin); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
     dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
 }
@@ -440,6 +460,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         if (e_ != hipSuccess) return fin(hipfail(ctx, e_, #call)); \
     } while (0)
     PCHK(dalloc(&p->d_bin, n));
+    PCHK(dalloc(&p->d_ang, n));
     PCHK(dalloc(&p->d_case, n));
     PCHK(dalloc(&p->d_E, n));
     PCHK(dalloc(&p->d_perm, n));
@@ -449,6 +470,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     PCHK(dalloc(&p->d_A, (size_t)std::max(p->max_rows, 1) * Qp));
     if (n > 0) {
         PCHK(hipMemcpyAsync(p->d_bin, p->bin.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(p->d_ang, p->ang.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_case, p->cas.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_E, p->E.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_perm, p->perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice,
@@ -461,9 +483,13 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     return LMMEW_OK;
 }
 
-int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st)
+// a_jq of subset s into the plan's scratch rows.  part: 0 the context's model
+// (exact, or unscattered + surrogate when a surrogate is set), 1 exact
+// scattered paths only, 2 unscattered only, 3 exact (ignoring the surrogate).
+int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0)
 {
     const lmmew_plan::Sub &sub = p->subs[s];
+    const bool surrogate = (part == 0 && ctx->mlp != nullptr);
     RowArgs r{};
     r.pix_xy = ctx->d_pix;
     r.dirs = ctx->d_dirs;
@@ -476,19 +502,38 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st)
     r.ev_bin = p->d_bin + sub.row0;
     r.ev_E = p->d_E + sub.row0;
     r.A = p->d_A;
-    if (p->prof && sub.ntiles > 0) {
+    r.mode = surrogate ? 2 : (part == 3 ? 0 : part);
+    const bool prof = p->prof && sub.ntiles > 0;
+    if (prof) {
         while (p->prof_ev.size() < p->prof_used + 2) {
             hipEvent_t e;
             HIPCHK(ctx, hipEventCreate(&e));
             p->prof_ev.push_back(e);
         }
         HIPCHK(ctx, hipEventRecord(p->prof_ev[p->prof_used], st));
-        HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
-        HIPCHK(ctx, hipEventRecord(p->prof_ev[p->prof_used + 1], st));
-        p->prof_used += 2;
-        return LMMEW_OK;
     }
     HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
+    if (prof) {
+        HIPCHK(ctx, hipEventRecord(p->prof_ev[p->prof_used + 1], st));
+        p->prof_used += 2;
+    }
+    if (surrogate) {
+        const lmmew_mlp *m = ctx->mlp;
+        MlpRowArgs a{};
+        a.pix_xy = ctx->d_pix;
+        a.dirs = ctx->d_dirs;
+        a.ev_bin = p->d_bin + sub.row0;
+        a.ev_ang = p->d_ang + sub.row0;
+        a.ev_E = p->d_E + sub.row0;
+        a.rows = sub.rows;
+        a.A = p->d_A;
+        a.P = m->P;
+        a.W2t = m->W2t;
+        a.W3t = m->W3t;
+        a.c0 = (float)m->c0;
+        a.floor_ = (float)m->floor_;
+        HIPCHK(ctx, mlp_rows(ctx->S, a, st));
+    }
     return LMMEW_OK;
 }
 
@@ -889,7 +934,7 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
     if (n_iters < 0) return fail(ctx, LMMEW_EINVAL, "n_iters < 0");
     if (n_iters == 0) return LMMEW_OK;
     if (!p->gexec || p->g_iters != n_iters || p->g_sens != sens || p->g_lambda != lambda ||
-        p->g_jt != p->JT) {
+        p->g_jt != p->JT || p->g_gen != ctx->model_gen) {
         if (p->gexec) {
             HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
             p->gexec = nullptr;
@@ -922,6 +967,7 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
         p->g_sens = sens;
         p->g_lambda = lambda;
         p->g_jt = p->JT;
+        p->g_gen = ctx->model_gen;
     }
     HIPCHK(ctx, hipGraphLaunch(p->gexec, st));
     return LMMEW_OK;
@@ -1145,6 +1191,393 @@ int lmmew_osem_subiter(lmmew_ctx *ctx, lmmew_plan *p, int subset, const float *s
     if (!sens || !lambda) return fail(ctx, LMMEW_EINVAL, "NULL image or sensitivity");
     if (subset < 0 || subset >= p->nsub) return fail(ctx, LMMEW_EINVAL, "subset out of range");
     return osem_run(ctx, p, subset, 1, sens, lambda, stats, st);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// per-event rows and the scatter surrogate
+// ---------------------------------------------------------------------------
+namespace {
+
+uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double unit_rand(uint64_t &x) { return (double)(splitmix64(x) >> 11) * (1.0 / 9007199254740992.0); }
+
+void free_mlp(lmmew_mlp *m)
+{
+    dfree(m->P); dfree(m->G); dfree(m->m1); dfree(m->m2);
+    dfree(m->W2b); dfree(m->W3b); dfree(m->W2t); dfree(m->W3t);
+    dfree(m->X); dfree(m->Z1); dfree(m->Z2); dfree(m->Z3); dfree(m->H3); dfree(m->dZ); dfree(m->dH);
+    dfree(m->y); dfree(m->dy); dfree(m->sq); dfree(m->H1b); dfree(m->H2b); dfree(m->dZb);
+    dfree(m->idx); dfree(m->dloss); dfree(m->part); dfree(m->split); dfree(m->dsum);
+}
+
+int mlp_workspace(lmmew_ctx *ctx, lmmew_mlp *m, int M)
+{
+    if (M <= m->cap) return LMMEW_OK;
+    dfree(m->X); dfree(m->Z1); dfree(m->Z2); dfree(m->Z3); dfree(m->H3); dfree(m->dZ); dfree(m->dH);
+    dfree(m->y); dfree(m->dy); dfree(m->sq); dfree(m->H1b); dfree(m->H2b); dfree(m->dZb);
+    dfree(m->idx); dfree(m->part); dfree(m->split); dfree(m->dsum);
+    const size_t n = (size_t)M * kMlpHidden;
+    HIPCHK(ctx, dalloc(&m->X, (size_t)M * kMlpIn));
+    HIPCHK(ctx, dalloc(&m->Z1, n));
+    HIPCHK(ctx, dalloc(&m->Z2, n));
+    HIPCHK(ctx, dalloc(&m->Z3, n));
+    HIPCHK(ctx, dalloc(&m->H3, n));
+    HIPCHK(ctx, dalloc(&m->dZ, n));
+    HIPCHK(ctx, dalloc(&m->dH, n));
+    HIPCHK(ctx, dalloc(&m->H1b, n));
+    HIPCHK(ctx, dalloc(&m->H2b, n));
+    HIPCHK(ctx, dalloc(&m->dZb, n));
+    HIPCHK(ctx, dalloc(&m->y, M));
+    HIPCHK(ctx, dalloc(&m->dy, M));
+    HIPCHK(ctx, dalloc(&m->sq, M));
+    HIPCHK(ctx, dalloc(&m->idx, M));
+    HIPCHK(ctx, dalloc(&m->part, (size_t)((M + 255) / 256) * 8 * kMlpHidden));
+    HIPCHK(ctx, dalloc(&m->split, (size_t)64 * kMlpHidden * kMlpHidden));
+    HIPCHK(ctx, dalloc(&m->dsum, 1));
+    m->cap = M;
+    return LMMEW_OK;
+}
+
+MlpWork mlp_work(const lmmew_mlp *m)
+{
+    MlpWork w{};
+    w.X = m->X; w.Z1 = m->Z1; w.Z2 = m->Z2; w.Z3 = m->Z3; w.H3 = m->H3; w.dZ = m->dZ; w.dH = m->dH;
+    w.y = m->y; w.dy = m->dy; w.sq = m->sq; w.H1b = m->H1b; w.H2b = m->H2b; w.dZb = m->dZb;
+    w.W2b = m->W2b; w.W3b = m->W3b;
+    w.part = m->part; w.split = m->split; w.dsum = m->dsum;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lmmew_rows(lmmew_ctx *ctx, const lmmew_events *ev, int part, float *rows, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!ev || (!rows && ev->n > 0)) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    if (part < 0 || part > 3) return fail(ctx, LMMEW_EINVAL, "part must be 0..3");
+    lmmew_plan *pl = nullptr;
+    int rc = make_plan(ctx, ev, nullptr, 1, subsets_for_budget(ctx, ev->n), st, &pl);
+    if (rc != LMMEW_OK) return rc;
+    hipError_t e = hipMemsetAsync(rows, 0, (size_t)ev->n * ctx->Q * sizeof(float), st);
+    if (e != hipSuccess) rc = hipfail(ctx, e, "memset");
+    for (int s = 0; s < pl->nsub && rc == LMMEW_OK; ++s) {
+        const int mode = part == 0 ? 0 : (part == 1 ? 1 : (part == 2 ? 2 : 3));
+        rc = run_rows(ctx, pl, s, st, mode);
+        if (rc == LMMEW_OK) {
+            const lmmew_plan::Sub &sub = pl->subs[s];
+            e = launch_rows_out(ctx->S, pl->d_A, sub.rows, pl->d_perm + sub.row0, ctx->d_pixq,
+                                ctx->Q, rows, st);
+            if (e != hipSuccess) rc = hipfail(ctx, e, "rows out");
+        }
+    }
+    e = hipStreamSynchronize(st);
+    if (rc == LMMEW_OK && e != hipSuccess) rc = hipfail(ctx, e, "synchronize");
+    lmmew_plan_destroy(pl);
+    return rc;
+}
+
+int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
+{
+    if (!ctx || !out) return LMMEW_EINVAL;
+    *out = nullptr;
+    lmmew_mlp *m = new (std::nothrow) lmmew_mlp;
+    if (!m) return fail(ctx, LMMEW_ENOMEM, "host allocation");
+    m->ctx = ctx;
+    auto bail = [&](int code) {
+        free_mlp(m);
+        delete m;
+        return code;
+    };
+#define MCHK(call)                                                 \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return bail(hipfail(ctx, e_, #call)); \
+    } while (0)
+    MCHK(dalloc(&m->P, kMlpParams));
+    MCHK(dalloc(&m->G, kMlpParams));
+    MCHK(dalloc(&m->m1, kMlpParams));
+    MCHK(dalloc(&m->m2, kMlpParams));
+    MCHK(dalloc(&m->W2b, kMlpHidden * kMlpHidden));
+    MCHK(dalloc(&m->W3b, kMlpHidden * kMlpHidden));
+    MCHK(dalloc(&m->W2t, kMlpHidden * kMlpTStride));
+    MCHK(dalloc(&m->W3t, kMlpHidden * kMlpTStride));
+    MCHK(dalloc(&m->dloss, 1));
+    // Glorot-uniform weights, zero biases, from a counter-based generator
+    std::vector<float> P(kMlpParams, 0.f);
+    uint64_t st_ = seed;
+    auto fill = [&](int off, int fin, int fout) {
+        const double a = std::sqrt(6.0 / (fin + fout));
+        for (int t = 0; t < fin * fout; ++t) P[off + t] = (float)((2.0 * unit_rand(st_) - 1.0) * a);
+    };
+    fill(kOffW1, kMlpIn, kMlpHidden);
+    fill(kOffW2, kMlpHidden, kMlpHidden);
+    fill(kOffW3, kMlpHidden, kMlpHidden);
+    fill(kOffW4, kMlpHidden, 1);
+    MCHK(hipMemcpy(m->P, P.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    MCHK(hipMemset(m->m1, 0, sizeof(float) * kMlpParams));
+    MCHK(hipMemset(m->m2, 0, sizeof(float) * kMlpParams));
+    MCHK(hipMemset(m->W2t, 0, sizeof(unsigned short) * kMlpHidden * kMlpTStride));
+    MCHK(hipMemset(m->W3t, 0, sizeof(unsigned short) * kMlpHidden * kMlpTStride));
+    MCHK(mlp_refresh(m->P, m->W2b, m->W3b, m->W2t, m->W3t, nullptr));
+    MCHK(hipDeviceSynchronize());
+#undef MCHK
+    *out = m;
+    return LMMEW_OK;
+}
+
+int lmmew_mlp_destroy(lmmew_mlp *m)
+{
+    if (!m) return LMMEW_EINVAL;
+    (void)hipDeviceSynchronize();
+    if (m->ctx && m->ctx->mlp == m) {
+        m->ctx->mlp = nullptr;
+        m->ctx->model_gen++;
+    }
+    free_mlp(m);
+    delete m;
+    return LMMEW_OK;
+}
+
+int lmmew_mlp_get_params(const lmmew_mlp *m, float *params, double *c0, double *floor_)
+{
+    if (!m) return LMMEW_EINVAL;
+    if (params &&
+        hipMemcpy(params, m->P, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost) != hipSuccess)
+        return LMMEW_EDEVICE;
+    if (c0) *c0 = m->c0;
+    if (floor_) *floor_ = m->floor_;
+    return LMMEW_OK;
+}
+
+int lmmew_mlp_set_params(lmmew_mlp *m, const float *params, double c0, double floor_)
+{
+    if (!m || !params) return LMMEW_EINVAL;
+    lmmew_ctx *ctx = m->ctx;
+    HIPCHK(ctx, hipMemcpy(m->P, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemset(m->m1, 0, sizeof(float) * kMlpParams));
+    HIPCHK(ctx, hipMemset(m->m2, 0, sizeof(float) * kMlpParams));
+    HIPCHK(ctx, mlp_refresh(m->P, m->W2b, m->W3b, m->W2t, m->W3t, nullptr));
+    HIPCHK(ctx, hipDeviceSynchronize());
+    m->step = 0;
+    m->c0 = c0;
+    m->floor_ = floor_;
+    ctx->model_gen++;
+    return LMMEW_OK;
+}
+
+int lmmew_mlp_forward(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, int64_t n, float *y,
+                      hipStream_t st)
+{
+    if (!ctx || !m || m->ctx != ctx) return LMMEW_EINVAL;
+    if (n < 0 || (n > 0 && (!feats || !y))) return fail(ctx, LMMEW_EINVAL, "bad arguments");
+    const int chunk = 65536;
+    int rc = mlp_workspace(ctx, m, chunk);
+    if (rc != LMMEW_OK) return rc;
+    std::vector<int> idx(chunk);
+    const MlpWork w = mlp_work(m);
+    for (int64_t b = 0; b < n; b += chunk) {
+        const int cnt = (int)std::min<int64_t>(chunk, n - b);
+        const int M = (cnt + 15) / 16 * 16;
+        for (int t = 0; t < M; ++t) idx[t] = (int)(b + std::min(t, cnt - 1));
+        HIPCHK(ctx, hipMemcpyAsync(m->idx, idx.data(), sizeof(int) * M, hipMemcpyHostToDevice, st));
+        HIPCHK(ctx, mlp_forward_batch(w, m->P, feats, m->idx, M, nullptr, st));
+        HIPCHK(ctx, hipMemcpyAsync(y + b, m->y, sizeof(float) * cnt, hipMemcpyDeviceToDevice, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));     // idx is reused for the next chunk
+    }
+    return LMMEW_OK;
+}
+
+int lmmew_mlp_grad(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const float *target,
+                   int64_t n, float *grad, double *loss, hipStream_t st)
+{
+    if (!ctx || !m || m->ctx != ctx) return LMMEW_EINVAL;
+    if (!feats || !target || !grad || n <= 0 || n % 16 != 0 || n > (1 << 24))
+        return fail(ctx, LMMEW_EINVAL, "n must be a positive multiple of 16 (<= 2^24)");
+    int rc = mlp_workspace(ctx, m, (int)n);
+    if (rc != LMMEW_OK) return rc;
+    const MlpWork w = mlp_work(m);
+    HIPCHK(ctx, mlp_forward_batch(w, m->P, feats, nullptr, (int)n, target, st));
+    HIPCHK(ctx, mlp_backward_batch(w, m->P, (int)n, m->G, st));
+    HIPCHK(ctx, hipMemcpyAsync(grad, m->G, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, mlp_loss(w, (int)n, m->dloss, st));
+    double l = 0.0;
+    HIPCHK(ctx, hipMemcpyAsync(&l, m->dloss, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (loss) *loss = l / (double)n;
+    return LMMEW_OK;
+}
+
+int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const float *target,
+                    int64_t n, int batch, int epochs, double lr, uint64_t seed, double *epoch_loss,
+                    hipStream_t st)
+{
+    const double lr0 = lr;
+    if (!ctx || !m || m->ctx != ctx) return LMMEW_EINVAL;
+    if (!feats || !target || batch <= 0 || batch % 16 != 0 || epochs < 0 || n < batch ||
+        n > ((int64_t)1 << 31) - 1)
+        return fail(ctx, LMMEW_EINVAL, "bad training arguments (batch a multiple of 16, n >= batch)");
+    int rc = mlp_workspace(ctx, m, batch);
+    if (rc != LMMEW_OK) return rc;
+    const int64_t nb = n / batch;
+    int *d_perm = nullptr;
+    double *d_losses = nullptr;
+    HIPCHK(ctx, dalloc(&d_perm, n));
+    if (dalloc(&d_losses, nb) != hipSuccess) {
+        dfree(d_perm);
+        return fail(ctx, LMMEW_ENOMEM, "training buffers");
+    }
+    std::vector<int> perm(n);
+    std::vector<double> losses(nb);
+    uint64_t rs = seed;
+    const MlpWork w = mlp_work(m);
+    hipError_t e = hipSuccess;
+    for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+        for (int64_t t = 0; t < n; ++t) perm[t] = (int)t;
+        for (int64_t t = n - 1; t > 0; --t) {          // Fisher-Yates
+            const int64_t j = (int64_t)(splitmix64(rs) % (uint64_t)(t + 1));
+            std::swap(perm[t], perm[j]);
+        }
+        e = hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+        for (int64_t b = 0; b < nb && e == hipSuccess; ++b) {
+            const int *idx = d_perm + b * batch;
+            e = mlp_forward_batch(w, m->P, feats, idx, batch, target, st);
+            if (e == hipSuccess) e = mlp_backward_batch(w, m->P, batch, m->G, st);
+            if (e == hipSuccess) e = mlp_loss(w, batch, d_losses + b, st);
+            // cosine decay of the step size from lr to lr/10 over the run
+            const double prog = (double)(ep * nb + b) / std::max<double>(1.0, (double)epochs * nb);
+            lr = lr0 * (0.1 + 0.9 * 0.5 * (1.0 + std::cos(kPi * prog)));
+            if (e == hipSuccess) e = mlp_adam(m->P, m->G, m->m1, m->m2, (float)lr, ++m->step, st);
+            if (e == hipSuccess) e = mlp_refresh(m->P, m->W2b, m->W3b, m->W2t, m->W3t, st);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(losses.data(), d_losses, sizeof(double) * nb, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess && epoch_loss) {
+            double sum = 0.0;
+            for (double v : losses) sum += v;
+            epoch_loss[ep] = sum / ((double)nb * batch);
+        }
+    }
+    dfree(d_perm);
+    dfree(d_losses);
+    if (e != hipSuccess) return hipfail(ctx, e, "training");
+    ctx->model_gen++;
+    return LMMEW_OK;
+}
+
+int lmmew_scatter_labels(lmmew_ctx *ctx, int64_t n_events, uint64_t seed, float *feats, float *raw,
+                         hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (n_events <= 0 || !feats || !raw) return fail(ctx, LMMEW_EINVAL, "bad arguments");
+    if ((size_t)n_events * ctx->S.Qp * sizeof(float) > kScratchBudget)
+        return fail(ctx, LMMEW_EINVAL, "too many label events for one pass");
+    const lmmew_system &s = ctx->sys;
+    // events: bin and angle uniform, energy uniform over the union of the windows
+    double wsum = 0.0;
+    for (int k = 0; k < s.n_windows; ++k) wsum += s.win_hi_keV[k] - s.win_lo_keV[k];
+    std::vector<int16_t> hb(n_events), ha(n_events);
+    std::vector<float> he(n_events);
+    uint64_t rs = seed;
+    for (int64_t j = 0; j < n_events; ++j) {
+        hb[j] = (int16_t)(splitmix64(rs) % (uint64_t)s.n_bins);
+        ha[j] = (int16_t)(splitmix64(rs) % (uint64_t)s.n_angles);
+        double x = unit_rand(rs) * wsum;
+        int k = 0;
+        while (k + 1 < s.n_windows && x > s.win_hi_keV[k] - s.win_lo_keV[k]) {
+            x -= s.win_hi_keV[k] - s.win_lo_keV[k];
+            ++k;
+        }
+        float E = (float)(s.win_lo_keV[k] + x);
+        E = std::min(std::max(E, (float)s.win_lo_keV[k]), (float)s.win_hi_keV[k]);
+        he[j] = E;
+    }
+    int16_t *db = nullptr, *da = nullptr;
+    float *de = nullptr;
+    HIPCHK(ctx, dalloc(&db, n_events));
+    HIPCHK(ctx, dalloc(&da, n_events));
+    HIPCHK(ctx, dalloc(&de, n_events));
+    int rc = LMMEW_OK;
+    hipError_t e = hipMemcpyAsync(db, hb.data(), n_events * 2, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(da, ha.data(), n_events * 2, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(de, he.data(), n_events * 4, hipMemcpyHostToDevice, st);
+    lmmew_plan *pl = nullptr;
+    if (e != hipSuccess) rc = hipfail(ctx, e, "label events");
+    if (rc == LMMEW_OK) {
+        lmmew_events ev{n_events, db, da, de};
+        rc = make_plan(ctx, &ev, nullptr, 1, 1, st, &pl);
+    }
+    if (rc == LMMEW_OK) rc = run_rows(ctx, pl, 0, st, 1);
+    if (rc == LMMEW_OK) {
+        e = mlp_labels(ctx->S, ctx->d_pix, ctx->d_dirs, pl->d_bin, pl->d_ang, pl->d_E, pl->d_A,
+                       (int)n_events, feats, raw, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hipfail(ctx, e, "labels");
+    }
+    if (pl) lmmew_plan_destroy(pl);
+    dfree(db);
+    dfree(da);
+    dfree(de);
+    return rc;
+}
+
+int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *m, int64_t n_label_events, int epochs, int batch,
+                  double lr, double floor_frac, uint64_t seed, double *epoch_loss, hipStream_t st)
+{
+    if (!(floor_frac > 0)) return fail(ctx, LMMEW_EINVAL, "floor_frac must be > 0");
+    if (!ctx || !m || m->ctx != ctx) return LMMEW_EINVAL;
+    if (n_label_events <= 0) return fail(ctx, LMMEW_EINVAL, "n_label_events must be > 0");
+    const int64_t n = n_label_events * ctx->S.Qm;
+    float *feats = nullptr, *raw = nullptr, *tgt = nullptr;
+    HIPCHK(ctx, dalloc(&feats, (size_t)n * kMlpIn));
+    int rc = LMMEW_OK;
+    if (dalloc(&raw, n) != hipSuccess || dalloc(&tgt, n) != hipSuccess)
+        rc = fail(ctx, LMMEW_ENOMEM, "label buffers");
+    if (rc == LMMEW_OK) rc = lmmew_scatter_labels(ctx, n_label_events, seed, feats, raw, st);
+    if (rc == LMMEW_OK) {
+        // floor = floor_frac x mean density, c0 = mean of log(density + floor)
+        std::vector<float> h(n);
+        hipError_t e = hipMemcpy(h.data(), raw, sizeof(float) * n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = hipfail(ctx, e, "labels to host");
+        if (rc == LMMEW_OK) {
+            double mean = 0.0;
+            for (float v : h) mean += v;
+            mean /= (double)n;
+            const double fl = mean > 0 ? floor_frac * mean : 1e-30;
+            double c0 = 0.0;
+            for (float v : h) c0 += std::log((double)v + fl);
+            c0 /= (double)n;
+            m->floor_ = fl;
+            m->c0 = c0;
+            e = mlp_targets(raw, n, (float)fl, (float)c0, tgt, st);
+            if (e != hipSuccess) rc = hipfail(ctx, e, "targets");
+        }
+    }
+    if (rc == LMMEW_OK)
+        rc = lmmew_mlp_train(ctx, m, feats, tgt, n, batch, epochs, lr, seed ^ 0x5eedull, epoch_loss, st);
+    dfree(feats);
+    dfree(raw);
+    dfree(tgt);
+    return rc;
+}
+
+int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *m)
+{
+    if (!ctx || (m && m->ctx != ctx)) return LMMEW_EINVAL;
+    ctx->mlp = m;
+    ctx->model_gen++;
+    return LMMEW_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,526 @@
+// Scatter surrogate network on gfx950: 6 -> 128 -> 128 -> 128 -> 1 with the tanh
+// form of GELU; the two 128x128 layers run on BF16 MFMA (v_mfma_f32_16x16x16
+// bf16, FP32 accumulation), the first and last layers on FP32 VALU.
+//
+// Parameter vector (FP32 master copy, 34049 floats):
+//   W1[6][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] w4[128] b4[1]
+// W[i][o] maps input unit i to output unit o.
+//
+// MFMA 16x16x16 operand layout (lane l, r = l % 16, g = l / 16, item t = 0..3):
+//   A[i][k]: i = r, k = 4g + t;  B[k][j]: k = 4g + t, j = r;  D[i][j]: i = 4g + t, j = r.
+// The D layout equals the B layout with k = i, so the output of one layer
+// computed as Z^T = W^T H^T is directly the B operand of the next.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace lmmew {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int H = kMlpHidden;
+
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+    // round to nearest even (finite inputs)
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+// tanh-form GELU: 0.5 z (1 + tanh(c (z + 0.044715 z^3))) = z * sigmoid(2 c (z + 0.044715 z^3))
+__device__ __forceinline__ float gelu(float z)
+{
+    const float c2 = 2.f * 0.7978845608028654f;
+    const float u = c2 * z * fmaf(0.044715f, z * z, 1.f);
+    return z / (1.f + __expf(-u));
+}
+
+__device__ __forceinline__ float gelu_prime(float z)
+{
+    const float c2 = 2.f * 0.7978845608028654f;
+    const float u = c2 * z * fmaf(0.044715f, z * z, 1.f);
+    const float sg = 1.f / (1.f + __expf(-u));
+    const float du = c2 * fmaf(3.f * 0.044715f, z * z, 1.f);
+    return sg + z * sg * (1.f - sg) * du;
+}
+
+// ---------------------------------------------------------------------------
+// generic GEMM: C[i][j] = sum_k A(i,k) B(k,j), A(i,k) = A[i*sai + k*sak],
+// B(k,j) = B[k*sbk + j*sbj] (bf16), C fp32 with row stride ldc.
+// One wavefront per 16x16 output tile; M, N, K multiples of 16.
+// ---------------------------------------------------------------------------
+// With gridDim.z > 1 the K range is split: slice z covers [z*K/Z, (z+1)*K/Z)
+// and writes C + z * cstride (partials summed afterwards in slice order).
+__global__ __launch_bounds__(64) void k_gemm(const unsigned short *A, long sai, long sak,
+                                             const unsigned short *B, long sbk, long sbj,
+                                             float *C, long ldc, int K, long cstride)
+{
+    const int l = threadIdx.x, r = l & 15, g = l >> 4;
+    const long i0 = (long)blockIdx.y * 16, j0 = (long)blockIdx.x * 16;
+    const int kz = K / gridDim.z;
+    C += blockIdx.z * cstride;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = blockIdx.z * kz; k0 < (int)(blockIdx.z + 1) * kz; k0 += 16) {
+        v4s a, b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const long k = k0 + 4 * g + t;
+            a[t] = (short)A[(i0 + r) * sai + k * sak];
+            b[t] = (short)B[k * sbk + (j0 + r) * sbj];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) C[(i0 + 4 * g + t) * ldc + j0 + r] = acc[t];
+}
+
+// ---------------------------------------------------------------------------
+// training kernels (batch of M samples, rows of [M][128] activations)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_l1(const float *feats, const int *idx, int M,
+                                                const float *P, float *X, float *Z1,
+                                                unsigned short *H1b)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)M * H) return;
+    const int m = (int)(t / H), u = (int)(t % H);
+    const long src = idx ? idx[m] : m;
+    float x[kMlpIn];
+#pragma unroll
+    for (int d = 0; d < kMlpIn; ++d) x[d] = feats[src * kMlpIn + d];
+    if (u < kMlpIn) X[(long)m * kMlpIn + u] = x[u];
+    float z = P[kOffB1 + u];
+#pragma unroll
+    for (int d = 0; d < kMlpIn; ++d) z = fmaf(x[d], P[kOffW1 + d * H + u], z);
+    Z1[t] = z;
+    H1b[t] = f2bf(gelu(z));
+}
+
+// Z = C + b (in place), H = GELU(Z) as bf16 and/or fp32
+__global__ __launch_bounds__(256) void k_bias_gelu(float *C, const float *b, long n,
+                                                   unsigned short *Hb, float *Hf)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    const float z = C[t] + b[t % H];
+    C[t] = z;
+    const float h = gelu(z);
+    if (Hb) Hb[t] = f2bf(h);
+    if (Hf) Hf[t] = h;
+}
+
+// y = b4 + sum_u w4[u] h3[u]; residual r = y - target; dy = 2 r / M
+__global__ __launch_bounds__(256) void k_mlp_out(const float *H3, const float *P, const float *tgt,
+                                                 const int *idx, int M, float *y, float *dy,
+                                                 float *sq)
+{
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    float acc = P[kOffB4];
+    for (int u = 0; u < H; ++u) acc = fmaf(P[kOffW4 + u], H3[(long)m * H + u], acc);
+    y[m] = acc;
+    if (tgt) {
+        const float r = acc - tgt[idx ? idx[m] : m];
+        dy[m] = 2.f * r / (float)M;
+        sq[m] = r * r;
+    }
+}
+
+// dZ3 = dy w4 * GELU'(Z3)
+__global__ __launch_bounds__(256) void k_dz_out(const float *dy, const float *P, const float *Z,
+                                                int M, float *dZ, unsigned short *dZb)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)M * H) return;
+    const int m = (int)(t / H), u = (int)(t % H);
+    const float v = dy[m] * P[kOffW4 + u] * gelu_prime(Z[t]);
+    dZ[t] = v;
+    dZb[t] = f2bf(v);
+}
+
+// dZ = dH * GELU'(Z) (dH read from the GEMM output), fp32 and optionally bf16
+__global__ __launch_bounds__(256) void k_gelu_back(const float *dH, const float *Z, long n,
+                                                   float *dZ, unsigned short *dZb)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    const float v = dH[t] * gelu_prime(Z[t]);
+    dZ[t] = v;
+    if (dZb) dZb[t] = f2bf(v);
+}
+
+// Column sums over a chunk of kRedRows rows, for the 8 x 128 outputs of one
+// layer's gradients: slot 0 = sum_m a[m][u] (bias), slot 1 = sum_m a[m][u] s[m]
+// (s may be NULL), slots 2..7 = sum_m X[m][d] a[m][u] (d = 0..5, X may be NULL).
+// part[chunk][8][128]; reduced afterwards in chunk order (deterministic).
+constexpr int kRedRows = 256;
+
+__global__ __launch_bounds__(128) void k_colsum_part(const float *a, const float *s,
+                                                     const float *X, int M, float *part)
+{
+    const int u = threadIdx.x;
+    const int m0 = blockIdx.x * kRedRows, m1 = min(m0 + kRedRows, M);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int m = m0; m < m1; ++m) {
+        const float v = a[(long)m * H + u];
+        acc[0] += v;
+        if (s) acc[1] = fmaf(v, s[m], acc[1]);
+        if (X) {
+#pragma unroll
+            for (int d = 0; d < kMlpIn; ++d) acc[2 + d] = fmaf(X[(long)m * kMlpIn + d], v, acc[2 + d]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[((long)blockIdx.x * 8 + k) * H + u] = acc[k];
+}
+
+// out_slot[u] = sum over chunks of part[chunk][slot][u] for the requested slots
+__global__ __launch_bounds__(256) void k_colsum_final(const float *part, int nchunks, float *bias,
+                                                      float *scaled, float *xw)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= 8 * H) return;
+    const int k = t / H, u = t % H;
+    float acc = 0.f;
+    for (int c = 0; c < nchunks; ++c) acc += part[((long)c * 8 + k) * H + u];
+    if (k == 0 && bias) bias[u] = acc;
+    if (k == 1 && scaled) scaled[u] = acc;
+    if (k >= 2 && xw) xw[(k - 2) * H + u] = acc;      // W1 layout [d][u]
+}
+
+// sum over split-K slices of a [128][128] gradient, in slice order
+__global__ __launch_bounds__(256) void k_split_sum(const float *part, int nz, float *out)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= H * H) return;
+    float acc = 0.f;
+    for (int z = 0; z < nz; ++z) acc += part[(long)z * H * H + t];
+    out[t] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_sum(const float *v, int n, double *out)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void k_store_sum(const double *v, float *out) { out[0] = (float)v[0]; }
+
+__global__ __launch_bounds__(256) void k_adam(float *P, const float *G, float *m1, float *m2,
+                                              float lr, float b1, float b2, float eps, float c1,
+                                              float c2)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= kMlpParams) return;
+    const float g = G[t];
+    const float a = b1 * m1[t] + (1.f - b1) * g;
+    const float v = b2 * m2[t] + (1.f - b2) * g * g;
+    m1[t] = a;
+    m2[t] = v;
+    P[t] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// bf16 copies of W2, W3: row-major [in][out] (training GEMMs) and transposed
+// [out][in] with padded rows (inference A operands)
+__global__ __launch_bounds__(256) void k_refresh_bf16(const float *P, unsigned short *W2b,
+                                                      unsigned short *W3b, unsigned short *W2t,
+                                                      unsigned short *W3t)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= H * H) return;
+    const int i = t / H, o = t % H;
+    const unsigned short w2 = f2bf(P[kOffW2 + t]), w3 = f2bf(P[kOffW3 + t]);
+    W2b[t] = w2;
+    W3b[t] = w3;
+    W2t[o * kMlpTStride + i] = w2;
+    W3t[o * kMlpTStride + i] = w3;
+}
+
+// ---------------------------------------------------------------------------
+// features of (event, pixel) pairs and training labels
+// ---------------------------------------------------------------------------
+// Features of an (event, pixel) pair in the detector frame of the event's
+// angle: bin centre minus the pixel's lateral projection, the pixel's depth
+// below the detector plane, its lateral projection (all / R), cos and sin of
+// the angle, and (E - kMlpEc) / kMlpEs.  The same information as (pixel x, y,
+// bin, angle, energy), arranged so that the collimator geometry is explicit.
+__device__ __forceinline__ void pair_features(const DevSys &S, float2 xy, int bin, float2 dir,
+                                              float E, float *f)
+{
+    const float iR = 1.f / S.R;
+    const float uq = -xy.x * dir.y + xy.y * dir.x;
+    const float dq = S.R - (xy.x * dir.x + xy.y * dir.y);
+    const float ub = -S.R + ((float)bin + 0.5f) * S.db;
+    f[0] = (ub - uq) * iR;
+    f[1] = dq * iR;
+    f[2] = uq * iR;
+    f[3] = dir.x;
+    f[4] = dir.y;
+    f[5] = (E - kMlpEc) * (1.f / kMlpEs);
+}
+
+// sample s = e * Qm + i: features and the raw once-scattered density a_jq
+__global__ __launch_bounds__(256) void k_labels(const DevSys S, const float2 *pix_xy,
+                                                const float2 *dirs, const int *ev_bin,
+                                                const int *ev_ang, const float *ev_E,
+                                                const float *A, int rows, float *feats, float *raw)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)rows * S.Qm) return;
+    const int e = (int)(t / S.Qm), i = (int)(t % S.Qm);
+    float f[kMlpIn];
+    pair_features(S, pix_xy[i], ev_bin[e], dirs[ev_ang[e]], ev_E[e], f);
+#pragma unroll
+    for (int d = 0; d < kMlpIn; ++d) feats[t * kMlpIn + d] = f[d];
+    raw[t] = A[(long)e * S.Qp + i];
+}
+
+// target = log(raw + floor) - c0
+__global__ __launch_bounds__(256) void k_targets(const float *raw, long n, float floor_, float c0,
+                                                 float *tgt)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) tgt[t] = logf(raw[t] + floor_) - c0;
+}
+
+// ---------------------------------------------------------------------------
+// fused inference: for every (row e, support pixel i) of a subset, add the
+// surrogate's once-scattered density max(exp(y + c0) - floor, 0) to A[e][i].
+// Workgroup: 4 wavefronts sharing W2^T, W3^T in LDS; a wavefront handles 16
+// pixels of one row at a time (16 pairs = the j dimension of the MFMAs).
+// ---------------------------------------------------------------------------
+constexpr int kRowsPerWG = 32;
+
+__global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowArgs a)
+{
+    __shared__ unsigned short sW2[H * kMlpTStride];
+    __shared__ unsigned short sW3[H * kMlpTStride];
+    __shared__ float sP[kOffW2];        // W1, b1
+    __shared__ float sB[3 * H + 1];     // b2, b3, w4, b4 (b2 at 0, b3 at H, w4 at 2H, b4 at 3H)
+
+    for (int t = threadIdx.x; t < H * kMlpTStride / 2; t += 256) {
+        reinterpret_cast<unsigned *>(sW2)[t] = reinterpret_cast<const unsigned *>(a.W2t)[t];
+        reinterpret_cast<unsigned *>(sW3)[t] = reinterpret_cast<const unsigned *>(a.W3t)[t];
+    }
+    for (int t = threadIdx.x; t < kOffW2; t += 256) sP[t] = a.P[t];
+    for (int t = threadIdx.x; t < H; t += 256) {
+        sB[t] = a.P[kOffB2 + t];
+        sB[H + t] = a.P[kOffB3 + t];
+        sB[2 * H + t] = a.P[kOffW4 + t];
+    }
+    if (threadIdx.x == 0) sB[3 * H] = a.P[kOffB4];
+    __syncthreads();
+
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    const int i = blockIdx.x * 64 + wv * 16 + r;          // this lane's pixel
+    const float2 xy = a.pix_xy[i];
+    const int e0 = blockIdx.y * kRowsPerWG, e1 = min(e0 + kRowsPerWG, a.rows);
+    for (int e = e0; e < e1; ++e) {
+        float f[kMlpIn];
+        pair_features(S, xy, a.ev_bin[e], a.dirs[a.ev_ang[e]], a.ev_E[e], f);
+        // layer 1 (FP32) straight into B-operand fragments: units 16 ks + 4 g + t
+        v4s h1[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int u = 16 * ks + 4 * g + t;
+                float z = sP[kOffB1 + u];
+#pragma unroll
+                for (int d = 0; d < kMlpIn; ++d) z = fmaf(f[d], sP[kOffW1 + d * H + u], z);
+                h1[ks][t] = (short)f2bf(gelu(z));
+            }
+        }
+        // layer 2: Z2^T = W2^T H1^T
+        v4s h2[8];
+#pragma unroll
+        for (int ib = 0; ib < 8; ++ib) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const v4s w = *reinterpret_cast<const v4s *>(&sW2[(16 * ib + r) * kMlpTStride +
+                                                                  16 * ks + 4 * g]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h1[ks], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) h2[ib][t] = (short)f2bf(gelu(acc[t] + sB[16 * ib + 4 * g + t]));
+        }
+        // layer 3 and the output unit
+        float part = 0.f;
+#pragma unroll
+        for (int ib = 0; ib < 8; ++ib) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const v4s w = *reinterpret_cast<const v4s *>(&sW3[(16 * ib + r) * kMlpTStride +
+                                                                  16 * ks + 4 * g]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h2[ks], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int u = 16 * ib + 4 * g + t;
+                part = fmaf(sB[2 * H + u], gelu(acc[t] + sB[H + u]), part);
+            }
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (g == 0 && i < S.Qm) {
+            const float y = part + sB[3 * H];
+            const float v = fmaxf(__expf(y + a.c0) - a.floor_, 0.f);
+            a.A[(long)e * S.Qp + i] += v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t mlp_gemm(const unsigned short *A, long sai, long sak, const unsigned short *B, long sbk,
+                    long sbj, float *C, long ldc, int M, int N, int K, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gemm, dim3(N / 16, M / 16, 1), dim3(64), 0, st, A, sai, sak, B, sbk, sbj,
+                       C, ldc, K, 0L);
+    return hipGetLastError();
+}
+
+// weight gradient [128][128] with the batch dimension as K: split-K over up to
+// 64 slices of >= 256 samples, then an ordered sum of the slices
+static hipError_t mlp_gemm_wgrad(const unsigned short *A, const unsigned short *B, int M, float *out,
+                                 float *scratch, hipStream_t st)
+{
+    int nz = 1;
+    while (nz < 64 && M % (nz * 2 * 16) == 0 && M / (nz * 2) >= 256) nz *= 2;
+    hipLaunchKernelGGL(k_gemm, dim3(H / 16, H / 16, nz), dim3(64), 0, st, A, 1L, (long)H, B,
+                       (long)H, 1L, scratch, (long)H, M, (long)H * H);
+    hipLaunchKernelGGL(k_split_sum, dim3(H * H / 256), dim3(256), 0, st, scratch, nz, out);
+    return hipGetLastError();
+}
+
+static hipError_t mlp_colsums(const float *a, const float *s, const float *X, int M, float *part,
+                              float *bias, float *scaled, float *xw, hipStream_t st)
+{
+    const int nc = (M + kRedRows - 1) / kRedRows;
+    hipLaunchKernelGGL(k_colsum_part, dim3(nc), dim3(128), 0, st, a, s, X, M, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3(8 * H / 256), dim3(256), 0, st, part, nc, bias,
+                       scaled, xw);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward_batch(const MlpWork &w, const float *P, const float *feats, const int *idx,
+                             int M, const float *tgt, hipStream_t st)
+{
+    const long n = (long)M * H;
+    hipLaunchKernelGGL(k_mlp_l1, dim3(nblk(n, 256)), dim3(256), 0, st, feats, idx, M, P, w.X,
+                       w.Z1, w.H1b);
+    hipError_t e = mlp_gemm(w.H1b, H, 1, w.W2b, H, 1, w.Z2, H, M, H, H, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bias_gelu, dim3(nblk(n, 256)), dim3(256), 0, st, w.Z2, P + kOffB2, n,
+                       w.H2b, (float *)nullptr);
+    e = mlp_gemm(w.H2b, H, 1, w.W3b, H, 1, w.Z3, H, M, H, H, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bias_gelu, dim3(nblk(n, 256)), dim3(256), 0, st, w.Z3, P + kOffB3, n,
+                       (unsigned short *)nullptr, w.H3);
+    hipLaunchKernelGGL(k_mlp_out, dim3(nblk(M, 256)), dim3(256), 0, st, w.H3, P, tgt, idx, M, w.y,
+                       w.dy, w.sq);
+    return hipGetLastError();
+}
+
+hipError_t mlp_backward_batch(const MlpWork &w, const float *P, int M, float *G, hipStream_t st)
+{
+    const long n = (long)M * H;
+    // output layer: dw4 = sum_m dy h3, db4 = sum_m dy
+    hipError_t e = mlp_colsums(w.H3, w.dy, nullptr, M, w.part, nullptr, G + kOffW4, nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, w.dy, M, w.dsum);
+    hipLaunchKernelGGL(k_store_sum, dim3(1), dim3(1), 0, st, w.dsum, G + kOffB4);
+    hipLaunchKernelGGL(k_dz_out, dim3(nblk(n, 256)), dim3(256), 0, st, w.dy, P, w.Z3, M, w.dZ,
+                       w.dZb);
+    // layer 3: dW3 = H2^T dZ3, db3, dH2 = dZ3 W3^T
+    e = mlp_gemm_wgrad(w.H2b, w.dZb, M, G + kOffW3, w.split, st);
+    if (e != hipSuccess) return e;
+    e = mlp_colsums(w.dZ, nullptr, nullptr, M, w.part, G + kOffB3, nullptr, nullptr, st);
+    if (e != hipSuccess) return e;
+    e = mlp_gemm(w.dZb, H, 1, w.W3b, 1, H, w.dH, H, M, H, H, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gelu_back, dim3(nblk(n, 256)), dim3(256), 0, st, w.dH, w.Z2, n, w.dZ,
+                       w.dZb);
+    // layer 2
+    e = mlp_gemm_wgrad(w.H1b, w.dZb, M, G + kOffW2, w.split, st);
+    if (e != hipSuccess) return e;
+    e = mlp_colsums(w.dZ, nullptr, nullptr, M, w.part, G + kOffB2, nullptr, nullptr, st);
+    if (e != hipSuccess) return e;
+    e = mlp_gemm(w.dZb, H, 1, w.W2b, 1, H, w.dH, H, M, H, H, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gelu_back, dim3(nblk(n, 256)), dim3(256), 0, st, w.dH, w.Z1, n, w.dZ,
+                       (unsigned short *)nullptr);
+    // layer 1: dW1 = X^T dZ1, db1
+    return mlp_colsums(w.dZ, nullptr, w.X, M, w.part, G + kOffB1, nullptr, G + kOffW1, st);
+}
+
+hipError_t mlp_loss(const MlpWork &w, int M, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, w.sq, M, out);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(float *P, const float *G, float *m1, float *m2, float lr, int step,
+                    hipStream_t st)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(kMlpParams, 256)), dim3(256), 0, st, P, G, m1, m2, lr, b1,
+                       b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t mlp_refresh(const float *P, unsigned short *W2b, unsigned short *W3b,
+                       unsigned short *W2t, unsigned short *W3t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refresh_bf16, dim3(nblk(H * H, 256)), dim3(256), 0, st, P, W2b, W3b, W2t,
+                       W3t);
+    return hipGetLastError();
+}
+
+hipError_t mlp_labels(const DevSys &S, const float2 *pix_xy, const float2 *dirs, const int *ev_bin,
+                      const int *ev_ang, const float *ev_E, const float *A, int rows, float *feats,
+                      float *raw, hipStream_t st)
+{
+    const long n = (long)rows * S.Qm;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_labels, dim3(nblk(n, 256)), dim3(256), 0, st, S, pix_xy, dirs, ev_bin,
+                       ev_ang, ev_E, A, rows, feats, raw);
+    return hipGetLastError();
+}
+
+hipError_t mlp_targets(const float *raw, long n, float floor_, float c0, float *tgt, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_targets, dim3(nblk(n, 256)), dim3(256), 0, st, raw, n, floor_, c0, tgt);
+    return hipGetLastError();
+}
+
+hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
+{
+    if (a.rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_rows, dim3(S.Qp / 64, nblk(a.rows, kRowsPerWG)), dim3(256), 0, st, S,
+                       a);
+    return hipGetLastError();
+}
+
+}  // namespace lmmew
