@@ -131,6 +131,9 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
 /* Releases the context and everything it owns (waits for its work). */
 int lmmew_destroy(lmmew_ctx *ctx);
 
+/* Number of support pixels (the pixels rows and labels cover), -1 for NULL. */
+int64_t lmmew_support_size(const lmmew_ctx *ctx);
+
 /* Sensitivity image per subset: sens[s][q] = T * sum over the subset's
  * angles of the probability that a decay in pixel q is recorded (on the
  * detector and inside a window), unscattered or once scattered: the
@@ -317,9 +320,18 @@ int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *mlp, const float *feats, const fl
 int lmmew_scatter_labels(lmmew_ctx *ctx, int64_t n_events, uint64_t seed, float *feats,
                          float *raw, hipStream_t stream);
 
-/* Labels (lmmew_scatter_labels), floor = floor_frac x mean density, c0 =
- * mean of log(density + floor), targets log(density + floor) - c0, then
- * lmmew_mlp_train. */
+/* Fits the network to given labels: floor = floor_frac x mean of raw, c0 =
+ * mean of log(raw + floor), targets log(raw + floor) - c0, then
+ * lmmew_mlp_train (seeded with seed).  feats, raw: device, n rows, as written
+ * by lmmew_scatter_labels of this or any context with the same system (so a
+ * network can be trained on labels of several attenuation maps; the batch
+ * shuffle mixes them).  Synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int lmmew_mlp_fit_labels(lmmew_ctx *ctx, lmmew_mlp *mlp, const float *feats, const float *raw,
+                         int64_t n, int epochs, int batch, double lr, double floor_frac,
+                         uint64_t seed, double *epoch_loss, hipStream_t stream);
+
+/* lmmew_scatter_labels on this context's map for n_label_events events, then
+ * lmmew_mlp_fit_labels. */
 int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, int64_t n_label_events, int epochs, int batch,
                   double lr, double floor_frac, uint64_t seed, double *epoch_loss,
                   hipStream_t stream);

@@ -94,7 +94,10 @@ def _load():
         "lmmew_scatter_labels": (i32, [vp, i64, C.c_uint64, vp, vp, vp]),
         "lmmew_mlp_fit": (i32, [vp, vp, i64, i32, i32, C.c_double, C.c_double, C.c_uint64,
                                 C.POINTER(C.c_double), vp]),
+        "lmmew_mlp_fit_labels": (i32, [vp, vp, vp, vp, i64, i32, i32, C.c_double, C.c_double,
+                                       C.c_uint64, C.POINTER(C.c_double), vp]),
         "lmmew_set_scatter_model": (i32, [vp, vp]),
+        "lmmew_support_size": (i64, [vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -222,7 +225,13 @@ class Context:
         self._check(_load().lmmew_rows(self._h, C.byref(e), int(part), _ptr(out), _stream()))
         return out
 
-    def lmmew_scatter_labels(self, n_events, seed, Qm):
+    @property
+    def support_size(self):
+        return int(_load().lmmew_support_size(self._h))
+
+    def lmmew_scatter_labels(self, n_events, seed):
+        """(feats [n_events*Qm, 6], raw [n_events*Qm]) from the exact scatter model."""
+        Qm = self.support_size
         feats = torch.empty((n_events * Qm, 6), device="cuda", dtype=torch.float32)
         raw = torch.empty(n_events * Qm, device="cuda", dtype=torch.float32)
         self._check(_load().lmmew_scatter_labels(self._h, int(n_events), C.c_uint64(seed),
@@ -429,3 +438,28 @@ class Mlp:
                                               float(floor_frac), C.c_uint64(seed), losses,
                                               _stream()))
         return list(losses)[:epochs]
+
+    def fit_labels(self, feats, raw, epochs=4, batch=4096, lr=1e-3, floor_frac=1e-2, seed=0):
+        """lmmew_mlp_fit_labels on device labels (feats [n, 6], raw [n])."""
+        feats, raw = feats.contiguous(), raw.contiguous()
+        losses = (C.c_double * max(epochs, 1))()
+        self.ctx._check(_load().lmmew_mlp_fit_labels(self.ctx._h, self._h, _ptr(feats), _ptr(raw),
+                                                     raw.numel(), int(epochs), int(batch),
+                                                     float(lr), float(floor_frac),
+                                                     C.c_uint64(seed), losses, _stream()))
+        return list(losses)[:epochs]
+
+    def fit_maps(self, mu_maps, n_label_events, epochs=4, batch=4096, lr=1e-3, floor_frac=1e-2,
+                 seed=0):
+        """Trains on labels of several attenuation maps of the same system:
+        n_label_events events per map (lmmew_scatter_labels on a context per
+        map, seeds seed + k), then lmmew_mlp_fit_labels on all of them."""
+        chunks = []
+        for k, m in enumerate(mu_maps):
+            c = Context(self.ctx.params, torch.as_tensor(m))
+            chunks.append(c.scatter_labels(n_label_events, seed + k))
+            c.close()
+        feats = torch.cat([f for f, _ in chunks])
+        raw = torch.cat([r for _, r in chunks])
+        del chunks
+        return self.fit_labels(feats, raw, epochs, batch, lr, floor_frac, seed)

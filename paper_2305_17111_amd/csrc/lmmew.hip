@@ -819,6 +819,8 @@ int lmmew_destroy(lmmew_ctx *ctx)
     return LMMEW_OK;
 }
 
+int64_t lmmew_support_size(const lmmew_ctx *ctx) { return ctx ? (int64_t)ctx->S.Qm : -1; }
+
 int lmmew_sensitivity(lmmew_ctx *ctx, int n_subsets, float *sens, hipStream_t st)
 {
     if (!ctx) return LMMEW_EINVAL;
@@ -1532,43 +1534,56 @@ int lmmew_scatter_labels(lmmew_ctx *ctx, int64_t n_events, uint64_t seed, float 
     return rc;
 }
 
-int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *m, int64_t n_label_events, int epochs, int batch,
-                  double lr, double floor_frac, uint64_t seed, double *epoch_loss, hipStream_t st)
+int lmmew_mlp_fit_labels(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const float *raw,
+                         int64_t n, int epochs, int batch, double lr, double floor_frac,
+                         uint64_t seed, double *epoch_loss, hipStream_t st)
 {
-    if (!(floor_frac > 0)) return fail(ctx, LMMEW_EINVAL, "floor_frac must be > 0");
     if (!ctx || !m || m->ctx != ctx) return LMMEW_EINVAL;
-    if (n_label_events <= 0) return fail(ctx, LMMEW_EINVAL, "n_label_events must be > 0");
-    const int64_t n = n_label_events * ctx->S.Qm;
-    float *feats = nullptr, *raw = nullptr, *tgt = nullptr;
-    HIPCHK(ctx, dalloc(&feats, (size_t)n * kMlpIn));
+    if (!(floor_frac > 0)) return fail(ctx, LMMEW_EINVAL, "floor_frac must be > 0");
+    if (n <= 0 || !feats || !raw) return fail(ctx, LMMEW_EINVAL, "bad arguments");
+    float *tgt = nullptr;
+    HIPCHK(ctx, dalloc(&tgt, n));
     int rc = LMMEW_OK;
-    if (dalloc(&raw, n) != hipSuccess || dalloc(&tgt, n) != hipSuccess)
-        rc = fail(ctx, LMMEW_ENOMEM, "label buffers");
-    if (rc == LMMEW_OK) rc = lmmew_scatter_labels(ctx, n_label_events, seed, feats, raw, st);
+    // floor = floor_frac x mean density, c0 = mean of log(density + floor)
+    std::vector<float> h(n);
+    hipError_t e = hipMemcpyAsync(h.data(), raw, sizeof(float) * n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = hipfail(ctx, e, "labels to host");
     if (rc == LMMEW_OK) {
-        // floor = floor_frac x mean density, c0 = mean of log(density + floor)
-        std::vector<float> h(n);
-        hipError_t e = hipMemcpy(h.data(), raw, sizeof(float) * n, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) rc = hipfail(ctx, e, "labels to host");
-        if (rc == LMMEW_OK) {
-            double mean = 0.0;
-            for (float v : h) mean += v;
-            mean /= (double)n;
-            const double fl = mean > 0 ? floor_frac * mean : 1e-30;
-            double c0 = 0.0;
-            for (float v : h) c0 += std::log((double)v + fl);
-            c0 /= (double)n;
-            m->floor_ = fl;
-            m->c0 = c0;
-            e = mlp_targets(raw, n, (float)fl, (float)c0, tgt, st);
-            if (e != hipSuccess) rc = hipfail(ctx, e, "targets");
-        }
+        double mean = 0.0;
+        for (float v : h) mean += v;
+        mean /= (double)n;
+        const double fl = mean > 0 ? floor_frac * mean : 1e-30;
+        double c0 = 0.0;
+        for (float v : h) c0 += std::log((double)v + fl);
+        c0 /= (double)n;
+        m->floor_ = fl;
+        m->c0 = c0;
+        e = mlp_targets(raw, n, (float)fl, (float)c0, tgt, st);
+        if (e != hipSuccess) rc = hipfail(ctx, e, "targets");
     }
     if (rc == LMMEW_OK)
         rc = lmmew_mlp_train(ctx, m, feats, tgt, n, batch, epochs, lr, seed ^ 0x5eedull, epoch_loss, st);
+    dfree(tgt);
+    return rc;
+}
+
+int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *m, int64_t n_label_events, int epochs, int batch,
+                  double lr, double floor_frac, uint64_t seed, double *epoch_loss, hipStream_t st)
+{
+    if (!ctx || !m || m->ctx != ctx) return LMMEW_EINVAL;
+    if (n_label_events <= 0) return fail(ctx, LMMEW_EINVAL, "n_label_events must be > 0");
+    const int64_t n = n_label_events * ctx->S.Qm;
+    float *feats = nullptr, *raw = nullptr;
+    HIPCHK(ctx, dalloc(&feats, (size_t)n * kMlpIn));
+    int rc = LMMEW_OK;
+    if (dalloc(&raw, n) != hipSuccess) rc = fail(ctx, LMMEW_ENOMEM, "label buffers");
+    if (rc == LMMEW_OK) rc = lmmew_scatter_labels(ctx, n_label_events, seed, feats, raw, st);
+    if (rc == LMMEW_OK)
+        rc = lmmew_mlp_fit_labels(ctx, m, feats, raw, n, epochs, batch, lr, floor_frac, seed,
+                                  epoch_loss, st);
     dfree(feats);
     dfree(raw);
-    dfree(tgt);
     return rc;
 }
 

@@ -10,6 +10,10 @@
 //   A[i][k]: i = r, k = 4g + t;  B[k][j]: k = 4g + t, j = r;  D[i][j]: i = 4g + t, j = r.
 // The D layout equals the B layout with k = i, so the output of one layer
 // computed as Z^T = W^T H^T is directly the B operand of the next.
+// The fused inference kernel uses v_mfma_f32_16x16x32_bf16 (8 items per lane
+// and operand, one contraction slot per (g, t) shared by A and B); it orders
+// the contraction index so that two consecutive D fragments form one B
+// fragment (see k_mlp_rows).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,32 +24,37 @@ namespace lmmew {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int H = kMlpHidden;
 
+// round to nearest even (v_cvt_pk_bf16_f32)
 __device__ __forceinline__ unsigned short f2bf(float f)
 {
-    // round to nearest even (finite inputs)
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
-// tanh-form GELU: 0.5 z (1 + tanh(c (z + 0.044715 z^3))) = z * sigmoid(2 c (z + 0.044715 z^3))
-__device__ __forceinline__ float gelu(float z)
+// tanh-form GELU: 0.5 z (1 + tanh(c (z + 0.044715 z^3))) = z * sigmoid(2 c (z + 0.044715 z^3)),
+// c = sqrt(2/pi).  The sigmoid is 1 / (1 + 2^s) with s = -2 c log2(e) (z + 0.044715 z^3),
+// evaluated with the hardware exp2 and reciprocal (1 ulp each); both limits are
+// exact (2^s = inf gives 0, 2^s = 0 gives z).
+constexpr float kGeluK1 = -2.f * 0.7978845608028654f * 1.4426950408889634f;
+constexpr float kGeluK2 = kGeluK1 * 0.044715f;
+
+__device__ __forceinline__ float gelu_sigmoid(float z)
 {
-    const float c2 = 2.f * 0.7978845608028654f;
-    const float u = c2 * z * fmaf(0.044715f, z * z, 1.f);
-    return z / (1.f + __expf(-u));
+    const float e = __builtin_amdgcn_exp2f(z * fmaf(kGeluK2, z * z, kGeluK1));
+    return __builtin_amdgcn_rcpf(1.f + e);
 }
+
+__device__ __forceinline__ float gelu(float z) { return z * gelu_sigmoid(z); }
 
 __device__ __forceinline__ float gelu_prime(float z)
 {
     const float c2 = 2.f * 0.7978845608028654f;
-    const float u = c2 * z * fmaf(0.044715f, z * z, 1.f);
-    const float sg = 1.f / (1.f + __expf(-u));
+    const float sg = gelu_sigmoid(z);
     const float du = c2 * fmaf(3.f * 0.044715f, z * z, 1.f);
     return sg + z * sg * (1.f - sg) * du;
 }
@@ -300,88 +309,201 @@ __global__ __launch_bounds__(256) void k_targets(const float *raw, long n, float
 // ---------------------------------------------------------------------------
 // fused inference: for every (row e, support pixel i) of a subset, add the
 // surrogate's once-scattered density max(exp(y + c0) - floor, 0) to A[e][i].
-// Workgroup: 4 wavefronts sharing W2^T, W3^T in LDS; a wavefront handles 16
-// pixels of one row at a time (16 pairs = the j dimension of the MFMAs).
+//
+// Workgroup: 4 wavefronts, 128 pixels, kRowsPerWG rows.  A wavefront holds two
+// groups of 16 pixels (the j dimension of the MFMAs); both groups share every
+// weight fragment read from LDS.  Every layer is Z^T = W^T H^T + b on
+// v_mfma_f32_16x16x32_bf16 with the weights as A fragments and the bias as
+// the initial accumulator.
+//
+// Hidden layers: the contraction index of chunk c (32 input units) is ordered
+// so that lane group g holds units 32c + 4g + {0..3} (items 0..3) and
+// 32c + 16 + 4g + {0..3} (items 4..7): those are exactly the units of the D
+// fragments of output blocks 2c and 2c + 1, so a layer's activations are the
+// next layer's B fragments without a shuffle.
+//
+// First layer (6 inputs, one 32-slot chunk): inputs and weights are split into
+// bf16 high and low parts, x = xh + xl, W = Wh + Wl, and the chunk carries
+// xh.Wh (group 0), xl.Wh (group 1) and xh.Wl (group 2); the dropped xl.Wl is
+// below 2^-16 of each product, so the first layer keeps about FP32 accuracy.
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerWG = 32;
+constexpr int kRowGroups = 2;                  // 16-pixel groups per wavefront
+constexpr int kPixPerWG = 4 * 16 * kRowGroups; // 128
+constexpr int kFrag = 8 * 4 * 4 * 16;          // A fragments per hidden layer: (ib, c, g, r)
+constexpr int kFrag1 = 8 * 4 * 16;             // first layer: (ib, g, r)
+
+__device__ __forceinline__ int frag_index(int ib, int c, int g, int r)
+{
+    return ((ib * 4 + c) * 4 + g) * 16 + r;
+}
+
+// A fragment (ib, c, g, r) of W^T from the transposed bf16 copy [out][kMlpTStride]
+__device__ __forceinline__ uint4 load_frag(const unsigned short *Wt, int f)
+{
+    const int r = f & 15, g = (f >> 4) & 3, c = (f >> 6) & 3, ib = f >> 8;
+    const unsigned short *row = Wt + (long)(16 * ib + r) * kMlpTStride + 32 * c + 4 * g;
+    const uint2 lo = *reinterpret_cast<const uint2 *>(row);        // 8-byte aligned
+    const uint2 hi = *reinterpret_cast<const uint2 *>(row + 16);
+    return make_uint4(lo.x, lo.y, hi.x, hi.y);
+}
+
+__device__ __forceinline__ unsigned pack2(unsigned short a, unsigned short b)
+{
+    return (unsigned)a | ((unsigned)b << 16);
+}
+
+// first-layer A fragment (ib, g, r): unit u = 16 ib + r; items d < 6 are the
+// weights of input d (high part for groups 0 and 1, low part for group 2);
+// group 0 items 6 and 7 are the bias high and low parts (their B items are 1)
+__device__ __forceinline__ uint4 load_frag1(const float *P, int f)
+{
+    const int r = f & 15, g = (f >> 4) & 3, ib = f >> 6, u = 16 * ib + r;
+    unsigned short v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g < 3) {
+        for (int d = 0; d < kMlpIn; ++d) {
+            const float w = P[kOffW1 + d * H + u];
+            const unsigned short wh = f2bf(w);
+            v[d] = g < 2 ? wh : f2bf(w - bf2f(wh));
+        }
+    }
+    if (g == 0) {
+        const float b = P[kOffB1 + u];
+        const unsigned short bh = f2bf(b);
+        v[6] = bh;
+        v[7] = f2bf(b - bf2f(bh));
+    }
+    return make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
+}
 
 __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowArgs a)
 {
-    __shared__ unsigned short sW2[H * kMlpTStride];
-    __shared__ unsigned short sW3[H * kMlpTStride];
-    __shared__ float sP[kOffW2];        // W1, b1
-    __shared__ float sB[3 * H + 1];     // b2, b3, w4, b4 (b2 at 0, b3 at H, w4 at 2H, b4 at 3H)
+    __shared__ uint4 sW1[kFrag1];                // 8 KB
+    __shared__ uint4 sW2[kFrag];                 // 32 KB
+    __shared__ uint4 sW3[kFrag];                 // 32 KB
+    __shared__ float4 sB[3 * H / 4];             // b2, b3, w4
 
-    for (int t = threadIdx.x; t < H * kMlpTStride / 2; t += 256) {
-        reinterpret_cast<unsigned *>(sW2)[t] = reinterpret_cast<const unsigned *>(a.W2t)[t];
-        reinterpret_cast<unsigned *>(sW3)[t] = reinterpret_cast<const unsigned *>(a.W3t)[t];
+    for (int f = threadIdx.x; f < kFrag; f += 256) {
+        sW2[f] = load_frag(a.W2t, f);
+        sW3[f] = load_frag(a.W3t, f);
     }
-    for (int t = threadIdx.x; t < kOffW2; t += 256) sP[t] = a.P[t];
-    for (int t = threadIdx.x; t < H; t += 256) {
-        sB[t] = a.P[kOffB2 + t];
-        sB[H + t] = a.P[kOffB3 + t];
-        sB[2 * H + t] = a.P[kOffW4 + t];
+    for (int f = threadIdx.x; f < kFrag1; f += 256) sW1[f] = load_frag1(a.P, f);
+    for (int t = threadIdx.x; t < H / 4; t += 256) {
+        sB[t] = reinterpret_cast<const float4 *>(a.P + kOffB2)[t];
+        sB[H / 4 + t] = reinterpret_cast<const float4 *>(a.P + kOffB3)[t];
+        sB[2 * H / 4 + t] = reinterpret_cast<const float4 *>(a.P + kOffW4)[t];
     }
-    if (threadIdx.x == 0) sB[3 * H] = a.P[kOffB4];
+    const float b4 = a.P[kOffB4];
     __syncthreads();
 
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
-    const int i = blockIdx.x * 64 + wv * 16 + r;          // this lane's pixel
-    const float2 xy = a.pix_xy[i];
+    int ip[kRowGroups];
+    float2 xy[kRowGroups];
+#pragma unroll
+    for (int p = 0; p < kRowGroups; ++p) {
+        ip[p] = blockIdx.x * kPixPerWG + wv * 16 * kRowGroups + 16 * p + r;
+        xy[p] = a.pix_xy[min(ip[p], S.Qp - 1)];
+    }
     const int e0 = blockIdx.y * kRowsPerWG, e1 = min(e0 + kRowsPerWG, a.rows);
     for (int e = e0; e < e1; ++e) {
-        float f[kMlpIn];
-        pair_features(S, xy, a.ev_bin[e], a.dirs[a.ev_ang[e]], a.ev_E[e], f);
-        // layer 1 (FP32) straight into B-operand fragments: units 16 ks + 4 g + t
-        v4s h1[8];
+        // An opaque zero offset keeps the weight reads inside the row loop:
+        // hoisted, they would take 512 registers and leave one wavefront per SIMD.
+        int off = 0;
+        asm volatile("" : "+v"(off));
+        const float4 *bb = sB + off;
+        const v8bf *w1 = reinterpret_cast<const v8bf *>(sW1) + off;
+        const v8bf *w2 = reinterpret_cast<const v8bf *>(sW2) + off;
+        const v8bf *w3 = reinterpret_cast<const v8bf *>(sW3) + off;
+
+        const int bin = a.ev_bin[e];
+        const float2 dir = a.dirs[a.ev_ang[e]];
+        const float E = a.ev_E[e];
+
+        // first-layer B fragments: group 0 (xh, 1, 1), group 1 (xl, 0, 0),
+        // group 2 (xh, 0, 0), group 3 zero
+        v8bf x1[kRowGroups];
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
+        for (int p = 0; p < kRowGroups; ++p) {
+            float f[kMlpIn];
+            pair_features(S, xy[p], bin, dir, E, f);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int u = 16 * ks + 4 * g + t;
-                float z = sP[kOffB1 + u];
-#pragma unroll
-                for (int d = 0; d < kMlpIn; ++d) z = fmaf(f[d], sP[kOffW1 + d * H + u], z);
-                h1[ks][t] = (short)f2bf(gelu(z));
+            for (int d = 0; d < kMlpIn; ++d) {
+                const __bf16 hi = (__bf16)f[d];
+                const __bf16 lo = (__bf16)(f[d] - (float)hi);
+                x1[p][d] = g == 1 ? lo : (g == 3 ? (__bf16)0.f : hi);
             }
+            const __bf16 one = g == 0 ? (__bf16)1.f : (__bf16)0.f;
+            x1[p][6] = one;
+            x1[p][7] = one;
         }
-        // layer 2: Z2^T = W2^T H1^T
-        v4s h2[8];
+        // layer 1: output block ib = units 16 ib + 4g + t -> item 4 (ib & 1) + t of chunk ib / 2
+        v8bf h1[kRowGroups][4];
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib) {
-            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            const v8bf w = w1[(ib * 4 + g) * 16 + r];
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                const v4s w = *reinterpret_cast<const v4s *>(&sW2[(16 * ib + r) * kMlpTStride +
-                                                                  16 * ks + 4 * g]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h1[ks], acc, 0, 0, 0);
+            for (int p = 0; p < kRowGroups; ++p) {
+                const v4f acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    w, x1[p], v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) h1[p][ib >> 1][4 * (ib & 1) + t] = (__bf16)gelu(acc[t]);
+            }
+        }
+        // layer 2
+        v8bf h2[kRowGroups][4];
+#pragma unroll
+        for (int ib = 0; ib < 8; ++ib) {
+            const float4 b = bb[(16 * ib + 4 * g) >> 2];
+            v4f acc[kRowGroups];
+#pragma unroll
+            for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const v8bf w = w2[frag_index(ib, c, g, r)];
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h1[p][c], acc[p], 0, 0, 0);
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) h2[ib][t] = (short)f2bf(gelu(acc[t] + sB[16 * ib + 4 * g + t]));
+            for (int p = 0; p < kRowGroups; ++p)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) h2[p][ib >> 1][4 * (ib & 1) + t] = (__bf16)gelu(acc[p][t]);
         }
         // layer 3 and the output unit
-        float part = 0.f;
+        float part[kRowGroups];
+#pragma unroll
+        for (int p = 0; p < kRowGroups; ++p) part[p] = 0.f;
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib) {
-            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            const float4 b = bb[H / 4 + ((16 * ib + 4 * g) >> 2)];
+            const float4 w4 = bb[2 * H / 4 + ((16 * ib + 4 * g) >> 2)];
+            v4f acc[kRowGroups];
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                const v4s w = *reinterpret_cast<const v4s *>(&sW3[(16 * ib + r) * kMlpTStride +
-                                                                  16 * ks + 4 * g]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h2[ks], acc, 0, 0, 0);
+            for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const v8bf w = w3[frag_index(ib, c, g, r)];
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h2[p][c], acc[p], 0, 0, 0);
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int u = 16 * ib + 4 * g + t;
-                part = fmaf(sB[2 * H + u], gelu(acc[t] + sB[H + u]), part);
+            for (int p = 0; p < kRowGroups; ++p) {
+                part[p] = fmaf(w4.x, gelu(acc[p][0]), part[p]);
+                part[p] = fmaf(w4.y, gelu(acc[p][1]), part[p]);
+                part[p] = fmaf(w4.z, gelu(acc[p][2]), part[p]);
+                part[p] = fmaf(w4.w, gelu(acc[p][3]), part[p]);
             }
         }
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (g == 0 && i < S.Qm) {
-            const float y = part + sB[3 * H];
-            const float v = fmaxf(__expf(y + a.c0) - a.floor_, 0.f);
-            a.A[(long)e * S.Qp + i] += v;
+#pragma unroll
+        for (int p = 0; p < kRowGroups; ++p) {
+            float y = part[p];
+            y += __shfl_xor(y, 16, 64);
+            y += __shfl_xor(y, 32, 64);
+            if (g == 0 && ip[p] < S.Qm) {
+                const float v = fmaxf(__expf(y + b4 + a.c0) - a.floor_, 0.f);
+                a.A[(long)e * S.Qp + ip[p]] += v;
+            }
         }
     }
 }
@@ -517,10 +639,21 @@ hipError_t mlp_targets(const float *raw, long n, float floor_, float c0, float *
 
 hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
 {
-    if (a.rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_rows, dim3(S.Qp / 64, nblk(a.rows, kRowsPerWG)), dim3(256), 0, st, S,
-                       a);
-    return hipGetLastError();
+    // grid.y is limited to 65535 workgroups: launch in slices of rows
+    constexpr int kSlice = 32768 * kRowsPerWG;
+    for (int r0 = 0; r0 < a.rows; r0 += kSlice) {
+        MlpRowArgs b = a;
+        b.rows = std::min(kSlice, a.rows - r0);
+        b.ev_bin += r0;
+        b.ev_ang += r0;
+        b.ev_E += r0;
+        b.A += (long)r0 * S.Qp;
+        hipLaunchKernelGGL(k_mlp_rows, dim3(nblk(S.Qp, kPixPerWG), nblk(b.rows, kRowsPerWG)),
+                           dim3(256), 0, st, S, b);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lmmew

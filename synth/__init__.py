@@ -164,6 +164,26 @@ def phantom_ellipse3(p: SysParams, seed: int, body=(110.0, 90.0), rim=8.0,
     return mu, act, rois
 
 
+def random_body_maps(p: SysParams, n_maps: int, seed: int, axes=(0.7, 0.95), shift=0.05,
+                     rim=8.0, mu_rim=0.021, mu_inner=0.018):
+    """Attenuation maps of random elliptical water bodies for one geometry:
+    semi-axes U[axes]*R, orientation U[0, pi), centre offset U[-shift, shift]*R
+    per coordinate, with the rim of phantom_ellipse3 (scaled like its body).
+    Returns [n_maps, n*n] float64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x, y = pixel_centres(p)
+    rim = rim * min(1.0, 0.9 * p.R / 110.0)
+    out = np.zeros((n_maps, p.n * p.n))
+    for k in range(n_maps):
+        A, B = rng.uniform(axes[0], axes[1], 2) * p.R
+        th = rng.uniform(0, np.pi)
+        cx, cy = rng.uniform(-shift, shift, 2) * p.R
+        outer = _in_ellipse(x, y, cx, cy, A, B, th)
+        inner = _in_ellipse(x, y, cx, cy, A - rim, B - rim, th)
+        out[k] = np.where(inner, mu_inner, np.where(outer, mu_rim, 0.0))
+    return out
+
+
 def phantom(w: Workload, case: int = 0):
     if w.phantom == "disk2":
         return phantom_disk2(w.params)
@@ -243,5 +263,5 @@ def workload_inputs(name: str, case: int = 0, n_events=None):
 
 
 __all__ = ["SysParams", "Workload", "CONFIGS", "EW1", "EW2", "EW3", "SW", "pixel_centres",
-           "fov_support", "phantom_disk2", "phantom_ellipse3", "phantom", "case_counts",
+           "fov_support", "phantom_disk2", "phantom_ellipse3", "random_body_maps", "phantom", "case_counts",
            "generic_events", "workload_inputs", "replace", "field"]
