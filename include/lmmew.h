@@ -175,6 +175,19 @@ int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, fl
 int lmmew_plan_create(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets,
                       int n_cases, int n_subsets, hipStream_t stream, lmmew_plan **out);
 
+/* A plan whose cases have their own attenuation maps (patients): case c is
+ * modelled with the tables of ctxs[c] (n_cases contexts that share the system
+ * parameters and the support; they may differ in the map and hence in their
+ * scatter points).  The plan belongs to ctxs[0]: pass ctxs[0] to the OSEM
+ * calls, whose sens argument is then device [n_cases][n_subsets][n*n], case
+ * c's block from lmmew_sensitivity(ctxs[c]).  The scatter model is ctxs[0]'s
+ * (lmmew_set_scatter_model).  The contexts must outlive the plan.  Otherwise
+ * as lmmew_plan_create.  Errors: EINVAL (also for contexts with a different
+ * system or support), ENOMEM, EDEVICE. */
+int lmmew_plan_create_maps(lmmew_ctx *const *ctxs, const lmmew_events *ev,
+                           const int64_t *case_offsets, int n_cases, int n_subsets,
+                           hipStream_t stream, lmmew_plan **out);
+
 int lmmew_plan_destroy(lmmew_plan *plan);
 
 /* Runs n_iters iterations of list-mode OSEM (Eq. (18)-(20)): for every
@@ -183,7 +196,8 @@ int lmmew_plan_destroy(lmmew_plan *plan);
  *   B_q = sum_{j, p_j > 0} a_jq / p_j
  *   lambda_c[q] <- lambda_c[q] * B_q / sens[s][q]  where sens[s][q] > 0.
  * The system model is evaluated afresh in every sub-iteration.
- *   sens     device [n_subsets][n*n] from lmmew_sensitivity (same n_subsets).
+ *   sens     device [n_subsets][n*n] from lmmew_sensitivity (same n_subsets);
+ *            [n_cases][n_subsets][n*n] for a plan from lmmew_plan_create_maps.
  *   lambda   device [n_cases][n*n], in: the current image, out: the image
  *            after n_iters iterations.  Initial values must be >= 0.
  *   stats    NULL, or host statistics; requesting them synchronises the

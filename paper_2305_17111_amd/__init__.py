@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     Plan,
     Mlp,
     events_to_device,
+    plan_maps,
     system_from_params,
     library_path,
 )

@@ -97,6 +97,7 @@ def _load():
         "lmmew_mlp_fit_labels": (i32, [vp, vp, vp, vp, i64, i32, i32, C.c_double, C.c_double,
                                        C.c_uint64, C.POINTER(C.c_double), vp]),
         "lmmew_set_scatter_model": (i32, [vp, vp]),
+        "lmmew_plan_create_maps": (i32, [vp, vp, vp, i32, i32, vp, vp]),
         "lmmew_support_size": (i64, [vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
@@ -133,6 +134,12 @@ def system_from_params(p) -> _System:
     s.mu_ref_keV, s.mu_power = float(p.mu_ref), float(p.mu_pow)
     s.T, s.electron_keV = float(p.T), float(p.me)
     return s
+
+
+def plan_maps(contexts, ev, n_subsets, case_offsets):
+    """A plan whose case c uses contexts[c]'s attenuation map
+    (lmmew_plan_create_maps); it belongs to contexts[0]."""
+    return Plan(contexts[0], ev, n_subsets, case_offsets, maps=contexts)
 
 
 def events_to_device(ev, device="cuda"):
@@ -261,9 +268,12 @@ class Context:
 
 
 class Plan:
-    """lmmew_plan_create / lmmew_osem_iter / lmmew_plan_destroy."""
+    """lmmew_plan_create / lmmew_osem_iter / lmmew_plan_destroy.
 
-    def __init__(self, ctx: Context, ev, n_subsets, case_offsets=None):
+    With ``maps`` (a list of Context, one per case, maps[0] is ctx) the plan
+    comes from lmmew_plan_create_maps and sens is [n_cases][n_subsets][n*n]."""
+
+    def __init__(self, ctx: Context, ev, n_subsets, case_offsets=None, maps=None):
         L = _load()
         self.ctx = ctx
         e = _events(ev)
@@ -276,8 +286,17 @@ class Plan:
             self.n_cases = len(case_offsets) - 1
             offs = C.cast(arr, C.c_void_p)
         h = C.c_void_p()
-        ctx._check(L.lmmew_plan_create(ctx._h, C.byref(e), offs, self.n_cases, self.n_subsets,
-                                       _stream(), C.byref(h)))
+        if maps is None:
+            ctx._check(L.lmmew_plan_create(ctx._h, C.byref(e), offs, self.n_cases,
+                                           self.n_subsets, _stream(), C.byref(h)))
+        else:
+            if len(maps) != self.n_cases or maps[0] is not ctx:
+                raise ValueError("maps must hold one context per case, maps[0] the plan's")
+            self.maps = list(maps)             # kept alive with the plan
+            hs = (C.c_void_p * len(maps))(*[m._h.value for m in maps])
+            ctx._check(L.lmmew_plan_create_maps(C.cast(hs, C.c_void_p), C.byref(e), offs,
+                                                self.n_cases, self.n_subsets, _stream(),
+                                                C.byref(h)))
         self._h = h
 
     def close(self):

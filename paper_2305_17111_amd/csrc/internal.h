@@ -87,12 +87,21 @@ hipError_t launch_tables_d(const DevSys &S, const double *mu, const double2 *pix
                            const double2 *dirs, const double2 *sc, float *g_qa, float *g_qs,
                            ScatA *sa, double pixmm, double R, hipStream_t st);
 
+// Tables of one attenuation map, for plans whose cases use different maps.
+struct MapTab {
+    const float *g_qa;       // [na][Qp]
+    const float *g_qs;       // [nsc][Qp]
+    const ScatA *sa;         // [na][nsc]
+    int nsc, pad;
+};
+
 struct RowArgs {
     const float2 *pix_xy;
     const float2 *dirs;
     const float *g_qa;
     const float *g_qs;
     const ScatA *sa;
+    const MapTab *maps;      // [ncases] tables per case, or NULL (g_qa, g_qs, sa, S.nsc)
     const Tile *tiles;
     const int *slist;        // scatter list entries referenced by the tiles
     int ntiles;
@@ -134,6 +143,7 @@ struct UpdArgs {
     const int *pixq;
     int Q;
     const float *sens;       // [Q] of this subset, or NULL (plain backprojection)
+    long sens_stride;        // elements from one case's sensitivity to the next (0: shared)
     float *lambda;           // [ncases][Q] in/out (update) or out (backprojection)
 };
 hipError_t launch_update(const DevSys &S, const UpdArgs &u, hipStream_t st);
@@ -155,6 +165,7 @@ struct ReduceArgs {          // deterministic sums for statistics
     const double *logp;
     int rows;
     const float *sens;       // [Q]
+    long sens_stride;        // elements from one case's sensitivity to the next (0: shared)
     const float *lambda;     // [ncases][Q]
     int ncases, Q;
     double *out;             // [1]: sum logp - sum sens*lambda

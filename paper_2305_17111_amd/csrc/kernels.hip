@@ -258,6 +258,17 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const int lane = threadIdx.x;
     const int i = blockIdx.x * kWave + lane;
     const int a = T.angle;
+    // attenuation tables of the tile's case
+    const float *g_qa = r.g_qa, *g_qs = r.g_qs;
+    const ScatA *sab = r.sa;
+    int nsc = S.nsc;
+    if (r.maps) {
+        const MapTab m = r.maps[T.ncase];
+        g_qa = m.g_qa;
+        g_qs = m.g_qs;
+        sab = m.sa;
+        nsc = m.nsc;
+    }
     const float2 dir = r.dirs[a];
     const float c = dir.x, s = dir.y;
     const bool valid = i < S.Qm;
@@ -283,7 +294,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         const float dq = S.R - (xq * c + yq * s);
         const float uq = -xq * s + yq * c;
         const float isq = 1.f / ((S.fwhm0 + S.fslope * dq) * S.inv_fwhm_to_sigma);
-        const float gqa = r.g_qa[(size_t)a * S.Qp + i];
+        const float gqa = g_qa[(size_t)a * S.Qp + i];
         float Pp[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) Pp[w] = S.pp[w] * fast_exp2(-S.f[w] * gqa * kLog2e);
@@ -308,7 +319,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
     for (int j = 0; j < JT; ++j) acc[j] = 0.f;
 
-    const ScatA *sa = r.sa + (size_t)a * S.nsc;
+    const ScatA *sa = sab + (size_t)a * nsc;
     const int kl = lane % KC, jg = lane / KC;
     const int kend = (r.mode == 2) ? T.k0 : T.k1;     // unscattered only: no scatter loop
     for (int lc0 = T.k0; lc0 < kend; lc0 += KC) {
@@ -336,7 +347,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         const int kn = min(KC, T.k1 - lc0);
         for (int kk = 0; kk < kn; ++kk) {
             const ScatA sp = sa[r.slist[lc0 + kk]];
-            const float gqs = r.g_qs[(size_t)sp.sidx * S.Qp + i];
+            const float gqs = g_qs[(size_t)sp.sidx * S.Qp + i];
             float Aw[NW], sw[NW], Fw[NW], Ep[NW];
             scatter_params<NW, true>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw, sw,
                                      Fw, Ep);
@@ -460,7 +471,7 @@ __global__ __launch_bounds__(256) void k_update(const DevSys S, const UpdArgs u)
     const int q = u.pixq[i];
     float *lam = u.lambda + (size_t)c * u.Q;
     if (u.sens) {
-        const float d = u.sens[q];
+        const float d = u.sens[(size_t)c * u.sens_stride + q];
         if (d > 0.f) lam[q] = lam[q] * B / d;
     } else {
         lam[q] = B;
@@ -537,7 +548,8 @@ __global__ __launch_bounds__(256) void k_loglik(const ReduceArgs r)
     for (int e = threadIdx.x; e < r.rows; e += 256) acc += r.logp[e];
     for (int c = 0; c < r.ncases; ++c)
         for (int q = threadIdx.x; q < r.Q; q += 256)
-            acc -= (double)r.sens[q] * (double)r.lambda[(size_t)c * r.Q + q];
+            acc -= (double)r.sens[(size_t)c * r.sens_stride + q] *
+                   (double)r.lambda[(size_t)c * r.Q + q];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {

@@ -61,6 +61,7 @@ struct lmmew_mlp {
 
 struct lmmew_plan {
     lmmew_ctx *ctx = nullptr;
+    std::vector<lmmew_ctx *> maps;    // [ncases] context (attenuation map) of each case, or empty
     int nsub = 1, ncases = 1, JT = 64;
     int64_t n = 0;
     std::vector<int> bin, ang, cas;   // sorted rows
@@ -85,6 +86,7 @@ struct lmmew_plan {
     int64_t *d_perm = nullptr;
     Tile *d_tiles = nullptr;
     int *d_slist = nullptr;
+    MapTab *d_maps = nullptr;
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
     double *d_logp = nullptr, *d_ll = nullptr;
@@ -215,6 +217,7 @@ void free_plan(lmmew_plan *p)
     dfree(p->d_bin); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
     dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
+    dfree(p->d_maps);
 }
 
 bool in_window(const lmmew_system &s, float e)
@@ -241,8 +244,7 @@ int relevant_scatter(const lmmew_ctx *c, int a, int b)
 // Builds tiles and chunks of a plan for the event tile size p->JT.
 void build_tiles(lmmew_plan *p)
 {
-    const lmmew_ctx *c = p->ctx;
-    const int nsc = c->S.nsc, na = c->S.na;
+    const int na = p->ctx->S.na;
     p->tiles.clear();
     p->slist.clear();
     p->chunks.clear();
@@ -260,6 +262,8 @@ void build_tiles(lmmew_plan *p)
         while (r < rend) {
             int e = r;
             const int cs = p->cas[r], a = p->ang[r];
+            const lmmew_ctx *c = p->maps.empty() ? p->ctx : p->maps[cs];
+            const int nsc = c->S.nsc;
             while (e < rend && e - r < p->JT && p->cas[e] == cs && p->ang[e] == a) ++e;
             int bmin = p->bin[r], bmax = p->bin[r];
             for (int k = r; k < e; ++k) {
@@ -348,10 +352,28 @@ int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
     return LMMEW_OK;
 }
 
+// Same geometry, support and model constants: contexts that differ only in
+// their attenuation map (and hence in their scatter points).
+bool same_system(const lmmew_ctx *a, const lmmew_ctx *b)
+{
+    DevSys x = a->S, y = b->S;
+    x.nsc = y.nsc = 0;
+    return std::memcmp(&x, &y, sizeof(DevSys)) == 0 && a->pixq == b->pixq;
+}
+
+// maps: NULL, or the context of each of the n_cases cases (maps[0] == ctx)
 int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets, int n_cases,
-              int n_subsets, hipStream_t st, lmmew_plan **out)
+              int n_subsets, hipStream_t st, lmmew_plan **out, lmmew_ctx *const *maps = nullptr)
 {
     *out = nullptr;
+    if (maps) {
+        for (int c = 0; c < n_cases; ++c) {
+            if (!maps[c]) return fail(ctx, LMMEW_EINVAL, "NULL context in the case list");
+            if (!same_system(ctx, maps[c]))
+                return fail(ctx, LMMEW_EINVAL,
+                            "contexts of a plan must share the system and the support");
+        }
+    }
     if (!ev || ev->n < 0 || (ev->n > 0 && (!ev->bin || !ev->angle || !ev->energy_keV)))
         return fail(ctx, LMMEW_EINVAL, "events: NULL array or negative count");
     if (n_subsets < 1 || n_subsets > ctx->S.na)
@@ -394,6 +416,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     lmmew_plan *p = new (std::nothrow) lmmew_plan;
     if (!p) return fail(ctx, LMMEW_ENOMEM, "host allocation");
     p->ctx = ctx;
+    if (maps) p->maps.assign(maps, maps + n_cases);
     p->nsub = n_subsets;
     p->ncases = n_cases;
     p->n = n;
@@ -435,15 +458,20 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     // algorithmic terms per iteration
     {
         const double QW = (double)ctx->S.Qm * ctx->S.nw;
-        std::vector<int> rel_cache((size_t)s.n_angles * s.n_bins, -1);
+        const size_t per = (size_t)s.n_angles * s.n_bins;
+        std::vector<int> rel_cache(per * (p->maps.empty() ? 1 : n_cases), -1);
         double t = 0;
         for (int64_t r = 0; r < n; ++r) {
-            int &rc = rel_cache[(size_t)p->ang[r] * s.n_bins + p->bin[r]];
-            if (rc < 0) rc = relevant_scatter(ctx, p->ang[r], p->bin[r]);
+            const int m = p->maps.empty() ? 0 : p->cas[r];
+            int &rc = rel_cache[m * per + (size_t)p->ang[r] * s.n_bins + p->bin[r]];
+            if (rc < 0) rc = relevant_scatter(m ? p->maps[m] : ctx, p->ang[r], p->bin[r]);
             t += QW * (1.0 + rc);
         }
         p->terms = t;
-        p->full_terms = (double)n * QW * (1.0 + ctx->S.nsc);
+        double full = 0;
+        for (int64_t r = 0; r < n; ++r)
+            full += 1.0 + (p->maps.empty() ? ctx : p->maps[p->cas[r]])->S.nsc;
+        p->full_terms = full * QW;
     }
     build_tiles(p);
     const int Qp = ctx->S.Qp;
@@ -476,6 +504,19 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         PCHK(hipMemcpyAsync(p->d_perm, p->perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice,
                             st));
     }
+    if (!p->maps.empty()) {
+        std::vector<MapTab> mt(n_cases);
+        for (int c = 0; c < n_cases; ++c) {
+            const lmmew_ctx *m = p->maps[c];
+            mt[c].g_qa = m->d_gqa;
+            mt[c].g_qs = m->d_gqs;
+            mt[c].sa = m->d_sa;
+            mt[c].nsc = m->S.nsc;
+        }
+        PCHK(dalloc(&p->d_maps, n_cases));
+        PCHK(hipMemcpyAsync(p->d_maps, mt.data(), n_cases * sizeof(MapTab), hipMemcpyHostToDevice,
+                            st));
+    }
     const int rc = upload_tiles(ctx, p, st);
     if (rc != LMMEW_OK) return fin(rc);
 #undef PCHK
@@ -496,6 +537,7 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0)
     r.g_qa = ctx->d_gqa;
     r.g_qs = ctx->d_gqs;
     r.sa = ctx->d_sa;
+    r.maps = p->d_maps;
     r.tiles = p->d_tiles + sub.tile0;
     r.slist = p->d_slist;
     r.ntiles = sub.ntiles;
@@ -983,6 +1025,17 @@ int lmmew_plan_create(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *cas
     return make_plan(ctx, ev, case_offsets, n_cases, n_subsets, st, out);
 }
 
+int lmmew_plan_create_maps(lmmew_ctx *const *ctxs, const lmmew_events *ev,
+                           const int64_t *case_offsets, int n_cases, int n_subsets, hipStream_t st,
+                           lmmew_plan **out)
+{
+    if (!ctxs || !ctxs[0]) return LMMEW_EINVAL;
+    lmmew_ctx *ctx = ctxs[0];
+    if (!out) return fail(ctx, LMMEW_EINVAL, "out is NULL");
+    if (n_cases < 1) return fail(ctx, LMMEW_EINVAL, "n_cases must be >= 1");
+    return make_plan(ctx, ev, case_offsets, n_cases, n_subsets, st, out, ctxs);
+}
+
 int lmmew_plan_destroy(lmmew_plan *plan)
 {
     if (!plan) return LMMEW_EINVAL;
@@ -1133,6 +1186,7 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
             ra.logp = p->d_logp + sub.row0;
             ra.rows = sub.rows;
             ra.sens = sens + (size_t)s * ctx->Q;
+            ra.sens_stride = p->maps.empty() ? 0 : (long)p->nsub * ctx->Q;
             ra.lambda = lambda;
             ra.ncases = p->ncases;
             ra.Q = ctx->Q;
@@ -1149,6 +1203,7 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
         u.pixq = ctx->d_pixq;
         u.Q = ctx->Q;
         u.sens = sens + (size_t)s * ctx->Q;
+        u.sens_stride = p->maps.empty() ? 0 : (long)p->nsub * ctx->Q;
         u.lambda = lambda;
         HIPCHK(ctx, launch_update(ctx->S, u, st));
     }
