@@ -11,6 +11,10 @@ Default workload: 64x64 object at 4 mm, 32x32 scatter grid, 64 bins x 120
 angles, lines 85/154/270 keV, windows 68-102/123-184/243-297 keV, ~50k events,
 8 subsets (the 20-iteration schedule runs as 20 steps).
 
+Beside it: 64 batched cases of that workload in one graph launch ("batched"),
+and the exact model against the MLP scatter surrogate ("surrogate") on 16
+patients with their own maps at 128x128 (1M events) and on the 16x16 workload.
+
 Prints ONE JSON line.
 """
 import argparse
@@ -29,6 +33,12 @@ sys.path.insert(0, ROOT)
 LANES_PER_S = 256 * 128 * 2.4e9
 SLOTS_PER_TERM = 6.0
 PEAK_TERMS_PER_S = LANES_PER_S / SLOTS_PER_TERM
+
+# scatter surrogate 6 -> 128 -> 128 -> 128 -> 1: multiply-adds per (event, pixel)
+# pair, and MI355X's dense BF16 MFMA peak
+MLP_MAC_PER_PAIR = 6 * 128 + 2 * 128 * 128 + 128
+MLP_GELU_PER_PAIR = 3 * 128
+PEAK_BF16_FLOPS = 2.5e15
 
 
 def workload_desc(name, p, J, nsub):
@@ -112,6 +122,137 @@ def batched(ctx, sens, args):
             "setup_s": {"events": gen_s, "plan": plan_s, "autotune": tune_s}}
 
 
+def _time_graph(plan, sens, lam, steps):
+    """Seconds per launch of a one-iteration graph (after one warmup launch)."""
+    import torch
+
+    plan.osem_graph(1, sens, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.osem_graph(1, sens, lam)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def surrogate(args):
+    """Exact model vs the MLP scatter surrogate.
+
+    c5: 16 patients (own phantom and attenuation map each, uneven counts, 1M
+    events in total) in one plan, 16 subsets, each iteration one graph launch;
+    the network is trained on the GPU on 10M samples of the exact scatter model
+    drawn over 16 random water bodies (it has no attenuation-map input).
+    c1: the 16x16 workload the surrogate's accuracy is tested on (10
+    iterations as one graph launch)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2305_17111_amd import Context, events_to_device, plan_maps
+
+    out = {}
+    w = synth.CONFIGS["c5"]
+    p = w.params
+    counts = synth.case_counts(w)
+    t = time.perf_counter()
+    ctxs, evs = [], []
+    for c in range(w.n_cases):
+        mu, act, _ = synth.phantom(w, c)
+        ctxs.append(Context(p, torch.from_numpy(mu.astype(np.float32))))
+        evs.append(synth.generic_events(p, act, int(counts[c]), w.seed_events + c))
+    sens = torch.stack([c.sensitivity(w.n_subsets) for c in ctxs]).contiguous()
+    cat = {k: np.concatenate([e[k] for e in evs]) for k in ("bin", "angle", "energy")}
+    offs = np.concatenate([[0], np.cumsum(counts)]).tolist()
+    plan = plan_maps(ctxs, events_to_device(cat), w.n_subsets, offs)
+    jt = plan.autotune(use_cache=False)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    J = int(counts.sum())
+    Qm = ctxs[0].support_size
+    lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+    lam0 = lam0.repeat(w.n_cases, 1).contiguous()
+
+    lam = lam0.clone()
+    exact_s = _time_graph(plan, sens, lam, args.surrogate_steps)
+
+    net = ctxs[0].mlp(seed=2)
+    maps = synth.random_body_maps(p, 16, seed=41).astype(np.float32)
+    n_lab = -(-10_000_000 // (16 * Qm))
+    t = time.perf_counter()
+    losses = net.fit_maps([torch.from_numpy(m) for m in maps], n_lab, epochs=args.surrogate_epochs,
+                          batch=8192, lr=2e-3, floor_frac=3e-2, seed=3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    ctxs[0].set_scatter_model(net)
+    lam = lam0.clone()
+    sur_s = _time_graph(plan, sens, lam, args.surrogate_steps)
+    assert bool(torch.isfinite(lam).all())
+    plan.profile(True)
+    plan.osem_iter(1, sens, lam)
+    k = plan.profile_read_kernels()
+    plan.profile(False)
+    ctxs[0].set_scatter_model(None)
+    mlp_ms, mlp_n = k["k_mlp_rows"]
+    row_ms, row_n = k["k_row"]
+    pairs = float(J) * Qm                            # (event, support pixel) pairs per iteration
+    flops = pairs * 2 * MLP_MAC_PER_PAIR / (mlp_ms * 1e-3)
+    out["c5_batched"] = {
+        "workload": f"c5: {w.n_cases} patients (own phantom and map) at {p.n}x{p.n}, "
+                    f"{p.pix:g} mm, scatter {p.ns}x{p.ns}, {p.nb} bins x {p.na} angles, "
+                    f"{len(p.windows)} windows, {J} events ({int(counts.min())}..{int(counts.max())}"
+                    f" per case), {w.n_subsets} subsets",
+        "unit": "events*iterations/s",
+        "exact": {"value": J / exact_s, "s_per_iteration": exact_s, "event_tile": jt},
+        "surrogate": {"value": J / sur_s, "s_per_iteration": sur_s,
+                      "unscattered_kernel_ms_per_iteration": row_ms},
+        "speedup": exact_s / sur_s,
+        "steps": args.surrogate_steps,
+        "training": {"samples": int(16 * n_lab * Qm), "epochs": args.surrogate_epochs,
+                     "batch": 8192, "seconds": train_s, "first_loss": losses[0],
+                     "last_loss": losses[-1], "maps": "16 random water bodies"},
+        "roofline": {"bound": "mfma", "kernel": "k_mlp_rows (surrogate inference)",
+                     "achieved": flops / 1e12, "peak": PEAK_BF16_FLOPS / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / PEAK_BF16_FLOPS, "traffic": None,
+                     "flop_per_pair": 2 * MLP_MAC_PER_PAIR, "gelu_per_pair": MLP_GELU_PER_PAIR,
+                     "pairs_per_s": pairs / (mlp_ms * 1e-3), "avg_launch_ms": mlp_ms / mlp_n},
+        "setup_s": setup_s,
+    }
+    del plan, ctxs, sens
+
+    w = synth.CONFIGS["c1"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    ctx = Context(p, torch.from_numpy(mu.astype(np.float32)))
+    sens = ctx.sensitivity(w.n_subsets)
+    ev = synth.generic_events(p, act, w.n_events, w.seed_events)
+    plan = ctx.plan(events_to_device(ev), w.n_subsets)
+    lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+    maps = synth.random_body_maps(p, 16, seed=41).astype(np.float32)
+    net = ctx.mlp(seed=2)
+    t = time.perf_counter()
+    net.fit_maps([torch.from_numpy(m) for m in maps], 3000, epochs=16, batch=8192, lr=2e-3,
+                 floor_frac=3e-2, seed=3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    res = {}
+    for key, model in (("exact", None), ("surrogate", net)):
+        ctx.set_scatter_model(model)
+        lam = lam0.clone()
+        plan.osem_graph(w.n_iters, sens, lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.osem_graph(w.n_iters, sens, lam)
+        torch.cuda.synchronize()
+        s_it = (time.perf_counter() - t0) / w.n_iters
+        res[key] = {"value": w.n_events / s_it, "s_per_iteration": s_it}
+    ctx.set_scatter_model(None)
+    out["c1"] = {"workload": workload_desc("c1", p, w.n_events, w.n_subsets),
+                 "unit": "events*iterations/s", **res,
+                 "training": {"samples": int(16 * 3000 * ctx.support_size), "epochs": 16,
+                              "seconds": train_s, "maps": "16 random water bodies"}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +263,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=1)
+    ap.add_argument("--surrogate-epochs", type=int, default=8)
     ap.add_argument("--event-tile", type=int, default=0,
                     help="0 = autotune over 16, 32, 64")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -244,6 +388,8 @@ def main():
     del plan
     if not args.no_batched:
         out["batched"] = batched(ctx, sens, args)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, mu, ev, args.cpu_seconds)
     print(json.dumps(out))

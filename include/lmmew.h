@@ -244,13 +244,19 @@ int lmmew_plan_set_event_tile(lmmew_ctx *ctx, lmmew_plan *plan, int event_tile,
                               hipStream_t stream);
 int lmmew_plan_get_event_tile(const lmmew_plan *plan);
 
-/* Timing of the per-event system-model kernel: with profiling enabled,
- * every launch of that kernel made for this plan is bracketed by two HIP
- * events recorded on the caller's stream.  lmmew_plan_profile_read waits for
- * the recorded launches, returns their summed duration (ms) and count, and
- * starts a new measurement. */
+/* Timing of the per-event system-model kernel (and of the scatter
+ * surrogate's kernel when a network is selected): with profiling enabled,
+ * every launch of those kernels made for this plan by lmmew_osem_iter or
+ * lmmew_osem_subiter is bracketed by two HIP events recorded on the caller's
+ * stream.  lmmew_plan_profile_read waits for the recorded launches, returns
+ * the per-event kernel's summed duration (ms) and launch count, and starts a
+ * new measurement; lmmew_plan_profile_read_kernels does the same for both
+ * kernels: ms[0], launches[0] the per-event kernel, ms[1], launches[1] the
+ * surrogate (host arrays of 2). */
 int lmmew_plan_profile(lmmew_ctx *ctx, lmmew_plan *plan, int enable);
 int lmmew_plan_profile_read(lmmew_ctx *ctx, lmmew_plan *plan, double *row_ms, int64_t *launches);
+int lmmew_plan_profile_read_kernels(lmmew_ctx *ctx, lmmew_plan *plan, double *ms,
+                                    int64_t *launches);
 
 /* Number of algorithmic terms one OSEM iteration of the plan evaluates in
  * the per-event system-model kernel: for every (event, support pixel) pair,

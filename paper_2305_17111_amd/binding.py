@@ -98,6 +98,8 @@ def _load():
                                        C.c_uint64, C.POINTER(C.c_double), vp]),
         "lmmew_set_scatter_model": (i32, [vp, vp]),
         "lmmew_plan_create_maps": (i32, [vp, vp, vp, i32, i32, vp, vp]),
+        "lmmew_plan_profile_read_kernels": (i32, [vp, vp, C.POINTER(C.c_double),
+                                                  C.POINTER(C.c_int64)]),
         "lmmew_support_size": (i64, [vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
@@ -376,8 +378,19 @@ class Plan:
                                                         C.byref(n)))
         return ms.value, n.value
 
+    def lmmew_plan_profile_read_kernels(self):
+        """{kernel: (summed ms, launches)} for the per-event kernel ("k_row") and
+        the surrogate ("k_mlp_rows") since the last read."""
+        ms = (C.c_double * 2)()
+        n = (C.c_int64 * 2)()
+        self.ctx._check(_load().lmmew_plan_profile_read_kernels(
+            self.ctx._h, self._h, C.cast(ms, C.POINTER(C.c_double)),
+            C.cast(n, C.POINTER(C.c_int64))))
+        return {"k_row": (ms[0], n[0]), "k_mlp_rows": (ms[1], n[1])}
+
     profile = lmmew_plan_profile
     profile_read = lmmew_plan_profile_read
+    profile_read_kernels = lmmew_plan_profile_read_kernels
 
     def terms(self):
         t, f = C.c_double(), C.c_double()

@@ -100,7 +100,8 @@ struct lmmew_plan {
     float *g_lambda = nullptr;
     // optional timing of the per-event kernel launches (HIP events on the caller's stream)
     bool prof = false;
-    std::vector<hipEvent_t> prof_ev;
+    std::vector<hipEvent_t> prof_ev;  // pairs of events around timed launches
+    std::vector<int> prof_kind;       // per pair: 0 k_row, 1 k_mlp_rows
     size_t prof_used = 0;
 };
 
@@ -524,6 +525,20 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     return LMMEW_OK;
 }
 
+// Records a timing event on the stream; two consecutive marks bracket one launch.
+hipError_t prof_mark(lmmew_ctx *, lmmew_plan *p, int kind, hipStream_t st)
+{
+    if (p->prof_ev.size() <= p->prof_used) {
+        hipEvent_t e;
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        p->prof_ev.push_back(e);
+    }
+    if (p->prof_used % 2 == 0) p->prof_kind.resize(p->prof_used / 2 + 1);
+    p->prof_kind[p->prof_used / 2] = kind;
+    return hipEventRecord(p->prof_ev[p->prof_used++], st);
+}
+
 // a_jq of subset s into the plan's scratch rows.  part: 0 the context's model
 // (exact, or unscattered + surrogate when a surrogate is set), 1 exact
 // scattered paths only, 2 unscattered only, 3 exact (ignoring the surrogate).
@@ -546,19 +561,9 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0)
     r.A = p->d_A;
     r.mode = surrogate ? 2 : (part == 3 ? 0 : part);
     const bool prof = p->prof && sub.ntiles > 0;
-    if (prof) {
-        while (p->prof_ev.size() < p->prof_used + 2) {
-            hipEvent_t e;
-            HIPCHK(ctx, hipEventCreate(&e));
-            p->prof_ev.push_back(e);
-        }
-        HIPCHK(ctx, hipEventRecord(p->prof_ev[p->prof_used], st));
-    }
+    if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
     HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
-    if (prof) {
-        HIPCHK(ctx, hipEventRecord(p->prof_ev[p->prof_used + 1], st));
-        p->prof_used += 2;
-    }
+    if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
     if (surrogate) {
         const lmmew_mlp *m = ctx->mlp;
         MlpRowArgs a{};
@@ -574,7 +579,10 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0)
         a.W3t = m->W3t;
         a.c0 = (float)m->c0;
         a.floor_ = (float)m->floor_;
+        const bool profm = p->prof && sub.rows > 0;
+        if (profm) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
         HIPCHK(ctx, mlp_rows(ctx->S, a, st));
+        if (profm) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
     }
     return LMMEW_OK;
 }
@@ -1141,19 +1149,36 @@ int lmmew_plan_profile(lmmew_ctx *ctx, lmmew_plan *plan, int enable)
     return LMMEW_OK;
 }
 
-int lmmew_plan_profile_read(lmmew_ctx *ctx, lmmew_plan *plan, double *row_ms, int64_t *launches)
+int lmmew_plan_profile_read_kernels(lmmew_ctx *ctx, lmmew_plan *plan, double *ms,
+                                    int64_t *launches)
 {
     if (!ctx || !plan || plan->ctx != ctx) return LMMEW_EINVAL;
-    double tot = 0.0;
+    double tot[2] = {0.0, 0.0};
+    int64_t cnt[2] = {0, 0};
     for (size_t k = 0; k + 1 < plan->prof_used; k += 2) {
         HIPCHK(ctx, hipEventSynchronize(plan->prof_ev[k + 1]));
-        float ms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, plan->prof_ev[k], plan->prof_ev[k + 1]));
-        tot += ms;
+        float t = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, plan->prof_ev[k], plan->prof_ev[k + 1]));
+        const int kind = plan->prof_kind[k / 2];
+        tot[kind] += t;
+        cnt[kind] += 1;
     }
-    if (row_ms) *row_ms = tot;
-    if (launches) *launches = (int64_t)(plan->prof_used / 2);
+    for (int i = 0; i < 2; ++i) {
+        if (ms) ms[i] = tot[i];
+        if (launches) launches[i] = cnt[i];
+    }
     plan->prof_used = 0;
+    return LMMEW_OK;
+}
+
+int lmmew_plan_profile_read(lmmew_ctx *ctx, lmmew_plan *plan, double *row_ms, int64_t *launches)
+{
+    double ms[2];
+    int64_t cnt[2];
+    const int rc = lmmew_plan_profile_read_kernels(ctx, plan, ms, cnt);
+    if (rc != LMMEW_OK) return rc;
+    if (row_ms) *row_ms = ms[0];
+    if (launches) *launches = cnt[0];
     return LMMEW_OK;
 }
 
