@@ -254,9 +254,19 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 {
     constexpr int KC = 16;               // scatter points per response block
     constexpr int TJ = JT / 4;           // events per lane in a response block
-    const Tile T = r.tiles[blockIdx.y];
+    // Work item p = (pixel block, tile) in block-major order.  Workgroups go to
+    // the 8 XCDs round-robin by id, so XCD k runs ids k, k+8, ...: mapping them
+    // to the k-th contiguous eighth of the items gives every XCD an equal share
+    // made of few pixel blocks, whose table columns then stay in its L2.
+    const int nb = S.Qp / kWave;
+    const int W = nb * r.ntiles;
+    const int per = (W + 7) >> 3;
+    const int p = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (p >= W) return;
+    const int bx = p / r.ntiles;
+    const Tile T = r.tiles[p - bx * r.ntiles];
     const int lane = threadIdx.x;
-    const int i = blockIdx.x * kWave + lane;
+    const int i = bx * kWave + lane;
     const int a = T.angle;
     // attenuation tables of the tile's case
     const float *g_qa = r.g_qa, *g_qs = r.g_qs;
@@ -289,7 +299,8 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const float2 xy = r.pix_xy[i];
     const float xq = xy.x, yq = xy.y;
 
-    // unscattered paths: written straight to the output rows
+    // unscattered paths, staged in LDS (each row element is written once, at the end)
+    __shared__ float prim[JT * kWave];
     {
         const float dq = S.R - (xq * c + yq * s);
         const float uq = -xq * s + yq * c;
@@ -307,7 +318,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                 if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
                 g = fmaf(Pp[w], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gq[w]), j)), g);
             }
-            r.A[(size_t)(T.e0 + j) * S.Qp + i] = ps * g;
+            prim[j * kWave + lane] = ps * g;
         }
     }
 
@@ -375,8 +386,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
     for (int j = 0; j < JT; ++j) {
         if (j < T.cnt) {
-            float *dst = r.A + (size_t)(T.e0 + j) * S.Qp + i;
-            *dst = valid ? *dst + acc[j] : 0.f;
+            r.A[(size_t)(T.e0 + j) * S.Qp + i] = valid ? prim[j * kWave + lane] + acc[j] : 0.f;
         }
     }
 }
@@ -384,7 +394,9 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 template <int JT>
 static hipError_t launch_row_jt(const DevSys &S, const RowArgs &r, hipStream_t st)
 {
-    dim3 grid(S.Qp / kWave, r.ntiles);
+    // one workgroup per (pixel block, tile), remapped per XCD inside the kernel
+    const long W = (long)(S.Qp / kWave) * r.ntiles;
+    dim3 grid((unsigned)((W + 7) / 8 * 8));
     switch (S.nw) {
     case 1: hipLaunchKernelGGL((k_row<JT, 1>), grid, dim3(kWave), 0, st, S, r); break;
     case 2: hipLaunchKernelGGL((k_row<JT, 2>), grid, dim3(kWave), 0, st, S, r); break;
