@@ -34,6 +34,11 @@ LANES_PER_S = 256 * 128 * 2.4e9
 SLOTS_PER_TERM = 6.0
 PEAK_TERMS_PER_S = LANES_PER_S / SLOTS_PER_TERM
 
+# HBM bytes per launch of the per-event kernel on the 64x64 workload at event
+# tile 16 (rocprofv3 FETCH_SIZE and WRITE_SIZE of this kernel version, scaled by
+# a 256 MiB copy kernel: fetch x2.000, write x1.000)
+MEASURED_TRAFFIC = {("c2", 16): {"fetch": 12.44e6, "write": 81.46e6}}
+
 # scatter surrogate 6 -> 128 -> 128 -> 128 -> 1: multiply-adds per (event, pixel)
 # pair, and MI355X's dense BF16 MFMA peak
 MLP_MAC_PER_PAIR = 6 * 128 + 2 * 128 * 128 + 128
@@ -350,6 +355,9 @@ def main():
 
     terms, full_terms = plan.terms()
     achieved = terms * args.steps / (row_ms * 1e-3)          # terms/s in the per-event kernel
+    mt = MEASURED_TRAFFIC.get((w.name, plan.event_tile))
+    rows_per_launch = J / nsub
+    out_bytes = rows_per_launch * ((int(synth.fov_support(p).sum()) + 63) // 64 * 64) * 4
     out = {
         "metric": "LM-MEW OSEM events*iterations/s (exact model), 1 GPU",
         "value": J * args.steps / elapsed,
@@ -376,7 +384,9 @@ def main():
             "peak": PEAK_TERMS_PER_S / 1e12,
             "unit": "Tterm/s",
             "frac": achieved / PEAK_TERMS_PER_S,
-            "traffic": None,
+            "traffic": (mt["fetch"] + mt["write"]) if mt else None,
+            "traffic_unit": "bytes per launch",
+            "traffic_detail": ({**mt, "algorithmic_write": out_bytes} if mt else None),
             "terms_per_launch": terms * args.steps / launches,
             "avg_launch_ms": row_ms / launches,
             "kernel_share_of_step": row_ms / (1e3 * elapsed),
