@@ -26,13 +26,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X unit counts: 256 CUs x 128 FP32 lanes per cycle x 2.4 GHz; a
-# transcendental (v_exp_f32) issues at a quarter of the FP32 rate.  One
-# algorithmic term needs one exp and at least two FP32 operations (forming the
-# exponent, accumulating), i.e. 4 + 2 = 6 issue slots.
+# MI355X unit counts: 256 CUs x 128 FP32 lane-operations per cycle (the 157.3
+# TFLOP/s vector rate, which needs packed FP32) x 2.4 GHz; v_exp_f32 at a
+# quarter of that rate.  One algorithmic term is one energy-Gaussian factor
+# exp(-(s E - F)^2 + A): two FMAs to form the exponent, one exp, one add to
+# accumulate, i.e. 3 + 4 = 7 issue slots.
 LANES_PER_S = 256 * 128 * 2.4e9
-SLOTS_PER_TERM = 6.0
+SLOTS_PER_TERM = 7.0
 PEAK_TERMS_PER_S = LANES_PER_S / SLOTS_PER_TERM
+# Without packed FP32 (not used anywhere in this library) a CU issues 64 FP32
+# lane-operations per cycle and the exp takes two of those slots: 3 + 2 = 5.
+NONPACKED_PEAK_TERMS_PER_S = 256 * 64 * 2.4e9 / 5.0
 
 # HBM bytes per launch of the per-event kernel on the 64x64 workload at event
 # tile 16 (rocprofv3 FETCH_SIZE and WRITE_SIZE of this kernel version, scaled by
@@ -384,6 +388,8 @@ def main():
             "peak": PEAK_TERMS_PER_S / 1e12,
             "unit": "Tterm/s",
             "frac": achieved / PEAK_TERMS_PER_S,
+            "nonpacked_peak": NONPACKED_PEAK_TERMS_PER_S / 1e12,
+            "frac_of_nonpacked_peak": achieved / NONPACKED_PEAK_TERMS_PER_S,
             "traffic": (mt["fetch"] + mt["write"]) if mt else None,
             "traffic_unit": "bytes per launch",
             "traffic_detail": ({**mt, "algorithmic_write": out_bytes} if mt else None),
