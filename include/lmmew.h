@@ -362,6 +362,28 @@ int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, int64_t n_label_events, int ep
  * alive while selected). */
 int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *mlp);
 
+/* ---------------------------------------------------------------------------
+ * Figures of merit for regional uptake (Sec. 3.1.4)
+ * ------------------------------------------------------------------------- */
+
+/* Uptake of each region in each image: out[c][k] = sum over the pixels q
+ * with masks[k][q] != 0 of lambda[c][q], summed in FP64 (deterministic).
+ *   lambda  device [n_cases][n*n] float;  masks  device [n_rois][n*n] uint8;
+ *   out     host [n_cases][n_rois] double.
+ * Synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int lmmew_roi_uptake(lmmew_ctx *ctx, const float *lambda, int n_cases, const uint8_t *masks,
+                     int n_rois, double *out, hipStream_t stream);
+
+/* Ensemble figures of merit of Sec. 3.1.4 over S object realisations x N
+ * noise realisations (N >= 2) for K regions (host arrays, no device work):
+ *   est    [S][N][K] estimated uptake, truth [S][K] true uptake (nonzero);
+ *   enrmse [K]  (1/S) sum_s sqrt(mean_n (est - y)^2) / y
+ *   bias   [K]  (1/(S N)) sum_s sum_n (est - y) / y
+ *   std_   [K]  (1/S) sum_s sqrt(sum_n (est - mean_n est)^2 / (N - 1)) / y
+ * Any output pointer may be NULL.  Errors: EINVAL. */
+int lmmew_roi_metrics(const double *est, const double *truth, int S, int N, int K, double *enrmse,
+                      double *bias, double *std_);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@ from .binding import (  # noqa: F401
     Mlp,
     events_to_device,
     plan_maps,
+    roi_metrics,
     system_from_params,
     library_path,
 )

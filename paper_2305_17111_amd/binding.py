@@ -101,6 +101,8 @@ def _load():
         "lmmew_plan_profile_read_kernels": (i32, [vp, vp, C.POINTER(C.c_double),
                                                   C.POINTER(C.c_int64)]),
         "lmmew_support_size": (i64, [vp]),
+        "lmmew_roi_uptake": (i32, [vp, vp, i32, vp, i32, vp, vp]),
+        "lmmew_roi_metrics": (i32, [vp, vp, i32, i32, i32, vp, vp, vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -136,6 +138,23 @@ def system_from_params(p) -> _System:
     s.mu_ref_keV, s.mu_power = float(p.mu_ref), float(p.mu_pow)
     s.T, s.electron_keV = float(p.T), float(p.me)
     return s
+
+
+def roi_metrics(est, truth):
+    """lmmew_roi_metrics: est [S, N, K], truth [S, K] -> (enrmse, bias, std), each [K]."""
+    import numpy as np
+
+    est = np.ascontiguousarray(est, np.float64)
+    truth = np.ascontiguousarray(truth, np.float64)
+    S, N, K = est.shape
+    if truth.shape != (S, K):
+        raise ValueError("truth must be [S, K]")
+    out = [np.zeros(K) for _ in range(3)]
+    rc = _load().lmmew_roi_metrics(C.c_void_p(est.ctypes.data), C.c_void_p(truth.ctypes.data),
+                                   S, N, K, *[C.c_void_p(o.ctypes.data) for o in out])
+    if rc != 0:
+        raise LmmewError(rc, "lmmew_roi_metrics: invalid arguments")
+    return tuple(out)
 
 
 def plan_maps(contexts, ev, n_subsets, case_offsets):
@@ -254,6 +273,21 @@ class Context:
     def lmmew_mlp_create(self, seed=0):
         return Mlp(self, seed)
 
+    def lmmew_roi_uptake(self, lam, masks):
+        """[n_cases, n_rois] FP64 host array of region sums of lam ([n_cases, Q] or [Q])
+        over masks ([n_rois, Q], nonzero = inside)."""
+        import numpy as np
+
+        lam = lam.contiguous()
+        m = torch.as_tensor(masks).to("cuda", torch.uint8).contiguous()
+        nc = 1 if lam.dim() == 1 else lam.shape[0]
+        nk = 1 if m.dim() == 1 else m.shape[0]
+        out = np.zeros((nc, nk), np.float64)
+        self._check(_load().lmmew_roi_uptake(self._h, _ptr(lam), nc, _ptr(m), nk,
+                                             C.c_void_p(out.ctypes.data), _stream()))
+        return out
+
+    roi_uptake = lmmew_roi_uptake
     rows = lmmew_rows
     scatter_labels = lmmew_scatter_labels
     set_scatter_model = lmmew_set_scatter_model

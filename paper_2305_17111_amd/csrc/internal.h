@@ -178,6 +178,8 @@ hipError_t launch_rows_out(const DevSys &S, const float *A, int rows, const int6
                            const int *pixq, int Q, float *out, hipStream_t st);
 hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float *dst,
                            hipStream_t st);
+hipError_t launch_roi_sums(const float *lam, int C, int Q, const uint8_t *masks, int K,
+                           double *out, hipStream_t st);
 
 // ---- scatter surrogate (mlp.hip) ------------------------------------------
 struct MlpWork {             // activations of one training batch

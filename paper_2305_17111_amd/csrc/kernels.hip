@@ -687,4 +687,36 @@ hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// ROI uptake (Sec. 3.1.4): sum of an image over a region, per (case, region).
+// One workgroup per (case, region); FP64 partial sums combined in a fixed
+// tree, so the result is deterministic.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_roi_sums(const float *lam, int Q, const uint8_t *masks,
+                                                  int K, double *out)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.y, k = blockIdx.x;
+    const float *l = lam + (size_t)c * Q;
+    const uint8_t *m = masks + (size_t)k * Q;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < Q; q += 256)
+        if (m[q]) acc += (double)l[q];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)c * K + k] = red[0];
+}
+
+hipError_t launch_roi_sums(const float *lam, int C, int Q, const uint8_t *masks, int K,
+                           double *out, hipStream_t st)
+{
+    if (C == 0 || K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_roi_sums, dim3(K, C), dim3(256), 0, st, lam, Q, masks, K, out);
+    return hipGetLastError();
+}
+
 }  // namespace lmmew

@@ -1667,6 +1667,58 @@ int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *m, int64_t n_label_events, int epoc
     return rc;
 }
 
+int lmmew_roi_uptake(lmmew_ctx *ctx, const float *lambda, int n_cases, const uint8_t *masks,
+                     int n_rois, double *out, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (n_cases < 0 || n_rois < 0) return fail(ctx, LMMEW_EINVAL, "negative count");
+    if ((int64_t)n_cases * n_rois == 0) return LMMEW_OK;
+    if (!lambda || !masks || !out) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    double *d = nullptr;
+    HIPCHK(ctx, dalloc(&d, (size_t)n_cases * n_rois));
+    hipError_t e = launch_roi_sums(lambda, n_cases, ctx->Q, masks, n_rois, d, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, d, sizeof(double) * n_cases * n_rois, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(d);
+    if (e != hipSuccess) return hipfail(ctx, e, "roi uptake");
+    return LMMEW_OK;
+}
+
+int lmmew_roi_metrics(const double *est, const double *truth, int S, int N, int K, double *enrmse,
+                      double *bias, double *std_)
+{
+    if (!est || !truth || S < 1 || N < 2 || K < 1) return LMMEW_EINVAL;
+    for (int i = 0; i < S * K; ++i)
+        if (!(truth[i] != 0.0) || !std::isfinite(truth[i])) return LMMEW_EINVAL;
+    for (int k = 0; k < K; ++k) {
+        double e_sum = 0.0, b_sum = 0.0, s_sum = 0.0;
+        for (int s = 0; s < S; ++s) {
+            const double y = truth[(size_t)s * K + k];
+            double se = 0.0, dsum = 0.0, mean = 0.0;
+            for (int n = 0; n < N; ++n) {
+                const double v = est[((size_t)s * N + n) * K + k];
+                se += (v - y) * (v - y);
+                dsum += v - y;
+                mean += v;
+            }
+            mean /= N;
+            double ss = 0.0;
+            for (int n = 0; n < N; ++n) {
+                const double d = est[((size_t)s * N + n) * K + k] - mean;
+                ss += d * d;
+            }
+            e_sum += std::sqrt(se / N) / y;
+            b_sum += dsum / y;
+            s_sum += std::sqrt(ss / (N - 1)) / y;
+        }
+        if (enrmse) enrmse[k] = e_sum / S;
+        if (bias) bias[k] = b_sum / ((double)S * N);
+        if (std_) std_[k] = s_sum / S;
+    }
+    return LMMEW_OK;
+}
+
 int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *m)
 {
     if (!ctx || (m && m->ctx != ctx)) return LMMEW_EINVAL;

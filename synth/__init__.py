@@ -118,6 +118,45 @@ def phantom_disk2(p: SysParams, mu85=0.018, body_r=28.0, hot_r=6.0, hot_x=14.0,
     return mu, act, rois
 
 
+def disk2_objects(p: SysParams, n_objects: int, seed: int, n_lumps=8, amp=(0.0, 0.6),
+                  width=6.0, ratio=4.0, **disk):
+    """Object realisations of phantom_disk2 with a lumpy background (Sec. 3.1.1
+    draws a new background sample per object realisation; its lumpy-model
+    parameters are not given, these are ours): background 1 + sum of n_lumps
+    Gaussian lumps (amplitude U[amp], standard deviation `width` mm, centres
+    uniform in the body), scaled to mean 1 in the body; the two hot disks hold
+    `ratio` times that mean.  Returns (mu [Q], activities [n_objects, Q], rois)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mu, act0, rois = phantom_disk2(p, ratio=ratio, **disk)
+    x, y = pixel_centres(p)
+    body = act0 > 0
+    r_body = np.sqrt((x[body] ** 2 + y[body] ** 2).max())
+    acts = np.zeros((n_objects, x.size))
+    for o in range(n_objects):
+        b = np.ones(x.size)
+        for _ in range(n_lumps):
+            rr, th = r_body * np.sqrt(rng.random()), 2 * np.pi * rng.random()
+            cx, cy = rr * np.cos(th), rr * np.sin(th)
+            b += rng.uniform(*amp) * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * width ** 2))
+        b = np.where(body, b / b[body].mean(), 0.0)
+        for roi in rois:
+            b = np.where(roi, ratio, b)
+        acts[o] = b
+    return mu, acts, rois
+
+
+def sew_events(ev, window, energy_keV=None):
+    """The events of one energy window (the single-window methods of Sec. 3.2.2);
+    with energy_keV, every kept event is assigned that energy (the binned-energy
+    variant)."""
+    e = np.asarray(ev["energy"])
+    keep = (e >= window[0]) & (e <= window[1])
+    out = {k: np.asarray(ev[k])[keep] for k in ("bin", "angle", "energy")}
+    if energy_keV is not None:
+        out["energy"] = np.full(int(keep.sum()), energy_keV, dtype=out["energy"].dtype)
+    return out
+
+
 def _in_ellipse(x, y, cx, cy, a, b, th):
     c, s = np.cos(th), np.sin(th)
     u = (x - cx) * c + (y - cy) * s
@@ -263,5 +302,6 @@ def workload_inputs(name: str, case: int = 0, n_events=None):
 
 
 __all__ = ["SysParams", "Workload", "CONFIGS", "EW1", "EW2", "EW3", "SW", "pixel_centres",
-           "fov_support", "phantom_disk2", "phantom_ellipse3", "random_body_maps", "phantom", "case_counts",
+           "fov_support", "phantom_disk2", "disk2_objects", "sew_events", "phantom_ellipse3",
+           "random_body_maps", "phantom", "case_counts",
            "generic_events", "workload_inputs", "replace", "field"]
