@@ -12,8 +12,10 @@ angles, lines 85/154/270 keV, windows 68-102/123-184/243-297 keV, ~50k events,
 8 subsets (the 20-iteration schedule runs as 20 steps).
 
 Beside it: 64 batched cases of that workload in one graph launch ("batched"),
-and the exact model against the MLP scatter surrogate ("surrogate") on 16
-patients with their own maps at 128x128 (1M events) and on the 16x16 workload.
+the exact model against the MLP scatter surrogate ("surrogate") on 16
+patients with their own maps at 128x128 (1M events) and on the 16x16 workload,
+and the cached-row mode ("cached_rows": rows computed once, iterations bound
+by HBM bandwidth; a different mode, never the headline value).
 
 Prints ONE JSON line.
 """
@@ -122,13 +124,48 @@ def batched(ctx, sens, args):
     J = int(counts.sum())
     terms, _ = plan.terms()
     assert bool(torch.isfinite(lam).all())
+    lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+    lam0 = lam0.repeat(len(counts), 1).contiguous()
+    Qp = (int(synth.fov_support(p).sum()) + 63) // 64 * 64
+    cached = None if args.no_cached else cached_rows(plan, sens, lam0, J, Qp, args.batched_steps)
     return {"workload": f"c3: {len(counts)} cases of the 64x64 workload, {J} events "
                         f"({int(counts.min())}..{int(counts.max())} per case), {w.n_subsets} subsets",
             "value": J * args.batched_steps / el, "unit": "events*iterations/s",
             "s_per_iteration": el / args.batched_steps, "steps": args.batched_steps,
             "event_tile": jt, "terms_per_s": terms * args.batched_steps / el,
             "frac_of_term_peak": terms * args.batched_steps / el / PEAK_TERMS_PER_S,
-            "setup_s": {"events": gen_s, "plan": plan_s, "autotune": tune_s}}
+            "setup_s": {"events": gen_s, "plan": plan_s, "autotune": tune_s},
+            "cached_rows": cached}
+
+
+PEAK_HBM_BYTES_PER_S = 8.0e12
+
+
+def cached_rows(plan, sens, lam0, J, Qp, steps):
+    """Cached-row mode: the rows of every subset computed once, the iterations
+    (forward projection, backprojection, update) read them.  Each iteration
+    reads every row twice (forward and backprojection): 2 x J x Qp x 4 bytes."""
+    import torch
+
+    from paper_2305_17111_amd import LmmewError
+
+    t = time.perf_counter()
+    try:
+        plan.cache_rows(True)
+    except LmmewError as e:
+        return {"skipped": str(e)}
+    torch.cuda.synchronize()
+    cache_s = time.perf_counter() - t
+    lam = lam0.clone()
+    s_it = _time_graph(plan, sens, lam, steps)
+    plan.cache_rows(False)
+    bytes_it = 2.0 * J * Qp * 4
+    return {"value": J / s_it, "unit": "events*iterations/s", "s_per_iteration": s_it,
+            "steps": steps, "cache_s": cache_s, "cached_bytes": J * Qp * 4.0,
+            "roofline": {"bound": "hbm", "kernel": "k_forward + k_back on cached rows",
+                         "achieved": bytes_it / s_it / 1e9, "peak": PEAK_HBM_BYTES_PER_S / 1e9,
+                         "unit": "GB/s", "frac": bytes_it / s_it / PEAK_HBM_BYTES_PER_S,
+                         "traffic": None, "bytes_per_iteration": bytes_it}}
 
 
 def _time_graph(plan, sens, lam, steps):
@@ -273,6 +310,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-cached", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=1)
     ap.add_argument("--surrogate-epochs", type=int, default=8)
     ap.add_argument("--event-tile", type=int, default=0,
@@ -401,6 +439,10 @@ def main():
         "model_terms_per_iteration": {"evaluated": terms, "unpruned": full_terms},
         "setup_ms": setup,
     }
+    if not args.no_cached:
+        lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+        Qp = (int(synth.fov_support(p).sum()) + 63) // 64 * 64
+        out["cached_rows"] = cached_rows(plan, sens, lam0, J, Qp, args.steps)
     del plan
     if not args.no_batched:
         out["batched"] = batched(ctx, sens, args)

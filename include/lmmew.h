@@ -190,6 +190,19 @@ int lmmew_plan_create_maps(lmmew_ctx *const *ctxs, const lmmew_events *ev,
 
 int lmmew_plan_destroy(lmmew_plan *plan);
 
+/* Cached-row mode (a mode of its own, outside the paper's matrix-free
+ * iteration): with enable != 0 the rows a_jq of every subset are computed
+ * once, with the context's current scatter model, into device memory owned by
+ * the plan (n_events x support pixels padded to 64 x 4 bytes: 0.7 GB for 50k
+ * events at 64x64); lmmew_osem_iter/_subiter/_graph then read them instead
+ * of evaluating the model, which makes an iteration bound by HBM bandwidth.
+ * Results are bitwise identical to the matrix-free iterations.  enable == 0
+ * frees them.  After lmmew_set_scatter_model the cached rows are stale and the
+ * OSEM calls fail with EINVAL until they are cached again.  Synchronises.
+ * Errors: EINVAL, ENOMEM (also when the rows would leave less than 1 GiB of
+ * device memory free), EDEVICE. */
+int lmmew_plan_cache_rows(lmmew_ctx *ctx, lmmew_plan *plan, int enable, hipStream_t stream);
+
 /* Runs n_iters iterations of list-mode OSEM (Eq. (18)-(20)): for every
  * subset s in order and every case c,
  *   p_j = sum_q a_jq lambda_c[q]                  (events j of case c in s)

@@ -102,6 +102,7 @@ def _load():
                                                   C.POINTER(C.c_int64)]),
         "lmmew_support_size": (i64, [vp]),
         "lmmew_roi_uptake": (i32, [vp, vp, i32, vp, i32, vp, vp]),
+        "lmmew_plan_cache_rows": (i32, [vp, vp, i32, vp]),
         "lmmew_roi_metrics": (i32, [vp, vp, i32, i32, i32, vp, vp, vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
@@ -391,8 +392,15 @@ class Plan:
                                                _stream(), C.byref(ch)))
         return ch.value
 
+    def lmmew_plan_cache_rows(self, enable=True):
+        """Computes every subset's rows once and keeps them (cached-row mode);
+        enable=False frees them."""
+        self.ctx._check(_load().lmmew_plan_cache_rows(self.ctx._h, self._h, int(bool(enable)),
+                                                      _stream()))
+
     osem_graph = lmmew_osem_graph
     autotune = lmmew_autotune
+    cache_rows = lmmew_plan_cache_rows
 
     def set_event_tile(self, jt):
         self.ctx._check(_load().lmmew_plan_set_event_tile(self.ctx._h, self._h, int(jt), _stream()))

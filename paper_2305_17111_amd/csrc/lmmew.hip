@@ -89,6 +89,8 @@ struct lmmew_plan {
     MapTab *d_maps = nullptr;
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
+    float *d_Acache = nullptr;        // [n][Qp] rows of every subset (lmmew_plan_cache_rows) or NULL
+    int cache_gen = -1;               // scatter-model generation the cached rows were computed with
     double *d_logp = nullptr, *d_ll = nullptr;
     float *d_part = nullptr, *d_comp = nullptr;
     unsigned long long *d_nskip = nullptr;
@@ -96,6 +98,7 @@ struct lmmew_plan {
     // captured OSEM sequence (lmmew_osem_graph) and the arguments it was captured with
     hipGraphExec_t gexec = nullptr;
     int g_iters = -1, g_jt = 0, g_gen = -1;
+    const float *g_cache = nullptr;
     const float *g_sens = nullptr;
     float *g_lambda = nullptr;
     // optional timing of the per-event kernel launches (HIP events on the caller's stream)
@@ -219,6 +222,7 @@ void free_plan(lmmew_plan *p)
     dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
+    dfree(p->d_Acache);
 }
 
 bool in_window(const lmmew_system &s, float e)
@@ -542,9 +546,17 @@ hipError_t prof_mark(lmmew_ctx *, lmmew_plan *p, int kind, hipStream_t st)
 // a_jq of subset s into the plan's scratch rows.  part: 0 the context's model
 // (exact, or unscattered + surrogate when a surrogate is set), 1 exact
 // scattered paths only, 2 unscattered only, 3 exact (ignoring the surrogate).
-int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0)
+// Rows a_jq of subset s: the cached rows, or the per-subset scratch.
+float *rows_of(lmmew_plan *p, int s)
+{
+    return p->d_Acache ? p->d_Acache + (size_t)p->subs[s].row0 * p->ctx->S.Qp : p->d_A;
+}
+
+int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
+             float *dst = nullptr)
 {
     const lmmew_plan::Sub &sub = p->subs[s];
+    float *const out = dst ? dst : p->d_A;
     const bool surrogate = (part == 0 && ctx->mlp != nullptr);
     RowArgs r{};
     r.pix_xy = ctx->d_pix;
@@ -558,7 +570,7 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0)
     r.ntiles = sub.ntiles;
     r.ev_bin = p->d_bin + sub.row0;
     r.ev_E = p->d_E + sub.row0;
-    r.A = p->d_A;
+    r.A = out;
     r.mode = surrogate ? 2 : (part == 3 ? 0 : part);
     const bool prof = p->prof && sub.ntiles > 0;
     if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
@@ -573,7 +585,7 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0)
         a.ev_ang = p->d_ang + sub.row0;
         a.ev_E = p->d_E + sub.row0;
         a.rows = sub.rows;
-        a.A = p->d_A;
+        a.A = out;
         a.P = m->P;
         a.W2t = m->W2t;
         a.W3t = m->W3t;
@@ -592,7 +604,7 @@ int run_forward(lmmew_ctx *ctx, lmmew_plan *p, int s, const float *lambda, bool 
 {
     const lmmew_plan::Sub &sub = p->subs[s];
     FwdArgs f{};
-    f.A = p->d_A;
+    f.A = rows_of(p, s);
     f.rows = sub.rows;
     f.row_case = p->d_case + sub.row0;
     f.pixq = ctx->d_pixq;
@@ -611,7 +623,7 @@ int run_back(lmmew_ctx *ctx, lmmew_plan *p, int s, const float *wt_rows, float *
 {
     const lmmew_plan::Sub &sub = p->subs[s];
     BackArgs b{};
-    b.A = p->d_A;
+    b.A = rows_of(p, s);
     b.wt = wt_rows;
     b.chunks = p->d_chunks + sub.chunk0;
     b.nchunks = sub.nchunks;
@@ -986,7 +998,7 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
     if (n_iters < 0) return fail(ctx, LMMEW_EINVAL, "n_iters < 0");
     if (n_iters == 0) return LMMEW_OK;
     if (!p->gexec || p->g_iters != n_iters || p->g_sens != sens || p->g_lambda != lambda ||
-        p->g_jt != p->JT || p->g_gen != ctx->model_gen) {
+        p->g_jt != p->JT || p->g_gen != ctx->model_gen || p->g_cache != p->d_Acache) {
         if (p->gexec) {
             HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
             p->gexec = nullptr;
@@ -1020,6 +1032,7 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
         p->g_lambda = lambda;
         p->g_jt = p->JT;
         p->g_gen = ctx->model_gen;
+        p->g_cache = p->d_Acache;
     }
     HIPCHK(ctx, hipGraphLaunch(p->gexec, st));
     return LMMEW_OK;
@@ -1042,6 +1055,44 @@ int lmmew_plan_create_maps(lmmew_ctx *const *ctxs, const lmmew_events *ev,
     if (!out) return fail(ctx, LMMEW_EINVAL, "out is NULL");
     if (n_cases < 1) return fail(ctx, LMMEW_EINVAL, "n_cases must be >= 1");
     return make_plan(ctx, ev, case_offsets, n_cases, n_subsets, st, out, ctxs);
+}
+
+int lmmew_plan_cache_rows(lmmew_ctx *ctx, lmmew_plan *p, int enable, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!p || p->ctx != ctx) return fail(ctx, LMMEW_EINVAL, "plan does not belong to context");
+    if (p->gexec) {                      // a captured graph may refer to the rows
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
+        p->gexec = nullptr;
+    }
+    if (p->d_Acache) {
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        dfree(p->d_Acache);
+        p->d_Acache = nullptr;
+        p->cache_gen = -1;
+    }
+    if (!enable || p->n == 0) return LMMEW_OK;
+    const size_t bytes = (size_t)p->n * ctx->S.Qp * sizeof(float);
+    size_t fr = 0, tot = 0;
+    HIPCHK(ctx, hipMemGetInfo(&fr, &tot));
+    if (bytes + (size_t(1) << 30) > fr)
+        return fail(ctx, LMMEW_ENOMEM, "not enough free device memory for the cached rows");
+    float *c = nullptr;
+    if (dalloc(&c, (size_t)p->n * ctx->S.Qp) != hipSuccess)
+        return fail(ctx, LMMEW_ENOMEM, "cached rows");
+    int rc = LMMEW_OK;
+    for (int s = 0; s < p->nsub && rc == LMMEW_OK; ++s)
+        rc = run_rows(ctx, p, s, st, 0, c + (size_t)p->subs[s].row0 * ctx->S.Qp);
+    const hipError_t e = hipStreamSynchronize(st);
+    if (rc == LMMEW_OK && e != hipSuccess) rc = hipfail(ctx, e, "caching rows");
+    if (rc != LMMEW_OK) {
+        dfree(c);
+        return rc;
+    }
+    p->d_Acache = c;
+    p->cache_gen = ctx->model_gen;
+    return LMMEW_OK;
 }
 
 int lmmew_plan_destroy(lmmew_plan *plan)
@@ -1195,6 +1246,9 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
 {
     const int K = count;
     const bool want = stats != nullptr;
+    if (p->d_Acache && p->cache_gen != ctx->model_gen)
+        return fail(ctx, LMMEW_EINVAL,
+                    "cached rows are stale: the scatter model changed (cache them again)");
     if (want) {
         int rc = ensure_stats(ctx, p, std::max(K, 1));
         if (rc != LMMEW_OK) return rc;
@@ -1203,7 +1257,7 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
     for (int k = 0; k < K; ++k) {
         const int s = (first_subset + k) % p->nsub;
         const lmmew_plan::Sub &sub = p->subs[s];
-        int rc = run_rows(ctx, p, s, st);
+        int rc = p->d_Acache ? LMMEW_OK : run_rows(ctx, p, s, st);
         if (rc == LMMEW_OK) rc = run_forward(ctx, p, s, lambda, want, k, st);
         if (rc != LMMEW_OK) return rc;
         if (want) {
