@@ -428,9 +428,20 @@ __global__ __launch_bounds__(256) void k_forward(const DevSys S, const FwdArgs f
     const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= f.rows) return;
     const float *lam = f.lambda + (size_t)f.row_case[e] * f.Q;
-    const float *A = f.A + (size_t)e * S.Qp;
+    // 16-byte loads: the row and the pixel index array are 64-element aligned
+    const float4 *A = reinterpret_cast<const float4 *>(f.A + (size_t)e * S.Qp);
+    const int4 *pq = reinterpret_cast<const int4 *>(f.pixq);
     float sum = 0.f;
-    for (int i = lane; i < S.Qm; i += kWave) sum = fmaf(lam[f.pixq[i]], A[i], sum);
+#pragma unroll 4
+    for (int k = lane; k < S.Qp / 4; k += kWave) {
+        const float4 a = A[k];
+        const int4 q = pq[k];
+        const int i = 4 * k;
+        if (i < S.Qm) sum = fmaf(lam[q.x], a.x, sum);
+        if (i + 1 < S.Qm) sum = fmaf(lam[q.y], a.y, sum);
+        if (i + 2 < S.Qm) sum = fmaf(lam[q.z], a.z, sum);
+        if (i + 3 < S.Qm) sum = fmaf(lam[q.w], a.w, sum);
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, kWave);
     if (lane == 0) {
@@ -441,25 +452,53 @@ __global__ __launch_bounds__(256) void k_forward(const DevSys S, const FwdArgs f
     }
 }
 
-// ---------------------------------------------------------------------------
-// backprojection: compensated (Neumaier) column sums over a chunk of rows
-// ---------------------------------------------------------------------------
+// Neumaier step: adds v to (sum, cmp)
+__device__ __forceinline__ void neumaier(float &sum, float &cmp, float v)
+{
+    const float t = sum + v;
+    cmp += (fabsf(sum) >= fabsf(v)) ? (sum - t) + v : (v - t) + sum;
+    sum = t;
+}
+
+// One workgroup per (64 pixels, chunk of rows): wavefront k of 4 sums the
+// chunk's rows r0 + k, r0 + k + 4, ... for its lane's pixel, loading four rows
+// ahead; the four compensated partials are combined in a fixed order.
 __global__ __launch_bounds__(256) void k_back(const DevSys S, const BackArgs b)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= S.Qp) return;
+    __shared__ float ps[4][kWave], pc[4][kWave];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * kWave + lane;
     const Chunk ch = b.chunks[blockIdx.y];
     float sum = 0.f, cmp = 0.f;
-    for (int e = ch.r0; e < ch.r1; ++e) {
-        const float w = b.wt[e];
-        if (w == 0.f) continue;
-        const float v = b.A[(size_t)e * S.Qp + i] * w;
-        const float t = sum + v;
-        cmp += (fabsf(sum) >= fabsf(v)) ? (sum - t) + v : (v - t) + sum;
-        sum = t;
+    int e = ch.r0 + wv;
+    for (; e + 12 < ch.r1; e += 16) {
+        float v[4], w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w[k] = b.wt[e + 4 * k];
+            v[k] = b.A[(size_t)(e + 4 * k) * S.Qp + i];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (w[k] != 0.f) neumaier(sum, cmp, v[k] * w[k]);
     }
-    b.part[(size_t)blockIdx.y * S.Qp + i] = sum;
-    b.comp[(size_t)blockIdx.y * S.Qp + i] = cmp;
+    for (; e < ch.r1; e += 4) {
+        const float w = b.wt[e];
+        if (w != 0.f) neumaier(sum, cmp, b.A[(size_t)e * S.Qp + i] * w);
+    }
+    ps[wv][lane] = sum;
+    pc[wv][lane] = cmp;
+    __syncthreads();
+    if (wv == 0) {
+        float s0 = ps[0][lane], c0 = pc[0][lane];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            neumaier(s0, c0, ps[k][lane]);
+            c0 += pc[k][lane];
+        }
+        b.part[(size_t)blockIdx.y * S.Qp + i] = s0;
+        b.comp[(size_t)blockIdx.y * S.Qp + i] = c0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -625,7 +664,7 @@ hipError_t launch_forward(const DevSys &S, const FwdArgs &f, hipStream_t st)
 hipError_t launch_back(const DevSys &S, const BackArgs &b, hipStream_t st)
 {
     if (b.nchunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_back, dim3((S.Qp + 255) / 256, b.nchunks), dim3(256), 0, st, S, b);
+    hipLaunchKernelGGL(k_back, dim3(S.Qp / kWave, b.nchunks), dim3(256), 0, st, S, b);
     return hipGetLastError();
 }
 
