@@ -116,15 +116,16 @@ struct FwdArgs {
     const float *A;          // [rows][Qp]
     int rows;
     const int *row_case;     // [rows]
-    const int *pixq;         // [Qp] full-grid index or -1
-    const float *lambda;     // [ncases][Q]
-    int Q;
+    const float *lamc;       // [ncases][Qp] image on the support pixels (0 in the padding)
     float *p;                // [rows]
     float *wt;               // [rows] 1/p (0 if p <= 0)
     double *logp;            // [rows] log p (0 if p <= 0), may be NULL
     unsigned long long *nskip;   // may be NULL
 };
 hipError_t launch_forward(const DevSys &S, const FwdArgs &f, hipStream_t st);
+// lamc[c][i] = lambda[c][pixq[i]] on the support, 0 in the padding
+hipError_t launch_compact(const DevSys &S, const float *lambda, int ncases, int Q, const int *pixq,
+                          float *lamc, hipStream_t st);
 
 struct BackArgs {
     const float *A;
@@ -145,6 +146,7 @@ struct UpdArgs {
     const float *sens;       // [Q] of this subset, or NULL (plain backprojection)
     long sens_stride;        // elements from one case's sensitivity to the next (0: shared)
     float *lambda;           // [ncases][Q] in/out (update) or out (backprojection)
+    float *lamc;             // [ncases][Qp] support copy of the updated image, or NULL
 };
 hipError_t launch_update(const DevSys &S, const UpdArgs &u, hipStream_t st);
 

@@ -427,20 +427,18 @@ __global__ __launch_bounds__(256) void k_forward(const DevSys S, const FwdArgs f
     const int lane = threadIdx.x & 63;
     const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= f.rows) return;
-    const float *lam = f.lambda + (size_t)f.row_case[e] * f.Q;
-    // 16-byte loads: the row and the pixel index array are 64-element aligned
+    // a contiguous dot product: the row and the support copy of the image,
+    // both padded with zeros to Qp (a multiple of 64), 16 bytes per load
     const float4 *A = reinterpret_cast<const float4 *>(f.A + (size_t)e * S.Qp);
-    const int4 *pq = reinterpret_cast<const int4 *>(f.pixq);
+    const float4 *L = reinterpret_cast<const float4 *>(f.lamc + (size_t)f.row_case[e] * S.Qp);
     float sum = 0.f;
 #pragma unroll 4
     for (int k = lane; k < S.Qp / 4; k += kWave) {
-        const float4 a = A[k];
-        const int4 q = pq[k];
-        const int i = 4 * k;
-        if (i < S.Qm) sum = fmaf(lam[q.x], a.x, sum);
-        if (i + 1 < S.Qm) sum = fmaf(lam[q.y], a.y, sum);
-        if (i + 2 < S.Qm) sum = fmaf(lam[q.z], a.z, sum);
-        if (i + 3 < S.Qm) sum = fmaf(lam[q.w], a.w, sum);
+        const float4 a = A[k], l = L[k];
+        sum = fmaf(l.x, a.x, sum);
+        sum = fmaf(l.y, a.y, sum);
+        sum = fmaf(l.z, a.z, sum);
+        sum = fmaf(l.w, a.w, sum);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, kWave);
@@ -450,6 +448,16 @@ __global__ __launch_bounds__(256) void k_forward(const DevSys S, const FwdArgs f
         if (f.logp) f.logp[e] = sum > 0.f ? log((double)sum) : 0.0;
         if (f.nskip && !(sum > 0.f)) atomicAdd(f.nskip, 1ull);
     }
+}
+
+__global__ __launch_bounds__(256) void k_compact(const DevSys S, const float *lambda, int Q,
+                                                 const int *pixq, float *lamc)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= S.Qp) return;
+    const int q = pixq[i];
+    lamc[(size_t)c * S.Qp + i] = (i < S.Qm) ? lambda[(size_t)c * Q + q] : 0.f;
 }
 
 // Neumaier step: adds v to (sum, cmp)
@@ -507,26 +515,41 @@ __global__ __launch_bounds__(256) void k_back(const DevSys S, const BackArgs b)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_update(const DevSys S, const UpdArgs u)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    // 64 pixels per workgroup; wave k of 4 sums chunks k, k + 4, ... of the
+    // case, and the four compensated partials are combined in a fixed order
+    __shared__ float ps[4][kWave], pc[4][kWave];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * kWave + lane;
     const int c = blockIdx.y;
-    if (i >= S.Qm) return;
     float sum = 0.f, cmp = 0.f;
-    for (int ch = u.case_chunk[c]; ch < u.case_chunk[c + 1]; ++ch) {
-        const float v = u.part[(size_t)ch * S.Qp + i];
+    const int c1 = u.case_chunk[c + 1];
+    for (int ch = u.case_chunk[c] + wv; ch < c1; ch += 4) {
         cmp += u.comp[(size_t)ch * S.Qp + i];
-        const float t = sum + v;
-        cmp += (fabsf(sum) >= fabsf(v)) ? (sum - t) + v : (v - t) + sum;
-        sum = t;
+        neumaier(sum, cmp, u.part[(size_t)ch * S.Qp + i]);
     }
-    const float B = sum + cmp;
+    ps[wv][lane] = sum;
+    pc[wv][lane] = cmp;
+    __syncthreads();
+    if (wv != 0 || i >= S.Qm) return;
+    float s0 = ps[0][lane], c0 = pc[0][lane];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        neumaier(s0, c0, ps[k][lane]);
+        c0 += pc[k][lane];
+    }
+    const float B = s0 + c0;
     const int q = u.pixq[i];
     float *lam = u.lambda + (size_t)c * u.Q;
+    float v;
     if (u.sens) {
         const float d = u.sens[(size_t)c * u.sens_stride + q];
-        if (d > 0.f) lam[q] = lam[q] * B / d;
+        v = lam[q];
+        if (d > 0.f) v = v * B / d;
     } else {
-        lam[q] = B;
+        v = B;
     }
+    lam[q] = v;
+    if (u.lamc) u.lamc[(size_t)c * S.Qp + i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -670,7 +693,7 @@ hipError_t launch_back(const DevSys &S, const BackArgs &b, hipStream_t st)
 
 hipError_t launch_update(const DevSys &S, const UpdArgs &u, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_update, dim3((S.Qm + 255) / 256, u.ncases), dim3(256), 0, st, S, u);
+    hipLaunchKernelGGL(k_update, dim3(S.Qp / kWave, u.ncases), dim3(256), 0, st, S, u);
     return hipGetLastError();
 }
 
@@ -714,6 +737,15 @@ hipError_t launch_rows_out(const DevSys &S, const float *A, int rows, const int6
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rows_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S, A, rows,
                        perm, pixq, Q, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const DevSys &S, const float *lambda, int ncases, int Q, const int *pixq,
+                          float *lamc, hipStream_t st)
+{
+    if (ncases == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3((S.Qp + 255) / 256, ncases), dim3(256), 0, st, S, lambda,
+                       Q, pixq, lamc);
     return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ struct lmmew_plan {
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
     float *d_Acache = nullptr;        // [n][Qp] rows of every subset (lmmew_plan_cache_rows) or NULL
+    float *d_lamc = nullptr;          // [ncases][Qp] support copy of the current images
     int cache_gen = -1;               // scatter-model generation the cached rows were computed with
     double *d_logp = nullptr, *d_ll = nullptr;
     float *d_part = nullptr, *d_comp = nullptr;
@@ -223,6 +224,7 @@ void free_plan(lmmew_plan *p)
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
     dfree(p->d_Acache);
+    dfree(p->d_lamc);
 }
 
 bool in_window(const lmmew_system &s, float e)
@@ -501,6 +503,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     PCHK(dalloc(&p->d_wt, n));
     PCHK(dalloc(&p->d_logp, n));
     PCHK(dalloc(&p->d_A, (size_t)std::max(p->max_rows, 1) * Qp));
+    PCHK(dalloc(&p->d_lamc, (size_t)n_cases * Qp));
     if (n > 0) {
         PCHK(hipMemcpyAsync(p->d_bin, p->bin.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_ang, p->ang.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
@@ -599,17 +602,22 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     return LMMEW_OK;
 }
 
-int run_forward(lmmew_ctx *ctx, lmmew_plan *p, int s, const float *lambda, bool stats, int k,
-                hipStream_t st)
+// The images on the support pixels, in the layout of the rows (read by the
+// forward projection; the EM update keeps it current within an OSEM call).
+int run_compact(lmmew_ctx *ctx, lmmew_plan *p, const float *lambda, hipStream_t st)
+{
+    HIPCHK(ctx, launch_compact(ctx->S, lambda, p->ncases, ctx->Q, ctx->d_pixq, p->d_lamc, st));
+    return LMMEW_OK;
+}
+
+int run_forward(lmmew_ctx *ctx, lmmew_plan *p, int s, bool stats, int k, hipStream_t st)
 {
     const lmmew_plan::Sub &sub = p->subs[s];
     FwdArgs f{};
     f.A = rows_of(p, s);
     f.rows = sub.rows;
     f.row_case = p->d_case + sub.row0;
-    f.pixq = ctx->d_pixq;
-    f.lambda = lambda;
-    f.Q = ctx->Q;
+    f.lamc = p->d_lamc;
     f.p = p->d_p + sub.row0;
     f.wt = p->d_wt + sub.row0;
     f.logp = stats ? p->d_logp + sub.row0 : nullptr;
@@ -922,9 +930,10 @@ int lmmew_forward(lmmew_ctx *ctx, const lmmew_events *ev, const float *lambda, f
     lmmew_plan *pl = nullptr;
     int rc = make_plan(ctx, ev, nullptr, 1, subsets_for_budget(ctx, ev->n), st, &pl);
     if (rc != LMMEW_OK) return rc;
+    if (rc == LMMEW_OK) rc = run_compact(ctx, pl, lambda, st);
     for (int s = 0; s < pl->nsub && rc == LMMEW_OK; ++s) {
         rc = run_rows(ctx, pl, s, st);
-        if (rc == LMMEW_OK) rc = run_forward(ctx, pl, s, lambda, false, 0, st);
+        if (rc == LMMEW_OK) rc = run_forward(ctx, pl, s, false, 0, st);
     }
     if (rc == LMMEW_OK) {
         hipError_t e = launch_scatter_out(pl->d_p, pl->d_perm, pl->n, p, st);
@@ -1249,6 +1258,10 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
     if (p->d_Acache && p->cache_gen != ctx->model_gen)
         return fail(ctx, LMMEW_EINVAL,
                     "cached rows are stale: the scatter model changed (cache them again)");
+    if (K > 0) {
+        const int rc = run_compact(ctx, p, lambda, st);
+        if (rc != LMMEW_OK) return rc;
+    }
     if (want) {
         int rc = ensure_stats(ctx, p, std::max(K, 1));
         if (rc != LMMEW_OK) return rc;
@@ -1258,7 +1271,7 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
         const int s = (first_subset + k) % p->nsub;
         const lmmew_plan::Sub &sub = p->subs[s];
         int rc = p->d_Acache ? LMMEW_OK : run_rows(ctx, p, s, st);
-        if (rc == LMMEW_OK) rc = run_forward(ctx, p, s, lambda, want, k, st);
+        if (rc == LMMEW_OK) rc = run_forward(ctx, p, s, want, k, st);
         if (rc != LMMEW_OK) return rc;
         if (want) {
             ReduceArgs ra{};
@@ -1284,6 +1297,7 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
         u.sens = sens + (size_t)s * ctx->Q;
         u.sens_stride = p->maps.empty() ? 0 : (long)p->nsub * ctx->Q;
         u.lambda = lambda;
+        u.lamc = p->d_lamc;
         HIPCHK(ctx, launch_update(ctx->S, u, st));
     }
     if (want) {
