@@ -4,8 +4,9 @@
 One step = one OSEM iteration (all angle subsets: per-event system model,
 forward projection, compensated backprojection, EM update) over the workload's
 whole event list, inputs resident in HBM.  Setup (attenuation tables,
-sensitivity, event plan, tile autotuning) is timed separately and reported in
-`setup_ms`.
+sensitivity, the scatter-path parameter table when it fits in device memory,
+event plan, tile autotuning) is timed separately and reported in `setup_ms`;
+the same iterations without the path table are reported beside the headline.
 
 Default workload: 64x64 object at 4 mm, 32x32 scatter grid, 64 bins x 120
 angles, lines 85/154/270 keV, windows 68-102/123-184/243-297 keV, ~50k events,
@@ -41,9 +42,11 @@ PEAK_TERMS_PER_S = LANES_PER_S / SLOTS_PER_TERM
 NONPACKED_PEAK_TERMS_PER_S = 256 * 64 * 2.4e9 / 5.0
 
 # HBM bytes per launch of the per-event kernel on the 64x64 workload at event
-# tile 16 (rocprofv3 FETCH_SIZE and WRITE_SIZE of this kernel version, scaled by
-# a 256 MiB copy kernel: fetch x2.000, write x1.000)
-MEASURED_TRAFFIC = {("c2", 16): {"fetch": 12.44e6, "write": 81.46e6}}
+# tile 16, without and with the path-parameter table (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE of these kernel versions, scaled by a 256 MiB copy kernel: fetch
+# x2.000, write x1.000)
+MEASURED_TRAFFIC = {("c2", 16, False): {"fetch": 14.1e6, "write": 81.46e6},
+                    ("c2", 16, True): {"fetch": 4910.1e6, "write": 81.46e6}}
 
 # scatter surrogate 6 -> 128 -> 128 -> 128 -> 1: multiply-adds per (event, pixel)
 # pair, and MI355X's dense BF16 MFMA peak
@@ -311,6 +314,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-cached", action="store_true")
+    ap.add_argument("--no-path-table", action="store_true",
+                    help="evaluate the scatter-path parameters inside the per-event kernel")
     ap.add_argument("--surrogate-steps", type=int, default=1)
     ap.add_argument("--surrogate-epochs", type=int, default=8)
     ap.add_argument("--event-tile", type=int, default=0,
@@ -358,6 +363,19 @@ def main():
     sens = ctx.sensitivity(nsub)
     torch.cuda.synchronize()
     setup["sensitivity_ms"] = 1e3 * (time.perf_counter() - t)
+    path_table = None
+    if not args.no_path_table:
+        # event-independent scatter-path parameters, evaluated once per map
+        from paper_2305_17111_amd import LmmewError
+
+        t = time.perf_counter()
+        try:
+            ctx.path_table(True)
+            path_table = ctx.path_table_bytes
+        except LmmewError as e:
+            print(f"path table not used: {e}", file=sys.stderr)
+        torch.cuda.synchronize()
+        setup["path_table_ms"] = 1e3 * (time.perf_counter() - t)
     t = time.perf_counter()
     plan = ctx.plan(events_to_device(ev), nsub)
     torch.cuda.synchronize()
@@ -397,7 +415,7 @@ def main():
 
     terms, full_terms = plan.terms()
     achieved = terms * args.steps / (row_ms * 1e-3)          # terms/s in the per-event kernel
-    mt = MEASURED_TRAFFIC.get((w.name, plan.event_tile))
+    mt = MEASURED_TRAFFIC.get((w.name, plan.event_tile, bool(path_table)))
     rows_per_launch = J / nsub
     out_bytes = rows_per_launch * ((int(synth.fov_support(p).sum()) + 63) // 64 * 64) * 4
     out = {
@@ -418,10 +436,11 @@ def main():
             "workload": workload_desc(w.name, p, J, nsub),
             "events": J, "subsets": nsub, "iterations_per_step": 1,
             "event_tile": plan.event_tile, "pixels_in_support": int(synth.fov_support(p).sum()),
+            "path_table_bytes": path_table,
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_row (per-event system model)",
+            "kernel": "k_row (per-event system model%s)" % (", path-parameter table" if path_table else ""),
             "achieved": achieved / 1e12,
             "peak": PEAK_TERMS_PER_S / 1e12,
             "unit": "Tterm/s",
@@ -443,9 +462,29 @@ def main():
         lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
         Qp = (int(synth.fov_support(p).sum()) + 63) // 64 * 64
         out["cached_rows"] = cached_rows(plan, sens, lam0, J, Qp, args.steps)
-    del plan
     if not args.no_batched:
         out["batched"] = batched(ctx, sens, args)
+    if path_table:
+        # the same iterations evaluating the path parameters inside the kernel
+        ctx.path_table(False)
+        plan.osem_iter(1, sens, lam)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        t0 = time.perf_counter()
+        n_nt = min(args.steps, 5)
+        for _ in range(n_nt):
+            plan.osem_iter(1, sens, lam)
+        torch.cuda.synchronize()
+        el_nt = time.perf_counter() - t0
+        ms_nt, n_launch = plan.profile_read()
+        plan.profile(False)
+        ach_nt = terms * n_nt / (ms_nt * 1e-3)
+        out["without_path_table"] = {"ms_per_step": 1e3 * el_nt / n_nt,
+                                     "value": J * n_nt / el_nt,
+                                     "k_row_avg_launch_ms": ms_nt / n_launch,
+                                     "frac": ach_nt / PEAK_TERMS_PER_S,
+                                     "frac_of_nonpacked_peak": ach_nt / NONPACKED_PEAK_TERMS_PER_S}
+    del plan
     if not args.no_surrogate:
         out["surrogate"] = surrogate(args)
     if not args.no_cpu_baseline:

@@ -134,6 +134,23 @@ int lmmew_destroy(lmmew_ctx *ctx);
 /* Number of support pixels (the pixels rows and labels cover), -1 for NULL. */
 int64_t lmmew_support_size(const lmmew_ctx *ctx);
 
+/* Path-parameter table (optional): the event-independent part of every
+ * once-scattered path of Eq. (3) -- for each (angle, scatter point, support
+ * pixel) and line: the log2 path weight (attenuation along both legs,
+ * Klein-Nishina, geometry, energy-Gaussian normalisation), s_w and F_w of the
+ * energy factor exp2(-(s_w E - F_w)^2) -- evaluated once into device memory
+ * owned by the context: n_angles x scatter points x 3 lines' worth x support
+ * pixels x 4 bytes (lmmew_path_table_bytes; 11.7 GB at 64x64 with a 32x32
+ * scatter grid and 3 lines).  With it the per-event kernel reads these values
+ * instead of recomputing them for every tile of events; the rows are still
+ * evaluated per event in every sub-iteration, and agree with the rows without
+ * the table to rounding.  enable == 0 frees it.  Plans over several maps use
+ * the tables only when every case's context has one.  Synchronises.
+ * Errors: EINVAL, ENOMEM (also when the table would leave less than 1 GiB of
+ * device memory free), EDEVICE. */
+int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t stream);
+int64_t lmmew_path_table_bytes(const lmmew_ctx *ctx);
+
 /* Sensitivity image per subset: sens[s][q] = T * sum over the subset's
  * angles of the probability that a decay in pixel q is recorded (on the
  * detector and inside a window), unscattered or once scattered: the

@@ -103,6 +103,8 @@ def _load():
         "lmmew_support_size": (i64, [vp]),
         "lmmew_roi_uptake": (i32, [vp, vp, i32, vp, i32, vp, vp]),
         "lmmew_plan_cache_rows": (i32, [vp, vp, i32, vp]),
+        "lmmew_path_table": (i32, [vp, i32, vp]),
+        "lmmew_path_table_bytes": (i64, [vp]),
         "lmmew_roi_metrics": (i32, [vp, vp, i32, i32, i32, vp, vp, vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
@@ -288,6 +290,15 @@ class Context:
                                              C.c_void_p(out.ctypes.data), _stream()))
         return out
 
+    def lmmew_path_table(self, enable=True):
+        """Builds (or frees) the context's scatter-path parameter table."""
+        self._check(_load().lmmew_path_table(self._h, int(bool(enable)), _stream()))
+
+    @property
+    def path_table_bytes(self):
+        return int(_load().lmmew_path_table_bytes(self._h))
+
+    path_table = lmmew_path_table
     roi_uptake = lmmew_roi_uptake
     rows = lmmew_rows
     scatter_labels = lmmew_scatter_labels

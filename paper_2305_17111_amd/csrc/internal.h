@@ -92,6 +92,7 @@ struct MapTab {
     const float *g_qa;       // [na][Qp]
     const float *g_qs;       // [nsc][Qp]
     const ScatA *sa;         // [na][nsc]
+    const float *ptab;       // path-parameter table (see RowArgs) or NULL
     int nsc, pad;
 };
 
@@ -102,8 +103,11 @@ struct RowArgs {
     const float *g_qs;
     const ScatA *sa;
     const MapTab *maps;      // [ncases] tables per case, or NULL (g_qa, g_qs, sa, S.nsc)
+    const float *ptab;       // scatter-path parameters [na][nsc][3 nw][Qp] (per line: log2
+                             // weight, s_w, F_w), or NULL to evaluate them in the kernel
     const Tile *tiles;
-    const int *slist;        // scatter list entries referenced by the tiles
+    const int2 *slist;       // scatter list entries of the tiles: (point in the angle's
+                             // sorted list, row of the point in the g_qs table)
     int ntiles;
     const int *ev_bin;       // sorted rows of this subset
     const float *ev_E;
@@ -111,6 +115,9 @@ struct RowArgs {
     int mode;                // 0: all paths, 1: scattered paths only, 2: unscattered only
 };
 hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st);
+// scatter-path parameters of every (angle, scatter point, support pixel)
+hipError_t launch_path_table(const DevSys &S, const float2 *pix_xy, const float2 *dirs,
+                             const float *g_qs, const ScatA *sa, float *ptab, hipStream_t st);
 
 struct FwdArgs {
     const float *A;          // [rows][Qp]

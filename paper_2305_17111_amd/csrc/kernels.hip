@@ -249,7 +249,7 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
 // branch.  For each listed scatter point every lane derives its pixel's path
 // parameters once and reuses them for all of the tile's events.
 // ---------------------------------------------------------------------------
-template <int JT, int NW>
+template <int JT, int NW, bool TAB>
 __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 {
     constexpr int KC = 16;               // scatter points per response block
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const int i = bx * kWave + lane;
     const int a = T.angle;
     // attenuation tables of the tile's case
-    const float *g_qa = r.g_qa, *g_qs = r.g_qs;
+    const float *g_qa = r.g_qa, *g_qs = r.g_qs, *ptab = r.ptab;
     const ScatA *sab = r.sa;
     int nsc = S.nsc;
     if (r.maps) {
@@ -277,6 +277,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         g_qa = m.g_qa;
         g_qs = m.g_qs;
         sab = m.sa;
+        ptab = m.ptab;
         nsc = m.nsc;
     }
     const float2 dir = r.dirs[a];
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
             const int l = lc0 + kl;
             float u = 0.f, isg = 0.f;
             if (l < T.k1) {
-                const ScatA &sp = sa[r.slist[l]];
+                const ScatA &sp = sa[r.slist[l].x];
                 u = sp.u;
                 isg = sp.isig;
             }
@@ -356,12 +357,59 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
             }
         }
         const int kn = min(KC, T.k1 - lc0);
+        // the next listed point's data is loaded one iteration ahead, so the
+        // dependent loads (list entry, point, table values) overlap the work
+        const size_t pstride = (size_t)3 * S.nw * S.Qp;       // one (angle, point) of ptab
+        const float *pbase = TAB ? ptab + (size_t)a * nsc * pstride + i : nullptr;
+        int2 en = r.slist[lc0];
+        ScatA spn{};
+        float gqn = 0.f;
+        float An[NW], sn[NW], Fn[NW];
+        if (TAB) {
+            const float *tp = pbase + (size_t)en.x * pstride;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+                An[w] = tp[(size_t)(3 * w) * S.Qp];
+                sn[w] = tp[(size_t)(3 * w + 1) * S.Qp];
+                Fn[w] = tp[(size_t)(3 * w + 2) * S.Qp];
+            }
+        } else {
+            spn = sa[en.x];
+            gqn = g_qs[(size_t)en.y * S.Qp + i];
+        }
         for (int kk = 0; kk < kn; ++kk) {
-            const ScatA sp = sa[r.slist[lc0 + kk]];
-            const float gqs = g_qs[(size_t)sp.sidx * S.Qp + i];
-            float Aw[NW], sw[NW], Fw[NW], Ep[NW];
-            scatter_params<NW, true>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw, sw,
-                                     Fw, Ep);
+            float Aw[NW], sw[NW], Fw[NW];
+            if (TAB) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    Aw[w] = An[w];
+                    sw[w] = sn[w];
+                    Fw[w] = Fn[w];
+                }
+                if (kk + 1 < kn) {
+                    en = r.slist[lc0 + kk + 1];
+                    const float *tp = pbase + (size_t)en.x * pstride;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+                        An[w] = tp[(size_t)(3 * w) * S.Qp];
+                        sn[w] = tp[(size_t)(3 * w + 1) * S.Qp];
+                        Fn[w] = tp[(size_t)(3 * w + 2) * S.Qp];
+                    }
+                }
+            } else {
+                const ScatA sp = spn;
+                const float gqs = gqn;
+                if (kk + 1 < kn) {
+                    en = r.slist[lc0 + kk + 1];
+                    spn = sa[en.x];
+                    gqn = g_qs[(size_t)en.y * S.Qp + i];
+                }
+                float Ep[NW];
+                scatter_params<NW, true>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw,
+                                         sw, Fw, Ep);
+            }
 #pragma unroll
             for (int j = 0; j < JT; ++j) {
                 // factor bits in a scalar register: a scalar compare decides the branch
@@ -391,19 +439,60 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     }
 }
 
-template <int JT>
+template <int JT, bool TAB>
 static hipError_t launch_row_jt(const DevSys &S, const RowArgs &r, hipStream_t st)
 {
     // one workgroup per (pixel block, tile), remapped per XCD inside the kernel
     const long W = (long)(S.Qp / kWave) * r.ntiles;
     dim3 grid((unsigned)((W + 7) / 8 * 8));
     switch (S.nw) {
-    case 1: hipLaunchKernelGGL((k_row<JT, 1>), grid, dim3(kWave), 0, st, S, r); break;
-    case 2: hipLaunchKernelGGL((k_row<JT, 2>), grid, dim3(kWave), 0, st, S, r); break;
-    case 3: hipLaunchKernelGGL((k_row<JT, 3>), grid, dim3(kWave), 0, st, S, r); break;
-    case 4: hipLaunchKernelGGL((k_row<JT, 4>), grid, dim3(kWave), 0, st, S, r); break;
+    case 1: hipLaunchKernelGGL((k_row<JT, 1, TAB>), grid, dim3(kWave), 0, st, S, r); break;
+    case 2: hipLaunchKernelGGL((k_row<JT, 2, TAB>), grid, dim3(kWave), 0, st, S, r); break;
+    case 3: hipLaunchKernelGGL((k_row<JT, 3, TAB>), grid, dim3(kWave), 0, st, S, r); break;
+    case 4: hipLaunchKernelGGL((k_row<JT, 4, TAB>), grid, dim3(kWave), 0, st, S, r); break;
     default:
-        hipLaunchKernelGGL((k_row<JT, LMMEW_MAX_LINES>), grid, dim3(kWave), 0, st, S, r);
+        hipLaunchKernelGGL((k_row<JT, LMMEW_MAX_LINES, TAB>), grid, dim3(kWave), 0, st, S, r);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// the path-parameter table: one workgroup per (64 pixels, scatter point, angle)
+template <int NW>
+__global__ __launch_bounds__(64) void k_path_table(const DevSys S, const float2 *pix_xy,
+                                                   const float2 *dirs, const float *g_qs,
+                                                   const ScatA *sa, float *ptab)
+{
+    const int i = blockIdx.x * kWave + threadIdx.x;
+    const int k = blockIdx.y, a = blockIdx.z;
+    const ScatA sp = sa[(size_t)a * S.nsc + k];
+    const float2 xy = pix_xy[i], dir = dirs[a];
+    const float gqs = g_qs[(size_t)sp.sidx * S.Qp + i];
+    float Aw[NW], sw[NW], Fw[NW], Ep[NW];
+    scatter_params<NW, true>(S, sp.x - xy.x, sp.y - xy.y, dir.x, dir.y, sp.lc, gqs, sp.gsa, Aw,
+                             sw, Fw, Ep);
+    float *tp = ptab + ((size_t)a * S.nsc + k) * 3 * S.nw * S.Qp + i;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+        tp[(size_t)(3 * w) * S.Qp] = Aw[w];
+        tp[(size_t)(3 * w + 1) * S.Qp] = sw[w];
+        tp[(size_t)(3 * w + 2) * S.Qp] = Fw[w];
+    }
+}
+
+hipError_t launch_path_table(const DevSys &S, const float2 *pix_xy, const float2 *dirs,
+                             const float *g_qs, const ScatA *sa, float *ptab, hipStream_t st)
+{
+    if (S.nsc == 0) return hipSuccess;
+    const dim3 grid(S.Qp / kWave, S.nsc, S.na);
+    switch (S.nw) {
+    case 1: hipLaunchKernelGGL((k_path_table<1>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
+    case 2: hipLaunchKernelGGL((k_path_table<2>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
+    case 3: hipLaunchKernelGGL((k_path_table<3>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
+    case 4: hipLaunchKernelGGL((k_path_table<4>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
+    default:
+        hipLaunchKernelGGL((k_path_table<LMMEW_MAX_LINES>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab);
         break;
     }
     return hipGetLastError();
@@ -412,10 +501,12 @@ static hipError_t launch_row_jt(const DevSys &S, const RowArgs &r, hipStream_t s
 hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st)
 {
     if (r.ntiles == 0) return hipSuccess;
+    // the table is used when the tiles' cases all have one (see the plan)
+    const bool tab = r.ptab != nullptr;
     switch (event_tile) {
-    case 16: return launch_row_jt<16>(S, r, st);
-    case 32: return launch_row_jt<32>(S, r, st);
-    default: return launch_row_jt<64>(S, r, st);
+    case 16: return tab ? launch_row_jt<16, true>(S, r, st) : launch_row_jt<16, false>(S, r, st);
+    case 32: return tab ? launch_row_jt<32, true>(S, r, st) : launch_row_jt<32, false>(S, r, st);
+    default: return tab ? launch_row_jt<64, true>(S, r, st) : launch_row_jt<64, false>(S, r, st);
     }
 }
 

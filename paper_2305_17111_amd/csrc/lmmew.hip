@@ -38,6 +38,7 @@ struct lmmew_ctx {
     ScatA *d_sa = nullptr;
     float *d_Sqa = nullptr;
     hipStream_t cap_stream = nullptr; // private stream that graph captures are recorded on
+    float *d_ptab = nullptr;          // scatter-path parameter table (lmmew_path_table) or NULL
     lmmew_mlp *mlp = nullptr;         // scatter surrogate used by OSEM (NULL: exact model)
     int model_gen = 0;                // bumped whenever the scatter model changes
 };
@@ -62,6 +63,7 @@ struct lmmew_mlp {
 struct lmmew_plan {
     lmmew_ctx *ctx = nullptr;
     std::vector<lmmew_ctx *> maps;    // [ncases] context (attenuation map) of each case, or empty
+    std::vector<MapTab> maptab;       // what d_maps holds
     int nsub = 1, ncases = 1, JT = 64;
     int64_t n = 0;
     std::vector<int> bin, ang, cas;   // sorted rows
@@ -76,7 +78,7 @@ struct lmmew_plan {
     std::vector<Sub> subs;
     std::vector<int> case_chunk;      // [nsub][ncases+1], chunk index relative to the subset
     std::vector<Tile> tiles;
-    std::vector<int> slist;           // scatter list entries of all tiles
+    std::vector<int2> slist;          // scatter list entries of all tiles: (point, table row)
     std::vector<Chunk> chunks;
     int max_rows = 0, max_chunks = 0;
     double terms = 0, full_terms = 0;
@@ -85,7 +87,7 @@ struct lmmew_plan {
     float *d_E = nullptr;
     int64_t *d_perm = nullptr;
     Tile *d_tiles = nullptr;
-    int *d_slist = nullptr;
+    int2 *d_slist = nullptr;
     MapTab *d_maps = nullptr;
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
@@ -99,7 +101,7 @@ struct lmmew_plan {
     // captured OSEM sequence (lmmew_osem_graph) and the arguments it was captured with
     hipGraphExec_t gexec = nullptr;
     int g_iters = -1, g_jt = 0, g_gen = -1;
-    const float *g_cache = nullptr;
+    const float *g_cache = nullptr, *g_tab = nullptr;
     const float *g_sens = nullptr;
     float *g_lambda = nullptr;
     // optional timing of the per-event kernel launches (HIP events on the caller's stream)
@@ -210,7 +212,7 @@ void free_ctx(lmmew_ctx *c)
     c->cap_stream = nullptr;
     dfree(c->d_pix); dfree(c->d_pixd); dfree(c->d_pixq); dfree(c->d_dirs); dfree(c->d_dirsd);
     dfree(c->d_scd); dfree(c->d_mu); dfree(c->d_gqa); dfree(c->d_gqs); dfree(c->d_sa);
-    dfree(c->d_Sqa);
+    dfree(c->d_Sqa); dfree(c->d_ptab);
 }
 
 void free_plan(lmmew_plan *p)
@@ -286,7 +288,7 @@ void build_tiles(lmmew_plan *p)
                 // the tile's bins are sorted: is one of them inside [lo, hi]?
                 const int *first = p->bin.data() + r, *lastp = p->bin.data() + e;
                 const int *it = std::lower_bound(first, lastp, lo);
-                if (it != lastp && *it <= hi) p->slist.push_back(k);
+                if (it != lastp && *it <= hi) p->slist.push_back(make_int2(k, c->sa[ak].sidx));
             }
             const int k1 = (int)p->slist.size();
             Tile t{};
@@ -348,7 +350,7 @@ int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
         HIPCHK(ctx, hipMemcpyAsync(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile),
                                    hipMemcpyHostToDevice, st));
     if (!p->slist.empty())
-        HIPCHK(ctx, hipMemcpyAsync(p->d_slist, p->slist.data(), p->slist.size() * sizeof(int),
+        HIPCHK(ctx, hipMemcpyAsync(p->d_slist, p->slist.data(), p->slist.size() * sizeof(int2),
                                    hipMemcpyHostToDevice, st));
     if (!p->chunks.empty())
         HIPCHK(ctx, hipMemcpyAsync(p->d_chunks, p->chunks.data(),
@@ -367,6 +369,8 @@ bool same_system(const lmmew_ctx *a, const lmmew_ctx *b)
     x.nsc = y.nsc = 0;
     return std::memcmp(&x, &y, sizeof(DevSys)) == 0 && a->pixq == b->pixq;
 }
+
+int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st);
 
 // maps: NULL, or the context of each of the n_cases cases (maps[0] == ctx)
 int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets, int n_cases,
@@ -513,17 +517,9 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
                             st));
     }
     if (!p->maps.empty()) {
-        std::vector<MapTab> mt(n_cases);
-        for (int c = 0; c < n_cases; ++c) {
-            const lmmew_ctx *m = p->maps[c];
-            mt[c].g_qa = m->d_gqa;
-            mt[c].g_qs = m->d_gqs;
-            mt[c].sa = m->d_sa;
-            mt[c].nsc = m->S.nsc;
-        }
         PCHK(dalloc(&p->d_maps, n_cases));
-        PCHK(hipMemcpyAsync(p->d_maps, mt.data(), n_cases * sizeof(MapTab), hipMemcpyHostToDevice,
-                            st));
+        const int rm = sync_maps(ctx, p, st);
+        if (rm != LMMEW_OK) return fin(rm);
     }
     const int rc = upload_tiles(ctx, p, st);
     if (rc != LMMEW_OK) return fin(rc);
@@ -549,6 +545,42 @@ hipError_t prof_mark(lmmew_ctx *, lmmew_plan *p, int kind, hipStream_t st)
 // a_jq of subset s into the plan's scratch rows.  part: 0 the context's model
 // (exact, or unscattered + surrogate when a surrogate is set), 1 exact
 // scattered paths only, 2 unscattered only, 3 exact (ignoring the surrogate).
+// Uploads the per-case tables of a plan over several maps when they changed
+// (a context's path-parameter table may be built or freed after the plan).
+int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
+{
+    if (p->maps.empty()) return LMMEW_OK;
+    std::vector<MapTab> mt(p->ncases);
+    for (int c = 0; c < p->ncases; ++c) {
+        const lmmew_ctx *m = p->maps[c];
+        mt[c].g_qa = m->d_gqa;
+        mt[c].g_qs = m->d_gqs;
+        mt[c].sa = m->d_sa;
+        mt[c].ptab = m->d_ptab;
+        mt[c].nsc = m->S.nsc;
+    }
+    if (mt.size() == p->maptab.size() &&
+        std::memcmp(mt.data(), p->maptab.data(), mt.size() * sizeof(MapTab)) == 0)
+        return LMMEW_OK;
+    HIPCHK(ctx, hipMemcpyAsync(p->d_maps, mt.data(), mt.size() * sizeof(MapTab),
+                               hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    p->maptab = mt;
+    return LMMEW_OK;
+}
+
+// The path-parameter table the per-event kernel may use for this plan: the
+// context's, or for a plan over several maps a non-NULL marker when every
+// case's map has one (the kernel then reads each case's from the plan's
+// table pointers); NULL to evaluate the parameters in the kernel.
+const float *plan_ptab(const lmmew_ctx *ctx, const lmmew_plan *p)
+{
+    if (p->maps.empty()) return ctx->d_ptab;
+    for (const MapTab &m : p->maptab)
+        if (!m.ptab) return nullptr;
+    return p->maptab.empty() ? nullptr : p->maptab[0].ptab;
+}
+
 // Rows a_jq of subset s: the cached rows, or the per-subset scratch.
 float *rows_of(lmmew_plan *p, int s)
 {
@@ -568,6 +600,7 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     r.g_qs = ctx->d_gqs;
     r.sa = ctx->d_sa;
     r.maps = p->d_maps;
+    r.ptab = plan_ptab(ctx, p);
     r.tiles = p->d_tiles + sub.tile0;
     r.slist = p->d_slist;
     r.ntiles = sub.ntiles;
@@ -891,6 +924,45 @@ int lmmew_destroy(lmmew_ctx *ctx)
 
 int64_t lmmew_support_size(const lmmew_ctx *ctx) { return ctx ? (int64_t)ctx->S.Qm : -1; }
 
+int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!enable) {
+        if (ctx->d_ptab) {
+            HIPCHK(ctx, hipDeviceSynchronize());
+            dfree(ctx->d_ptab);
+            ctx->d_ptab = nullptr;
+        }
+        return LMMEW_OK;
+    }
+    if (ctx->d_ptab || ctx->S.nsc == 0) return LMMEW_OK;
+    const size_t n = (size_t)ctx->S.na * ctx->S.nsc * 3 * ctx->S.nw * ctx->S.Qp;
+    size_t fr = 0, tot = 0;
+    HIPCHK(ctx, hipMemGetInfo(&fr, &tot));
+    if (n * sizeof(float) + (size_t(1) << 30) > fr) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "the path-parameter table needs %.1f GB of device memory",
+                 n * sizeof(float) / 1e9);
+        return fail(ctx, LMMEW_ENOMEM, buf);
+    }
+    float *t = nullptr;
+    if (dalloc(&t, n) != hipSuccess) return fail(ctx, LMMEW_ENOMEM, "path-parameter table");
+    hipError_t e = launch_path_table(ctx->S, ctx->d_pix, ctx->d_dirs, ctx->d_gqs, ctx->d_sa, t, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        dfree(t);
+        return hipfail(ctx, e, "path-parameter table");
+    }
+    ctx->d_ptab = t;
+    return LMMEW_OK;
+}
+
+int64_t lmmew_path_table_bytes(const lmmew_ctx *ctx)
+{
+    if (!ctx) return -1;
+    return (int64_t)ctx->S.na * ctx->S.nsc * 3 * ctx->S.nw * ctx->S.Qp * (int64_t)sizeof(float);
+}
+
 int lmmew_sensitivity(lmmew_ctx *ctx, int n_subsets, float *sens, hipStream_t st)
 {
     if (!ctx) return LMMEW_EINVAL;
@@ -1006,8 +1078,13 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
     if (!sens || !lambda) return fail(ctx, LMMEW_EINVAL, "NULL image or sensitivity");
     if (n_iters < 0) return fail(ctx, LMMEW_EINVAL, "n_iters < 0");
     if (n_iters == 0) return LMMEW_OK;
+    {
+        const int rm = sync_maps(ctx, p, st);
+        if (rm != LMMEW_OK) return rm;
+    }
     if (!p->gexec || p->g_iters != n_iters || p->g_sens != sens || p->g_lambda != lambda ||
-        p->g_jt != p->JT || p->g_gen != ctx->model_gen || p->g_cache != p->d_Acache) {
+        p->g_jt != p->JT || p->g_gen != ctx->model_gen || p->g_cache != p->d_Acache ||
+        p->g_tab != plan_ptab(ctx, p)) {
         if (p->gexec) {
             HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
             p->gexec = nullptr;
@@ -1042,6 +1119,7 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
         p->g_jt = p->JT;
         p->g_gen = ctx->model_gen;
         p->g_cache = p->d_Acache;
+        p->g_tab = plan_ptab(ctx, p);
     }
     HIPCHK(ctx, hipGraphLaunch(p->gexec, st));
     return LMMEW_OK;
@@ -1082,6 +1160,10 @@ int lmmew_plan_cache_rows(lmmew_ctx *ctx, lmmew_plan *p, int enable, hipStream_t
         p->cache_gen = -1;
     }
     if (!enable || p->n == 0) return LMMEW_OK;
+    {
+        const int rm = sync_maps(ctx, p, st);
+        if (rm != LMMEW_OK) return rm;
+    }
     const size_t bytes = (size_t)p->n * ctx->S.Qp * sizeof(float);
     size_t fr = 0, tot = 0;
     HIPCHK(ctx, hipMemGetInfo(&fr, &tot));
@@ -1152,6 +1234,10 @@ TuneKey tune_key(const lmmew_ctx *ctx, const lmmew_plan *p)
 int lmmew_autotune(lmmew_ctx *ctx, lmmew_plan *p, int use_cache, hipStream_t st, int *chosen)
 {
     if (!ctx || !p || p->ctx != ctx) return LMMEW_EINVAL;
+    {
+        const int rm = sync_maps(ctx, p, st);
+        if (rm != LMMEW_OK) return rm;
+    }
     const TuneKey key = tune_key(ctx, p);
     if (use_cache) {
         for (const auto &kv : g_tune_cache)
@@ -1330,6 +1416,8 @@ int lmmew_osem_iter(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *sen
     if (!p || p->ctx != ctx) return fail(ctx, LMMEW_EINVAL, "plan does not belong to context");
     if (!sens || !lambda) return fail(ctx, LMMEW_EINVAL, "NULL image or sensitivity");
     if (n_iters < 0) return fail(ctx, LMMEW_EINVAL, "n_iters < 0");
+    const int rm = sync_maps(ctx, p, st);
+    if (rm != LMMEW_OK) return rm;
     return osem_run(ctx, p, 0, n_iters * p->nsub, sens, lambda, stats, st);
 }
 
@@ -1340,6 +1428,8 @@ int lmmew_osem_subiter(lmmew_ctx *ctx, lmmew_plan *p, int subset, const float *s
     if (!p || p->ctx != ctx) return fail(ctx, LMMEW_EINVAL, "plan does not belong to context");
     if (!sens || !lambda) return fail(ctx, LMMEW_EINVAL, "NULL image or sensitivity");
     if (subset < 0 || subset >= p->nsub) return fail(ctx, LMMEW_EINVAL, "subset out of range");
+    const int rm = sync_maps(ctx, p, st);
+    if (rm != LMMEW_OK) return rm;
     return osem_run(ctx, p, subset, 1, sens, lambda, stats, st);
 }
 
