@@ -93,6 +93,7 @@ struct MapTab {
     const float *g_qs;       // [nsc][Qp]
     const ScatA *sa;         // [na][nsc]
     const float *ptab;       // path-parameter table (see RowArgs) or NULL
+    const float *resp;       // collimator-response factors (see RowArgs)
     int nsc, pad;
 };
 
@@ -105,6 +106,8 @@ struct RowArgs {
     const MapTab *maps;      // [ncases] tables per case, or NULL (g_qa, g_qs, sa, S.nsc)
     const float *ptab;       // scatter-path parameters [na][nsc][3 nw][Qp] (per line: log2
                              // weight, s_w, F_w), or NULL to evaluate them in the kernel
+    const float *resp;       // [na][nsc][nb] collimator-response factor of scatter point k
+                             // (angle's sorted order) for bin b, 0 beyond 7 sigma
     const Tile *tiles;
     const int2 *slist;       // scatter list entries of the tiles: (point in the angle's
                              // sorted list, row of the point in the g_qs table)
@@ -115,6 +118,8 @@ struct RowArgs {
     int mode;                // 0: all paths, 1: scattered paths only, 2: unscattered only
 };
 hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st);
+// collimator-response factors of every (angle, scatter point, bin)
+hipError_t launch_resp_table(const DevSys &S, const ScatA *sa, float *resp, hipStream_t st);
 // scatter-path parameters of every (angle, scatter point, support pixel)
 hipError_t launch_path_table(const DevSys &S, const float2 *pix_xy, const float2 *dirs,
                              const float *g_qs, const ScatA *sa, float *ptab, hipStream_t st);

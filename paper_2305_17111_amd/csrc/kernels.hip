@@ -297,7 +297,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const int i = bx * kWave + lane;
     const int a = T.angle;
     // attenuation tables of the tile's case
-    const float *g_qa = r.g_qa, *g_qs = r.g_qs, *ptab = r.ptab;
+    const float *g_qa = r.g_qa, *g_qs = r.g_qs, *ptab = r.ptab, *resp = r.resp;
     const ScatA *sab = r.sa;
     int nsc = S.nsc;
     if (r.maps) {
@@ -306,6 +306,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         g_qs = m.g_qs;
         sab = m.sa;
         ptab = m.ptab;
+        resp = m.resp;
         nsc = m.nsc;
     }
     const float2 dir = r.dirs[a];
@@ -363,25 +364,17 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const int kl = lane % KC, jg = lane / KC;
     const int kend = (r.mode == 2) ? T.k0 : T.k1;     // unscattered only: no scatter loop
     for (int lc0 = T.k0; lc0 < kend; lc0 += KC) {
-        // response factors of (listed scatter point lc0+kl, events jg*TJ .. jg*TJ+TJ-1)
+        // response factors of (listed scatter point lc0+kl, events jg*TJ .. jg*TJ+TJ-1),
+        // read from the map's [angle][point][bin] table
         float pv[TJ];
         {
             const int l = lc0 + kl;
-            float u = 0.f, isg = 0.f;
-            if (l < T.k1) {
-                const ScatA &sp = sa[r.slist[l].x];
-                u = sp.u;
-                isg = sp.isig;
-            }
+            const float *rrow =
+                resp + ((size_t)a * nsc + (l < T.k1 ? r.slist[l].x : 0)) * S.nb;
 #pragma unroll
             for (int t = 0; t < TJ; ++t) {
                 const int j = jg * TJ + t;
-                float ps = 0.f;
-                if (l < T.k1 && j < T.cnt) {
-                    const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
-                    ps = psf_cut((lo + S.db - u) * isg, (lo - u) * isg);
-                }
-                pv[t] = ps;
+                pv[t] = (l < T.k1 && j < T.cnt) ? rrow[r.ev_bin[T.e0 + min(j, last)]] : 0.f;
             }
         }
         const int kn = min(KC, T.k1 - lc0);
@@ -482,6 +475,28 @@ static hipError_t launch_row_jt(const DevSys &S, const RowArgs &r, hipStream_t s
         hipLaunchKernelGGL((k_row<JT, LMMEW_MAX_LINES, TAB>), grid, dim3(kWave), 0, st, S, r);
         break;
     }
+    return hipGetLastError();
+}
+
+// the response-factor table: one thread per (angle, scatter point, bin); the
+// same expression as the per-event kernel's unscattered term
+__global__ __launch_bounds__(256) void k_resp_table(const DevSys S, const ScatA *sa, float *resp)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)S.na * S.nsc * S.nb) return;
+    const int b = (int)(t % S.nb);
+    const long ak = t / S.nb;                       // a * nsc + k
+    const ScatA sp = sa[ak];
+    const float lo = -S.R + (float)b * S.db;
+    resp[t] = psf_cut((lo + S.db - sp.u) * sp.isig, (lo - sp.u) * sp.isig);
+}
+
+hipError_t launch_resp_table(const DevSys &S, const ScatA *sa, float *resp, hipStream_t st)
+{
+    const long n = (long)S.na * S.nsc * S.nb;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resp_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S, sa,
+                       resp);
     return hipGetLastError();
 }
 

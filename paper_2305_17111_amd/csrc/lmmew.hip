@@ -39,6 +39,7 @@ struct lmmew_ctx {
     float *d_Sqa = nullptr;
     hipStream_t cap_stream = nullptr; // private stream that graph captures are recorded on
     float *d_ptab = nullptr;          // scatter-path parameter table (lmmew_path_table) or NULL
+    float *d_resp = nullptr;          // [na][nsc][nb] collimator-response factors
     lmmew_mlp *mlp = nullptr;         // scatter surrogate used by OSEM (NULL: exact model)
     int model_gen = 0;                // bumped whenever the scatter model changes
 };
@@ -212,7 +213,7 @@ void free_ctx(lmmew_ctx *c)
     c->cap_stream = nullptr;
     dfree(c->d_pix); dfree(c->d_pixd); dfree(c->d_pixq); dfree(c->d_dirs); dfree(c->d_dirsd);
     dfree(c->d_scd); dfree(c->d_mu); dfree(c->d_gqa); dfree(c->d_gqs); dfree(c->d_sa);
-    dfree(c->d_Sqa); dfree(c->d_ptab);
+    dfree(c->d_Sqa); dfree(c->d_ptab); dfree(c->d_resp);
 }
 
 void free_plan(lmmew_plan *p)
@@ -557,6 +558,7 @@ int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
         mt[c].g_qs = m->d_gqs;
         mt[c].sa = m->d_sa;
         mt[c].ptab = m->d_ptab;
+        mt[c].resp = m->d_resp;
         mt[c].nsc = m->S.nsc;
     }
     if (mt.size() == p->maptab.size() &&
@@ -599,6 +601,7 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     r.g_qa = ctx->d_gqa;
     r.g_qs = ctx->d_gqs;
     r.sa = ctx->d_sa;
+    r.resp = ctx->d_resp;
     r.maps = p->d_maps;
     r.ptab = plan_ptab(ctx, p);
     r.tiles = p->d_tiles + sub.tile0;
@@ -894,6 +897,7 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     CCHK(dalloc(&ctx->d_gqa, (size_t)na * Qp));
     CCHK(dalloc(&ctx->d_gqs, (size_t)std::max(nsc, 1) * Qp));
     CCHK(dalloc(&ctx->d_sa, (size_t)na * std::max(nsc, 1)));
+    CCHK(dalloc(&ctx->d_resp, (size_t)na * std::max(nsc, 1) * s.n_bins));
     CCHK(hipMemcpyAsync(ctx->d_pix, pix_f.data(), Qp * sizeof(float2), hipMemcpyHostToDevice, st));
     CCHK(hipMemcpyAsync(ctx->d_pixd, pix_d.data(), Qp * sizeof(double2), hipMemcpyHostToDevice, st));
     CCHK(hipMemcpyAsync(ctx->d_pixq, ctx->pixq.data(), Qp * sizeof(int), hipMemcpyHostToDevice, st));
@@ -907,6 +911,7 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     CCHK(hipMemcpyAsync(ctx->d_mu, mu.data(), Q * sizeof(double), hipMemcpyHostToDevice, st));
     CCHK(launch_tables_d(S, ctx->d_mu, ctx->d_pixd, ctx->d_dirsd, ctx->d_scd, ctx->d_gqa,
                          ctx->d_gqs, ctx->d_sa, pix, R, st));
+    CCHK(launch_resp_table(S, ctx->d_sa, ctx->d_resp, st));
     CCHK(hipStreamSynchronize(st));
 #undef CCHK
     *out = ctx;
