@@ -104,7 +104,7 @@ struct RowArgs {
     const float *g_qs;
     const ScatA *sa;
     const MapTab *maps;      // [ncases] tables per case, or NULL (g_qa, g_qs, sa, S.nsc)
-    const float *ptab;       // scatter-path parameters [na][nsc][3 nw][Qp] (per line: log2
+    const float *ptab;       // scatter-path parameters [na][nsc][Qp][3 nw] (per line: log2
                              // weight, s_w, F_w), or NULL to evaluate them in the kernel
     const float *resp;       // [na][nsc][nb] collimator-response factor of scatter point k
                              // (angle's sorted order) for bin b, 0 beyond 7 sigma

@@ -380,8 +380,10 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         const int kn = min(KC, T.k1 - lc0);
         // the next listed point's data is loaded one iteration ahead, so the
         // dependent loads (list entry, point, table values) overlap the work
-        const size_t pstride = (size_t)3 * S.nw * S.Qp;       // one (angle, point) of ptab
-        const float *pbase = TAB ? ptab + (size_t)a * nsc * pstride + i : nullptr;
+        // ptab: [angle][point][pixel][3 nw] -- a lane's 3 nw values are contiguous
+        const int pw = 3 * S.nw;
+        const float *pbase = TAB ? ptab + (size_t)a * nsc * S.Qp * pw + (size_t)i * pw : nullptr;
+        const size_t pstride = (size_t)S.Qp * pw;                  // one point of the angle
         int2 en = r.slist[lc0];
         ScatA spn{};
         float gqn = 0.f;
@@ -391,9 +393,9 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                An[w] = tp[(size_t)(3 * w) * S.Qp];
-                sn[w] = tp[(size_t)(3 * w + 1) * S.Qp];
-                Fn[w] = tp[(size_t)(3 * w + 2) * S.Qp];
+                An[w] = tp[3 * w];
+                sn[w] = tp[3 * w + 1];
+                Fn[w] = tp[3 * w + 2];
             }
         } else {
             spn = sa[en.x];
@@ -414,9 +416,9 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
                     for (int w = 0; w < NW; ++w) {
                         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                        An[w] = tp[(size_t)(3 * w) * S.Qp];
-                        sn[w] = tp[(size_t)(3 * w + 1) * S.Qp];
-                        Fn[w] = tp[(size_t)(3 * w + 2) * S.Qp];
+                        An[w] = tp[3 * w];
+                        sn[w] = tp[3 * w + 1];
+                        Fn[w] = tp[3 * w + 2];
                     }
                 }
             } else {
@@ -514,13 +516,13 @@ __global__ __launch_bounds__(64) void k_path_table(const DevSys S, const float2 
     float Aw[NW], sw[NW], Fw[NW], Ep[NW];
     scatter_params<NW, true>(S, sp.x - xy.x, sp.y - xy.y, dir.x, dir.y, sp.lc, gqs, sp.gsa, Aw,
                              sw, Fw, Ep);
-    float *tp = ptab + ((size_t)a * S.nsc + k) * 3 * S.nw * S.Qp + i;
+    float *tp = ptab + (((size_t)a * S.nsc + k) * S.Qp + i) * 3 * S.nw;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-        tp[(size_t)(3 * w) * S.Qp] = Aw[w];
-        tp[(size_t)(3 * w + 1) * S.Qp] = sw[w];
-        tp[(size_t)(3 * w + 2) * S.Qp] = Fw[w];
+        tp[3 * w] = Aw[w];
+        tp[3 * w + 1] = sw[w];
+        tp[3 * w + 2] = Fw[w];
     }
 }
 
