@@ -25,6 +25,11 @@ namespace lmmew {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef __fp16 f2p __attribute__((ext_vector_type(2)));
+
+extern "C" __device__ _Float16 __ocml_exp2_f16(_Float16);
 
 constexpr int H = kMlpHidden;
 
@@ -338,14 +343,42 @@ __device__ __forceinline__ int frag_index(int ib, int c, int g, int r)
     return ((ib * 4 + c) * 4 + g) * 16 + r;
 }
 
-// A fragment (ib, c, g, r) of W^T from the transposed bf16 copy [out][kMlpTStride]
-__device__ __forceinline__ uint4 load_frag(const unsigned short *Wt, int f)
+// A fragment (ib, c, g, r) of W^T in FP16 (round to nearest) from the FP32
+// master W[in][out] at P + off: output unit 16 ib + r, input units
+// 32c + 4g + {0..3} (items 0..3) and 32c + 16 + 4g + {0..3} (items 4..7)
+__device__ __forceinline__ v8h load_frag_h(const float *P, int off, int f)
 {
     const int r = f & 15, g = (f >> 4) & 3, c = (f >> 6) & 3, ib = f >> 8;
-    const unsigned short *row = Wt + (long)(16 * ib + r) * kMlpTStride + 32 * c + 4 * g;
-    const uint2 lo = *reinterpret_cast<const uint2 *>(row);        // 8-byte aligned
-    const uint2 hi = *reinterpret_cast<const uint2 *>(row + 16);
-    return make_uint4(lo.x, lo.y, hi.x, hi.y);
+    const float *W = P + off + 16 * ib + r;
+    v8h v;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = (_Float16)W[(32 * c + 16 * (t >> 2) + 4 * g + (t & 3)) * H];
+    return v;
+}
+
+// GELU of two values in packed FP16 (the same z * sigmoid form as gelu(),
+// with exp2 and reciprocal of the half-precision transcendental unit); the
+// limits are exact: 2^s = inf gives 0, 2^s = 0 gives z
+__device__ __forceinline__ h2 gelu_h2(h2 z)
+{
+    const h2 k1 = {(_Float16)kGeluK1, (_Float16)kGeluK1};
+    const h2 k2 = {(_Float16)kGeluK2, (_Float16)kGeluK2};
+    const h2 one = {(_Float16)1.f, (_Float16)1.f};
+    const h2 s = z * (k1 + k2 * (z * z));
+    h2 e;
+    e.x = __ocml_exp2_f16(s.x);
+    e.y = __ocml_exp2_f16(s.y);
+    const h2 d = one + e;
+    h2 rc;
+    rc.x = __builtin_amdgcn_rcph(d.x);
+    rc.y = __builtin_amdgcn_rcph(d.y);
+    return z * rc;
+}
+
+// two FP32 accumulators -> FP16 pair (round toward zero) -> GELU
+__device__ __forceinline__ h2 gelu_pair(float a, float b)
+{
+    return gelu_h2(__builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b)));
 }
 
 __device__ __forceinline__ unsigned pack2(unsigned short a, unsigned short b)
@@ -378,20 +411,26 @@ __device__ __forceinline__ uint4 load_frag1(const float *P, int f)
 
 __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowArgs a)
 {
-    __shared__ uint4 sW1[kFrag1];                // 8 KB
-    __shared__ uint4 sW2[kFrag];                 // 32 KB
-    __shared__ uint4 sW3[kFrag];                 // 32 KB
-    __shared__ float4 sB[3 * H / 4];             // b2, b3, w4
+    __shared__ uint4 sW1[kFrag1];                // 8 KB, bf16
+    __shared__ v8h sW2[kFrag];                   // 32 KB, fp16
+    __shared__ v8h sW3[kFrag];                   // 32 KB, fp16
+    __shared__ float4 sB[2 * H / 4];             // b2, b3
+    __shared__ h2 sW4[H / 2];                    // w4 in fp16 pairs
 
     for (int f = threadIdx.x; f < kFrag; f += 256) {
-        sW2[f] = load_frag(a.W2t, f);
-        sW3[f] = load_frag(a.W3t, f);
+        sW2[f] = load_frag_h(a.P, kOffW2, f);
+        sW3[f] = load_frag_h(a.P, kOffW3, f);
     }
     for (int f = threadIdx.x; f < kFrag1; f += 256) sW1[f] = load_frag1(a.P, f);
     for (int t = threadIdx.x; t < H / 4; t += 256) {
         sB[t] = reinterpret_cast<const float4 *>(a.P + kOffB2)[t];
         sB[H / 4 + t] = reinterpret_cast<const float4 *>(a.P + kOffB3)[t];
-        sB[2 * H / 4 + t] = reinterpret_cast<const float4 *>(a.P + kOffW4)[t];
+    }
+    for (int t = threadIdx.x; t < H / 2; t += 256) {
+        h2 w;
+        w.x = (_Float16)a.P[kOffW4 + 2 * t];
+        w.y = (_Float16)a.P[kOffW4 + 2 * t + 1];
+        sW4[t] = w;
     }
     const float b4 = a.P[kOffB4];
     __syncthreads();
@@ -411,9 +450,10 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
         int off = 0;
         asm volatile("" : "+v"(off));
         const float4 *bb = sB + off;
+        const h2 *w4 = sW4 + off;
         const v8bf *w1 = reinterpret_cast<const v8bf *>(sW1) + off;
-        const v8bf *w2 = reinterpret_cast<const v8bf *>(sW2) + off;
-        const v8bf *w3 = reinterpret_cast<const v8bf *>(sW3) + off;
+        const v8h *w2 = sW2 + off;
+        const v8h *w3 = sW3 + off;
 
         const int bin = a.ev_bin[e];
         const float2 dir = a.dirs[a.ev_ang[e]];
@@ -436,8 +476,9 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             x1[p][6] = one;
             x1[p][7] = one;
         }
-        // layer 1: output block ib = units 16 ib + 4g + t -> item 4 (ib & 1) + t of chunk ib / 2
-        v8bf h1[kRowGroups][4];
+        // layer 1 (bf16 hi/lo MFMA): output block ib = units 16 ib + 4g + t ->
+        // item 4 (ib & 1) + t of chunk ib / 2, GELU in packed FP16
+        v8h h1[kRowGroups][4];
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib) {
             const v8bf w = w1[(ib * 4 + g) * 16 + r];
@@ -445,12 +486,15 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             for (int p = 0; p < kRowGroups; ++p) {
                 const v4f acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     w, x1[p], v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) h1[p][ib >> 1][4 * (ib & 1) + t] = (__bf16)gelu(acc[t]);
+                const h2 lo = gelu_pair(acc[0], acc[1]), hi = gelu_pair(acc[2], acc[3]);
+                h1[p][ib >> 1][4 * (ib & 1) + 0] = lo.x;
+                h1[p][ib >> 1][4 * (ib & 1) + 1] = lo.y;
+                h1[p][ib >> 1][4 * (ib & 1) + 2] = hi.x;
+                h1[p][ib >> 1][4 * (ib & 1) + 3] = hi.y;
             }
         }
-        // layer 2
-        v8bf h2[kRowGroups][4];
+        // layer 2 (fp16 MFMA, fp32 accumulation from the bias)
+        v8h h2v[kRowGroups][4];
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib) {
             const float4 b = bb[(16 * ib + 4 * g) >> 2];
@@ -459,40 +503,44 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const v8bf w = w2[frag_index(ib, c, g, r)];
+                const v8h w = w2[frag_index(ib, c, g, r)];
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h1[p][c], acc[p], 0, 0, 0);
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, h1[p][c], acc[p], 0, 0, 0);
             }
 #pragma unroll
-            for (int p = 0; p < kRowGroups; ++p)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) h2[p][ib >> 1][4 * (ib & 1) + t] = (__bf16)gelu(acc[p][t]);
+            for (int p = 0; p < kRowGroups; ++p) {
+                const h2 lo = gelu_pair(acc[p][0], acc[p][1]), hi = gelu_pair(acc[p][2], acc[p][3]);
+                h2v[p][ib >> 1][4 * (ib & 1) + 0] = lo.x;
+                h2v[p][ib >> 1][4 * (ib & 1) + 1] = lo.y;
+                h2v[p][ib >> 1][4 * (ib & 1) + 2] = hi.x;
+                h2v[p][ib >> 1][4 * (ib & 1) + 3] = hi.y;
+            }
         }
-        // layer 3 and the output unit
+        // layer 3 and the output unit (FP16 pairs dotted with w4, FP32 sum)
         float part[kRowGroups];
 #pragma unroll
         for (int p = 0; p < kRowGroups; ++p) part[p] = 0.f;
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib) {
             const float4 b = bb[H / 4 + ((16 * ib + 4 * g) >> 2)];
-            const float4 w4 = bb[2 * H / 4 + ((16 * ib + 4 * g) >> 2)];
+            const f2p wa = __builtin_bit_cast(f2p, w4[(16 * ib + 4 * g) >> 1]);
+            const f2p wb = __builtin_bit_cast(f2p, w4[((16 * ib + 4 * g) >> 1) + 1]);
             v4f acc[kRowGroups];
 #pragma unroll
             for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const v8bf w = w3[frag_index(ib, c, g, r)];
+                const v8h w = w3[frag_index(ib, c, g, r)];
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h2[p][c], acc[p], 0, 0, 0);
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, h2v[p][c], acc[p], 0, 0, 0);
             }
 #pragma unroll
             for (int p = 0; p < kRowGroups; ++p) {
-                part[p] = fmaf(w4.x, gelu(acc[p][0]), part[p]);
-                part[p] = fmaf(w4.y, gelu(acc[p][1]), part[p]);
-                part[p] = fmaf(w4.z, gelu(acc[p][2]), part[p]);
-                part[p] = fmaf(w4.w, gelu(acc[p][3]), part[p]);
+                const h2 lo = gelu_pair(acc[p][0], acc[p][1]), hi = gelu_pair(acc[p][2], acc[p][3]);
+                part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, lo), wa, part[p], false);
+                part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, hi), wb, part[p], false);
             }
         }
 #pragma unroll
