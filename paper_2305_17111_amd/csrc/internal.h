@@ -30,6 +30,7 @@ constexpr int kOffB4 = kOffW4 + kMlpHidden;
 constexpr int kMlpParams = kOffB4 + 1;            // 34049
 constexpr int kMlpTStride = kMlpHidden + 4;       // padded row of the transposed bf16 weights
 constexpr float kMlpEc = 180.f, kMlpEs = 120.f;   // energy feature: (E - kMlpEc) / kMlpEs
+constexpr int kRedRows = 32;                      // rows per chunk of the bias-gradient column sums
 
 // Per-run constants passed by value to the kernels.
 struct DevSys {

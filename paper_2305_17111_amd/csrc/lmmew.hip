@@ -1485,7 +1485,7 @@ int mlp_workspace(lmmew_ctx *ctx, lmmew_mlp *m, int M)
     HIPCHK(ctx, dalloc(&m->dy, M));
     HIPCHK(ctx, dalloc(&m->sq, M));
     HIPCHK(ctx, dalloc(&m->idx, M));
-    HIPCHK(ctx, dalloc(&m->part, (size_t)((M + 255) / 256) * 8 * kMlpHidden));
+    HIPCHK(ctx, dalloc(&m->part, (size_t)((M + kRedRows - 1) / kRedRows) * 8 * kMlpHidden));
     HIPCHK(ctx, dalloc(&m->split, (size_t)64 * kMlpHidden * kMlpHidden));
     HIPCHK(ctx, dalloc(&m->dsum, 1));
     m->cap = M;

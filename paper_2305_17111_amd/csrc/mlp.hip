@@ -173,7 +173,6 @@ __global__ __launch_bounds__(256) void k_gelu_back(const float *dH, const float 
 // layer's gradients: slot 0 = sum_m a[m][u] (bias), slot 1 = sum_m a[m][u] s[m]
 // (s may be NULL), slots 2..7 = sum_m X[m][d] a[m][u] (d = 0..5, X may be NULL).
 // part[chunk][8][128]; reduced afterwards in chunk order (deterministic).
-constexpr int kRedRows = 256;
 
 __global__ __launch_bounds__(128) void k_colsum_part(const float *a, const float *s,
                                                      const float *X, int M, float *part)
@@ -194,15 +193,20 @@ __global__ __launch_bounds__(128) void k_colsum_part(const float *a, const float
     for (int k = 0; k < 8; ++k) part[((long)blockIdx.x * 8 + k) * H + u] = acc[k];
 }
 
-// out_slot[u] = sum over chunks of part[chunk][slot][u] for the requested slots
+// out_slot[u] = sum over chunks of part[chunk][slot][u] for the requested slots:
+// one wavefront per (slot, u); lane l sums chunks l, l + 64, ... and the lanes
+// are combined by a fixed butterfly (deterministic)
 __global__ __launch_bounds__(256) void k_colsum_final(const float *part, int nchunks, float *bias,
                                                       float *scaled, float *xw)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (t >= 8 * H) return;
     const int k = t / H, u = t % H;
     float acc = 0.f;
-    for (int c = 0; c < nchunks; ++c) acc += part[((long)c * 8 + k) * H + u];
+    for (int c = lane; c < nchunks; c += 64) acc += part[((long)c * 8 + k) * H + u];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane != 0) return;
     if (k == 0 && bias) bias[u] = acc;
     if (k == 1 && scaled) scaled[u] = acc;
     if (k >= 2 && xw) xw[(k - 2) * H + u] = acc;      // W1 layout [d][u]
@@ -587,7 +591,7 @@ static hipError_t mlp_colsums(const float *a, const float *s, const float *X, in
 {
     const int nc = (M + kRedRows - 1) / kRedRows;
     hipLaunchKernelGGL(k_colsum_part, dim3(nc), dim3(128), 0, st, a, s, X, M, part);
-    hipLaunchKernelGGL(k_colsum_final, dim3(8 * H / 256), dim3(256), 0, st, part, nc, bias,
+    hipLaunchKernelGGL(k_colsum_final, dim3(8 * H / 4), dim3(256), 0, st, part, nc, bias,
                        scaled, xw);
     return hipGetLastError();
 }
