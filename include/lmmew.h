@@ -322,9 +322,13 @@ int lmmew_rows(lmmew_ctx *ctx, const lmmew_events *ev, int part, float *rows, hi
  * projection)/R, pixel depth below the detector plane/R, pixel's lateral
  * projection/R, cos(angle), sin(angle), (E - 180 keV)/120 keV.
  * Architecture: 6 -> 128 -> 128 -> 128 -> 1, tanh-form GELU after each hidden
- * layer; the 128x128 layers run as BF16 MFMA with FP32 accumulation, the
- * first and last layers in FP32.  The output y is the shifted logarithm of
- * the density: density = max(exp(y + c0) - floor, 0).
+ * layer.  Training (lmmew_mlp_grad/_train/_fit): the 128x128 layers as BF16
+ * MFMA with FP32 accumulation, the first and last layers in FP32, FP32 master
+ * weights.  Inference inside OSEM: the first layer as BF16 MFMA with
+ * high/low splitting (about FP32 accuracy), the 128x128 layers as FP16 MFMA
+ * with FP32 accumulation and FP16 activations (its densities are closer to
+ * the FP64 network than lmmew_mlp_forward's BF16 ones).  The output y is the
+ * shifted logarithm of the density: density = max(exp(y + c0) - floor, 0).
  * Parameters (FP32 master copy, 34049 floats, in this order):
  *   W1[6][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] w4[128] b4[1],
  * W[i][o] mapping input unit i to output unit o.

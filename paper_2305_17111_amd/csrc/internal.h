@@ -28,7 +28,6 @@ constexpr int kOffB3 = kOffW3 + kMlpHidden * kMlpHidden;
 constexpr int kOffW4 = kOffB3 + kMlpHidden;
 constexpr int kOffB4 = kOffW4 + kMlpHidden;
 constexpr int kMlpParams = kOffB4 + 1;            // 34049
-constexpr int kMlpTStride = kMlpHidden + 4;       // padded row of the transposed bf16 weights
 constexpr float kMlpEc = 180.f, kMlpEs = 120.f;   // energy feature: (E - kMlpEc) / kMlpEs
 constexpr int kRedRows = 32;                      // rows per chunk of the bias-gradient column sums
 
@@ -211,7 +210,6 @@ struct MlpRowArgs {
     int rows;
     float *A;
     const float *P;                    // fp32 parameters
-    const unsigned short *W2t, *W3t;   // bf16 [out][kMlpTStride]
     float c0, floor_;
 };
 hipError_t mlp_gemm(const unsigned short *A, long sai, long sak, const unsigned short *B, long sbk,
@@ -223,7 +221,7 @@ hipError_t mlp_loss(const MlpWork &w, int M, double *out, hipStream_t st);
 hipError_t mlp_adam(float *P, const float *G, float *m1, float *m2, float lr, int step,
                     hipStream_t st);
 hipError_t mlp_refresh(const float *P, unsigned short *W2b, unsigned short *W3b,
-                       unsigned short *W2t, unsigned short *W3t, hipStream_t st);
+                       hipStream_t st);
 hipError_t mlp_labels(const DevSys &S, const float2 *pix_xy, const float2 *dirs, const int *ev_bin,
                       const int *ev_ang, const float *ev_E, const float *A, int rows, float *feats,
                       float *raw, hipStream_t st);

@@ -47,7 +47,7 @@ struct lmmew_ctx {
 struct lmmew_mlp {
     lmmew_ctx *ctx = nullptr;
     float *P = nullptr, *G = nullptr, *m1 = nullptr, *m2 = nullptr;   // [kMlpParams]
-    unsigned short *W2b = nullptr, *W3b = nullptr, *W2t = nullptr, *W3t = nullptr;
+    unsigned short *W2b = nullptr, *W3b = nullptr;   // bf16 copies [in][out] for training
     double c0 = 0.0, floor_ = 0.0;    // target = log(density + floor) - c0
     int step = 0;                     // Adam step count
     // training workspace for batches of up to cap samples
@@ -626,8 +626,6 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
         a.rows = sub.rows;
         a.A = out;
         a.P = m->P;
-        a.W2t = m->W2t;
-        a.W3t = m->W3t;
         a.c0 = (float)m->c0;
         a.floor_ = (float)m->floor_;
         const bool profm = p->prof && sub.rows > 0;
@@ -1458,7 +1456,7 @@ double unit_rand(uint64_t &x) { return (double)(splitmix64(x) >> 11) * (1.0 / 90
 void free_mlp(lmmew_mlp *m)
 {
     dfree(m->P); dfree(m->G); dfree(m->m1); dfree(m->m2);
-    dfree(m->W2b); dfree(m->W3b); dfree(m->W2t); dfree(m->W3t);
+    dfree(m->W2b); dfree(m->W3b);
     dfree(m->X); dfree(m->Z1); dfree(m->Z2); dfree(m->Z3); dfree(m->H3); dfree(m->dZ); dfree(m->dH);
     dfree(m->y); dfree(m->dy); dfree(m->sq); dfree(m->H1b); dfree(m->H2b); dfree(m->dZb);
     dfree(m->idx); dfree(m->dloss); dfree(m->part); dfree(m->split); dfree(m->dsum);
@@ -1555,8 +1553,6 @@ int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
     MCHK(dalloc(&m->m2, kMlpParams));
     MCHK(dalloc(&m->W2b, kMlpHidden * kMlpHidden));
     MCHK(dalloc(&m->W3b, kMlpHidden * kMlpHidden));
-    MCHK(dalloc(&m->W2t, kMlpHidden * kMlpTStride));
-    MCHK(dalloc(&m->W3t, kMlpHidden * kMlpTStride));
     MCHK(dalloc(&m->dloss, 1));
     // Glorot-uniform weights, zero biases, from a counter-based generator
     std::vector<float> P(kMlpParams, 0.f);
@@ -1572,9 +1568,7 @@ int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
     MCHK(hipMemcpy(m->P, P.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
     MCHK(hipMemset(m->m1, 0, sizeof(float) * kMlpParams));
     MCHK(hipMemset(m->m2, 0, sizeof(float) * kMlpParams));
-    MCHK(hipMemset(m->W2t, 0, sizeof(unsigned short) * kMlpHidden * kMlpTStride));
-    MCHK(hipMemset(m->W3t, 0, sizeof(unsigned short) * kMlpHidden * kMlpTStride));
-    MCHK(mlp_refresh(m->P, m->W2b, m->W3b, m->W2t, m->W3t, nullptr));
+    MCHK(mlp_refresh(m->P, m->W2b, m->W3b, nullptr));
     MCHK(hipDeviceSynchronize());
 #undef MCHK
     *out = m;
@@ -1612,7 +1606,7 @@ int lmmew_mlp_set_params(lmmew_mlp *m, const float *params, double c0, double fl
     HIPCHK(ctx, hipMemcpy(m->P, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemset(m->m1, 0, sizeof(float) * kMlpParams));
     HIPCHK(ctx, hipMemset(m->m2, 0, sizeof(float) * kMlpParams));
-    HIPCHK(ctx, mlp_refresh(m->P, m->W2b, m->W3b, m->W2t, m->W3t, nullptr));
+    HIPCHK(ctx, mlp_refresh(m->P, m->W2b, m->W3b, nullptr));
     HIPCHK(ctx, hipDeviceSynchronize());
     m->step = 0;
     m->c0 = c0;
@@ -1703,7 +1697,7 @@ int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const floa
             const double prog = (double)(ep * nb + b) / std::max<double>(1.0, (double)epochs * nb);
             lr = lr0 * (0.1 + 0.9 * 0.5 * (1.0 + std::cos(kPi * prog)));
             if (e == hipSuccess) e = mlp_adam(m->P, m->G, m->m1, m->m2, (float)lr, ++m->step, st);
-            if (e == hipSuccess) e = mlp_refresh(m->P, m->W2b, m->W3b, m->W2t, m->W3t, st);
+            if (e == hipSuccess) e = mlp_refresh(m->P, m->W2b, m->W3b, st);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(losses.data(), d_losses, sizeof(double) * nb, hipMemcpyDeviceToHost, st);

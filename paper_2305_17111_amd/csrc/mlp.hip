@@ -1,6 +1,9 @@
 // Scatter surrogate network on gfx950: 6 -> 128 -> 128 -> 128 -> 1 with the tanh
-// form of GELU; the two 128x128 layers run on BF16 MFMA (v_mfma_f32_16x16x16
-// bf16, FP32 accumulation), the first and last layers on FP32 VALU.
+// form of GELU.  Training: the two 128x128 layers run on BF16 MFMA
+// (v_mfma_f32_16x16x16 bf16, FP32 accumulation), the first and last layers on
+// FP32 VALU, Adam on the FP32 master copy.  Inference inside OSEM (k_mlp_rows):
+// every layer on 16x16x32 MFMA (first layer BF16 with high/low splitting,
+// hidden layers FP16), GELUs on packed FP16.
 //
 // Parameter vector (FP32 master copy, 34049 floats):
 //   W1[6][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] w4[128] b4[1]
@@ -10,8 +13,8 @@
 //   A[i][k]: i = r, k = 4g + t;  B[k][j]: k = 4g + t, j = r;  D[i][j]: i = 4g + t, j = r.
 // The D layout equals the B layout with k = i, so the output of one layer
 // computed as Z^T = W^T H^T is directly the B operand of the next.
-// The fused inference kernel uses v_mfma_f32_16x16x32_bf16 (8 items per lane
-// and operand, one contraction slot per (g, t) shared by A and B); it orders
+// The fused inference kernel uses the 16x16x32 MFMAs (8 items per lane and
+// operand, one contraction slot per (g, t) shared by A and B); it orders
 // the contraction index so that two consecutive D fragments form one B
 // fragment (see k_mlp_rows).
 #include <hip/hip_runtime.h>
@@ -252,20 +255,14 @@ __global__ __launch_bounds__(256) void k_adam(float *P, const float *G, float *m
     P[t] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
-// bf16 copies of W2, W3: row-major [in][out] (training GEMMs) and transposed
-// [out][in] with padded rows (inference A operands)
+// bf16 copies of W2, W3, row-major [in][out], for the training GEMMs
 __global__ __launch_bounds__(256) void k_refresh_bf16(const float *P, unsigned short *W2b,
-                                                      unsigned short *W3b, unsigned short *W2t,
-                                                      unsigned short *W3t)
+                                                      unsigned short *W3b)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= H * H) return;
-    const int i = t / H, o = t % H;
-    const unsigned short w2 = f2bf(P[kOffW2 + t]), w3 = f2bf(P[kOffW3 + t]);
-    W2b[t] = w2;
-    W3b[t] = w3;
-    W2t[o * kMlpTStride + i] = w2;
-    W3t[o * kMlpTStride + i] = w3;
+    W2b[t] = f2bf(P[kOffW2 + t]);
+    W3b[t] = f2bf(P[kOffW3 + t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -664,10 +661,9 @@ hipError_t mlp_adam(float *P, const float *G, float *m1, float *m2, float lr, in
 }
 
 hipError_t mlp_refresh(const float *P, unsigned short *W2b, unsigned short *W3b,
-                       unsigned short *W2t, unsigned short *W3t, hipStream_t st)
+                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_refresh_bf16, dim3(nblk(H * H, 256)), dim3(256), 0, st, P, W2b, W3b, W2t,
-                       W3t);
+    hipLaunchKernelGGL(k_refresh_bf16, dim3(nblk(H * H, 256)), dim3(256), 0, st, P, W2b, W3b);
     return hipGetLastError();
 }
 
