@@ -94,19 +94,21 @@ def lib():
             "or_psf_sigma": (C.c_double, [_S, C.c_double]),
             "or_psf_bin": (C.c_double, [_G, C.c_int, C.c_double, C.c_double, C.c_int]),
             "or_psf_total": (C.c_double, [_G, C.c_double, C.c_double, C.c_int]),
+            "or_psf_density": (C.c_double, [_G, C.c_double, C.c_double, C.c_double, C.c_int]),
             "or_geom_build": (C.c_int, [_G, _S, _D, C.POINTER(C.c_uint8)]),
             "or_geom_free": (None, [_G]),
             "or_Pp": (C.c_double, [_G, C.c_int, C.c_int, C.c_int]),
             "or_Ps": (C.c_double, [_G, C.c_int, C.c_int, C.c_int, C.c_int, _D]),
             "or_event_row": (None, [_G, C.c_int, C.c_int, C.c_double, _D]),
             "or_event_row_scatter": (None, [_G, C.c_int, C.c_int, C.c_double, _D]),
+            "or_event_row_pos": (None, [_G, C.c_double, C.c_int, C.c_double, _D]),
             "or_sens_qa": (C.c_double, [_G, C.c_int, C.c_int]),
             "or_sensitivity": (None, [_G, C.c_int, _D]),
             "or_sample_masses": (C.c_long, [_G, _D, _D]),
-            "or_check_events": (C.c_int, [_G, C.c_long, _I, _I, _D]),
-            "or_forward": (None, [_G, C.c_long, _I, _I, _D, _D, _D]),
-            "or_backproject": (None, [_G, C.c_long, _I, _I, _D, _D, _D]),
-            "or_osem": (C.c_int, [_G, C.c_long, _I, _I, _D, C.c_int, C.c_int, _D, _D,
+            "or_check_events": (C.c_int, [_G, C.c_long, _I, _D, _I, _D]),
+            "or_forward": (None, [_G, C.c_long, _I, _D, _I, _D, _D, _D]),
+            "or_backproject": (None, [_G, C.c_long, _I, _D, _I, _D, _D, _D]),
+            "or_osem": (C.c_int, [_G, C.c_long, _I, _D, _I, _D, C.c_int, C.c_int, _D, _D,
                                   _D, _D, _L]),
         }
         for name, (res, args) in sig.items():
@@ -252,6 +254,9 @@ class Oracle:
     def psf_total(self, x, y, a):
         return lib().or_psf_total(C.byref(self._g), float(x), float(y), int(a))
 
+    def psf_density(self, u, x, y, a):
+        return lib().or_psf_density(C.byref(self._g), float(u), float(x), float(y), int(a))
+
     def acc(self, E):
         return lib().or_acc(C.byref(self.sys), float(E))
 
@@ -267,6 +272,12 @@ class Oracle:
     def row(self, b, a, E):
         out = np.zeros(self.Q)
         lib().or_event_row(C.byref(self._g), int(b), int(a), float(E), _dp(out))
+        return out
+
+    def row_pos(self, u, a, E):
+        """Row of an event recorded at continuous lateral position u (mm)."""
+        out = np.zeros(self.Q)
+        lib().or_event_row_pos(C.byref(self._g), float(u), int(a), float(E), _dp(out))
         return out
 
     def row_scatter(self, b, a, E):
@@ -285,33 +296,44 @@ class Oracle:
     # -- events
     @staticmethod
     def _ev(events):
-        b = np.ascontiguousarray(events["bin"], dtype=np.int32)
+        """Event arrays for the C calls.  A list carries either "bin" (detector
+        bins) or "position" (continuous lateral position, mm); one that has
+        both is taken as binned."""
         a = np.ascontiguousarray(events["angle"], dtype=np.int32)
         e = np.ascontiguousarray(events["energy"], dtype=np.float64)
-        return b, a, e
+        if "bin" in events:
+            b = np.ascontiguousarray(events["bin"], dtype=np.int32)
+            return b, None, a, e
+        u = np.ascontiguousarray(events["position"], dtype=np.float64)
+        return None, u, a, e
+
+    @staticmethod
+    def _bu(b, u):
+        return (_ip(b) if b is not None else None), (_dp(u) if u is not None else None)
 
     def check_events(self, events):
-        b, a, e = self._ev(events)
-        return lib().or_check_events(C.byref(self._g), b.size, _ip(b), _ip(a), _dp(e))
+        b, u, a, e = self._ev(events)
+        return lib().or_check_events(C.byref(self._g), a.size, *self._bu(b, u), _ip(a), _dp(e))
 
     def forward(self, events, lam):
-        b, a, e = self._ev(events)
+        b, u, a, e = self._ev(events)
         lam = np.ascontiguousarray(lam, dtype=np.float64)
-        p = np.zeros(b.size)
-        lib().or_forward(C.byref(self._g), b.size, _ip(b), _ip(a), _dp(e), _dp(lam), _dp(p))
+        p = np.zeros(a.size)
+        lib().or_forward(C.byref(self._g), a.size, *self._bu(b, u), _ip(a), _dp(e), _dp(lam),
+                         _dp(p))
         return p
 
     def backproject(self, events, wj):
-        b, a, e = self._ev(events)
+        b, u, a, e = self._ev(events)
         wj = np.ascontiguousarray(wj, dtype=np.float64)
         out = np.zeros(self.Q)
-        lib().or_backproject(C.byref(self._g), b.size, _ip(b), _ip(a), _dp(e), _dp(wj),
+        lib().or_backproject(C.byref(self._g), a.size, *self._bu(b, u), _ip(a), _dp(e), _dp(wj),
                              _dp(out))
         return out
 
     def osem(self, events, nsub, niter, lam0, sens=None):
         """Returns (final image, history [niter*nsub, Q], ll [niter*nsub], skipped)."""
-        b, a, e = self._ev(events)
+        b, u, a, e = self._ev(events)
         if sens is None:
             sens = self.sensitivity(nsub)
         sens = np.ascontiguousarray(sens, dtype=np.float64)
@@ -320,7 +342,8 @@ class Oracle:
         hist = np.zeros((K, self.Q))
         ll = np.zeros(K)
         sk = np.zeros(K, dtype=np.int64)
-        lib().or_osem(C.byref(self._g), b.size, _ip(b), _ip(a), _dp(e), int(nsub), int(niter),
+        lib().or_osem(C.byref(self._g), a.size, *self._bu(b, u), _ip(a), _dp(e), int(nsub),
+                      int(niter),
                       _dp(sens), _dp(lam), _dp(hist), _dp(ll),
                       sk.ctypes.data_as(_L))
         return lam, hist, ll, sk
@@ -342,7 +365,10 @@ class Oracle:
         acceptance; then the lateral position from the depth-dependent Gaussian
         truncated to the detector, and the energy from the resolution Gaussian
         at the true energy truncated to the windows.  With ``poisson`` the
-        count is Poisson with mean ``n_events``."""
+        count is Poisson with mean ``n_events``.  The result holds both the
+        bin and the continuous lateral position ("position", mm) of every
+        event; a list handed to the other calls with "bin" removed is taken
+        as continuous."""
         p = self.params
         rng = np.random.Generator(np.random.PCG64(seed))
         m = self.sample_masses(lam)
@@ -361,6 +387,7 @@ class Oracle:
         q = qs[qi]
         sxy, _ = self.scatter_points()
         bins = np.zeros(J, dtype=np.int32)
+        pos = np.zeros(J)
         energies = np.zeros(J)
         db = 2 * self.R / int(p.nb)
         for j in range(J):
@@ -379,6 +406,7 @@ class Oracle:
                 u = rng.normal(u0, sig)
                 if -self.R <= u < self.R:
                     break
+            pos[j] = u
             bins[j] = min(int(np.floor((u + self.R) / db)), int(p.nb) - 1)
             se = self.sigmaE(Et)
             while True:
@@ -386,5 +414,5 @@ class Oracle:
                 if any(lo <= e <= hi for lo, hi in p.windows):
                     break
             energies[j] = e
-        return {"bin": bins, "angle": a.astype(np.int32), "energy": energies,
+        return {"bin": bins, "position": pos, "angle": a.astype(np.int32), "energy": energies,
                 "pixel": q, "line": w, "component": comp, "total_mass": tot}

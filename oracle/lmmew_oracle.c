@@ -224,6 +224,20 @@ double or_psf_bin(const or_geom *G, int b, double x, double y, int a)
     return or_Phi_diff((hi - u) / sig, (lo - u) / sig);
 }
 
+/* Density per mm of the lateral position u at which a photon leaving (x,y)
+ * along n_a is recorded, for a detector that reports a continuous position
+ * instead of a bin: the position attribute of pr(A_hat | P, E) in Eq. (3)
+ * as a density.  Its integral over bin b is or_psf_bin, and over [-R, R]
+ * or_psf_total. */
+double or_psf_density(const or_geom *G, double u, double x, double y, int a)
+{
+    double c, s;
+    or_angle_dir(a, G->S.na, &c, &s);
+    double u0 = -x * s + y * c;
+    double depth = G->R - (x * c + y * s);
+    return or_gauss(u, u0, or_psf_sigma(&G->S, depth));
+}
+
 /* Probability that the photon lands anywhere on the detector [-R, R]. */
 double or_psf_total(const or_geom *G, double x, double y, int a)
 {
@@ -382,13 +396,24 @@ double or_Ps(const or_geom *G, int q, int si, int a, int w, double *Eprime)
     return v;
 }
 
+/* Position factor of an event for a photon leaving (x,y) along n_a: the bin
+ * probability when the event carries detector bin b (pos == NULL), the
+ * density at *pos when it carries a continuous position. */
+static double pos_factor(const or_geom *G, int b, const double *pos, double x,
+                         double y, int a)
+{
+    return pos ? or_psf_density(G, *pos, x, y, a) : or_psf_bin(G, b, x, y, a);
+}
+
 /* Per-event system row (Eq. (3) with Eq. (4)'s numerator, per unit
  * activity): for every pixel q,
  *   a_q = sum_w [ Pp(q,a,w) psf(b | x_q, a) G(E_hat; E_w)
  *               + sum_s Ps(q,s,a,w) psf(b | x_s, a) G(E_hat; E'_{qsaw}) ]
  * with the energy Gaussian evaluated at the photon's true energy.  Pixels
- * outside the support get 0. */
-void or_event_row(const or_geom *G, int b, int a, double Ehat, double *row)
+ * outside the support get 0.  With primary == 0 only the scattered terms
+ * are summed. */
+static void event_row(const or_geom *G, int b, const double *pos, int a,
+                      double Ehat, int primary, double *row)
 {
     const or_sys *S = &G->S;
     for (int q = 0; q < G->Q; ++q) {
@@ -396,15 +421,16 @@ void or_event_row(const or_geom *G, int b, int a, double Ehat, double *row)
         if (!G->support[q]) continue;
         double xq, yq;
         pixel_centre(G, q, &xq, &yq);
-        double psf_q = or_psf_bin(G, b, xq, yq, a);
+        double psf_q = primary ? pos_factor(G, b, pos, xq, yq, a) : 0.0;
         double acc = 0.0;
         for (int w = 0; w < S->nw; ++w) {
-            acc += or_Pp(G, q, a, w) * psf_q *
-                   or_gauss(Ehat, S->E[w], or_sigmaE(S, S->E[w]));
+            if (primary)
+                acc += or_Pp(G, q, a, w) * psf_q *
+                       or_gauss(Ehat, S->E[w], or_sigmaE(S, S->E[w]));
             for (int si = 0; si < G->nsc; ++si) {
                 double Ep;
                 double ps = or_Ps(G, q, si, a, w, &Ep);
-                acc += ps * or_psf_bin(G, b, G->sx[si], G->sy[si], a) *
+                acc += ps * pos_factor(G, b, pos, G->sx[si], G->sy[si], a) *
                        or_gauss(Ehat, Ep, or_sigmaE(S, Ep));
             }
         }
@@ -412,25 +438,32 @@ void or_event_row(const or_geom *G, int b, int a, double Ehat, double *row)
     }
 }
 
+void or_event_row(const or_geom *G, int b, int a, double Ehat, double *row)
+{
+    event_row(G, b, NULL, a, Ehat, 1, row);
+}
+
+/* The row of an event recorded at continuous lateral position u (mm): the
+ * same sum with the bin probability replaced by the density. */
+void or_event_row_pos(const or_geom *G, double u, int a, double Ehat, double *row)
+{
+    event_row(G, 0, &u, a, Ehat, 1, row);
+}
+
 /* The once-scattered part of or_event_row alone (the quantity the scatter
  * surrogate learns): sum over lines and scatter points of the scattered
  * path terms. */
 void or_event_row_scatter(const or_geom *G, int b, int a, double Ehat, double *row)
 {
-    const or_sys *S = &G->S;
-    for (int q = 0; q < G->Q; ++q) {
-        row[q] = 0.0;
-        if (!G->support[q]) continue;
-        double acc = 0.0;
-        for (int w = 0; w < S->nw; ++w)
-            for (int si = 0; si < G->nsc; ++si) {
-                double Ep;
-                double ps = or_Ps(G, q, si, a, w, &Ep);
-                acc += ps * or_psf_bin(G, b, G->sx[si], G->sy[si], a) *
-                       or_gauss(Ehat, Ep, or_sigmaE(S, Ep));
-            }
-        row[q] = acc;
-    }
+    event_row(G, b, NULL, a, Ehat, 0, row);
+}
+
+/* Row of event j of a list whose position attribute is bin[j], or pos[j]
+ * when pos is not NULL. */
+static void list_row(const or_geom *G, const int *bin, const double *pos, long j,
+                     const int *ang, const double *E, double *row)
+{
+    event_row(G, pos ? 0 : bin[j], pos ? pos + j : NULL, ang[j], E[j], 1, row);
 }
 
 /* Detection probability per unit activity of pixel q at angle a (Eq. (7)
@@ -510,14 +543,19 @@ long or_sample_masses(const or_geom *G, const double *lambda, double *mass)
 /* List-mode OSEM (Sec. 2.4, Eq. (18)-(20); Algorithm 1)                     */
 /* ------------------------------------------------------------------------ */
 
-/* Returns the index of the first event with a bin or angle out of range or
- * an energy outside every window, or -1 when all are valid. */
+/* Event lists carry either detector bins (bin, with pos == NULL) or
+ * continuous lateral positions in mm (pos, with bin unused).
+ * Returns the index of the first event with a bin, position or angle out of
+ * range (positions must lie in [-R, R)) or an energy outside every window,
+ * or -1 when all are valid. */
 int or_check_events(const or_geom *G, long nev, const int *bin,
-                    const int *ang, const double *E)
+                    const double *pos, const int *ang, const double *E)
 {
     const or_sys *S = &G->S;
     for (long j = 0; j < nev; ++j) {
-        if (bin[j] < 0 || bin[j] >= S->nb || ang[j] < 0 || ang[j] >= S->na)
+        if (ang[j] < 0 || ang[j] >= S->na) return (int)j;
+        if (pos ? !(pos[j] >= -G->R && pos[j] < G->R)
+                : (bin[j] < 0 || bin[j] >= S->nb))
             return (int)j;
         int in = 0;
         for (int k = 0; k < S->nwin; ++k)
@@ -528,15 +566,15 @@ int or_check_events(const or_geom *G, long nev, const int *bin,
 }
 
 /* p_j = sum_q a_jq lambda_q: the denominator of Eq. (19). */
-void or_forward(const or_geom *G, long nev, const int *bin, const int *ang,
-                const double *E, const double *lambda, double *p)
+void or_forward(const or_geom *G, long nev, const int *bin, const double *pos,
+                const int *ang, const double *E, const double *lambda, double *p)
 {
 #pragma omp parallel
     {
         double *row = (double *)malloc(sizeof(double) * G->Q);
 #pragma omp for schedule(static)
         for (long j = 0; j < nev; ++j) {
-            or_event_row(G, bin[j], ang[j], E[j], row);
+            list_row(G, bin, pos, j, ang, E, row);
             double s = 0.0;
             for (int q = 0; q < G->Q; ++q) s += row[q] * lambda[q];
             p[j] = s;
@@ -547,13 +585,13 @@ void or_forward(const or_geom *G, long nev, const int *bin, const int *ang,
 
 /* out_q = sum_j a_jq w_j, events in input order. */
 void or_backproject(const or_geom *G, long nev, const int *bin,
-                    const int *ang, const double *E, const double *wj,
-                    double *out)
+                    const double *pos, const int *ang, const double *E,
+                    const double *wj, double *out)
 {
     double *rows = (double *)malloc(sizeof(double) * (size_t)nev * G->Q);
 #pragma omp parallel for schedule(static)
     for (long j = 0; j < nev; ++j)
-        or_event_row(G, bin[j], ang[j], E[j], rows + (size_t)j * G->Q);
+        list_row(G, bin, pos, j, ang, E, rows + (size_t)j * G->Q);
     for (int q = 0; q < G->Q; ++q) out[q] = 0.0;
     for (long j = 0; j < nev; ++j) {
         if (wj[j] == 0.0) continue;
@@ -574,8 +612,8 @@ void or_backproject(const or_geom *G, long nev, const int *bin,
  * lambda_q evaluated before the update (with one subset this is the
  * log-likelihood of Eq. (8) up to a constant); skipped (optional) receives
  * the number of skipped events. */
-int or_osem(const or_geom *G, long nev, const int *bin, const int *ang,
-            const double *E, int nsub, int niter, const double *sens,
+int or_osem(const or_geom *G, long nev, const int *bin, const double *pos,
+            const int *ang, const double *E, int nsub, int niter, const double *sens,
             double *lambda, double *hist, double *ll, long *skipped)
 {
     int Q = G->Q;
@@ -593,8 +631,7 @@ int or_osem(const or_geom *G, long nev, const int *bin, const int *ang,
             rows = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1) * Q);
 #pragma omp parallel for schedule(static)
             for (long i = 0; i < ns; ++i) {
-                long j = idx[i];
-                or_event_row(G, bin[j], ang[j], E[j], rows + (size_t)i * Q);
+                list_row(G, bin, pos, idx[i], ang, E, rows + (size_t)i * Q);
             }
             long skip = 0;
             double llv = 0.0;

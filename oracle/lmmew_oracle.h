@@ -85,6 +85,7 @@ double or_mu_scale(const or_sys *S, double E);
 double or_psf_sigma(const or_sys *S, double depth);
 double or_psf_bin(const or_geom *G, int b, double x, double y, int a);
 double or_psf_total(const or_geom *G, double x, double y, int a);
+double or_psf_density(const or_geom *G, double u, double x, double y, int a);
 
 /* ---- model ------------------------------------------------------------- */
 int    or_geom_build(or_geom *G, const or_sys *S, const double *mu85,
@@ -93,21 +94,24 @@ void   or_geom_free(or_geom *G);
 double or_Pp(const or_geom *G, int q, int a, int w);
 double or_Ps(const or_geom *G, int q, int si, int a, int w, double *Eprime);
 void   or_event_row(const or_geom *G, int b, int a, double Ehat, double *row);
+void   or_event_row_pos(const or_geom *G, double u, int a, double Ehat, double *row);
 void   or_event_row_scatter(const or_geom *G, int b, int a, double Ehat, double *row);
 double or_sens_qa(const or_geom *G, int q, int a);
 void   or_sensitivity(const or_geom *G, int nsub, double *sens);
 long   or_sample_masses(const or_geom *G, const double *lambda, double *mass);
 
 /* ---- list-mode OSEM ----------------------------------------------------- */
+/* Event lists: bin[j] (detector bin) when pos is NULL, else pos[j] (lateral
+ * position in mm, continuous); ang[j] angle index; E[j] energy in keV. */
 int  or_check_events(const or_geom *G, long nev, const int *bin,
-                     const int *ang, const double *E);
-void or_forward(const or_geom *G, long nev, const int *bin, const int *ang,
-                const double *E, const double *lambda, double *p);
+                     const double *pos, const int *ang, const double *E);
+void or_forward(const or_geom *G, long nev, const int *bin, const double *pos,
+                const int *ang, const double *E, const double *lambda, double *p);
 void or_backproject(const or_geom *G, long nev, const int *bin,
-                    const int *ang, const double *E, const double *wj,
-                    double *out);
-int  or_osem(const or_geom *G, long nev, const int *bin, const int *ang,
-             const double *E, int nsub, int niter, const double *sens,
+                    const double *pos, const int *ang, const double *E,
+                    const double *wj, double *out);
+int  or_osem(const or_geom *G, long nev, const int *bin, const double *pos,
+             const int *ang, const double *E, int nsub, int niter, const double *sens,
              double *lambda, double *hist, double *ll, long *skipped);
 
 #endif
