@@ -171,6 +171,35 @@ def cached_rows(plan, sens, lam0, J, Qp, steps):
                          "traffic": None, "bytes_per_iteration": bytes_it}}
 
 
+def positions(ctx, ev, nsub, sens, lam0, J, steps):
+    """The headline iterations on the same events handed over with their
+    continuous lateral positions instead of bins (density response)."""
+    import torch
+
+    from paper_2305_17111_amd import events_to_device
+
+    plan = ctx.plan(events_to_device({k: ev[k] for k in ("position", "angle", "energy")}), nsub)
+    plan.autotune(use_cache=False)
+    lam = lam0.clone()
+    plan.osem_iter(1, sens, lam)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.osem_iter(1, sens, lam)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n_launch = plan.profile_read()
+    plan.profile(False)
+    terms, _ = plan.terms()
+    ach = terms * steps / (ms * 1e-3)
+    assert bool(torch.isfinite(lam).all())
+    return {"ms_per_step": 1e3 * el / steps, "value": J * steps / el,
+            "unit": "events*iterations/s", "event_tile": plan.event_tile,
+            "k_row_avg_launch_ms": ms / n_launch, "terms_per_iteration": terms,
+            "frac": ach / PEAK_TERMS_PER_S, "frac_of_nonpacked_peak": ach / NONPACKED_PEAK_TERMS_PER_S}
+
+
 def _time_graph(plan, sens, lam, steps):
     """Seconds per launch of a one-iteration graph (after one warmup launch)."""
     import torch
@@ -314,6 +343,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-cached", action="store_true")
+    ap.add_argument("--no-position", action="store_true",
+                    help="skip the continuous-position variant of the headline iterations")
     ap.add_argument("--no-path-table", action="store_true",
                     help="evaluate the scatter-path parameters inside the per-event kernel")
     ap.add_argument("--surrogate-steps", type=int, default=1)
@@ -462,6 +493,9 @@ def main():
         lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
         Qp = (int(synth.fov_support(p).sum()) + 63) // 64 * 64
         out["cached_rows"] = cached_rows(plan, sens, lam0, J, Qp, args.steps)
+    if not args.no_position:
+        lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+        out["continuous_positions"] = positions(ctx, ev, nsub, sens, lam0, J, args.steps)
     if not args.no_batched:
         out["batched"] = batched(ctx, sens, args)
     if path_table:

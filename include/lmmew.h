@@ -82,14 +82,22 @@ typedef struct lmmew_system {
 } lmmew_system;
 
 /* List-mode data (lmData of Algorithm 1): one entry per detected photon.
- * All three arrays are device arrays of n entries.  An event is valid when
- * 0 <= bin < n_bins, 0 <= angle < n_angles and energy_keV is finite and lies
- * in some window [lo, hi]. */
+ * All arrays are device arrays of n entries.  The position attribute of
+ * Eq. (3) is either a detector bin (position_mm == NULL: the collimator
+ * response is the probability of the bin) or, when position_mm is not NULL,
+ * a continuous lateral position on the detector in mm (bin is then ignored
+ * and may be NULL; the collimator response is the Gaussian density per mm at
+ * that position, 0 beyond 7 standard deviations).  The sensitivity is the
+ * same for both, since the density integrates over the detector to the same
+ * probability.  An event is valid when 0 <= angle < n_angles, energy_keV is
+ * finite and lies in some window [lo, hi], and 0 <= bin < n_bins, or
+ * -R <= position_mm < R with R = n * pixel_mm / 2. */
 typedef struct lmmew_events {
     int64_t n;
     const int16_t *bin;
     const int16_t *angle;
     const float *energy_keV;
+    const float *position_mm;
 } lmmew_events;
 
 /* Optional statistics of an OSEM call (host memory owned by the caller). */
@@ -179,7 +187,8 @@ int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, fl
                       hipStream_t stream);
 
 /* Prepares list-mode data for OSEM: validates every event, sorts each
- * subset's events by (case, angle, bin, energy) (stable) and lays out the
+ * subset's events by (case, angle, bin or position, energy) (stable) and
+ * lays out the
  * work tiles and the per-subset scratch.  A plan holds one or more
  * independent cases (noise realisations or patients) that share the context's
  * attenuation map and sensitivity.
@@ -393,7 +402,9 @@ int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, int64_t n_label_events, int ep
 /* Selects the scatter model that lmmew_osem_iter/_subiter/_graph,
  * lmmew_forward and lmmew_backproject use for this context: NULL for the
  * exact model, or a network of this context (kept by pointer: it must stay
- * alive while selected). */
+ * alive while selected).  The network models binned events: a call on
+ * events with continuous positions while a network is selected fails with
+ * EINVAL. */
 int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *mlp);
 
 /* ---------------------------------------------------------------------------

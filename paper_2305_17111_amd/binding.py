@@ -40,7 +40,7 @@ class _System(C.Structure):
 
 class _Events(C.Structure):
     _fields_ = [("n", C.c_int64), ("bin", C.c_void_p), ("angle", C.c_void_p),
-                ("energy_keV", C.c_void_p)]
+                ("energy_keV", C.c_void_p), ("position_mm", C.c_void_p)]
 
 
 class _Stats(C.Structure):
@@ -167,23 +167,36 @@ def plan_maps(contexts, ev, n_subsets, case_offsets):
 
 
 def events_to_device(ev, device="cuda"):
-    """dict(bin, angle, energy) of arrays -> dict of device tensors (int16, int16, float32)."""
-    return {
-        "bin": torch.as_tensor(ev["bin"]).to(device=device, dtype=torch.int16).contiguous(),
+    """dict(bin, angle, energy) of arrays -> dict of device tensors (int16, int16,
+    float32).  A dict without "bin" carries continuous lateral positions in mm
+    under "position" (float32 on the device) instead."""
+    out = {
         "angle": torch.as_tensor(ev["angle"]).to(device=device, dtype=torch.int16).contiguous(),
         "energy": torch.as_tensor(ev["energy"]).to(device=device, dtype=torch.float32).contiguous(),
     }
+    if "bin" in ev:
+        out["bin"] = torch.as_tensor(ev["bin"]).to(device=device, dtype=torch.int16).contiguous()
+    else:
+        out["position"] = torch.as_tensor(ev["position"]).to(device=device,
+                                                             dtype=torch.float32).contiguous()
+    return out
 
 
 def _events(ev):
-    b, a, e = ev["bin"], ev["angle"], ev["energy"]
-    for t, dt in ((b, torch.int16), (a, torch.int16), (e, torch.float32)):
+    a, e = ev["angle"], ev["energy"]
+    cont = "bin" not in ev
+    x = ev["position"] if cont else ev["bin"]
+    for t, dt in ((x, torch.float32 if cont else torch.int16), (a, torch.int16),
+                  (e, torch.float32)):
         if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
-            raise TypeError("events must be contiguous device tensors (int16, int16, float32)")
-    n = b.numel()
-    if a.numel() != n or e.numel() != n:
+            raise TypeError("events must be contiguous device tensors (bin int16 or position "
+                            "float32, angle int16, energy float32)")
+    n = a.numel()
+    if x.numel() != n or e.numel() != n:
         raise ValueError("event arrays differ in length")
-    return _Events(n, b.data_ptr(), a.data_ptr(), e.data_ptr())
+    if cont:
+        return _Events(n, None, a.data_ptr(), e.data_ptr(), x.data_ptr())
+    return _Events(n, x.data_ptr(), a.data_ptr(), e.data_ptr(), None)
 
 
 class Context:

@@ -112,7 +112,8 @@ struct RowArgs {
     const int2 *slist;       // scatter list entries of the tiles: (point in the angle's
                              // sorted list, row of the point in the g_qs table)
     int ntiles;
-    const int *ev_bin;       // sorted rows of this subset
+    const int *ev_bin;       // sorted rows of this subset: detector bins (NULL for positions)
+    const float *ev_u;       // sorted rows: continuous lateral positions (mm), or NULL (bins)
     const float *ev_E;
     float *A;                // [rows][Qp]
     int mode;                // 0: all paths, 1: scattered paths only, 2: unscattered only

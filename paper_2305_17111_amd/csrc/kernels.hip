@@ -71,6 +71,14 @@ __device__ __forceinline__ float psf_cut(float zhi, float zlo)
     return (zlo >= kPsfCut || zhi <= -kPsfCut) ? 0.f : p;
 }
 
+// Collimator-response density per mm at a continuous position whose
+// deviation from the projected point is z standard deviations (isig = 1 /
+// sigma); exactly 0 beyond kPsfCut standard deviations.
+__device__ __forceinline__ float pdf_cut(float z, float isig)
+{
+    const float g = (0.39894228040143268f * isig) * fast_exp2(-0.5f * kLog2e * z * z);
+    return (z >= kPsfCut || z <= -kPsfCut) ? 0.f : g;
+}
 
 __device__ __forceinline__ float uniform_f(float v)
 {
@@ -340,8 +348,15 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
         for (int w = 0; w < NW; ++w) Pp[w] = S.pp[w] * fast_exp2(-S.f[w] * gqa * kLog2e);
         for (int j = 0; j < T.cnt; ++j) {
-            const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
-            const float ps = (r.mode == 1) ? 0.f : psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
+            float ps = 0.f;
+            if (r.mode != 1) {
+                if (r.ev_u) {
+                    ps = pdf_cut((r.ev_u[T.e0 + j] - uq) * isq, isq);
+                } else {
+                    const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
+                    ps = psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
+                }
+            }
             float g = 0.f;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
@@ -364,17 +379,28 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const int kl = lane % KC, jg = lane / KC;
     const int kend = (r.mode == 2) ? T.k0 : T.k1;     // unscattered only: no scatter loop
     for (int lc0 = T.k0; lc0 < kend; lc0 += KC) {
-        // response factors of (listed scatter point lc0+kl, events jg*TJ .. jg*TJ+TJ-1),
-        // read from the map's [angle][point][bin] table
+        // response factors of (listed scatter point lc0+kl, events jg*TJ .. jg*TJ+TJ-1):
+        // read from the map's [angle][point][bin] table for binned events, the
+        // density at the position otherwise
         float pv[TJ];
         {
             const int l = lc0 + kl;
-            const float *rrow =
-                resp + ((size_t)a * nsc + (l < T.k1 ? r.slist[l].x : 0)) * S.nb;
+            const int k = l < T.k1 ? r.slist[l].x : 0;
+            if (r.ev_u) {
+                const ScatA sp = sa[k];
 #pragma unroll
-            for (int t = 0; t < TJ; ++t) {
-                const int j = jg * TJ + t;
-                pv[t] = (l < T.k1 && j < T.cnt) ? rrow[r.ev_bin[T.e0 + min(j, last)]] : 0.f;
+                for (int t = 0; t < TJ; ++t) {
+                    const int j = jg * TJ + t;
+                    const float z = (r.ev_u[T.e0 + min(j, last)] - sp.u) * sp.isig;
+                    pv[t] = (l < T.k1 && j < T.cnt) ? pdf_cut(z, sp.isig) : 0.f;
+                }
+            } else {
+                const float *rrow = resp + ((size_t)a * nsc + k) * S.nb;
+#pragma unroll
+                for (int t = 0; t < TJ; ++t) {
+                    const int j = jg * TJ + t;
+                    pv[t] = (l < T.k1 && j < T.cnt) ? rrow[r.ev_bin[T.e0 + min(j, last)]] : 0.f;
+                }
             }
         }
         const int kn = min(KC, T.k1 - lc0);

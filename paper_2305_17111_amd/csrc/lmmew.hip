@@ -70,6 +70,8 @@ struct lmmew_plan {
     std::vector<int> bin, ang, cas;   // sorted rows
     int *d_ang = nullptr;
     std::vector<float> E;
+    bool cont = false;                // events carry continuous positions (u), not bins
+    std::vector<float> u;             // sorted rows: lateral position (mm) when cont
     std::vector<int64_t> perm;        // sorted row -> input index
     struct Sub {
         int row0 = 0, rows = 0;
@@ -85,7 +87,7 @@ struct lmmew_plan {
     double terms = 0, full_terms = 0;
     // device
     int *d_bin = nullptr, *d_case = nullptr, *d_case_chunk = nullptr;
-    float *d_E = nullptr;
+    float *d_E = nullptr, *d_u = nullptr;
     int64_t *d_perm = nullptr;
     Tile *d_tiles = nullptr;
     int2 *d_slist = nullptr;
@@ -222,7 +224,7 @@ void free_plan(lmmew_plan *p)
     p->gexec = nullptr;
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
     p->prof_ev.clear();
-    dfree(p->d_bin); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
+    dfree(p->d_bin); dfree(p->d_u); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
     dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
@@ -251,6 +253,22 @@ int relevant_scatter(const lmmew_ctx *c, int a, int b)
     return cnt;
 }
 
+// Continuous positions: the standardised deviation of position u from scatter
+// point e's projection, in the per-event kernel's float arithmetic (monotone
+// in u).
+inline float pos_z(const ScatA &e, float u) { return (u - e.u) * e.isig; }
+
+// Rows [first, last) of one angle with ascending positions: the sub-range
+// whose density factor for scatter point e is not cut (|z| < kPsfCut).
+std::pair<int, int> reached(const ScatA &e, const float *u, int first, int last)
+{
+    const float *lo = std::partition_point(u + first, u + last,
+                                           [&](float v) { return pos_z(e, v) <= -kPsfCut; });
+    const float *hi =
+        std::partition_point(lo, u + last, [&](float v) { return pos_z(e, v) < kPsfCut; });
+    return {(int)(lo - u), (int)(hi - u)};
+}
+
 // Builds tiles and chunks of a plan for the event tile size p->JT.
 void build_tiles(lmmew_plan *p)
 {
@@ -275,21 +293,30 @@ void build_tiles(lmmew_plan *p)
             const lmmew_ctx *c = p->maps.empty() ? p->ctx : p->maps[cs];
             const int nsc = c->S.nsc;
             while (e < rend && e - r < p->JT && p->cas[e] == cs && p->ang[e] == a) ++e;
-            int bmin = p->bin[r], bmax = p->bin[r];
-            for (int k = r; k < e; ++k) {
-                bmin = std::min(bmin, p->bin[k]);
-                bmax = std::max(bmax, p->bin[k]);
-            }
-            // scatter points whose response reaches some bin of the tile
             const int k0 = (int)p->slist.size();
-            for (int k = 0; k < nsc; ++k) {
-                const size_t ak = (size_t)a * nsc + k;
-                const int lo = c->rb_lo[ak], hi = c->rb_hi[ak];
-                if (hi < bmin || lo > bmax) continue;
-                // the tile's bins are sorted: is one of them inside [lo, hi]?
-                const int *first = p->bin.data() + r, *lastp = p->bin.data() + e;
-                const int *it = std::lower_bound(first, lastp, lo);
-                if (it != lastp && *it <= hi) p->slist.push_back(make_int2(k, c->sa[ak].sidx));
+            if (p->cont) {
+                // scatter points whose density reaches some position of the tile
+                for (int k = 0; k < nsc; ++k) {
+                    const ScatA &sp = c->sa[(size_t)a * nsc + k];
+                    const std::pair<int, int> rr = reached(sp, p->u.data(), r, e);
+                    if (rr.first < rr.second) p->slist.push_back(make_int2(k, sp.sidx));
+                }
+            } else {
+                int bmin = p->bin[r], bmax = p->bin[r];
+                for (int k = r; k < e; ++k) {
+                    bmin = std::min(bmin, p->bin[k]);
+                    bmax = std::max(bmax, p->bin[k]);
+                }
+                // scatter points whose response reaches some bin of the tile
+                for (int k = 0; k < nsc; ++k) {
+                    const size_t ak = (size_t)a * nsc + k;
+                    const int lo = c->rb_lo[ak], hi = c->rb_hi[ak];
+                    if (hi < bmin || lo > bmax) continue;
+                    // the tile's bins are sorted: is one of them inside [lo, hi]?
+                    const int *first = p->bin.data() + r, *lastp = p->bin.data() + e;
+                    const int *it = std::lower_bound(first, lastp, lo);
+                    if (it != lastp && *it <= hi) p->slist.push_back(make_int2(k, c->sa[ak].sidx));
+                }
             }
             const int k1 = (int)p->slist.size();
             Tile t{};
@@ -386,7 +413,9 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
                             "contexts of a plan must share the system and the support");
         }
     }
-    if (!ev || ev->n < 0 || (ev->n > 0 && (!ev->bin || !ev->angle || !ev->energy_keV)))
+    const bool cont = ev && ev->position_mm != nullptr;
+    if (!ev || ev->n < 0 ||
+        (ev->n > 0 && ((!cont && !ev->bin) || !ev->angle || !ev->energy_keV)))
         return fail(ctx, LMMEW_EINVAL, "events: NULL array or negative count");
     if (n_subsets < 1 || n_subsets > ctx->S.na)
         return fail(ctx, LMMEW_EINVAL, "n_subsets must be in 1..n_angles");
@@ -405,23 +434,35 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         off[0] = 0;
         off[1] = n;
     }
-    std::vector<int16_t> hb(n), ha(n);
-    std::vector<float> he(n);
+    std::vector<int16_t> hb(cont ? 0 : n), ha(n);
+    std::vector<float> he(n), hu(cont ? n : 0);
     if (n > 0) {
-        HIPCHK(ctx, hipMemcpyAsync(hb.data(), ev->bin, n * sizeof(int16_t), hipMemcpyDeviceToHost, st));
+        if (cont)
+            HIPCHK(ctx, hipMemcpyAsync(hu.data(), ev->position_mm, n * sizeof(float),
+                                       hipMemcpyDeviceToHost, st));
+        else
+            HIPCHK(ctx, hipMemcpyAsync(hb.data(), ev->bin, n * sizeof(int16_t),
+                                       hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipMemcpyAsync(ha.data(), ev->angle, n * sizeof(int16_t), hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipMemcpyAsync(he.data(), ev->energy_keV, n * sizeof(float),
                                    hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipStreamSynchronize(st));
     }
     const lmmew_system &s = ctx->sys;
+    const double Rmm = 0.5 * s.n * s.pixel_mm;
     for (int64_t j = 0; j < n; ++j) {
-        if (hb[j] < 0 || hb[j] >= s.n_bins || ha[j] < 0 || ha[j] >= s.n_angles ||
-            !in_window(s, he[j])) {
+        const bool pos_ok = cont ? ((double)hu[j] >= -Rmm && (double)hu[j] < Rmm)
+                                 : (hb[j] >= 0 && hb[j] < s.n_bins);
+        if (!pos_ok || ha[j] < 0 || ha[j] >= s.n_angles || !in_window(s, he[j])) {
             char buf[160];
-            snprintf(buf, sizeof buf,
-                     "event %lld invalid (bin %d, angle %d, energy %g keV)", (long long)j,
-                     (int)hb[j], (int)ha[j], (double)he[j]);
+            if (cont)
+                snprintf(buf, sizeof buf,
+                         "event %lld invalid (position %g mm, angle %d, energy %g keV)",
+                         (long long)j, (double)hu[j], (int)ha[j], (double)he[j]);
+            else
+                snprintf(buf, sizeof buf,
+                         "event %lld invalid (bin %d, angle %d, energy %g keV)", (long long)j,
+                         (int)hb[j], (int)ha[j], (double)he[j]);
             return fail(ctx, LMMEW_EINVAL, buf);
         }
     }
@@ -432,6 +473,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     p->nsub = n_subsets;
     p->ncases = n_cases;
     p->n = n;
+    p->cont = cont;
     std::vector<int> casev(n);
     for (int c = 0; c < n_cases; ++c)
         for (int64_t j = off[c]; j < off[c + 1]; ++j) casev[j] = c;
@@ -442,17 +484,25 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         if (sx != sy) return sx < sy;
         if (casev[x] != casev[y]) return casev[x] < casev[y];
         if (ha[x] != ha[y]) return ha[x] < ha[y];
-        if (hb[x] != hb[y]) return hb[x] < hb[y];
+        if (cont) {
+            if (hu[x] != hu[y]) return hu[x] < hu[y];
+        } else if (hb[x] != hb[y]) {
+            return hb[x] < hb[y];
+        }
         return he[x] < he[y];
     });
-    p->bin.resize(n);
+    p->bin.resize(cont ? 0 : n);
+    p->u.resize(cont ? n : 0);
     p->ang.resize(n);
     p->cas.resize(n);
     p->E.resize(n);
     p->perm = order;
     for (int64_t r = 0; r < n; ++r) {
         const int64_t j = order[r];
-        p->bin[r] = hb[j];
+        if (cont)
+            p->u[r] = hu[j];
+        else
+            p->bin[r] = hb[j];
         p->ang[r] = ha[j];
         p->cas[r] = casev[j];
         p->E[r] = he[j];
@@ -470,14 +520,32 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     // algorithmic terms per iteration
     {
         const double QW = (double)ctx->S.Qm * ctx->S.nw;
-        const size_t per = (size_t)s.n_angles * s.n_bins;
-        std::vector<int> rel_cache(per * (p->maps.empty() ? 1 : n_cases), -1);
         double t = 0;
-        for (int64_t r = 0; r < n; ++r) {
-            const int m = p->maps.empty() ? 0 : p->cas[r];
-            int &rc = rel_cache[m * per + (size_t)p->ang[r] * s.n_bins + p->bin[r]];
-            if (rc < 0) rc = relevant_scatter(m ? p->maps[m] : ctx, p->ang[r], p->bin[r]);
-            t += QW * (1.0 + rc);
+        if (cont) {
+            // runs of one (case, angle) have ascending positions: count each
+            // scatter point's reached rows by bisection
+            for (int64_t r = 0; r < n;) {
+                int64_t e = r;
+                while (e < n && p->cas[e] == p->cas[r] && p->ang[e] == p->ang[r]) ++e;
+                const lmmew_ctx *c = p->maps.empty() ? ctx : p->maps[p->cas[r]];
+                double rel = 0;
+                for (int k = 0; k < c->S.nsc; ++k) {
+                    const std::pair<int, int> rr =
+                        reached(c->sa[(size_t)p->ang[r] * c->S.nsc + k], p->u.data(), (int)r, (int)e);
+                    rel += rr.second - rr.first;
+                }
+                t += QW * ((double)(e - r) + rel);
+                r = e;
+            }
+        } else {
+            const size_t per = (size_t)s.n_angles * s.n_bins;
+            std::vector<int> rel_cache(per * (p->maps.empty() ? 1 : n_cases), -1);
+            for (int64_t r = 0; r < n; ++r) {
+                const int m = p->maps.empty() ? 0 : p->cas[r];
+                int &rc = rel_cache[m * per + (size_t)p->ang[r] * s.n_bins + p->bin[r]];
+                if (rc < 0) rc = relevant_scatter(m ? p->maps[m] : ctx, p->ang[r], p->bin[r]);
+                t += QW * (1.0 + rc);
+            }
         }
         p->terms = t;
         double full = 0;
@@ -499,7 +567,10 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         hipError_t e_ = (call);                                  \
         if (e_ != hipSuccess) return fin(hipfail(ctx, e_, #call)); \
     } while (0)
-    PCHK(dalloc(&p->d_bin, n));
+    if (cont)
+        PCHK(dalloc(&p->d_u, n));
+    else
+        PCHK(dalloc(&p->d_bin, n));
     PCHK(dalloc(&p->d_ang, n));
     PCHK(dalloc(&p->d_case, n));
     PCHK(dalloc(&p->d_E, n));
@@ -510,7 +581,11 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     PCHK(dalloc(&p->d_A, (size_t)std::max(p->max_rows, 1) * Qp));
     PCHK(dalloc(&p->d_lamc, (size_t)n_cases * Qp));
     if (n > 0) {
-        PCHK(hipMemcpyAsync(p->d_bin, p->bin.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        if (cont)
+            PCHK(hipMemcpyAsync(p->d_u, p->u.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+        else
+            PCHK(hipMemcpyAsync(p->d_bin, p->bin.data(), n * sizeof(int), hipMemcpyHostToDevice,
+                                st));
         PCHK(hipMemcpyAsync(p->d_ang, p->ang.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_case, p->cas.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_E, p->E.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
@@ -595,6 +670,9 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     const lmmew_plan::Sub &sub = p->subs[s];
     float *const out = dst ? dst : p->d_A;
     const bool surrogate = (part == 0 && ctx->mlp != nullptr);
+    if (surrogate && p->cont)
+        return fail(ctx, LMMEW_EINVAL,
+                    "the scatter surrogate models binned events; these carry continuous positions");
     RowArgs r{};
     r.pix_xy = ctx->d_pix;
     r.dirs = ctx->d_dirs;
@@ -607,7 +685,8 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     r.tiles = p->d_tiles + sub.tile0;
     r.slist = p->d_slist;
     r.ntiles = sub.ntiles;
-    r.ev_bin = p->d_bin + sub.row0;
+    r.ev_bin = p->cont ? nullptr : p->d_bin + sub.row0;
+    r.ev_u = p->cont ? p->d_u + sub.row0 : nullptr;
     r.ev_E = p->d_E + sub.row0;
     r.A = out;
     r.mode = surrogate ? 2 : (part == 3 ? 0 : part);

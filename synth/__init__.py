@@ -251,7 +251,9 @@ def generic_events(p: SysParams, activity, n_events: int, seed: int, poisson=Fal
     plus a fixed Gaussian blur (`blur_mm`), energy either near an emission line
     (line chosen by yield, fixed Gaussian spread `peak_sigma`) or uniform below
     it (a stand-in for the scatter continuum), kept only inside the windows.
-    None of these draws uses the reconstruction model."""
+    None of these draws uses the reconstruction model.  "position" holds the
+    continuous lateral position (mm, float32, in [-R, R)) that "bin" quantises;
+    drop "bin" to hand the events over as continuous."""
     rng = np.random.Generator(np.random.PCG64(seed))
     J = int(rng.poisson(n_events)) if poisson else int(n_events)
     act = np.asarray(activity, dtype=np.float64).ravel()
@@ -262,9 +264,11 @@ def generic_events(p: SysParams, activity, n_events: int, seed: int, poisson=Fal
     yields = np.asarray(p.yields) / np.sum(p.yields)
     wins = np.asarray(p.windows)
     bins = np.empty(J, np.int16)
+    pos = np.empty(J, np.float32)
     angs = np.empty(J, np.int16)
     ener = np.empty(J, np.float32)
     db = p.fov / p.nb
+    below_R = np.nextafter(np.float32(p.R), np.float32(0))
     filled = 0
     while filled < J:
         m = max(1024, 2 * (J - filled))
@@ -283,10 +287,11 @@ def generic_events(p: SysParams, activity, n_events: int, seed: int, poisson=Fal
         k = min(int(ok.sum()), J - filled)
         idx = np.flatnonzero(ok)[:k]
         bins[filled:filled + k] = b[idx]
+        pos[filled:filled + k] = np.minimum(u[idx].astype(np.float32), below_R)
         angs[filled:filled + k] = a[idx]
         ener[filled:filled + k] = e[idx]
         filled += k
-    return {"bin": bins, "angle": angs, "energy": ener}
+    return {"bin": bins, "angle": angs, "energy": ener, "position": pos}
 
 
 def workload_inputs(name: str, case: int = 0, n_events=None):

@@ -8,6 +8,8 @@ receives it, and the oracle then works in double precision on those values.
     python tests/golden/make_oracle_golden.py c2        # sampled rows + sensitivity
     python tests/golden/make_oracle_golden.py c2iter    # one full iteration, 2000 events
     python tests/golden/make_oracle_golden.py c5        # sampled rows at 128x128
+    python tests/golden/make_oracle_golden.py c1pos     # continuous positions, 16x16
+    python tests/golden/make_oracle_golden.py c2pos     # continuous positions, sampled rows
 """
 import hashlib
 import os
@@ -124,6 +126,59 @@ def c5():
     print("c5 rows", time.time() - t, "s")
     np.savez_compressed(os.path.join(OUT, "c5_oracle.npz"), digest=digest(ev), idx=idx,
                         p_act=p_act)
+
+
+def below_R(u, p):
+    """Positions as the GPU receives them: float32, kept inside [-R, R)."""
+    return np.minimum(np.asarray(u, dtype=np.float32), np.nextafter(np.float32(p.R), np.float32(0)))
+
+
+def c1pos():
+    w = synth.CONFIGS["c1"]
+    p = w.params
+    mu, act, rois = synth.phantom(w)
+    mu32 = f32(mu)
+    o = oracle.Oracle(p, mu32)
+    ev = o.sample_events(act, 1500, seed=77)
+    ev = {"position": below_R(ev["position"], p), "angle": ev["angle"].astype(np.int16),
+          "energy": ev["energy"].astype(np.float32)}
+    evd = {"position": ev["position"].astype(np.float64), "angle": ev["angle"],
+           "energy": ev["energy"].astype(np.float64)}
+    assert o.check_events(evd) == -1
+    sens = o.sensitivity(w.n_subsets)
+    lam0 = o.support.astype(np.float64)
+    t = time.time()
+    lam, hist, ll, sk = o.osem(evd, w.n_subsets, 2, lam0, f32(sens))
+    print("c1pos osem", time.time() - t, "s")
+    p_act = o.forward(evd, f32(act))
+    idx = np.arange(0, ev["angle"].size, 97)
+    rows = np.stack([o.row_pos(evd["position"][j], evd["angle"][j], evd["energy"][j])
+                     for j in idx])
+    np.savez_compressed(os.path.join(OUT, "c1pos_oracle.npz"), position=ev["position"],
+                        angle=ev["angle"], energy=ev["energy"], sens=sens, lam0=lam0,
+                        hist=hist, ll=ll, skipped=sk, p_act=p_act, idx=idx, rows=rows)
+
+
+def c2pos():
+    w = synth.CONFIGS["c2"]
+    p = w.params
+    mu, act, rois = synth.phantom(w)
+    mu32, act32 = f32(mu), f32(act)
+    ev = synth.generic_events(p, act, w.n_events, w.seed_events, poisson=True)
+    o = oracle.Oracle(p, mu32)
+    rng = np.random.default_rng(3333)
+    J = ev["angle"].size
+    idx = np.sort(rng.choice(J, 12, replace=False))
+    sub = {"position": ev["position"][idx].astype(np.float64), "angle": ev["angle"][idx],
+           "energy": ev["energy"][idx].astype(np.float64)}
+    t = time.time()
+    p_act = o.forward(sub, act32)
+    print("c2pos rows", time.time() - t, "s")
+    h = hashlib.sha256()
+    for k in ("position", "angle", "energy"):
+        h.update(np.ascontiguousarray(ev[k]).tobytes())
+    np.savez_compressed(os.path.join(OUT, "c2pos_oracle.npz"), digest=h.hexdigest(), J=J,
+                        idx=idx, p_act=p_act)
 
 
 if __name__ == "__main__":
