@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lmmew_oracle.c")
+_SRC3 = os.path.join(_HERE, "lmmew_oracle3.c")
 _LIB = os.path.join(_HERE, "liblmmew_oracle.so")
 _lib = None
 
@@ -30,10 +31,12 @@ MAXW = 8
 
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (OpenMP, -O2, strict IEEE: no -ffast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = (not os.path.exists(_LIB) or
+             os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in (_SRC, _SRC3)))
+    if force or stale:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-o", tmp, _SRC, "-lm"]
+               "-o", tmp, _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True, cwd=_HERE)
         os.replace(tmp, _LIB)
     return _LIB
@@ -66,11 +69,32 @@ class _Geom(C.Structure):
     ]
 
 
+class _Sys3(C.Structure):
+    _fields_ = [("S", _Sys), ("nz", C.c_int), ("nsz", C.c_int), ("nbz", C.c_int),
+                ("domega", C.c_double)]
+
+
+class _Geom3(C.Structure):
+    _fields_ = [
+        ("S3", _Sys3), ("R", C.c_double), ("Zh", C.c_double), ("hs", C.c_double),
+        ("hz", C.c_double), ("db", C.c_double), ("dbz", C.c_double), ("Q", C.c_int),
+        ("mu", C.POINTER(C.c_double)), ("support", C.POINTER(C.c_uint8)),
+        ("nsc", C.c_int),
+        ("sx", C.POINTER(C.c_double)), ("sy", C.POINTER(C.c_double)),
+        ("sz", C.POINTER(C.c_double)), ("smu", C.POINTER(C.c_double)),
+        ("g_qa", C.POINTER(C.c_double)), ("g_qs", C.POINTER(C.c_double)),
+        ("g_sa", C.POINTER(C.c_double)),
+        ("Zw", C.c_double * MAXL),
+    ]
+
+
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int)
 _L = C.POINTER(C.c_long)
 _G = C.POINTER(_Geom)
 _S = C.POINTER(_Sys)
+_G3 = C.POINTER(_Geom3)
+_S3 = C.POINTER(_Sys3)
 
 
 def lib():
@@ -110,6 +134,25 @@ def lib():
             "or_backproject": (None, [_G, C.c_long, _I, _D, _I, _D, _D, _D]),
             "or_osem": (C.c_int, [_G, C.c_long, _I, _D, _I, _D, C.c_int, C.c_int, _D, _D,
                                   _D, _D, _L]),
+            "or3_segment_integral": (C.c_double, [_D, C.c_int, C.c_int, C.c_double]
+                                     + [C.c_double] * 6),
+            "or3_kn_Z": (C.c_double, [C.c_double, C.c_double]),
+            "or3_geom_build": (C.c_int, [_G3, _S3, _D, C.POINTER(C.c_uint8)]),
+            "or3_geom_free": (None, [_G3]),
+            "or3_voxel_centre": (None, [_G3, C.c_int, _D, _D, _D]),
+            "or3_Pp": (C.c_double, [_G3, C.c_int, C.c_int, C.c_int]),
+            "or3_Ps": (C.c_double, [_G3, C.c_int, C.c_int, C.c_int, C.c_int, _D]),
+            "or3_psf_bin": (C.c_double, [_G3, C.c_int, C.c_int, C.c_double, C.c_double,
+                                         C.c_double, C.c_int]),
+            "or3_psf_total": (C.c_double, [_G3, C.c_double, C.c_double, C.c_double, C.c_int]),
+            "or3_event_row": (None, [_G3, C.c_int, C.c_int, C.c_int, C.c_double, _D]),
+            "or3_event_row_scatter": (None, [_G3, C.c_int, C.c_int, C.c_int, C.c_double, _D]),
+            "or3_sens_qa": (C.c_double, [_G3, C.c_int, C.c_int]),
+            "or3_sensitivity": (None, [_G3, C.c_int, _D]),
+            "or3_check_events": (C.c_int, [_G3, C.c_long, _I, _I, _I, _D]),
+            "or3_forward": (None, [_G3, C.c_long, _I, _I, _I, _D, _D, _D]),
+            "or3_osem": (C.c_int, [_G3, C.c_long, _I, _I, _I, _D, C.c_int, C.c_int, _D, _D,
+                                   _D, _D, _L]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -416,3 +459,145 @@ class Oracle:
             energies[j] = e
         return {"bin": bins, "position": pos, "angle": a.astype(np.int32), "energy": energies,
                 "pixel": q, "line": w, "component": comp, "total_mass": tot}
+
+
+def segment_integral3(mu, n, nz, pix, x0, y0, z0, x1, y1, z1):
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    return lib().or3_segment_integral(_dp(mu), int(n), int(nz), float(pix), float(x0),
+                                      float(y0), float(z0), float(x1), float(y1), float(z1))
+
+
+def kn_Z3(E, me=510.99895):
+    return lib().or3_kn_Z(float(E), float(me))
+
+
+class Oracle3:
+    """The 3-D single-scatter model on one voxelised attenuation map (nz
+    slices of n x n; flat index (iz*n + iy)*n + ix): tables, rows,
+    sensitivity, OSEM.  Events carry "bin", "bin_z", "angle", "energy"."""
+
+    def __init__(self, params, mu85, mask=None):
+        self.params = params
+        s3 = _Sys3()
+        s3.S = make_sys(params)
+        s3.nz, s3.nsz, s3.nbz = int(params.nz), int(params.nsz), int(params.nbz)
+        s3.domega = float(params.domega)
+        self.sys = s3
+        n, nz = int(params.n), int(params.nz)
+        self.mu85 = np.ascontiguousarray(mu85, dtype=np.float64).ravel()
+        assert self.mu85.size == n * n * nz
+        self._g = _Geom3()
+        m = None
+        if mask is not None:
+            self._mask = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+            m = self._mask.ctypes.data_as(C.POINTER(C.c_uint8))
+        rc = lib().or3_geom_build(C.byref(self._g), C.byref(self.sys), _dp(self.mu85), m)
+        if rc != 0:
+            raise ValueError("invalid geometry (n/ns and nz/nsz must be even integers)")
+        self.Q = n * n * nz
+
+    def __del__(self):
+        try:
+            lib().or3_geom_free(C.byref(self._g))
+        except Exception:
+            pass
+
+    @property
+    def R(self):
+        return self._g.R
+
+    @property
+    def Zh(self):
+        return self._g.Zh
+
+    @property
+    def nsc(self):
+        return self._g.nsc
+
+    @property
+    def support(self):
+        return np.ctypeslib.as_array(self._g.support, shape=(self.Q,)).astype(bool).copy()
+
+    def scatter_points(self):
+        k = self._g.nsc
+        if k == 0:
+            return np.zeros((0, 3)), np.zeros(0)
+        xyz = [np.ctypeslib.as_array(getattr(self._g, f), shape=(k,)).copy()
+               for f in ("sx", "sy", "sz")]
+        mu = np.ctypeslib.as_array(self._g.smu, shape=(k,)).copy()
+        return np.stack(xyz, 1), mu
+
+    def voxel_centre(self, q):
+        x, y, z = C.c_double(), C.c_double(), C.c_double()
+        lib().or3_voxel_centre(C.byref(self._g), int(q), C.byref(x), C.byref(y), C.byref(z))
+        return x.value, y.value, z.value
+
+    def Pp(self, q, a, w):
+        return lib().or3_Pp(C.byref(self._g), int(q), int(a), int(w))
+
+    def Ps(self, q, si, a, w):
+        ep = C.c_double()
+        v = lib().or3_Ps(C.byref(self._g), int(q), int(si), int(a), int(w), C.byref(ep))
+        return v, ep.value
+
+    def psf_bin(self, b, bz, x, y, z, a):
+        return lib().or3_psf_bin(C.byref(self._g), int(b), int(bz), float(x), float(y),
+                                 float(z), int(a))
+
+    def psf_total(self, x, y, z, a):
+        return lib().or3_psf_total(C.byref(self._g), float(x), float(y), float(z), int(a))
+
+    def row(self, b, bz, a, E):
+        out = np.zeros(self.Q)
+        lib().or3_event_row(C.byref(self._g), int(b), int(bz), int(a), float(E), _dp(out))
+        return out
+
+    def row_scatter(self, b, bz, a, E):
+        out = np.zeros(self.Q)
+        lib().or3_event_row_scatter(C.byref(self._g), int(b), int(bz), int(a), float(E),
+                                    _dp(out))
+        return out
+
+    def sens_qa(self, q, a):
+        return lib().or3_sens_qa(C.byref(self._g), int(q), int(a))
+
+    def sensitivity(self, nsub):
+        out = np.zeros((int(nsub), self.Q))
+        lib().or3_sensitivity(C.byref(self._g), int(nsub), _dp(out))
+        return out
+
+    @staticmethod
+    def _ev(events):
+        b = np.ascontiguousarray(events["bin"], dtype=np.int32)
+        bz = np.ascontiguousarray(events["bin_z"], dtype=np.int32)
+        a = np.ascontiguousarray(events["angle"], dtype=np.int32)
+        e = np.ascontiguousarray(events["energy"], dtype=np.float64)
+        return b, bz, a, e
+
+    def check_events(self, events):
+        b, bz, a, e = self._ev(events)
+        return lib().or3_check_events(C.byref(self._g), a.size, _ip(b), _ip(bz), _ip(a), _dp(e))
+
+    def forward(self, events, lam):
+        b, bz, a, e = self._ev(events)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        p = np.zeros(a.size)
+        lib().or3_forward(C.byref(self._g), a.size, _ip(b), _ip(bz), _ip(a), _dp(e),
+                          _dp(lam), _dp(p))
+        return p
+
+    def osem(self, events, nsub, niter, lam0, sens=None):
+        """Returns (final image, history [niter*nsub, Q], ll [niter*nsub], skipped)."""
+        b, bz, a, e = self._ev(events)
+        if sens is None:
+            sens = self.sensitivity(nsub)
+        sens = np.ascontiguousarray(sens, dtype=np.float64)
+        lam = np.array(lam0, dtype=np.float64).copy()
+        K = int(nsub) * int(niter)
+        hist = np.zeros((K, self.Q))
+        ll = np.zeros(K)
+        sk = np.zeros(K, dtype=np.int64)
+        lib().or3_osem(C.byref(self._g), a.size, _ip(b), _ip(bz), _ip(a), _dp(e), int(nsub),
+                       int(niter), _dp(sens), _dp(lam), _dp(hist), _dp(ll),
+                       sk.ctypes.data_as(_L))
+        return lam, hist, ll, sk

@@ -611,12 +611,12 @@ void or_backproject(const or_geom *G, long nev, const int *bin,
  * sub-iteration; ll (optional) receives sum_j log p_j - sum_q sens_s[q]
  * lambda_q evaluated before the update (with one subset this is the
  * log-likelihood of Eq. (8) up to a constant); skipped (optional) receives
- * the number of skipped events. */
-int or_osem(const or_geom *G, long nev, const int *bin, const double *pos,
-            const int *ang, const double *E, int nsub, int niter, const double *sens,
-            double *lambda, double *hist, double *ll, long *skipped)
+ * the number of skipped events.  The rows come from row(ctx, j, out), so the
+ * loop serves every system model. */
+int or_osem_rows(long nev, const int *ang, int Q, int nsub, int niter,
+                 const double *sens, double *lambda, double *hist, double *ll,
+                 long *skipped, or_row_fn row, const void *ctx)
 {
-    int Q = G->Q;
     long *idx = (long *)malloc(sizeof(long) * (nev > 0 ? nev : 1));
     double *rows = NULL;
     double *p = (double *)malloc(sizeof(double) * (nev > 0 ? nev : 1));
@@ -630,9 +630,8 @@ int or_osem(const or_geom *G, long nev, const int *bin, const double *pos,
             free(rows);
             rows = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1) * Q);
 #pragma omp parallel for schedule(static)
-            for (long i = 0; i < ns; ++i) {
-                list_row(G, bin, pos, idx[i], ang, E, rows + (size_t)i * Q);
-            }
+            for (long i = 0; i < ns; ++i)
+                row(ctx, idx[i], rows + (size_t)i * Q);
             long skip = 0;
             double llv = 0.0;
             for (long i = 0; i < ns; ++i) {
@@ -659,4 +658,26 @@ int or_osem(const or_geom *G, long nev, const int *bin, const double *pos,
     }
     free(idx); free(rows); free(p); free(B);
     return 0;
+}
+
+/* Event list of the planar model, for the row callback. */
+typedef struct {
+    const or_geom *G;
+    const int *bin, *ang;
+    const double *pos, *E;
+} list2d;
+
+static void list2d_row(const void *ctx, long j, double *row)
+{
+    const list2d *L = (const list2d *)ctx;
+    list_row(L->G, L->bin, L->pos, j, L->ang, L->E, row);
+}
+
+int or_osem(const or_geom *G, long nev, const int *bin, const double *pos,
+            const int *ang, const double *E, int nsub, int niter, const double *sens,
+            double *lambda, double *hist, double *ll, long *skipped)
+{
+    list2d L = {G, bin, ang, pos, E};
+    return or_osem_rows(nev, ang, G->Q, nsub, niter, sens, lambda, hist, ll, skipped,
+                        list2d_row, &L);
 }

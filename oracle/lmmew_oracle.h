@@ -110,6 +110,11 @@ void or_forward(const or_geom *G, long nev, const int *bin, const double *pos,
 void or_backproject(const or_geom *G, long nev, const int *bin,
                     const double *pos, const int *ang, const double *E,
                     const double *wj, double *out);
+/* Row a_j of event j (Q values) for the OSEM loop below. */
+typedef void (*or_row_fn)(const void *ctx, long j, double *row);
+int  or_osem_rows(long nev, const int *ang, int Q, int nsub, int niter,
+                  const double *sens, double *lambda, double *hist, double *ll,
+                  long *skipped, or_row_fn row, const void *ctx);
 int  or_osem(const or_geom *G, long nev, const int *bin, const double *pos,
              const int *ang, const double *E, int nsub, int niter, const double *sens,
              double *lambda, double *hist, double *ll, long *skipped);

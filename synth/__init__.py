@@ -25,6 +25,9 @@ EW1 = (68.0, 102.0)
 EW2 = (123.0, 184.0)
 EW3 = (243.0, 297.0)
 SW = (184.0, 243.0)
+# collimator acceptance solid angle of the 3-D model: a cone whose full
+# opening angle is the planar model's acceptance angle (0.03 rad)
+DOMEGA = float(2.0 * np.pi * (1.0 - np.cos(0.015)))
 
 
 @dataclass(frozen=True)
@@ -46,6 +49,10 @@ class SysParams:
     mu_pow: float = 1.0 / 3.0
     T: float = 1.0
     me: float = 510.99895  # electron rest energy, keV
+    nz: int = 0            # slices (0: the planar model of the paper's evaluation)
+    nsz: int = 0           # scatter points along z (3-D)
+    nbz: int = 0           # axial detector bins (3-D)
+    domega: float = DOMEGA # collimator acceptance solid angle, sr (3-D)
 
     @property
     def fov(self):
@@ -54,6 +61,10 @@ class SysParams:
     @property
     def R(self):
         return 0.5 * self.n * self.pix
+
+    @property
+    def Zh(self):
+        return 0.5 * self.nz * self.pix
 
 
 @dataclass(frozen=True)
@@ -89,6 +100,16 @@ CONFIGS = {
     "c5": Workload("c5", SysParams(128, 2.0, 64, 128, 120, windows=(EW1, EW2, SW, EW3)),
                    1000000, 16, 20, "ellipse3", 5200, 5300, poisson=False, n_cases=16,
                    case_min=20000, case_max=200000, seed_cases=51),
+    # 3-D single scatter: 16x16x8 voxels of 4 mm, 8x8x4 scatter grid, 16x8 bins,
+    # 16 angles, EW1+EW2, 600 events.
+    "c1_3d": Workload("c1_3d", SysParams(16, 4.0, 8, 16, 16, windows=(EW1, EW2), nz=8, nsz=4,
+                                         nbz=8),
+                      600, 4, 2, "disk2_3d", 11, 13),
+    # 3-D: the 64x64 workload's slice geometry over 16 slices (256x256x64 mm),
+    # 32x32x8 scatter grid, 64x16 bins, 120 angles, EW1-3, ~50k events.
+    "c2_3d": Workload("c2_3d", SysParams(64, 4.0, 32, 64, 120, windows=(EW1, EW2, EW3), nz=16,
+                                         nsz=8, nbz=16),
+                      50000, 8, 20, "ellipse3_3d", 21, 23, poisson=True),
 }
 
 
@@ -223,9 +244,112 @@ def random_body_maps(p: SysParams, n_maps: int, seed: int, axes=(0.7, 0.95), shi
     return out
 
 
+def voxel_centres(p: SysParams):
+    """Voxel centres of a 3-D grid, flat index (iz*n + iy)*n + ix."""
+    c = (np.arange(p.n) + 0.5) * p.pix - p.R
+    cz = (np.arange(p.nz) + 0.5) * p.pix - p.Zh
+    z, y, x = np.meshgrid(cz, c, c, indexing="ij")
+    return x.ravel(), y.ravel(), z.ravel()
+
+
+def fov_support3(p: SysParams):
+    x, y, _ = voxel_centres(p)
+    return x * x + y * y <= p.R * p.R
+
+
+def phantom_disk2_3d(p: SysParams, mu85=0.018, body_r=28.0, half_z=None, hot_r=6.0,
+                     hot=((-14.0, 0.0, -4.0), (14.0, 0.0, 4.0)), ratio=4.0):
+    """Water cylinder (radius body_r, |z| <= half_z, default 3/4 of the axial
+    half-length) with two hot spheres (activity ratio `ratio`:1)."""
+    x, y, z = voxel_centres(p)
+    hz = 0.75 * p.Zh if half_z is None else half_z
+    body = (x * x + y * y <= body_r * body_r) & (np.abs(z) <= hz)
+    mu = np.where(body, mu85, 0.0)
+    act = np.where(body, 1.0, 0.0)
+    rois = []
+    for cx, cy, cz in hot:
+        roi = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= hot_r * hot_r
+        act = np.where(roi, ratio, act)
+        rois.append(roi)
+    return mu, act, rois
+
+
+def phantom_ellipse3_3d(p: SysParams, seed: int, half_z_frac=0.8):
+    """phantom_ellipse3's elliptical body extruded over |z| <= half_z_frac * Zh;
+    each of its three hot regions becomes an elliptic cylinder of axial
+    half-length U[7,20] mm centred at z uniform in the middle half of the
+    body."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    p2 = replace(p, nz=0, nsz=0, nbz=0)
+    mu2, act2, rois2 = phantom_ellipse3(p2, seed)
+    zc = (np.arange(p.nz) + 0.5) * p.pix - p.Zh
+    hz = half_z_frac * p.Zh
+    inside = (np.abs(zc) <= hz)[:, None]
+    mu = np.where(inside, mu2[None, :], 0.0)
+    act = np.where(inside, (act2 > 0).astype(np.float64)[None, :], 0.0)
+    rois = []
+    for roi2 in rois2:
+        ratio = float(act2[roi2].max())
+        cz = rng.uniform(-0.5 * hz, 0.5 * hz)
+        c = rng.uniform(7.0, 20.0)
+        roi = roi2[None, :] & ((np.abs(zc - cz) <= c) & (np.abs(zc) <= hz))[:, None]
+        act = np.where(roi, ratio, act)
+        rois.append(roi.ravel())
+    return mu.ravel(), act.ravel(), rois
+
+
+def generic_events3(p: SysParams, activity, n_events: int, seed: int, poisson=False,
+                    blur_mm=3.0, peak_frac=0.7, peak_sigma=5.0):
+    """generic_events for the 3-D geometry: emission voxel drawn in
+    proportion to `activity`, angle uniform, detector position = projection
+    of the voxel centre (u) and its z (v) plus a fixed Gaussian blur, energy as
+    in generic_events.  Returns bin, bin_z, angle, energy."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    J = int(rng.poisson(n_events)) if poisson else int(n_events)
+    act = np.asarray(activity, dtype=np.float64).ravel()
+    cdf = np.cumsum(act)
+    cdf /= cdf[-1]
+    x, y, z = voxel_centres(p)
+    lines = np.asarray(p.lines)
+    yields = np.asarray(p.yields) / np.sum(p.yields)
+    wins = np.asarray(p.windows)
+    out = {"bin": np.empty(J, np.int16), "bin_z": np.empty(J, np.int16),
+           "angle": np.empty(J, np.int16), "energy": np.empty(J, np.float32)}
+    db, dbz = p.fov / p.nb, 2 * p.Zh / p.nbz
+    filled = 0
+    while filled < J:
+        m = max(1024, 2 * (J - filled))
+        q = np.minimum(np.searchsorted(cdf, rng.random(m), side="right"), act.size - 1)
+        a = rng.integers(0, p.na, m)
+        th = 2 * np.pi * a / p.na
+        u = -x[q] * np.sin(th) + y[q] * np.cos(th) + rng.normal(0, blur_mm, m)
+        v = z[q] + rng.normal(0, blur_mm, m)
+        b = np.floor((u + p.R) / db).astype(np.int64)
+        bz = np.floor((v + p.Zh) / dbz).astype(np.int64)
+        w = rng.choice(len(lines), size=m, p=yields)
+        peak = rng.random(m) < peak_frac
+        e = np.where(peak, rng.normal(lines[w], peak_sigma), rng.uniform(0.4 * lines[w], lines[w]))
+        inwin = np.zeros(m, bool)
+        for lo, hi in wins:
+            inwin |= (e >= lo) & (e <= hi)
+        ok = (b >= 0) & (b < p.nb) & (bz >= 0) & (bz < p.nbz) & inwin
+        k = min(int(ok.sum()), J - filled)
+        idx = np.flatnonzero(ok)[:k]
+        out["bin"][filled:filled + k] = b[idx]
+        out["bin_z"][filled:filled + k] = bz[idx]
+        out["angle"][filled:filled + k] = a[idx]
+        out["energy"][filled:filled + k] = e[idx]
+        filled += k
+    return out
+
+
 def phantom(w: Workload, case: int = 0):
     if w.phantom == "disk2":
         return phantom_disk2(w.params)
+    if w.phantom == "disk2_3d":
+        return phantom_disk2_3d(w.params)
+    if w.phantom == "ellipse3_3d":
+        return phantom_ellipse3_3d(w.params, w.seed_phantom)
     seed = w.seed_phantom + (case if w.name == "c5" else 0)
     return phantom_ellipse3(w.params, seed)
 
@@ -308,5 +432,6 @@ def workload_inputs(name: str, case: int = 0, n_events=None):
 
 __all__ = ["SysParams", "Workload", "CONFIGS", "EW1", "EW2", "EW3", "SW", "pixel_centres",
            "fov_support", "phantom_disk2", "disk2_objects", "sew_events", "phantom_ellipse3",
-           "random_body_maps", "phantom", "case_counts",
+           "random_body_maps", "phantom", "case_counts", "DOMEGA", "voxel_centres",
+           "fov_support3", "phantom_disk2_3d", "phantom_ellipse3_3d", "generic_events3",
            "generic_events", "workload_inputs", "replace", "field"]
