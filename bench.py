@@ -200,6 +200,62 @@ def positions(ctx, ev, nsub, sens, lam0, J, steps):
             "frac": ach / PEAK_TERMS_PER_S, "frac_of_nonpacked_peak": ach / NONPACKED_PEAK_TERMS_PER_S}
 
 
+def three_d(steps):
+    """The 3-D single-scatter model on the 64x64 workload's slice geometry over
+    16 slices (64x64x16 voxels of 4 mm, 32x32x8 scatter grid, 64x16 bins,
+    120 angles, ~50k events, 8 subsets), matrix-free with the parameters
+    evaluated in the kernel (its path table would need 680 GB)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2305_17111_amd import Context, events_to_device
+
+    w = synth.CONFIGS["c2_3d"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    ev = synth.generic_events3(p, act, w.n_events, w.seed_events, poisson=w.poisson)
+    J = int(ev["angle"].size)
+    setup = {}
+    t = time.perf_counter()
+    ctx = Context(p, torch.from_numpy(np.asarray(mu, np.float32)))
+    torch.cuda.synchronize()
+    setup["tables_ms"] = 1e3 * (time.perf_counter() - t)
+    t = time.perf_counter()
+    sens = ctx.sensitivity(w.n_subsets)
+    torch.cuda.synchronize()
+    setup["sensitivity_ms"] = 1e3 * (time.perf_counter() - t)
+    t = time.perf_counter()
+    plan = ctx.plan(events_to_device(ev), w.n_subsets)
+    torch.cuda.synchronize()
+    setup["plan_ms"] = 1e3 * (time.perf_counter() - t)
+    plan.autotune(use_cache=False)
+    lam = torch.from_numpy(synth.fov_support3(p).astype(np.float32)).cuda()
+    plan.osem_iter(1, sens, lam)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.osem_iter(1, sens, lam)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n_launch = plan.profile_read()
+    plan.profile(False)
+    assert bool(torch.isfinite(lam).all())
+    terms, full = plan.terms()
+    ach = terms * steps / (ms * 1e-3)
+    return {"workload": "3-D single scatter: 64x64x16 voxels at 4 mm, 32x32x8 scatter grid "
+                        "(3048 points), 64x16 bins, 120 angles, EW1-3, %d events, %d subsets"
+                        % (J, w.n_subsets),
+            "value": J * steps / el, "unit": "events*iterations/s",
+            "s_per_iteration": el / steps, "steps": steps, "event_tile": plan.event_tile,
+            "k_row_avg_launch_ms": ms / n_launch, "k_row_share_of_step": ms / (1e3 * el),
+            "terms_per_iteration": {"evaluated": terms, "unpruned": full},
+            "frac": ach / PEAK_TERMS_PER_S,
+            "frac_of_nonpacked_peak": ach / NONPACKED_PEAK_TERMS_PER_S,
+            "setup_ms": setup}
+
+
 def _time_graph(plan, sens, lam, steps):
     """Seconds per launch of a one-iteration graph (after one warmup launch)."""
     import torch
@@ -345,6 +401,9 @@ def main():
     ap.add_argument("--no-cached", action="store_true")
     ap.add_argument("--no-position", action="store_true",
                     help="skip the continuous-position variant of the headline iterations")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the 3-D single-scatter workload")
+    ap.add_argument("--steps-3d", type=int, default=2)
     ap.add_argument("--no-path-table", action="store_true",
                     help="evaluate the scatter-path parameters inside the per-event kernel")
     ap.add_argument("--surrogate-steps", type=int, default=1)
@@ -519,6 +578,8 @@ def main():
                                      "frac": ach_nt / PEAK_TERMS_PER_S,
                                      "frac_of_nonpacked_peak": ach_nt / NONPACKED_PEAK_TERMS_PER_S}
     del plan
+    if not args.no_3d:
+        out["three_d"] = three_d(args.steps_3d)
     if not args.no_surrogate:
         out["surrogate"] = surrogate(args)
     if not args.no_cpu_baseline:

@@ -26,6 +26,13 @@
  *     n_angles (exact at multiples of 90 degrees); bin b covers the lateral
  *     coordinate u = -x sin t + y cos t in [-R + b*db, -R + (b+1)*db),
  *     db = 2R / n_bins; the detector plane is x.n = R.
+ *   - The 3-D model (nz > 0 in lmmew_system): the grid stacks nz slices of
+ *     n x n voxels of side pixel_mm; voxel (ix, iy, iz) has flat index
+ *     q = (iz*n + iy)*n + ix and centre z = (iz+1/2)pix - Zh, Zh = nz*pix/2;
+ *     every "n*n" below then reads n*n*nz.  The camera rotates about z: bin
+ *     b is as above and axial bin bz covers z in [-Zh + bz*dbz,
+ *     -Zh + (bz+1)*dbz), dbz = 2 Zh / n_bins_z.  The support is the
+ *     cylinder of radius R (and the caller's mask).
  *   - Subset s of an n_subsets partition holds the angles a with
  *     a mod n_subsets == s; subsets are visited in order 0..n_subsets-1.
  *   - Every pointer argument documented as "device" is memory the caller
@@ -79,6 +86,18 @@ typedef struct lmmew_system {
     double mu_power;           /* mu(E) = mu(mu_ref) * (E / mu_ref)^(-mu_power) */
     double T;                  /* acquisition time (Eq. (2)) */
     double electron_keV;       /* electron rest energy used by Klein-Nishina */
+    /* 3-D single-scatter model (the extension the paper names as its next
+     * step, Sec. 5 and the appendix on 3-D computational requirements): Eq.
+     * (5) with emission into the solid angle coll_solid_angle / (4 pi), the
+     * scattered photon's direction drawn from the Klein-Nishina density per
+     * steradian, scatter points on an ns x ns x ns_z grid, and a
+     * depth-dependent Gaussian response separable in u and z.  nz = 0 keeps
+     * the planar model of the paper's evaluation (coll_dtheta), and then the
+     * three fields below are ignored. */
+    int32_t nz;                /* slices; 0: planar model */
+    int32_t ns_z;              /* scatter points along z; nz/ns_z must be an even integer */
+    int32_t n_bins_z;          /* axial detector bins, 1..32767 */
+    double coll_solid_angle;   /* collimator acceptance solid angle, sr */
 } lmmew_system;
 
 /* List-mode data (lmData of Algorithm 1): one entry per detected photon.
@@ -98,6 +117,9 @@ typedef struct lmmew_events {
     const int16_t *angle;
     const float *energy_keV;
     const float *position_mm;
+    const int16_t *bin_z;      /* 3-D model: axial bins (required, 0 <= bin_z < n_bins_z;
+                                  continuous positions are not supported there); planar:
+                                  ignored */
 } lmmew_events;
 
 /* Optional statistics of an OSEM call (host memory owned by the caller). */
@@ -345,7 +367,9 @@ int lmmew_rows(lmmew_ctx *ctx, const lmmew_events *ev, int part, float *rows, hi
 #define LMMEW_MLP_PARAMS 34049
 
 /* Creates a network for the context with Glorot-uniform weights (zero biases)
- * drawn from a counter-based generator seeded with seed.  Synchronises. */
+ * drawn from a counter-based generator seeded with seed.  Synchronises.
+ * The surrogate models the planar system: EINVAL for a 3-D context (as for
+ * lmmew_scatter_labels). */
 int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out);
 int lmmew_mlp_destroy(lmmew_mlp *mlp);
 

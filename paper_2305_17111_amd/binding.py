@@ -35,12 +35,15 @@ class _System(C.Structure):
         ("eres_frac", C.c_double), ("eres_ref_keV", C.c_double),
         ("mu_ref_keV", C.c_double), ("mu_power", C.c_double),
         ("T", C.c_double), ("electron_keV", C.c_double),
+        ("nz", C.c_int32), ("ns_z", C.c_int32), ("n_bins_z", C.c_int32),
+        ("coll_solid_angle", C.c_double),
     ]
 
 
 class _Events(C.Structure):
     _fields_ = [("n", C.c_int64), ("bin", C.c_void_p), ("angle", C.c_void_p),
-                ("energy_keV", C.c_void_p), ("position_mm", C.c_void_p)]
+                ("energy_keV", C.c_void_p), ("position_mm", C.c_void_p),
+                ("bin_z", C.c_void_p)]
 
 
 class _Stats(C.Structure):
@@ -127,7 +130,7 @@ def _ptr(t):
 def system_from_params(p) -> _System:
     """Fill lmmew_system from any object with the system attributes (n, pix, ns, nb,
     na, fwhm0, fwhm_slope, dtheta, lines, yields, windows, eres_frac, eres_ref,
-    mu_ref, mu_pow, T, me)."""
+    mu_ref, mu_pow, T, me; for the 3-D model also nz, nsz, nbz, domega)."""
     s = _System()
     s.n, s.ns, s.n_bins, s.n_angles = int(p.n), int(p.ns), int(p.nb), int(p.na)
     s.n_lines, s.n_windows = len(p.lines), len(p.windows)
@@ -140,6 +143,10 @@ def system_from_params(p) -> _System:
     s.eres_frac, s.eres_ref_keV = float(p.eres_frac), float(p.eres_ref)
     s.mu_ref_keV, s.mu_power = float(p.mu_ref), float(p.mu_pow)
     s.T, s.electron_keV = float(p.T), float(p.me)
+    nz = int(getattr(p, "nz", 0) or 0)
+    if nz > 0:
+        s.nz, s.ns_z, s.n_bins_z = nz, int(p.nsz), int(p.nbz)
+        s.coll_solid_angle = float(p.domega)
     return s
 
 
@@ -179,6 +186,9 @@ def events_to_device(ev, device="cuda"):
     else:
         out["position"] = torch.as_tensor(ev["position"]).to(device=device,
                                                              dtype=torch.float32).contiguous()
+    if "bin_z" in ev:
+        out["bin_z"] = torch.as_tensor(ev["bin_z"]).to(device=device,
+                                                       dtype=torch.int16).contiguous()
     return out
 
 
@@ -194,9 +204,15 @@ def _events(ev):
     n = a.numel()
     if x.numel() != n or e.numel() != n:
         raise ValueError("event arrays differ in length")
+    bz = None
+    if "bin_z" in ev:
+        z = ev["bin_z"]
+        if z.dtype != torch.int16 or not z.is_cuda or not z.is_contiguous() or z.numel() != n:
+            raise TypeError("bin_z must be a contiguous int16 device tensor of the events' length")
+        bz = z.data_ptr()
     if cont:
-        return _Events(n, None, a.data_ptr(), e.data_ptr(), x.data_ptr())
-    return _Events(n, x.data_ptr(), a.data_ptr(), e.data_ptr(), None)
+        return _Events(n, None, a.data_ptr(), e.data_ptr(), x.data_ptr(), bz)
+    return _Events(n, x.data_ptr(), a.data_ptr(), e.data_ptr(), None, bz)
 
 
 class Context:
@@ -207,10 +223,11 @@ class Context:
         self.params = params
         self.sys = system_from_params(params)
         self.n = int(params.n)
-        self.Q = self.n * self.n
+        self.nz = int(getattr(params, "nz", 0) or 0)
+        self.Q = self.n * self.n * max(self.nz, 1)
         self.mu85 = torch.as_tensor(mu85).to("cuda", torch.float32).contiguous().view(-1)
         if self.mu85.numel() != self.Q:
-            raise ValueError("mu85 must have n*n entries")
+            raise ValueError("mu85 must have n*n (3-D: n*n*nz) entries")
         self.support = None
         if support is not None:
             self.support = torch.as_tensor(support).to("cuda", torch.uint8).contiguous().view(-1)

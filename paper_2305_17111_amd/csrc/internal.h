@@ -41,13 +41,15 @@ struct DevSys {
     float T;
     float eres_k;                   // sigma_E^2 = eres_k * E
     float mu_pow;
-    float rmin;                     // hs / (2 sqrt(pi))
+    float rmin;                     // planar: hs / (2 sqrt(pi)); 3-D: (3 V / 4 pi)^(1/3) / sqrt(3)
+    int nz, nbz;                    // 3-D: slices and axial bins (nz = 0: the planar model)
+    float Zh, dbz;                  // 3-D: axial half-length and axial bin width
     // per line
     float E[LMMEW_MAX_LINES];
     float eps[LMMEW_MAX_LINES];     // E / m_e c^2
     float f[LMMEW_MAX_LINES];       // mu(E_w)/mu_ref
-    float pp[LMMEW_MAX_LINES];      // alpha_w * dtheta / (2 pi)
-    float lsc[LMMEW_MAX_LINES];     // log2(alpha_w * f_w * dtheta / Z_w)
+    float pp[LMMEW_MAX_LINES];      // alpha_w * dtheta / (2 pi); 3-D: alpha_w * dOmega / (4 pi)
+    float lsc[LMMEW_MAX_LINES];     // log2(alpha_w * f_w * dtheta / Z_w); 3-D: dOmega, sphere Z_w
     float c0[LMMEW_MAX_LINES];      // log2(e) / (2 eres_k E_w)
     float sqc0[LMMEW_MAX_LINES];    // sqrt(c0)
     float nc[LMMEW_MAX_LINES];      // -0.5 log2(2 pi eres_k E_w)
@@ -61,7 +63,7 @@ struct ScatA {
     float u;            // lateral detector coordinate
     float isig;         // 1 / PSF sigma at its depth
     float gsa;          // attenuation integral at mu_ref to the detector plane
-    float lc;           // log2(hs^2 * mu_s / (2 pi))
+    float lc;           // log2(hs^2 * mu_s / (2 pi)); 3-D: log2(V * mu_s / (4 pi))
     float D;            // probability of landing on the detector
     int sidx;           // index into the [nsc][Qp] pixel->scatter table
 };
@@ -82,10 +84,12 @@ struct Chunk {
 };
 
 // ---- launchers (kernels.hip) ------------------------------------------------
-// Attenuation tables, computed in double precision.
+// Attenuation tables, computed in double precision.  In 3-D, pixz and scz
+// hold the z of the support voxels and of the scatter points (NULL in 2-D).
 hipError_t launch_tables_d(const DevSys &S, const double *mu, const double2 *pix,
-                           const double2 *dirs, const double2 *sc, float *g_qa, float *g_qs,
-                           ScatA *sa, double pixmm, double R, hipStream_t st);
+                           const double *pixz, const double2 *dirs, const double2 *sc,
+                           const double *scz, float *g_qa, float *g_qs, ScatA *sa, double pixmm,
+                           double R, hipStream_t st);
 
 // Tables of one attenuation map, for plans whose cases use different maps.
 struct MapTab {
@@ -94,6 +98,8 @@ struct MapTab {
     const ScatA *sa;         // [na][nsc]
     const float *ptab;       // path-parameter table (see RowArgs) or NULL
     const float *resp;       // collimator-response factors (see RowArgs)
+    const float *respz;      // 3-D: axial response factors (see RowArgs)
+    const float *sz;         // 3-D: scatter-point z (see RowArgs)
     int nsc, pad;
 };
 
@@ -108,22 +114,29 @@ struct RowArgs {
                              // weight, s_w, F_w), or NULL to evaluate them in the kernel
     const float *resp;       // [na][nsc][nb] collimator-response factor of scatter point k
                              // (angle's sorted order) for bin b, 0 beyond 7 sigma
+    const float *respz;      // 3-D: [na][nsc][nbz] the same for the axial bin
+    const float *pix_z;      // 3-D: [Qp] z of the support voxels
+    const float *sz;         // 3-D: [nsc] z of the scatter points (by g_qs row)
     const Tile *tiles;
     const int2 *slist;       // scatter list entries of the tiles: (point in the angle's
                              // sorted list, row of the point in the g_qs table)
     int ntiles;
     const int *ev_bin;       // sorted rows of this subset: detector bins (NULL for positions)
+    const int *ev_binz;      // 3-D: sorted rows: axial bins
     const float *ev_u;       // sorted rows: continuous lateral positions (mm), or NULL (bins)
     const float *ev_E;
     float *A;                // [rows][Qp]
     int mode;                // 0: all paths, 1: scattered paths only, 2: unscattered only
 };
 hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st);
-// collimator-response factors of every (angle, scatter point, bin)
-hipError_t launch_resp_table(const DevSys &S, const ScatA *sa, float *resp, hipStream_t st);
+// collimator-response factors of every (angle, scatter point, bin); in 3-D also
+// every (angle, scatter point, axial bin) into respz (sz: scatter-point z by g_qs row)
+hipError_t launch_resp_table(const DevSys &S, const ScatA *sa, float *resp, const float *sz,
+                             float *respz, hipStream_t st);
 // scatter-path parameters of every (angle, scatter point, support pixel)
-hipError_t launch_path_table(const DevSys &S, const float2 *pix_xy, const float2 *dirs,
-                             const float *g_qs, const ScatA *sa, float *ptab, hipStream_t st);
+hipError_t launch_path_table(const DevSys &S, const float2 *pix_xy, const float *pix_z,
+                             const float2 *dirs, const float *g_qs, const ScatA *sa,
+                             const float *sz, float *ptab, hipStream_t st);
 
 struct FwdArgs {
     const float *A;          // [rows][Qp]
@@ -165,6 +178,8 @@ hipError_t launch_update(const DevSys &S, const UpdArgs &u, hipStream_t st);
 
 struct SensArgs {
     const float2 *pix_xy;
+    const float *pix_z;      // 3-D: [Qp] voxel z
+    const float *sz;         // 3-D: [nsc] scatter-point z by g_qs row
     const float2 *dirs;
     const float *g_qa;
     const float *g_qs;

@@ -177,7 +177,74 @@ struct TabArgsD {
     const double2 *sc;      // [nsc]
     float *g_qa, *g_qs;
     ScatA *sa;
+    const double *pixz;     // 3-D: [Qp] voxel z
+    const double *scz;      // 3-D: [nsc] scatter-point z
 };
+
+// ---- 3-D: voxel maps of nz slices of n x n, flat index (iz*n + iy)*n + ix ----
+
+// Integral of the voxel map over a segment, walking the voxels it crosses in
+// order (the segments from voxel centres to scatter points never lie in a
+// grid plane: both sit at different offsets from the planes).
+__device__ double walk_segment3(const double *mu, int n, int nz, double pix, double R, double Zh,
+                                double x0, double y0, double z0, double x1, double y1,
+                                double z1)
+{
+    const double d[3] = {x1 - x0, y1 - y0, z1 - z0};
+    const double o[3] = {x0, y0, z0};
+    const double lo[3] = {-R, -R, -Zh}, hi[3] = {R, R, Zh};
+    const int cells[3] = {n, n, nz};
+    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (L == 0.0) return 0.0;
+    double tmin = 0.0, tmax = 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (d[k] != 0.0) {
+            const double ta = (lo[k] - o[k]) / d[k], tb = (hi[k] - o[k]) / d[k];
+            tmin = fmax(tmin, fmin(ta, tb));
+            tmax = fmin(tmax, fmax(ta, tb));
+        } else if (o[k] < lo[k] || o[k] > hi[k]) {
+            return 0.0;
+        }
+    }
+    if (!(tmax > tmin)) return 0.0;
+    int idx[3], step[3];
+    double tn[3], dt[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double f = (o[k] + tmin * d[k] - lo[k]) / pix;
+        int c = (d[k] >= 0.0) ? (int)floor(f) : (int)ceil(f) - 1;   // cell entered
+        c = min(max(c, 0), cells[k] - 1);
+        idx[k] = c;
+        step[k] = d[k] > 0.0 ? 1 : -1;
+        if (d[k] != 0.0) {
+            const double b = (d[k] > 0.0 ? c + 1 : c) * pix + lo[k];
+            tn[k] = (b - o[k]) / d[k];
+            dt[k] = pix / fabs(d[k]);
+        } else {
+            tn[k] = INFINITY;
+            dt[k] = INFINITY;
+        }
+    }
+    double t = tmin, sum = 0.0;
+    for (int guard = 0; guard < 2 * (2 * n + nz) + 4; ++guard) {
+        const double tnx = fmin(fmin(tn[0], tn[1]), fmin(tn[2], tmax));
+        if (tnx > t) sum += mu[((size_t)idx[2] * n + idx[1]) * n + idx[0]] * (tnx - t);
+        t = tnx;
+        if (t >= tmax) break;
+        bool out = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (tn[k] <= tnx) {
+                idx[k] += step[k];
+                tn[k] += dt[k];
+                out |= idx[k] < 0 || idx[k] >= cells[k];
+            }
+        }
+        if (out) break;
+    }
+    return sum * L;
+}
 
 __global__ __launch_bounds__(256) void k_tab_qa(const DevSys S, const TabArgsD t, double pix,
                                                 double R)
@@ -229,6 +296,85 @@ __global__ __launch_bounds__(256) void k_tab_sa(const DevSys S, const TabArgsD t
     e.D = (float)D;
 }
 
+// Detector probability of a Gaussian of 1/sigma isig about (u, z) on
+// [-R, R] x [-Zh, Zh], in double precision.
+__device__ double detector_prob3(double u, double z, double isig, double R, double Zh)
+{
+    const double r2 = 0.70710678118654752;
+    auto pd = [&](double zhi, double zlo) {
+        if (zlo >= 0.0) return 0.5 * (erfc(zlo * r2) - erfc(zhi * r2));
+        if (zhi <= 0.0) return 0.5 * (erfc(-zhi * r2) - erfc(-zlo * r2));
+        return 1.0 - 0.5 * erfc(zhi * r2) - 0.5 * erfc(-zlo * r2);
+    };
+    return pd((R - u) * isig, (-R - u) * isig) * pd((Zh - z) * isig, (-Zh - z) * isig);
+}
+
+// 3-D: voxel -> detector plane, a horizontal segment inside the voxel's slice
+__global__ __launch_bounds__(256) void k_tab3_qa(const DevSys S, const TabArgsD t, double pix,
+                                                 double R)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = blockIdx.y;
+    if (i >= S.Qp) return;
+    float v = 0.f;
+    if (i < S.Qm) {
+        const double2 p = t.pix[i], d = t.dirs[a];
+        const int iz = (int)floor((t.pixz[i] + (double)S.nz * 0.5 * pix) / pix);
+        const double depth = R - (p.x * d.x + p.y * d.y);
+        v = (float)seg_integral(t.mu + (size_t)iz * S.n * S.n, S.n, pix, R, p.x, p.y,
+                                p.x + depth * d.x, p.y + depth * d.y);
+    }
+    t.g_qa[(size_t)a * S.Qp + i] = v;
+}
+
+// 3-D: voxel -> scatter point
+__global__ __launch_bounds__(256) void k_tab3_qs(const DevSys S, const TabArgsD t, double pix,
+                                                 double R)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = blockIdx.y;
+    if (i >= S.Qp) return;
+    float v = 0.f;
+    if (i < S.Qm) {
+        const double2 p = t.pix[i], q = t.sc[s];
+        const double Zh = (double)S.nz * 0.5 * pix;
+        v = (float)walk_segment3(t.mu, S.n, S.nz, pix, R, Zh, p.x, p.y, t.pixz[i], q.x, q.y,
+                                 t.scz[s]);
+    }
+    t.g_qs[(size_t)s * S.Qp + i] = v;
+}
+
+// 3-D: scatter point -> detector plane, a horizontal segment at the point's z.
+// A point on a slice boundary sees the mean of the two slices that share it
+// (the limit of segments displaced by +-delta; a slice outside the grid
+// contributes zero).  Also the point's probability of landing on the detector.
+__global__ __launch_bounds__(256) void k_tab3_sa(const DevSys S, const TabArgsD t, double pix,
+                                                 double R)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = blockIdx.y;
+    if (k >= S.nsc) return;
+    ScatA &e = t.sa[(size_t)a * S.nsc + k];
+    const double2 q = t.sc[e.sidx], d = t.dirs[a];
+    const double z = t.scz[e.sidx];
+    const double Zh = (double)S.nz * 0.5 * pix;
+    const double depth = R - (q.x * d.x + q.y * d.y);
+    const double x1 = q.x + depth * d.x, y1 = q.y + depth * d.y;
+    const double f = (z + Zh) / pix, kz = rint(f);
+    auto slice = [&](int iz) {
+        if (iz < 0 || iz >= S.nz) return 0.0;
+        return seg_integral(t.mu + (size_t)iz * S.n * S.n, S.n, pix, R, q.x, q.y, x1, y1);
+    };
+    double g;
+    if (fabs(f - kz) < 1e-9)
+        g = 0.5 * (slice((int)kz - 1) + slice((int)kz));
+    else
+        g = slice((int)floor(f));
+    e.gsa = (float)g;
+    const double u = -q.x * d.y + q.y * d.x;
+    e.D = (float)detector_prob3(u, z, (double)e.isig, R, Zh);
+}
+
 // ---------------------------------------------------------------------------
 // scatter-path parameters of one (pixel, scatter point, angle)
 // ---------------------------------------------------------------------------
@@ -236,20 +382,21 @@ __global__ __launch_bounds__(256) void k_tab_sa(const DevSys S, const TabArgsD t
 // For each line w: log2 of the path weight (with or without the energy
 // Gaussian's normalisation), the scaled Compton energy sw*E' and sw =
 // sqrt(log2(e) / (2 sigma'^2)), so that the energy factor of an event with
-// measured energy E is exp2(-(sw*E - Fw)^2).
-template <int NW, bool NORM>
-__device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float dy, float c,
-                                               float s, float lc, float gqs, float gsa,
+// measured energy E is exp2(-(sw*E - Fw)^2).  The planar model's cell
+// interaction probability falls as 1/r, the 3-D model's (D3) as 1/r^2.
+template <int NW, bool NORM, bool D3 = false>
+__device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float dy, float dz,
+                                               float c, float s, float lc, float gqs, float gsa,
                                                float *Aw, float *sw, float *Fw, float *Ep)
 {
-    const float r2 = dx * dx + dy * dy;
+    const float r2 = D3 ? fmaf(dz, dz, fmaf(dx, dx, dy * dy)) : dx * dx + dy * dy;
     const float rinv = fast_rsq(r2);
     const float r = r2 * rinv;
     const float reff = fmaxf(r, S.rmin);
     const float cosphi = (dx * c + dy * s) * rinv;
     const float omc = 1.f - cosphi;
     const float sin2 = omc * (1.f + cosphi);
-    const float base = lc - fast_log2(reff);
+    const float base = D3 ? lc - 2.f * fast_log2(reff) : lc - fast_log2(reff);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
@@ -285,7 +432,7 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
 // branch.  For each listed scatter point every lane derives its pixel's path
 // parameters once and reuses them for all of the tile's events.
 // ---------------------------------------------------------------------------
-template <int JT, int NW, bool TAB>
+template <int JT, int NW, bool TAB, bool D3>
 __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 {
     constexpr int KC = 16;               // scatter points per response block
@@ -306,6 +453,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const int a = T.angle;
     // attenuation tables of the tile's case
     const float *g_qa = r.g_qa, *g_qs = r.g_qs, *ptab = r.ptab, *resp = r.resp;
+    const float *respz = r.respz, *szs = r.sz;
     const ScatA *sab = r.sa;
     int nsc = S.nsc;
     if (r.maps) {
@@ -315,6 +463,8 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         sab = m.sa;
         ptab = m.ptab;
         resp = m.resp;
+        respz = m.respz;
+        szs = m.sz;
         nsc = m.nsc;
     }
     const float2 dir = r.dirs[a];
@@ -336,6 +486,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 
     const float2 xy = r.pix_xy[i];
     const float xq = xy.x, yq = xy.y;
+    const float zq = D3 ? r.pix_z[i] : 0.f;
 
     // unscattered paths, staged in LDS (each row element is written once, at the end)
     __shared__ float prim[JT * kWave];
@@ -355,6 +506,10 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                 } else {
                     const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
                     ps = psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
+                    if (D3) {
+                        const float lz = -S.Zh + (float)r.ev_binz[T.e0 + j] * S.dbz;
+                        ps *= psf_cut((lz + S.dbz - zq) * isq, (lz - zq) * isq);
+                    }
                 }
             }
             float g = 0.f;
@@ -401,6 +556,14 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                     const int j = jg * TJ + t;
                     pv[t] = (l < T.k1 && j < T.cnt) ? rrow[r.ev_bin[T.e0 + min(j, last)]] : 0.f;
                 }
+                if (D3) {
+                    const float *zrow = respz + ((size_t)a * nsc + k) * S.nbz;
+#pragma unroll
+                    for (int t = 0; t < TJ; ++t) {
+                        const int j = jg * TJ + t;
+                        pv[t] *= zrow[r.ev_binz[T.e0 + min(j, last)]];
+                    }
+                }
             }
         }
         const int kn = min(KC, T.k1 - lc0);
@@ -412,7 +575,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         const size_t pstride = (size_t)S.Qp * pw;                  // one point of the angle
         int2 en = r.slist[lc0];
         ScatA spn{};
-        float gqn = 0.f;
+        float gqn = 0.f, szn = 0.f;
         float An[NW], sn[NW], Fn[NW];
         if (TAB) {
             const float *tp = pbase + (size_t)en.x * pstride;
@@ -426,6 +589,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         } else {
             spn = sa[en.x];
             gqn = g_qs[(size_t)en.y * S.Qp + i];
+            if (D3) szn = szs[en.y];
         }
         for (int kk = 0; kk < kn; ++kk) {
             float Aw[NW], sw[NW], Fw[NW];
@@ -449,15 +613,16 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                 }
             } else {
                 const ScatA sp = spn;
-                const float gqs = gqn;
+                const float gqs = gqn, zs = szn;
                 if (kk + 1 < kn) {
                     en = r.slist[lc0 + kk + 1];
                     spn = sa[en.x];
                     gqn = g_qs[(size_t)en.y * S.Qp + i];
+                    if (D3) szn = szs[en.y];
                 }
                 float Ep[NW];
-                scatter_params<NW, true>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw,
-                                         sw, Fw, Ep);
+                scatter_params<NW, true, D3>(S, sp.x - xq, sp.y - yq, zs - zq, c, s, sp.lc, gqs,
+                                             sp.gsa, Aw, sw, Fw, Ep);
             }
 #pragma unroll
             for (int j = 0; j < JT; ++j) {
@@ -488,19 +653,19 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     }
 }
 
-template <int JT, bool TAB>
+template <int JT, bool TAB, bool D3>
 static hipError_t launch_row_jt(const DevSys &S, const RowArgs &r, hipStream_t st)
 {
     // one workgroup per (pixel block, tile), remapped per XCD inside the kernel
     const long W = (long)(S.Qp / kWave) * r.ntiles;
     dim3 grid((unsigned)((W + 7) / 8 * 8));
     switch (S.nw) {
-    case 1: hipLaunchKernelGGL((k_row<JT, 1, TAB>), grid, dim3(kWave), 0, st, S, r); break;
-    case 2: hipLaunchKernelGGL((k_row<JT, 2, TAB>), grid, dim3(kWave), 0, st, S, r); break;
-    case 3: hipLaunchKernelGGL((k_row<JT, 3, TAB>), grid, dim3(kWave), 0, st, S, r); break;
-    case 4: hipLaunchKernelGGL((k_row<JT, 4, TAB>), grid, dim3(kWave), 0, st, S, r); break;
+    case 1: hipLaunchKernelGGL((k_row<JT, 1, TAB, D3>), grid, dim3(kWave), 0, st, S, r); break;
+    case 2: hipLaunchKernelGGL((k_row<JT, 2, TAB, D3>), grid, dim3(kWave), 0, st, S, r); break;
+    case 3: hipLaunchKernelGGL((k_row<JT, 3, TAB, D3>), grid, dim3(kWave), 0, st, S, r); break;
+    case 4: hipLaunchKernelGGL((k_row<JT, 4, TAB, D3>), grid, dim3(kWave), 0, st, S, r); break;
     default:
-        hipLaunchKernelGGL((k_row<JT, LMMEW_MAX_LINES, TAB>), grid, dim3(kWave), 0, st, S, r);
+        hipLaunchKernelGGL((k_row<JT, LMMEW_MAX_LINES, TAB, D3>), grid, dim3(kWave), 0, st, S, r);
         break;
     }
     return hipGetLastError();
@@ -519,29 +684,50 @@ __global__ __launch_bounds__(256) void k_resp_table(const DevSys S, const ScatA 
     resp[t] = psf_cut((lo + S.db - sp.u) * sp.isig, (lo - sp.u) * sp.isig);
 }
 
-hipError_t launch_resp_table(const DevSys &S, const ScatA *sa, float *resp, hipStream_t st)
+// 3-D: the axial factors, one thread per (angle, scatter point, axial bin)
+__global__ __launch_bounds__(256) void k_resp_table_z(const DevSys S, const ScatA *sa,
+                                                      const float *sz, float *respz)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)S.na * S.nsc * S.nbz) return;
+    const int b = (int)(t % S.nbz);
+    const ScatA sp = sa[t / S.nbz];
+    const float z = sz[sp.sidx];
+    const float lo = -S.Zh + (float)b * S.dbz;
+    respz[t] = psf_cut((lo + S.dbz - z) * sp.isig, (lo - z) * sp.isig);
+}
+
+hipError_t launch_resp_table(const DevSys &S, const ScatA *sa, float *resp, const float *sz,
+                             float *respz, hipStream_t st)
 {
     const long n = (long)S.na * S.nsc * S.nb;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_resp_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S, sa,
                        resp);
+    if (S.nz > 0) {
+        const long nz = (long)S.na * S.nsc * S.nbz;
+        hipLaunchKernelGGL(k_resp_table_z, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st,
+                           S, sa, sz, respz);
+    }
     return hipGetLastError();
 }
 
 // the path-parameter table: one workgroup per (64 pixels, scatter point, angle)
-template <int NW>
+template <int NW, bool D3>
 __global__ __launch_bounds__(64) void k_path_table(const DevSys S, const float2 *pix_xy,
-                                                   const float2 *dirs, const float *g_qs,
-                                                   const ScatA *sa, float *ptab)
+                                                   const float *pix_z, const float2 *dirs,
+                                                   const float *g_qs, const ScatA *sa,
+                                                   const float *sz, float *ptab)
 {
     const int i = blockIdx.x * kWave + threadIdx.x;
     const int k = blockIdx.y, a = blockIdx.z;
     const ScatA sp = sa[(size_t)a * S.nsc + k];
     const float2 xy = pix_xy[i], dir = dirs[a];
     const float gqs = g_qs[(size_t)sp.sidx * S.Qp + i];
+    const float dz = D3 ? sz[sp.sidx] - pix_z[i] : 0.f;
     float Aw[NW], sw[NW], Fw[NW], Ep[NW];
-    scatter_params<NW, true>(S, sp.x - xy.x, sp.y - xy.y, dir.x, dir.y, sp.lc, gqs, sp.gsa, Aw,
-                             sw, Fw, Ep);
+    scatter_params<NW, true, D3>(S, sp.x - xy.x, sp.y - xy.y, dz, dir.x, dir.y, sp.lc, gqs,
+                                 sp.gsa, Aw, sw, Fw, Ep);
     float *tp = ptab + (((size_t)a * S.nsc + k) * S.Qp + i) * 3 * S.nw;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -552,20 +738,33 @@ __global__ __launch_bounds__(64) void k_path_table(const DevSys S, const float2 
     }
 }
 
-hipError_t launch_path_table(const DevSys &S, const float2 *pix_xy, const float2 *dirs,
-                             const float *g_qs, const ScatA *sa, float *ptab, hipStream_t st)
+template <bool D3>
+static void launch_path_table_d(const DevSys &S, const float2 *pix_xy, const float *pix_z,
+                                const float2 *dirs, const float *g_qs, const ScatA *sa,
+                                const float *sz, float *ptab, hipStream_t st)
+{
+    const dim3 grid(S.Qp / kWave, S.nsc, S.na);
+#define PT(NWV) hipLaunchKernelGGL((k_path_table<NWV, D3>), grid, dim3(kWave), 0, st, S, pix_xy, \
+                                   pix_z, dirs, g_qs, sa, sz, ptab)
+    switch (S.nw) {
+    case 1: PT(1); break;
+    case 2: PT(2); break;
+    case 3: PT(3); break;
+    case 4: PT(4); break;
+    default: PT(LMMEW_MAX_LINES); break;
+    }
+#undef PT
+}
+
+hipError_t launch_path_table(const DevSys &S, const float2 *pix_xy, const float *pix_z,
+                             const float2 *dirs, const float *g_qs, const ScatA *sa,
+                             const float *sz, float *ptab, hipStream_t st)
 {
     if (S.nsc == 0) return hipSuccess;
-    const dim3 grid(S.Qp / kWave, S.nsc, S.na);
-    switch (S.nw) {
-    case 1: hipLaunchKernelGGL((k_path_table<1>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
-    case 2: hipLaunchKernelGGL((k_path_table<2>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
-    case 3: hipLaunchKernelGGL((k_path_table<3>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
-    case 4: hipLaunchKernelGGL((k_path_table<4>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab); break;
-    default:
-        hipLaunchKernelGGL((k_path_table<LMMEW_MAX_LINES>), grid, dim3(kWave), 0, st, S, pix_xy, dirs, g_qs, sa, ptab);
-        break;
-    }
+    if (S.nz > 0)
+        launch_path_table_d<true>(S, pix_xy, pix_z, dirs, g_qs, sa, sz, ptab, st);
+    else
+        launch_path_table_d<false>(S, pix_xy, pix_z, dirs, g_qs, sa, sz, ptab, st);
     return hipGetLastError();
 }
 
@@ -574,10 +773,23 @@ hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStre
     if (r.ntiles == 0) return hipSuccess;
     // the table is used when the tiles' cases all have one (see the plan)
     const bool tab = r.ptab != nullptr;
+    if (S.nz > 0) {
+        switch (event_tile) {
+        case 16: return tab ? launch_row_jt<16, true, true>(S, r, st)
+                            : launch_row_jt<16, false, true>(S, r, st);
+        case 32: return tab ? launch_row_jt<32, true, true>(S, r, st)
+                            : launch_row_jt<32, false, true>(S, r, st);
+        default: return tab ? launch_row_jt<64, true, true>(S, r, st)
+                            : launch_row_jt<64, false, true>(S, r, st);
+        }
+    }
     switch (event_tile) {
-    case 16: return tab ? launch_row_jt<16, true>(S, r, st) : launch_row_jt<16, false>(S, r, st);
-    case 32: return tab ? launch_row_jt<32, true>(S, r, st) : launch_row_jt<32, false>(S, r, st);
-    default: return tab ? launch_row_jt<64, true>(S, r, st) : launch_row_jt<64, false>(S, r, st);
+    case 16: return tab ? launch_row_jt<16, true, false>(S, r, st)
+                        : launch_row_jt<16, false, false>(S, r, st);
+    case 32: return tab ? launch_row_jt<32, true, false>(S, r, st)
+                        : launch_row_jt<32, false, false>(S, r, st);
+    default: return tab ? launch_row_jt<64, true, false>(S, r, st)
+                        : launch_row_jt<64, false, false>(S, r, st);
     }
 }
 
@@ -717,7 +929,7 @@ __global__ __launch_bounds__(256) void k_update(const DevSys S, const UpdArgs u)
 // ---------------------------------------------------------------------------
 // sensitivity: per (pixel, angle) detection probability, then per subset
 // ---------------------------------------------------------------------------
-template <int NW>
+template <int NW, bool D3>
 __global__ __launch_bounds__(64) void k_sens(const DevSys S, const SensArgs g)
 {
     const int i = blockIdx.x * kWave + threadIdx.x;
@@ -726,10 +938,12 @@ __global__ __launch_bounds__(64) void k_sens(const DevSys S, const SensArgs g)
     const float c = dir.x, s = dir.y;
     const float2 xy = g.pix_xy[i];
     const float xq = xy.x, yq = xy.y;
+    const float zq = D3 ? g.pix_z[i] : 0.f;
     const float dq = S.R - (xq * c + yq * s);
     const float uq = -xq * s + yq * c;
     const float isq = 1.f / ((S.fwhm0 + S.fslope * dq) * S.inv_fwhm_to_sigma);
-    const float Dq = phi_diff((S.R - uq) * isq, (-S.R - uq) * isq);
+    float Dq = phi_diff((S.R - uq) * isq, (-S.R - uq) * isq);
+    if (D3) Dq *= phi_diff((S.Zh - zq) * isq, (-S.Zh - zq) * isq);
     const float gqa = g.g_qa[(size_t)a * S.Qp + i];
 
     auto acceptance = [&](float E) {
@@ -750,9 +964,10 @@ __global__ __launch_bounds__(64) void k_sens(const DevSys S, const SensArgs g)
     for (int k = 0; k < S.nsc; ++k) {
         const ScatA sp = sa[k];
         const float gqs = g.g_qs[(size_t)sp.sidx * S.Qp + i];
+        const float dz = D3 ? g.sz[sp.sidx] - zq : 0.f;
         float Aw[NW], sw[NW], Fw[NW], Ep[NW];
-        scatter_params<NW, false>(S, sp.x - xq, sp.y - yq, c, s, sp.lc, gqs, sp.gsa, Aw, sw, Fw,
-                                  Ep);
+        scatter_params<NW, false, D3>(S, sp.x - xq, sp.y - yq, dz, c, s, sp.lc, gqs, sp.gsa, Aw,
+                                      sw, Fw, Ep);
         float t = 0.f;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
@@ -824,10 +1039,22 @@ __global__ __launch_bounds__(256) void k_gather_w(const float *w, const int64_t 
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_tables_d(const DevSys &S, const double *mu, const double2 *pix,
-                           const double2 *dirs, const double2 *sc, float *g_qa, float *g_qs,
-                           ScatA *sa, double pixmm, double R, hipStream_t st)
+                           const double *pixz, const double2 *dirs, const double2 *sc,
+                           const double *scz, float *g_qa, float *g_qs, ScatA *sa, double pixmm,
+                           double R, hipStream_t st)
 {
-    TabArgsD d{mu, pix, dirs, sc, g_qa, g_qs, sa};
+    TabArgsD d{mu, pix, dirs, sc, g_qa, g_qs, sa, pixz, scz};
+    if (S.nz > 0) {
+        hipLaunchKernelGGL(k_tab3_qa, dim3((S.Qp + 255) / 256, S.na), dim3(256), 0, st, S, d,
+                           pixmm, R);
+        if (S.nsc > 0) {
+            hipLaunchKernelGGL(k_tab3_qs, dim3((S.Qp + 255) / 256, S.nsc), dim3(256), 0, st, S,
+                               d, pixmm, R);
+            hipLaunchKernelGGL(k_tab3_sa, dim3((S.nsc + 255) / 256, S.na), dim3(256), 0, st, S,
+                               d, pixmm, R);
+        }
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_tab_qa, dim3((S.Qp + 255) / 256, S.na), dim3(256), 0, st, S, d, pixmm,
                        R);
     if (S.nsc > 0) {
@@ -862,15 +1089,21 @@ hipError_t launch_update(const DevSys &S, const UpdArgs &u, hipStream_t st)
 hipError_t launch_sens(const DevSys &S, const SensArgs &g, hipStream_t st)
 {
     dim3 grid(S.Qp / kWave, S.na);
+#define SENS(NWV)                                                                          \
+    do {                                                                                   \
+        if (S.nz > 0)                                                                      \
+            hipLaunchKernelGGL((k_sens<NWV, true>), grid, dim3(kWave), 0, st, S, g);       \
+        else                                                                               \
+            hipLaunchKernelGGL((k_sens<NWV, false>), grid, dim3(kWave), 0, st, S, g);      \
+    } while (0)
     switch (S.nw) {
-    case 1: hipLaunchKernelGGL((k_sens<1>), grid, dim3(kWave), 0, st, S, g); break;
-    case 2: hipLaunchKernelGGL((k_sens<2>), grid, dim3(kWave), 0, st, S, g); break;
-    case 3: hipLaunchKernelGGL((k_sens<3>), grid, dim3(kWave), 0, st, S, g); break;
-    case 4: hipLaunchKernelGGL((k_sens<4>), grid, dim3(kWave), 0, st, S, g); break;
-    default:
-        hipLaunchKernelGGL((k_sens<LMMEW_MAX_LINES>), grid, dim3(kWave), 0, st, S, g);
-        break;
+    case 1: SENS(1); break;
+    case 2: SENS(2); break;
+    case 3: SENS(3); break;
+    case 4: SENS(4); break;
+    default: SENS(LMMEW_MAX_LINES); break;
     }
+#undef SENS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sens_subsets, dim3((S.Qm + 255) / 256, g.nsub), dim3(256), 0, st, S, g);

@@ -26,6 +26,7 @@ struct lmmew_ctx {
     std::vector<ScatA> sa;            // [na][nsc] host copy (x, y, u, isig, lc, sidx)
     std::vector<double> sig_max;      // [na] largest PSF sigma over the scatter points
     std::vector<int> rb_lo, rb_hi;    // [na][nsc] bins reached by each scatter point's response
+    std::vector<int> rbz_lo, rbz_hi;  // 3-D: [na][nsc] axial bins reached
     // device
     float2 *d_pix = nullptr;
     double2 *d_pixd = nullptr;
@@ -40,6 +41,11 @@ struct lmmew_ctx {
     hipStream_t cap_stream = nullptr; // private stream that graph captures are recorded on
     float *d_ptab = nullptr;          // scatter-path parameter table (lmmew_path_table) or NULL
     float *d_resp = nullptr;          // [na][nsc][nb] collimator-response factors
+    float *d_respz = nullptr;         // 3-D: [na][nsc][nbz] axial response factors
+    float *d_pixz = nullptr;          // 3-D: [Qp] voxel z
+    double *d_pixzd = nullptr;        // 3-D: [Qp] voxel z (double, for the tables)
+    float *d_scz = nullptr;           // 3-D: [nsc] scatter-point z
+    double *d_sczd = nullptr;         // 3-D: [nsc] scatter-point z (double)
     lmmew_mlp *mlp = nullptr;         // scatter surrogate used by OSEM (NULL: exact model)
     int model_gen = 0;                // bumped whenever the scatter model changes
 };
@@ -72,6 +78,7 @@ struct lmmew_plan {
     std::vector<float> E;
     bool cont = false;                // events carry continuous positions (u), not bins
     std::vector<float> u;             // sorted rows: lateral position (mm) when cont
+    std::vector<int> binz;            // 3-D: sorted rows: axial bins
     std::vector<int64_t> perm;        // sorted row -> input index
     struct Sub {
         int row0 = 0, rows = 0;
@@ -86,7 +93,7 @@ struct lmmew_plan {
     int max_rows = 0, max_chunks = 0;
     double terms = 0, full_terms = 0;
     // device
-    int *d_bin = nullptr, *d_case = nullptr, *d_case_chunk = nullptr;
+    int *d_bin = nullptr, *d_binz = nullptr, *d_case = nullptr, *d_case_chunk = nullptr;
     float *d_E = nullptr, *d_u = nullptr;
     int64_t *d_perm = nullptr;
     Tile *d_tiles = nullptr;
@@ -154,6 +161,16 @@ void dfree(T *&p)
 
 double fwhm_per_sigma() { return 2.0 * std::sqrt(2.0 * std::log(2.0)); }
 
+// Klein-Nishina normaliser over the sphere: the integral of P^2 (P + 1/P -
+// sin^2 phi) over all directions, 2 sigma_KN / r_e^2, from the closed-form
+// total Klein-Nishina cross-section (k = E / m_e c^2 >= 1e-3 here).
+double kn_norm_sphere(double E, double me)
+{
+    const double k = E / me, l = std::log1p(2.0 * k);
+    return 4.0 * kPi * ((1.0 + k) / (k * k) * (2.0 * (1.0 + k) / (1.0 + 2.0 * k) - l / k) +
+                        l / (2.0 * k) - (1.0 + 3.0 * k) / ((1.0 + 2.0 * k) * (1.0 + 2.0 * k)));
+}
+
 // Planar Klein-Nishina normaliser: integral over the circle of
 // P^2 (P + 1/P - sin^2 phi), by the periodic trapezoid rule.
 double kn_norm(double E, double me)
@@ -206,6 +223,17 @@ int validate_sys(lmmew_ctx *ctx, const lmmew_system *s)
         if (!(s->win_hi_keV[k] > s->win_lo_keV[k]) || !std::isfinite(s->win_lo_keV[k]) ||
             !std::isfinite(s->win_hi_keV[k]))
             return fail(ctx, LMMEW_EINVAL, "bad energy window");
+    if (s->nz < 0) return fail(ctx, LMMEW_EINVAL, "nz must be >= 0");
+    if (s->nz > 0) {
+        if (s->ns_z <= 0 || s->nz % s->ns_z != 0 || ((s->nz / s->ns_z) % 2) != 0)
+            return fail(ctx, LMMEW_EINVAL, "nz must be a positive multiple of ns_z with an even ratio");
+        if (s->n_bins_z <= 0 || s->n_bins_z > 32767)
+            return fail(ctx, LMMEW_EINVAL, "n_bins_z must be in 1..32767");
+        if (!(s->coll_solid_angle > 0) || !std::isfinite(s->coll_solid_angle))
+            return fail(ctx, LMMEW_EINVAL, "coll_solid_angle must be positive");
+        if ((int64_t)s->n * s->n * s->nz > ((int64_t)1 << 30))
+            return fail(ctx, LMMEW_EINVAL, "too many voxels");
+    }
     return LMMEW_OK;
 }
 
@@ -216,6 +244,7 @@ void free_ctx(lmmew_ctx *c)
     dfree(c->d_pix); dfree(c->d_pixd); dfree(c->d_pixq); dfree(c->d_dirs); dfree(c->d_dirsd);
     dfree(c->d_scd); dfree(c->d_mu); dfree(c->d_gqa); dfree(c->d_gqs); dfree(c->d_sa);
     dfree(c->d_Sqa); dfree(c->d_ptab); dfree(c->d_resp);
+    dfree(c->d_respz); dfree(c->d_pixz); dfree(c->d_pixzd); dfree(c->d_scz); dfree(c->d_sczd);
 }
 
 void free_plan(lmmew_plan *p)
@@ -224,7 +253,7 @@ void free_plan(lmmew_plan *p)
     p->gexec = nullptr;
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
     p->prof_ev.clear();
-    dfree(p->d_bin); dfree(p->d_u); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
+    dfree(p->d_bin); dfree(p->d_binz); dfree(p->d_u); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
     dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
@@ -242,13 +271,15 @@ bool in_window(const lmmew_system &s, float e)
 
 // Relevant (not pruned) scatter points of one event: those whose collimator
 // response reaches the event's bin within kPsfCut standard deviations.
-int relevant_scatter(const lmmew_ctx *c, int a, int b)
+int relevant_scatter(const lmmew_ctx *c, int a, int b, int bz = 0)
 {
     const int nsc = c->S.nsc;
+    const bool d3 = c->S.nz > 0;
     int cnt = 0;
     for (int k = 0; k < nsc; ++k) {
         const size_t ak = (size_t)a * nsc + k;
-        cnt += (b >= c->rb_lo[ak] && b <= c->rb_hi[ak]);
+        cnt += (b >= c->rb_lo[ak] && b <= c->rb_hi[ak]) &&
+               (!d3 || (bz >= c->rbz_lo[ak] && bz <= c->rbz_hi[ak]));
     }
     return cnt;
 }
@@ -294,7 +325,28 @@ void build_tiles(lmmew_plan *p)
             const int nsc = c->S.nsc;
             while (e < rend && e - r < p->JT && p->cas[e] == cs && p->ang[e] == a) ++e;
             const int k0 = (int)p->slist.size();
-            if (p->cont) {
+            if (c->S.nz > 0) {
+                // 3-D: scatter points whose response reaches some (bin, axial bin)
+                // of the tile; the tile's bounding box first, then each event
+                int bmin = p->bin[r], bmax = p->bin[r], zmin = p->binz[r], zmax = p->binz[r];
+                for (int k = r; k < e; ++k) {
+                    bmin = std::min(bmin, p->bin[k]);
+                    bmax = std::max(bmax, p->bin[k]);
+                    zmin = std::min(zmin, p->binz[k]);
+                    zmax = std::max(zmax, p->binz[k]);
+                }
+                for (int k = 0; k < nsc; ++k) {
+                    const size_t ak = (size_t)a * nsc + k;
+                    const int lo = c->rb_lo[ak], hi = c->rb_hi[ak];
+                    const int lz = c->rbz_lo[ak], hz = c->rbz_hi[ak];
+                    if (hi < bmin || lo > bmax || hz < zmin || lz > zmax) continue;
+                    bool any = false;
+                    for (int j = r; j < e && !any; ++j)
+                        any = p->bin[j] >= lo && p->bin[j] <= hi && p->binz[j] >= lz &&
+                              p->binz[j] <= hz;
+                    if (any) p->slist.push_back(make_int2(k, c->sa[ak].sidx));
+                }
+            } else if (p->cont) {
                 // scatter points whose density reaches some position of the tile
                 for (int k = 0; k < nsc; ++k) {
                     const ScatA &sp = c->sa[(size_t)a * nsc + k];
@@ -414,9 +466,13 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         }
     }
     const bool cont = ev && ev->position_mm != nullptr;
+    const bool d3 = ctx->S.nz > 0;
     if (!ev || ev->n < 0 ||
-        (ev->n > 0 && ((!cont && !ev->bin) || !ev->angle || !ev->energy_keV)))
+        (ev->n > 0 && ((!cont && !ev->bin) || !ev->angle || !ev->energy_keV ||
+                       (d3 && !ev->bin_z))))
         return fail(ctx, LMMEW_EINVAL, "events: NULL array or negative count");
+    if (d3 && cont)
+        return fail(ctx, LMMEW_EINVAL, "continuous positions are not supported by the 3-D model");
     if (n_subsets < 1 || n_subsets > ctx->S.na)
         return fail(ctx, LMMEW_EINVAL, "n_subsets must be in 1..n_angles");
     if (n_cases < 1) return fail(ctx, LMMEW_EINVAL, "n_cases must be >= 1");
@@ -434,7 +490,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         off[0] = 0;
         off[1] = n;
     }
-    std::vector<int16_t> hb(cont ? 0 : n), ha(n);
+    std::vector<int16_t> hb(cont ? 0 : n), ha(n), hz(d3 ? n : 0);
     std::vector<float> he(n), hu(cont ? n : 0);
     if (n > 0) {
         if (cont)
@@ -442,6 +498,9 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
                                        hipMemcpyDeviceToHost, st));
         else
             HIPCHK(ctx, hipMemcpyAsync(hb.data(), ev->bin, n * sizeof(int16_t),
+                                       hipMemcpyDeviceToHost, st));
+        if (d3)
+            HIPCHK(ctx, hipMemcpyAsync(hz.data(), ev->bin_z, n * sizeof(int16_t),
                                        hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipMemcpyAsync(ha.data(), ev->angle, n * sizeof(int16_t), hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipMemcpyAsync(he.data(), ev->energy_keV, n * sizeof(float),
@@ -451,14 +510,19 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     const lmmew_system &s = ctx->sys;
     const double Rmm = 0.5 * s.n * s.pixel_mm;
     for (int64_t j = 0; j < n; ++j) {
-        const bool pos_ok = cont ? ((double)hu[j] >= -Rmm && (double)hu[j] < Rmm)
-                                 : (hb[j] >= 0 && hb[j] < s.n_bins);
+        const bool pos_ok = (cont ? ((double)hu[j] >= -Rmm && (double)hu[j] < Rmm)
+                                  : (hb[j] >= 0 && hb[j] < s.n_bins)) &&
+                            (!d3 || (hz[j] >= 0 && hz[j] < s.n_bins_z));
         if (!pos_ok || ha[j] < 0 || ha[j] >= s.n_angles || !in_window(s, he[j])) {
             char buf[160];
             if (cont)
                 snprintf(buf, sizeof buf,
                          "event %lld invalid (position %g mm, angle %d, energy %g keV)",
                          (long long)j, (double)hu[j], (int)ha[j], (double)he[j]);
+            else if (d3)
+                snprintf(buf, sizeof buf,
+                         "event %lld invalid (bin %d, axial bin %d, angle %d, energy %g keV)",
+                         (long long)j, (int)hb[j], (int)hz[j], (int)ha[j], (double)he[j]);
             else
                 snprintf(buf, sizeof buf,
                          "event %lld invalid (bin %d, angle %d, energy %g keV)", (long long)j,
@@ -484,6 +548,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         if (sx != sy) return sx < sy;
         if (casev[x] != casev[y]) return casev[x] < casev[y];
         if (ha[x] != ha[y]) return ha[x] < ha[y];
+        if (d3 && hz[x] != hz[y]) return hz[x] < hz[y];
         if (cont) {
             if (hu[x] != hu[y]) return hu[x] < hu[y];
         } else if (hb[x] != hb[y]) {
@@ -493,6 +558,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     });
     p->bin.resize(cont ? 0 : n);
     p->u.resize(cont ? n : 0);
+    p->binz.resize(d3 ? n : 0);
     p->ang.resize(n);
     p->cas.resize(n);
     p->E.resize(n);
@@ -503,6 +569,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
             p->u[r] = hu[j];
         else
             p->bin[r] = hb[j];
+        if (d3) p->binz[r] = hz[j];
         p->ang[r] = ha[j];
         p->cas[r] = casev[j];
         p->E[r] = he[j];
@@ -538,12 +605,15 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
                 r = e;
             }
         } else {
-            const size_t per = (size_t)s.n_angles * s.n_bins;
+            const int nbz = d3 ? s.n_bins_z : 1;
+            const size_t per = (size_t)s.n_angles * s.n_bins * nbz;
             std::vector<int> rel_cache(per * (p->maps.empty() ? 1 : n_cases), -1);
             for (int64_t r = 0; r < n; ++r) {
                 const int m = p->maps.empty() ? 0 : p->cas[r];
-                int &rc = rel_cache[m * per + (size_t)p->ang[r] * s.n_bins + p->bin[r]];
-                if (rc < 0) rc = relevant_scatter(m ? p->maps[m] : ctx, p->ang[r], p->bin[r]);
+                const int bz = d3 ? p->binz[r] : 0;
+                int &rc = rel_cache[m * per + ((size_t)p->ang[r] * s.n_bins + p->bin[r]) * nbz + bz];
+                if (rc < 0)
+                    rc = relevant_scatter(m ? p->maps[m] : ctx, p->ang[r], p->bin[r], bz);
                 t += QW * (1.0 + rc);
             }
         }
@@ -571,6 +641,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         PCHK(dalloc(&p->d_u, n));
     else
         PCHK(dalloc(&p->d_bin, n));
+    if (d3) PCHK(dalloc(&p->d_binz, n));
     PCHK(dalloc(&p->d_ang, n));
     PCHK(dalloc(&p->d_case, n));
     PCHK(dalloc(&p->d_E, n));
@@ -581,6 +652,9 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     PCHK(dalloc(&p->d_A, (size_t)std::max(p->max_rows, 1) * Qp));
     PCHK(dalloc(&p->d_lamc, (size_t)n_cases * Qp));
     if (n > 0) {
+        if (d3)
+            PCHK(hipMemcpyAsync(p->d_binz, p->binz.data(), n * sizeof(int), hipMemcpyHostToDevice,
+                                st));
         if (cont)
             PCHK(hipMemcpyAsync(p->d_u, p->u.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
         else
@@ -634,6 +708,8 @@ int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
         mt[c].sa = m->d_sa;
         mt[c].ptab = m->d_ptab;
         mt[c].resp = m->d_resp;
+        mt[c].respz = m->d_respz;
+        mt[c].sz = m->d_scz;
         mt[c].nsc = m->S.nsc;
     }
     if (mt.size() == p->maptab.size() &&
@@ -680,6 +756,9 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     r.g_qs = ctx->d_gqs;
     r.sa = ctx->d_sa;
     r.resp = ctx->d_resp;
+    r.respz = ctx->d_respz;
+    r.pix_z = ctx->d_pixz;
+    r.sz = ctx->d_scz;
     r.maps = p->d_maps;
     r.ptab = plan_ptab(ctx, p);
     r.tiles = p->d_tiles + sub.tile0;
@@ -687,6 +766,7 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     r.ntiles = sub.ntiles;
     r.ev_bin = p->cont ? nullptr : p->d_bin + sub.row0;
     r.ev_u = p->cont ? p->d_u + sub.row0 : nullptr;
+    r.ev_binz = p->d_binz ? p->d_binz + sub.row0 : nullptr;
     r.ev_E = p->d_E + sub.row0;
     r.A = out;
     r.mode = surrogate ? 2 : (part == 3 ? 0 : part);
@@ -802,9 +882,15 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     if (rc != LMMEW_OK) return bail(rc);
     ctx->sys = *sys;
     const lmmew_system &s = *sys;
-    const int n = s.n, Q = n * n, na = s.n_angles, ns = s.ns, m = n / ns;
+    // the 3-D model (nz > 0) stacks nz slices of n x n; the planar one has one
+    const bool d3 = s.nz > 0;
+    const int nzs = d3 ? s.nz : 1, nsz = d3 ? s.ns_z : 1;
+    const int n = s.n, Q = n * n * nzs, na = s.n_angles, ns = s.ns, m = n / ns;
+    const int mz = d3 ? s.nz / s.ns_z : 1;
     ctx->Q = Q;
     const double pix = s.pixel_mm, R = 0.5 * n * pix, hs = 2.0 * R / ns, db = 2.0 * R / s.n_bins;
+    const double Zh = d3 ? 0.5 * s.nz * pix : 0.0;
+    const double hz = d3 ? 2.0 * Zh / nsz : 0.0, dbz = d3 ? 2.0 * Zh / s.n_bins_z : 0.0;
     ctx->R = R;
     ctx->hs = hs;
     ctx->db = db;
@@ -825,14 +911,16 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
             return bail(fail(ctx, LMMEW_EINVAL, "mu85 must be finite and >= 0"));
         mu[q] = mu_f[q];
     }
-    // support pixels
-    std::vector<double> px, py;
+    // support pixels (voxels: slice-major, q = (iz*n + iy)*n + ix)
+    std::vector<double> px, py, pz;
     std::vector<int> pq;
     for (int q = 0; q < Q; ++q) {
-        const double x = ((q % n) + 0.5) * pix - R, y = ((q / n) + 0.5) * pix - R;
+        const int qq = q % (n * n);
+        const double x = ((qq % n) + 0.5) * pix - R, y = ((qq / n) + 0.5) * pix - R;
         if (x * x + y * y <= R * R && mask[q]) {
             px.push_back(x);
             py.push_back(y);
+            pz.push_back(d3 ? ((q / (n * n)) + 0.5) * pix - Zh : 0.0);
             pq.push_back(q);
         }
     }
@@ -840,28 +928,38 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     const int Qp = std::max(kWave, (Qm + kWave - 1) / kWave * kWave);
     std::vector<float2> pix_f(Qp);
     std::vector<double2> pix_d(Qp);
+    std::vector<float> pixz_f(d3 ? Qp : 0);
+    std::vector<double> pixz_d(d3 ? Qp : 0);
     ctx->pixq.assign(Qp, -1);
     for (int i = 0; i < Qp; ++i) {
         const double x = i < Qm ? px[i] : -10.0 * R, y = i < Qm ? py[i] : -10.0 * R;
         pix_f[i] = make_float2((float)x, (float)y);
         pix_d[i] = make_double2(x, y);
+        if (d3) {
+            pixz_d[i] = i < Qm ? pz[i] : 0.0;
+            pixz_f[i] = (float)pixz_d[i];
+        }
         if (i < Qm) ctx->pixq[i] = pq[i];
     }
     // scatter points: cell centres with mean attenuation of the covered pixels
     std::vector<double2> sc;
-    std::vector<double> smu;
-    for (int ky = 0; ky < ns; ++ky)
-        for (int kx = 0; kx < ns; ++kx) {
-            const double x = (kx + 0.5) * hs - R, y = (ky + 0.5) * hs - R;
-            double acc = 0.0;
-            for (int j = 0; j < m; ++j)
-                for (int i = 0; i < m; ++i) acc += mu[(size_t)(ky * m + j) * n + (kx * m + i)];
-            acc /= (double)(m * m);
-            if (x * x + y * y <= R * R && acc > 0.0) {
-                sc.push_back(make_double2(x, y));
-                smu.push_back(acc);
+    std::vector<double> scz, smu;
+    for (int kz = 0; kz < nsz; ++kz)
+        for (int ky = 0; ky < ns; ++ky)
+            for (int kx = 0; kx < ns; ++kx) {
+                const double x = (kx + 0.5) * hs - R, y = (ky + 0.5) * hs - R;
+                double acc = 0.0;
+                for (int l = 0; l < mz; ++l)
+                    for (int j = 0; j < m; ++j)
+                        for (int i = 0; i < m; ++i)
+                            acc += mu[((size_t)(kz * mz + l) * n + (ky * m + j)) * n + (kx * m + i)];
+                acc /= (double)(m * m * mz);
+                if (x * x + y * y <= R * R && acc > 0.0) {
+                    sc.push_back(make_double2(x, y));
+                    scz.push_back(d3 ? (kz + 0.5) * hz - Zh : 0.0);
+                    smu.push_back(acc);
+                }
             }
-        }
     const int nsc = (int)sc.size();
     // directions and per-angle scatter lists sorted by lateral coordinate
     ctx->dir_c.resize(na);
@@ -874,6 +972,8 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
         dirs_d[a] = make_double2(ctx->dir_c[a], ctx->dir_s[a]);
     }
     const double fps = fwhm_per_sigma();
+    // planar: hs^2 mu_s / (2 pi) per unit 1/r; 3-D: V mu_s / (4 pi) per unit 1/r^2
+    const double cellw = d3 ? hs * hs * hz / (4.0 * kPi) : hs * hs / (2.0 * kPi);
     ctx->sa.resize((size_t)na * nsc);
     ctx->sig_max.assign(na, 0.0);
     for (int a = 0; a < na; ++a) {
@@ -894,7 +994,7 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
             e.u = (float)u[si];
             e.isig = (float)(1.0 / sig);
             e.gsa = 0.f;
-            e.lc = (float)std::log2(hs * hs * smu[si] / (2.0 * kPi));
+            e.lc = (float)std::log2(cellw * smu[si]);
             e.D = 0.f;
             e.sidx = si;
             ctx->sa[(size_t)a * nsc + k] = e;
@@ -902,23 +1002,31 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     }
     // bins reached by each scatter point's response (the kernel's 7-sigma rule,
     // evaluated in the kernel's float arithmetic)
+    auto reach = [](float lo0, float width, int nbins, float c, float isig, int &lo, int &hi) {
+        lo = nbins;
+        hi = -1;
+        for (int b = 0; b < nbins; ++b) {
+            const float blo = lo0 + (float)b * width;
+            const float zhi = (blo + width - c) * isig, zlo = (blo - c) * isig;
+            if (!(zlo >= kPsfCut || zhi <= -kPsfCut)) {
+                lo = std::min(lo, b);
+                hi = std::max(hi, b);
+            }
+        }
+    };
     ctx->rb_lo.assign((size_t)na * nsc, 0);
     ctx->rb_hi.assign((size_t)na * nsc, -1);
-    {
-        const float fR = (float)R, fdb = (float)db;
+    for (size_t ak = 0; ak < (size_t)na * nsc; ++ak) {
+        const ScatA &e = ctx->sa[ak];
+        reach(-(float)R, (float)db, s.n_bins, e.u, e.isig, ctx->rb_lo[ak], ctx->rb_hi[ak]);
+    }
+    if (d3) {
+        ctx->rbz_lo.assign((size_t)na * nsc, 0);
+        ctx->rbz_hi.assign((size_t)na * nsc, -1);
         for (size_t ak = 0; ak < (size_t)na * nsc; ++ak) {
             const ScatA &e = ctx->sa[ak];
-            int lo = s.n_bins, hi = -1;
-            for (int b = 0; b < s.n_bins; ++b) {
-                const float blo = -fR + (float)b * fdb;
-                const float zhi = (blo + fdb - e.u) * e.isig, zlo = (blo - e.u) * e.isig;
-                if (!(zlo >= kPsfCut || zhi <= -kPsfCut)) {
-                    lo = std::min(lo, b);
-                    hi = std::max(hi, b);
-                }
-            }
-            ctx->rb_lo[ak] = lo;
-            ctx->rb_hi[ak] = hi;
+            reach(-(float)Zh, (float)dbz, s.n_bins_z, (float)scz[e.sidx], e.isig,
+                  ctx->rbz_lo[ak], ctx->rbz_hi[ak]);
         }
     }
     // constants
@@ -936,6 +1044,10 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     S.R = (float)R;
     S.hs = (float)hs;
     S.db = (float)db;
+    S.nz = d3 ? s.nz : 0;
+    S.nbz = d3 ? s.n_bins_z : 0;
+    S.Zh = (float)Zh;
+    S.dbz = (float)dbz;
     S.fwhm0 = (float)s.psf_fwhm0_mm;
     S.fslope = (float)s.psf_fwhm_slope;
     S.inv_fwhm_to_sigma = (float)(1.0 / fps);
@@ -943,17 +1055,26 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     const double k = s.eres_frac * s.eres_frac * s.eres_ref_keV / (fps * fps);
     S.eres_k = (float)k;
     S.mu_pow = (float)s.mu_power;
-    S.rmin = (float)(hs / (2.0 * std::sqrt(kPi)));
+    // r is clamped below: planar at the mean of 1/r over a disk of area hs^2,
+    // 3-D where 1/r^2 equals its mean over a ball of volume hs^2 hz
+    S.rmin = d3 ? (float)(std::cbrt(3.0 * hs * hs * hz / (4.0 * kPi)) / std::sqrt(3.0))
+                : (float)(hs / (2.0 * std::sqrt(kPi)));
     const double log2e = 1.0 / std::log(2.0);
     for (int w = 0; w < s.n_lines; ++w) {
         const double E = s.line_keV[w];
         const double f = std::pow(E / s.mu_ref_keV, -s.mu_power);
-        const double Z = kn_norm(E, s.electron_keV);
         S.E[w] = (float)E;
         S.eps[w] = (float)(E / s.electron_keV);
         S.f[w] = (float)f;
-        S.pp[w] = (float)(s.line_yield[w] * s.coll_dtheta / (2.0 * kPi));
-        S.lsc[w] = (float)std::log2(s.line_yield[w] * f * s.coll_dtheta / Z);
+        if (d3) {
+            const double Z = kn_norm_sphere(E, s.electron_keV);
+            S.pp[w] = (float)(s.line_yield[w] * s.coll_solid_angle / (4.0 * kPi));
+            S.lsc[w] = (float)std::log2(s.line_yield[w] * f * s.coll_solid_angle / Z);
+        } else {
+            const double Z = kn_norm(E, s.electron_keV);
+            S.pp[w] = (float)(s.line_yield[w] * s.coll_dtheta / (2.0 * kPi));
+            S.lsc[w] = (float)std::log2(s.line_yield[w] * f * s.coll_dtheta / Z);
+        }
         S.c0[w] = (float)(log2e / (2.0 * k * E));
         S.sqc0[w] = (float)std::sqrt(log2e / (2.0 * k * E));
         S.nc[w] = (float)(-0.5 * std::log2(2.0 * kPi * k * E));
@@ -975,6 +1096,25 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     CCHK(dalloc(&ctx->d_gqs, (size_t)std::max(nsc, 1) * Qp));
     CCHK(dalloc(&ctx->d_sa, (size_t)na * std::max(nsc, 1)));
     CCHK(dalloc(&ctx->d_resp, (size_t)na * std::max(nsc, 1) * s.n_bins));
+    if (d3) {
+        CCHK(dalloc(&ctx->d_pixz, Qp));
+        CCHK(dalloc(&ctx->d_pixzd, Qp));
+        CCHK(dalloc(&ctx->d_scz, std::max(nsc, 1)));
+        CCHK(dalloc(&ctx->d_sczd, std::max(nsc, 1)));
+        CCHK(dalloc(&ctx->d_respz, (size_t)na * std::max(nsc, 1) * s.n_bins_z));
+        CCHK(hipMemcpyAsync(ctx->d_pixz, pixz_f.data(), Qp * sizeof(float), hipMemcpyHostToDevice,
+                            st));
+        CCHK(hipMemcpyAsync(ctx->d_pixzd, pixz_d.data(), Qp * sizeof(double),
+                            hipMemcpyHostToDevice, st));
+        if (nsc > 0) {
+            std::vector<float> scz_f(scz.begin(), scz.end());
+            CCHK(hipMemcpyAsync(ctx->d_scz, scz_f.data(), nsc * sizeof(float),
+                                hipMemcpyHostToDevice, st));
+            CCHK(hipMemcpyAsync(ctx->d_sczd, scz.data(), nsc * sizeof(double),
+                                hipMemcpyHostToDevice, st));
+            CCHK(hipStreamSynchronize(st));      // scz_f goes out of scope
+        }
+    }
     CCHK(hipMemcpyAsync(ctx->d_pix, pix_f.data(), Qp * sizeof(float2), hipMemcpyHostToDevice, st));
     CCHK(hipMemcpyAsync(ctx->d_pixd, pix_d.data(), Qp * sizeof(double2), hipMemcpyHostToDevice, st));
     CCHK(hipMemcpyAsync(ctx->d_pixq, ctx->pixq.data(), Qp * sizeof(int), hipMemcpyHostToDevice, st));
@@ -986,9 +1126,9 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
                             hipMemcpyHostToDevice, st));
     }
     CCHK(hipMemcpyAsync(ctx->d_mu, mu.data(), Q * sizeof(double), hipMemcpyHostToDevice, st));
-    CCHK(launch_tables_d(S, ctx->d_mu, ctx->d_pixd, ctx->d_dirsd, ctx->d_scd, ctx->d_gqa,
-                         ctx->d_gqs, ctx->d_sa, pix, R, st));
-    CCHK(launch_resp_table(S, ctx->d_sa, ctx->d_resp, st));
+    CCHK(launch_tables_d(S, ctx->d_mu, ctx->d_pixd, ctx->d_pixzd, ctx->d_dirsd, ctx->d_scd,
+                         ctx->d_sczd, ctx->d_gqa, ctx->d_gqs, ctx->d_sa, pix, R, st));
+    CCHK(launch_resp_table(S, ctx->d_sa, ctx->d_resp, ctx->d_scz, ctx->d_respz, st));
     CCHK(hipStreamSynchronize(st));
 #undef CCHK
     *out = ctx;
@@ -1029,7 +1169,8 @@ int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t st)
     }
     float *t = nullptr;
     if (dalloc(&t, n) != hipSuccess) return fail(ctx, LMMEW_ENOMEM, "path-parameter table");
-    hipError_t e = launch_path_table(ctx->S, ctx->d_pix, ctx->d_dirs, ctx->d_gqs, ctx->d_sa, t, st);
+    hipError_t e = launch_path_table(ctx->S, ctx->d_pix, ctx->d_pixz, ctx->d_dirs, ctx->d_gqs,
+                                     ctx->d_sa, ctx->d_scz, t, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         dfree(t);
@@ -1055,6 +1196,8 @@ int lmmew_sensitivity(lmmew_ctx *ctx, int n_subsets, float *sens, hipStream_t st
     HIPCHK(ctx, hipMemsetAsync(sens, 0, (size_t)n_subsets * ctx->Q * sizeof(float), st));
     SensArgs g{};
     g.pix_xy = ctx->d_pix;
+    g.pix_z = ctx->d_pixz;
+    g.sz = ctx->d_scz;
     g.dirs = ctx->d_dirs;
     g.g_qa = ctx->d_gqa;
     g.g_qs = ctx->d_gqs;
@@ -1613,6 +1756,8 @@ int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
 {
     if (!ctx || !out) return LMMEW_EINVAL;
     *out = nullptr;
+    if (ctx->S.nz > 0)
+        return fail(ctx, LMMEW_EINVAL, "the scatter surrogate models the planar system only");
     lmmew_mlp *m = new (std::nothrow) lmmew_mlp;
     if (!m) return fail(ctx, LMMEW_ENOMEM, "host allocation");
     m->ctx = ctx;
@@ -1799,6 +1944,8 @@ int lmmew_scatter_labels(lmmew_ctx *ctx, int64_t n_events, uint64_t seed, float 
 {
     if (!ctx) return LMMEW_EINVAL;
     if (n_events <= 0 || !feats || !raw) return fail(ctx, LMMEW_EINVAL, "bad arguments");
+    if (ctx->S.nz > 0)
+        return fail(ctx, LMMEW_EINVAL, "the scatter surrogate models the planar system only");
     if ((size_t)n_events * ctx->S.Qp * sizeof(float) > kScratchBudget)
         return fail(ctx, LMMEW_EINVAL, "too many label events for one pass");
     const lmmew_system &s = ctx->sys;

@@ -10,6 +10,8 @@ receives it, and the oracle then works in double precision on those values.
     python tests/golden/make_oracle_golden.py c5        # sampled rows at 128x128
     python tests/golden/make_oracle_golden.py c1pos     # continuous positions, 16x16
     python tests/golden/make_oracle_golden.py c2pos     # continuous positions, sampled rows
+    python tests/golden/make_oracle_golden.py c1_3d     # 3-D model, 16x16x8
+    python tests/golden/make_oracle_golden.py c2_3d     # 3-D model, sampled rows at 64x64x16
 """
 import hashlib
 import os
@@ -179,6 +181,64 @@ def c2pos():
         h.update(np.ascontiguousarray(ev[k]).tobytes())
     np.savez_compressed(os.path.join(OUT, "c2pos_oracle.npz"), digest=h.hexdigest(), J=J,
                         idx=idx, p_act=p_act)
+
+
+def digest3(ev):
+    h = hashlib.sha256()
+    for k in ("bin", "bin_z", "angle", "energy"):
+        h.update(np.ascontiguousarray(ev[k]).tobytes())
+    return h.hexdigest()
+
+
+def c1_3d():
+    w = synth.CONFIGS["c1_3d"]
+    p = w.params
+    mu, act, rois = synth.phantom(w)
+    mu32, act32 = f32(mu), f32(act)
+    o = oracle.Oracle3(p, mu32)
+    ev = synth.generic_events3(p, act, w.n_events, w.seed_events)
+    evd = {"bin": ev["bin"], "bin_z": ev["bin_z"], "angle": ev["angle"],
+           "energy": ev["energy"].astype(np.float64)}
+    assert o.check_events(evd) == -1
+    t = time.time()
+    sens = o.sensitivity(w.n_subsets)
+    lam0 = o.support.astype(np.float64)
+    lam, hist, ll, sk = o.osem(evd, w.n_subsets, w.n_iters, lam0, f32(sens))
+    p_act = o.forward(evd, act32)
+    idx = np.arange(0, ev["angle"].size, 50)
+    rows = np.stack([o.row(evd["bin"][j], evd["bin_z"][j], evd["angle"][j], evd["energy"][j])
+                     for j in idx])
+    print("c1_3d", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "c1_3d_oracle.npz"), digest=digest3(ev), mu=mu32,
+                        act=act32, support=o.support, sens=sens, lam0=lam0, hist=hist, ll=ll,
+                        skipped=sk, p_act=p_act, idx=idx, rows=rows)
+
+
+def c2_3d():
+    w = synth.CONFIGS["c2_3d"]
+    p = w.params
+    mu, act, rois = synth.phantom(w)
+    mu32, act32 = f32(mu), f32(act)
+    ev = synth.generic_events3(p, act, w.n_events, w.seed_events, poisson=True)
+    rng = np.random.default_rng(4444)
+    J = ev["angle"].size
+    idx = np.sort(rng.choice(J, 8, replace=False))
+    t = time.time()
+    o = oracle.Oracle3(p, mu32)
+    print("c2_3d tables", time.time() - t, "s")
+    sub = {"bin": ev["bin"][idx], "bin_z": ev["bin_z"][idx], "angle": ev["angle"][idx],
+           "energy": ev["energy"][idx].astype(np.float64)}
+    p_act = o.forward(sub, act32)
+    qs = np.flatnonzero(o.support)
+    pix = np.sort(rng.choice(qs, 8, replace=False))
+    nsub = w.n_subsets
+    sens = np.zeros((nsub, pix.size))
+    for k, q in enumerate(pix):
+        for a in range(p.na):
+            sens[a % nsub, k] += p.T * o.sens_qa(int(q), a)
+    print("c2_3d rows and sensitivity", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "c2_3d_oracle.npz"), digest=digest3(ev), J=J,
+                        idx=idx, p_act=p_act, pix=pix, sens=sens)
 
 
 if __name__ == "__main__":

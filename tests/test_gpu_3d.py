@@ -1,0 +1,182 @@
+"""GPU parity of the 3-D single-scatter model (voxel grid of nz slices,
+coarse 3-D scatter grid, 2-D detector) through the C ABI.  Expected values
+come from tests/golden/make_oracle_golden.py (c1_3d, c2_3d), which calls only
+the FP64 oracle (oracle/lmmew_oracle3.c) and the seeded generators.  The bar
+is the parity tests' 1e-4 relative error in max-norm and L2."""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-4
+
+
+def _rel(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = got - ref
+    return (np.abs(d).max() / np.abs(ref).max(), np.linalg.norm(d) / np.linalg.norm(ref))
+
+
+def _digest3(ev):
+    h = hashlib.sha256()
+    for k in ("bin", "bin_z", "angle", "energy"):
+        h.update(np.ascontiguousarray(ev[k]).tobytes())
+    return h.hexdigest()
+
+
+@pytest.fixture(scope="module")
+def c1_3d():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2305_17111_amd as lm
+
+    g = np.load(os.path.join(GOLD, "c1_3d_oracle.npz"))
+    w = synth.CONFIGS["c1_3d"]
+    p = w.params
+    ev = synth.generic_events3(p, synth.phantom(w)[1], w.n_events, w.seed_events)
+    assert _digest3(ev) == str(g["digest"])
+    ctx = lm.Context(p, torch.from_numpy(g["mu"].astype(np.float32)))
+    return lm, w, g, ctx, lm.events_to_device(ev)
+
+
+def test_3d_sensitivity_rows_and_forward(c1_3d):
+    import torch
+
+    lm, w, g, ctx, ev = c1_3d
+    sens = ctx.sensitivity(w.n_subsets).cpu().numpy()
+    mx, l2 = _rel(sens, g["sens"])
+    assert mx < TOL and l2 < TOL, (mx, l2)
+    assert np.array_equal(sens[:, ~g["support"]], np.zeros((w.n_subsets, int((~g["support"]).sum()))))
+    rows = ctx.rows(ev, part=0).cpu().numpy()
+    for k, j in enumerate(g["idx"]):
+        mx, l2 = _rel(rows[j], g["rows"][k])
+        assert mx < TOL and l2 < TOL, (j, mx, l2)
+    pj = ctx.forward(ev, torch.from_numpy(g["act"].astype(np.float32)).cuda()).cpu().numpy()
+    rel = np.abs(pj - g["p_act"]) / g["p_act"]
+    assert rel.max() < TOL, rel.max()
+
+
+def test_3d_osem_every_subiteration_and_graph(c1_3d):
+    import torch
+
+    lm, w, g, ctx, ev = c1_3d
+    nsub = w.n_subsets
+    sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan = ctx.plan(ev, nsub)
+    for k in range(g["hist"].shape[0]):
+        sk, ll = plan.osem_subiter(k % nsub, sens, lam, stats=True)
+        assert sk == int(g["skipped"][k])
+        assert ll == pytest.approx(float(g["ll"][k]), rel=1e-5, abs=1e-3)
+        mx, l2 = _rel(lam.cpu().numpy(), g["hist"][k])
+        assert mx < TOL and l2 < TOL, (k, mx, l2)
+    graphed = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan.osem_graph(w.n_iters, sens, graphed)
+    assert torch.equal(graphed, lam)
+
+
+def test_3d_event_tiles_table_cached_and_batched(c1_3d):
+    import torch
+
+    lm, w, g, ctx, ev = c1_3d
+    nsub = w.n_subsets
+    sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
+    lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    ref = g["hist"][-1]
+    plan = ctx.plan(ev, nsub)
+    outs = {}
+    for jt in (16, 32, 64):
+        plan.set_event_tile(jt)
+        lam = lam0.clone()
+        plan.osem_iter(w.n_iters, sens, lam)
+        mx, l2 = _rel(lam.cpu().numpy(), ref)
+        assert mx < TOL and l2 < TOL, (jt, mx, l2)
+        outs[jt] = lam
+    ctx.path_table(True)
+    try:
+        assert ctx.path_table_bytes > 0
+        tab = lam0.clone()
+        plan.osem_iter(w.n_iters, sens, tab)
+        mx, l2 = _rel(tab.cpu().numpy(), outs[64].cpu().numpy())
+        assert mx < 1e-5 and l2 < 1e-5, (mx, l2)
+    finally:
+        ctx.path_table(False)
+    plan.cache_rows(True)
+    cached = lam0.clone()
+    plan.osem_graph(w.n_iters, sens, cached)
+    assert torch.equal(cached, outs[64])
+    plan.cache_rows(False)
+    n = ev["angle"].numel()
+    offs = [0, 250, n]
+    batched = lam0.repeat(2, 1).contiguous()
+    bp = ctx.plan(ev, nsub, case_offsets=offs)
+    bp.set_event_tile(64)
+    bp.osem_iter(1, sens, batched)
+    for c in range(2):
+        one = {k: v[offs[c]:offs[c + 1]].contiguous() for k, v in ev.items()}
+        lam = lam0.clone()
+        op = ctx.plan(one, nsub)
+        op.set_event_tile(64)
+        op.osem_iter(1, sens, lam)
+        assert torch.equal(lam, batched[c]), c
+
+
+def test_3d_rejections(c1_3d):
+    import torch
+
+    lm, w, g, ctx, ev = c1_3d
+    p = w.params
+    bad = {k: v.clone() for k, v in ev.items()}
+    bad["bin_z"][5] = p.nbz
+    with pytest.raises(lm.LmmewError) as e:
+        ctx.plan(bad, 4)
+    assert "event 5" in str(e.value)
+    no_z = {k: v for k, v in ev.items() if k != "bin_z"}
+    with pytest.raises(lm.LmmewError):
+        ctx.plan(no_z, 4)
+    pos = {"position": torch.zeros(ev["angle"].numel(), device="cuda"),
+           "angle": ev["angle"], "energy": ev["energy"], "bin_z": ev["bin_z"]}
+    with pytest.raises(lm.LmmewError):
+        ctx.plan(pos, 4)
+    with pytest.raises(lm.LmmewError):
+        ctx.mlp(seed=1)
+    with pytest.raises(lm.LmmewError):
+        lm.Context(synth.replace(p, nsz=3), torch.from_numpy(g["mu"].astype(np.float32)))
+
+
+def test_c2_3d_sampled_rows_and_sensitivity_full_size():
+    import torch
+
+    import paper_2305_17111_amd as lm
+
+    path = os.path.join(GOLD, "c2_3d_oracle.npz")
+    g = np.load(path)
+    w = synth.CONFIGS["c2_3d"]
+    p = w.params
+    mu, act, _ = synth.phantom(w)
+    ev = synth.generic_events3(p, act, w.n_events, w.seed_events, poisson=True)
+    assert _digest3(ev) == str(g["digest"])
+    ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+    evd = lm.events_to_device(ev)
+    pj = ctx.forward(evd, torch.from_numpy(act.astype(np.float32)).cuda()).cpu().numpy()
+    rel = np.abs(pj[g["idx"]] - g["p_act"]) / g["p_act"]
+    assert rel.max() < TOL, rel.max()
+    sens = ctx.sensitivity(w.n_subsets)
+    got = sens.cpu().numpy()[:, g["pix"]]
+    assert np.abs(got - g["sens"]).max() / np.abs(g["sens"]).max() < TOL
+    # count conservation of one full iteration at full size
+    plan = ctx.plan(evd, w.n_subsets)
+    lam = torch.from_numpy(synth.fov_support3(p).astype(np.float32)).cuda()
+    for s in range(w.n_subsets):
+        sk, _ = plan.osem_subiter(s, sens, lam, stats=True)
+        Js = int(np.sum(ev["angle"] % w.n_subsets == s))
+        tot = float((sens[s].double() * lam.double()).sum())
+        assert tot == pytest.approx(Js - sk, rel=TOL)
+        assert bool(torch.all(lam >= 0))
