@@ -1437,11 +1437,11 @@ int lmmew_plan_get_event_tile(const lmmew_plan *plan) { return plan ? plan->JT :
 namespace {
 // Autotuner cache: problem shape -> fastest event tile.
 struct TuneKey {
-    int Qm, nsc, nw, na, nsub, per_angle;
+    int Qm, nsc, nw, na, nsub, per_angle, nz, cont;
     bool operator==(const TuneKey &o) const
     {
         return Qm == o.Qm && nsc == o.nsc && nw == o.nw && na == o.na && nsub == o.nsub &&
-               per_angle == o.per_angle;
+               per_angle == o.per_angle && nz == o.nz && cont == o.cont;
     }
 };
 std::vector<std::pair<TuneKey, int>> g_tune_cache;
@@ -1452,7 +1452,8 @@ TuneKey tune_key(const lmmew_ctx *ctx, const lmmew_plan *p)
     const double per = (double)p->n / std::max(1, p->ncases) / std::max(1, ctx->S.na);
     int b = 0;
     while ((1 << b) < per) ++b;
-    return TuneKey{ctx->S.Qm, ctx->S.nsc, ctx->S.nw, ctx->S.na, p->nsub, b};
+    return TuneKey{ctx->S.Qm, ctx->S.nsc, ctx->S.nw, ctx->S.na, p->nsub, b, ctx->S.nz,
+                   p->cont ? 1 : 0};
 }
 }  // namespace
 
