@@ -209,7 +209,9 @@ int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, fl
                       hipStream_t stream);
 
 /* Prepares list-mode data for OSEM: validates every event, sorts each
- * subset's events by (case, angle, bin or position, energy) (stable) and
+ * subset's events by (case, angle, bin or position, energy) (stable; in the
+ * 3-D model by (case, angle, square block of the detector, bin_z, bin,
+ * energy)) and
  * lays out the
  * work tiles and the per-subset scratch.  A plan holds one or more
  * independent cases (noise realisations or patients) that share the context's

@@ -541,6 +541,32 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     std::vector<int> casev(n);
     for (int c = 0; c < n_cases; ++c)
         for (int64_t j = off[c]; j < off[c + 1]; ++j) casev[j] = c;
+    // 3-D: an angle's events spread over the whole 2-D detector, so ordering
+    // them by (bin_z, bin) makes tiles of consecutive events long strips in u
+    // whose scatter lists are several times longer than one event's.  They
+    // are ordered by square detector blocks first (side chosen for about 16
+    // events per block at the case's mean density, so that a case orders its
+    // events alike in any plan), then by (bin_z, bin).  Blocks follow a Morton
+    // curve, so runs of 2 and 4 blocks (the larger event tiles) are compact too.
+    auto morton = [](uint32_t x, uint32_t y) {
+        int64_t r = 0;
+        for (int b = 0; b < 15; ++b)
+            r |= ((int64_t)((x >> b) & 1u) << (2 * b)) | ((int64_t)((y >> b) & 1u) << (2 * b + 1));
+        return r;
+    };
+    std::vector<int64_t> blk(d3 ? n : 0);
+    if (d3) {
+        const double area = 2.0 * Rmm * s.nz * s.pixel_mm;
+        const double dbm = 2.0 * Rmm / s.n_bins, dbzm = s.nz * s.pixel_mm / s.n_bins_z;
+        for (int c = 0; c < n_cases; ++c) {
+            const double per = (double)(off[c + 1] - off[c]) / s.n_angles;
+            const double side = std::sqrt(16.0 * area / std::max(per, 1.0));
+            const int BU = std::min(s.n_bins, std::max(1, (int)std::lround(side / dbm)));
+            const int BZ = std::min(s.n_bins_z, std::max(1, (int)std::lround(side / dbzm)));
+            for (int64_t j = off[c]; j < off[c + 1]; ++j)
+                blk[j] = morton((uint32_t)(hb[j] / BU), (uint32_t)(hz[j] / BZ));
+        }
+    }
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
@@ -548,6 +574,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         if (sx != sy) return sx < sy;
         if (casev[x] != casev[y]) return casev[x] < casev[y];
         if (ha[x] != ha[y]) return ha[x] < ha[y];
+        if (d3 && blk[x] != blk[y]) return blk[x] < blk[y];
         if (d3 && hz[x] != hz[y]) return hz[x] < hz[y];
         if (cont) {
             if (hu[x] != hu[y]) return hu[x] < hu[y];

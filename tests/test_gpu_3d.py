@@ -128,6 +128,33 @@ def test_3d_event_tiles_table_cached_and_batched(c1_3d):
         assert torch.equal(lam, batched[c]), c
 
 
+def test_3d_maps_plan_equals_independent_plans(c1_3d):
+    import torch
+
+    lm, w, g, ctx, ev = c1_3d
+    p = w.params
+    mu2 = g["mu"].reshape(p.nz, -1).copy()
+    mu2[:, : p.n * p.n // 2] *= 1.5                 # a second, different map
+    other = lm.Context(p, torch.from_numpy(mu2.ravel().astype(np.float32)))
+    ctxs = [ctx, other]
+    n = ev["angle"].numel()
+    offs = [0, 280, n]
+    sens = torch.stack([c.sensitivity(w.n_subsets) for c in ctxs]).contiguous()
+    lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    batched = lam0.repeat(2, 1).contiguous()
+    plan = lm.plan_maps(ctxs, ev, w.n_subsets, offs)
+    plan.set_event_tile(32)
+    plan.osem_graph(1, sens, batched)
+    for c in range(2):
+        one = {k: v[offs[c]:offs[c + 1]].contiguous() for k, v in ev.items()}
+        lam = lam0.clone()
+        op = ctxs[c].plan(one, w.n_subsets)
+        op.set_event_tile(32)
+        op.osem_iter(1, sens[c], lam)
+        assert torch.equal(lam, batched[c]), c
+    assert not torch.equal(sens[0], sens[1])
+
+
 def test_3d_rejections(c1_3d):
     import torch
 
