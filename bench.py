@@ -308,6 +308,14 @@ def surrogate(args):
 
     lam = lam0.clone()
     exact_s = _time_graph(plan, sens, lam, args.surrogate_steps)
+    # the exact model's per-event kernel on its own: one profiled eager iteration
+    plan.profile(True)
+    plan.osem_iter(1, sens, lam)
+    k_ex = plan.profile_read_kernels()
+    plan.profile(False)
+    ex_ms, ex_n = k_ex["k_row"]
+    ex_terms, _ = plan.terms()
+    ex_ach = ex_terms / (ex_ms * 1e-3)
 
     net = ctxs[0].mlp(seed=2)
     maps = synth.random_body_maps(p, 16, seed=41).astype(np.float32)
@@ -336,7 +344,13 @@ def surrogate(args):
                     f"{len(p.windows)} windows, {J} events ({int(counts.min())}..{int(counts.max())}"
                     f" per case), {w.n_subsets} subsets",
         "unit": "events*iterations/s",
-        "exact": {"value": J / exact_s, "s_per_iteration": exact_s, "event_tile": jt},
+        "exact": {"value": J / exact_s, "s_per_iteration": exact_s, "event_tile": jt,
+                  "roofline": {"bound": "alu", "kernel": "k_row (path parameters in the kernel)",
+                               "achieved": ex_ach / 1e12, "peak": PEAK_TERMS_PER_S / 1e12,
+                               "unit": "Tterm/s", "frac": ex_ach / PEAK_TERMS_PER_S,
+                               "frac_of_nonpacked_peak": ex_ach / NONPACKED_PEAK_TERMS_PER_S,
+                               "avg_launch_ms": ex_ms / ex_n,
+                               "kernel_share_of_iteration": ex_ms * 1e-3 / exact_s}},
         "surrogate": {"value": J / sur_s, "s_per_iteration": sur_s,
                       "unscattered_kernel_ms_per_iteration": row_ms},
         "speedup": exact_s / sur_s,
