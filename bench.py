@@ -46,7 +46,7 @@ NONPACKED_PEAK_TERMS_PER_S = 256 * 64 * 2.4e9 / 5.0
 # WRITE_SIZE of these kernel versions, scaled by a 256 MiB copy kernel: fetch
 # x2.000, write x1.000)
 MEASURED_TRAFFIC = {("c2", 16, False): {"fetch": 58.6e6, "write": 81.5e6},
-                    ("c2", 16, True): {"fetch": 5225.4e6, "write": 81.5e6}}
+                    ("c2", 16, True): {"fetch": 5229.3e6, "write": 81.5e6}}
 
 # scatter surrogate 6 -> 128 -> 128 -> 128 -> 1: multiply-adds per (event, pixel)
 # pair, and MI355X's dense BF16 MFMA peak

@@ -3,7 +3,7 @@
 // (v_mfma_f32_16x16x16 bf16, FP32 accumulation), the first and last layers on
 // FP32 VALU, Adam on the FP32 master copy.  Inference inside OSEM (k_mlp_rows):
 // every layer on 16x16x32 MFMA (first layer BF16 with high/low splitting,
-// hidden layers FP16), GELUs on packed FP16.
+// hidden layers FP16), GELUs by linear interpolation in an FP16 table in LDS.
 //
 // Parameter vector (FP32 master copy, 34049 floats):
 //   W1[6][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] w4[128] b4[1]
@@ -357,29 +357,51 @@ __device__ __forceinline__ v8h load_frag_h(const float *P, int off, int f)
     return v;
 }
 
-// GELU of two values in packed FP16 (the same z * sigmoid form as gelu(),
-// with exp2 and reciprocal of the half-precision transcendental unit); the
-// limits are exact: 2^s = inf gives 0, 2^s = 0 gives z
-__device__ __forceinline__ h2 gelu_h2(h2 z)
+// GELU of two values by linear interpolation in an FP16 table.  Entry k of
+// kGeluTab is indexed by the top 10 bits of an FP16 encoding (sign, exponent,
+// top 4 mantissa bits): for z_k, the value whose encoding is k << 6, it holds
+// GELU(z_k) and the slope of the chord to the next entry, as an FP16 pair.
+// A value z in the entry's interval gets GELU(z_k) + slope (z - z_k), where
+// z - z_k is exact.  Over every finite FP16 input the result is within
+// 1.9e-3 of the exact GELU (2 FP16 ulps at z near 2.7; the interpolation part
+// is below 2e-4), against 9.7e-4 for rounding the exact value to FP16 once;
+// beyond |z| = 16 the chords are exactly z and 0.  It replaces the two exp2
+// and two reciprocals per pair on the quarter-rate transcendental unit by two
+// LDS reads and a few full-rate instructions.
+constexpr int kGeluTab = 1024;
+
+// fills the table (one entry per call) from the FP32 gelu()
+__device__ __forceinline__ unsigned gelu_table_entry(int k)
 {
-    const h2 k1 = {(_Float16)kGeluK1, (_Float16)kGeluK1};
-    const h2 k2 = {(_Float16)kGeluK2, (_Float16)kGeluK2};
-    const h2 one = {(_Float16)1.f, (_Float16)1.f};
-    const h2 s = z * (k1 + k2 * (z * z));
-    h2 e;
-    e.x = __ocml_exp2_f16(s.x);
-    e.y = __ocml_exp2_f16(s.y);
-    const h2 d = one + e;
-    h2 rc;
-    rc.x = __builtin_amdgcn_rcph(d.x);
-    rc.y = __builtin_amdgcn_rcph(d.y);
-    return z * rc;
+    const float z0 = (float)__builtin_bit_cast(_Float16, (unsigned short)(k << 6));
+    const float z1 = (float)__builtin_bit_cast(_Float16, (unsigned short)((k + 1) << 6));
+    if (!__builtin_isfinite(z0)) return 0u;                  // Inf / NaN encodings: unused
+    const float g0 = gelu(z0);
+    float sl = (gelu(z1) - g0) / (z1 - z0);
+    if (!__builtin_isfinite(z1) || !__builtin_isfinite(sl)) sl = z0 > 0.f ? 1.f : 0.f;
+    const h2 v = {(_Float16)g0, (_Float16)sl};
+    return __builtin_bit_cast(unsigned, v);
 }
 
-// two FP32 accumulators -> FP16 pair (round toward zero) -> GELU
-__device__ __forceinline__ h2 gelu_pair(float a, float b)
+// two FP32 accumulators -> FP16 pair (round toward zero) -> GELU, as the
+// 32-bit encoding of the FP16 pair; tab must sit at LDS address 0 so that an
+// entry's address is just its index times 4
+__device__ __forceinline__ unsigned gelu_pair(float a, float b, const unsigned *tab)
 {
-    return gelu_h2(__builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b)));
+    const h2 z = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b));
+    const unsigned bits = __builtin_bit_cast(unsigned, z);
+    const unsigned e0 = tab[(bits >> 6) & 0x3FFu], e1 = tab[bits >> 22];
+    const h2 dz = z - __builtin_bit_cast(h2, bits & 0xFFC0FFC0u);
+    // (value, slope) of the two entries -> (value0, value1), (slope0, slope1)
+    const h2 G = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x05040100u));
+    const h2 D = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x07060302u));
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_fma(D, dz, G));
+}
+
+// four 32-bit words (FP16 pairs) as an MFMA operand fragment
+__device__ __forceinline__ v8h frag_of(const unsigned *w)
+{
+    return __builtin_bit_cast(v8h, make_uint4(w[0], w[1], w[2], w[3]));
 }
 
 __device__ __forceinline__ unsigned pack2(unsigned short a, unsigned short b)
@@ -412,11 +434,15 @@ __device__ __forceinline__ uint4 load_frag1(const float *P, int f)
 
 __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowArgs a)
 {
-    __shared__ uint4 sW1[kFrag1];                // 8 KB, bf16
-    __shared__ v8h sW2[kFrag];                   // 32 KB, fp16
-    __shared__ v8h sW3[kFrag];                   // 32 KB, fp16
-    __shared__ float4 sB[2 * H / 4];             // b2, b3
-    __shared__ h2 sW4[H / 2];                    // w4 in fp16 pairs
+    // one LDS buffer (77 KB, two workgroups per CU): the GELU table at address
+    // 0, then the weight fragments, biases and output weights
+    __shared__ uint4 lds[kGeluTab / 4 + kFrag1 + 2 * kFrag + 2 * H / 4 + H / 8];
+    unsigned *const sTab = reinterpret_cast<unsigned *>(lds);            // 4 KB
+    uint4 *const sW1 = lds + kGeluTab / 4;                               // 8 KB, bf16
+    v8h *const sW2 = reinterpret_cast<v8h *>(sW1 + kFrag1);               // 32 KB, fp16
+    v8h *const sW3 = sW2 + kFrag;                                        // 32 KB, fp16
+    float4 *const sB = reinterpret_cast<float4 *>(sW3 + kFrag);          // b2, b3
+    h2 *const sW4 = reinterpret_cast<h2 *>(sB + 2 * H / 4);              // w4 in fp16 pairs
 
     for (int f = threadIdx.x; f < kFrag; f += 256) {
         sW2[f] = load_frag_h(a.P, kOffW2, f);
@@ -434,6 +460,7 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
         sW4[t] = w;
     }
     const float b4 = a.P[kOffB4];
+    for (int k = threadIdx.x; k < kGeluTab; k += 256) sTab[k] = gelu_table_entry(k);
     __syncthreads();
 
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
@@ -478,8 +505,8 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             x1[p][7] = one;
         }
         // layer 1 (bf16 hi/lo MFMA): output block ib = units 16 ib + 4g + t ->
-        // item 4 (ib & 1) + t of chunk ib / 2, GELU in packed FP16
-        v8h h1[kRowGroups][4];
+        // item 4 (ib & 1) + t of chunk ib / 2, GELU from the table
+        unsigned h1[kRowGroups][4][4];            // FP16 pairs: items 2t, 2t + 1 of chunk c
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib) {
             const v8bf w = w1[(ib * 4 + g) * 16 + r];
@@ -487,15 +514,12 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             for (int p = 0; p < kRowGroups; ++p) {
                 const v4f acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     w, x1[p], v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-                const h2 lo = gelu_pair(acc[0], acc[1]), hi = gelu_pair(acc[2], acc[3]);
-                h1[p][ib >> 1][4 * (ib & 1) + 0] = lo.x;
-                h1[p][ib >> 1][4 * (ib & 1) + 1] = lo.y;
-                h1[p][ib >> 1][4 * (ib & 1) + 2] = hi.x;
-                h1[p][ib >> 1][4 * (ib & 1) + 3] = hi.y;
+                h1[p][ib >> 1][2 * (ib & 1) + 0] = gelu_pair(acc[0], acc[1], sTab);
+                h1[p][ib >> 1][2 * (ib & 1) + 1] = gelu_pair(acc[2], acc[3], sTab);
             }
         }
         // layer 2 (fp16 MFMA, fp32 accumulation from the bias)
-        v8h h2v[kRowGroups][4];
+        unsigned h2v[kRowGroups][4][4];
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib) {
             const float4 b = bb[(16 * ib + 4 * g) >> 2];
@@ -507,15 +531,13 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
                 const v8h w = w2[frag_index(ib, c, g, r)];
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, h1[p][c], acc[p], 0, 0, 0);
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h1[p][c]), acc[p],
+                                                                   0, 0, 0);
             }
 #pragma unroll
             for (int p = 0; p < kRowGroups; ++p) {
-                const h2 lo = gelu_pair(acc[p][0], acc[p][1]), hi = gelu_pair(acc[p][2], acc[p][3]);
-                h2v[p][ib >> 1][4 * (ib & 1) + 0] = lo.x;
-                h2v[p][ib >> 1][4 * (ib & 1) + 1] = lo.y;
-                h2v[p][ib >> 1][4 * (ib & 1) + 2] = hi.x;
-                h2v[p][ib >> 1][4 * (ib & 1) + 3] = hi.y;
+                h2v[p][ib >> 1][2 * (ib & 1) + 0] = gelu_pair(acc[p][0], acc[p][1], sTab);
+                h2v[p][ib >> 1][2 * (ib & 1) + 1] = gelu_pair(acc[p][2], acc[p][3], sTab);
             }
         }
         // layer 3 and the output unit (FP16 pairs dotted with w4, FP32 sum)
@@ -535,11 +557,13 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
                 const v8h w = w3[frag_index(ib, c, g, r)];
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, h2v[p][c], acc[p], 0, 0, 0);
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h2v[p][c]), acc[p],
+                                                                   0, 0, 0);
             }
 #pragma unroll
             for (int p = 0; p < kRowGroups; ++p) {
-                const h2 lo = gelu_pair(acc[p][0], acc[p][1]), hi = gelu_pair(acc[p][2], acc[p][3]);
+                const unsigned lo = gelu_pair(acc[p][0], acc[p][1], sTab);
+                const unsigned hi = gelu_pair(acc[p][2], acc[p][3], sTab);
                 part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, lo), wa, part[p], false);
                 part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, hi), wb, part[p], false);
             }
