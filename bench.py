@@ -48,6 +48,10 @@ NONPACKED_PEAK_TERMS_PER_S = 256 * 64 * 2.4e9 / 5.0
 MEASURED_TRAFFIC = {("c2", 16, False): {"fetch": 58.6e6, "write": 81.5e6},
                     ("c2", 16, True): {"fetch": 5229.3e6, "write": 81.5e6}}
 
+# iterations after which the 16-patient images of the exact model, the
+# surrogate and no scatter model are compared region by region
+ROI_ITERS = 10
+
 # scatter surrogate 6 -> 128 -> 128 -> 128 -> 1: multiply-adds per (event, pixel)
 # pair, and MI355X's dense BF16 MFMA peak
 MLP_MAC_PER_PAIR = 6 * 128 + 2 * 128 * 128 + 128
@@ -289,9 +293,10 @@ def surrogate(args):
     p = w.params
     counts = synth.case_counts(w)
     t = time.perf_counter()
-    ctxs, evs = [], []
+    ctxs, evs, rois = [], [], []
     for c in range(w.n_cases):
-        mu, act, _ = synth.phantom(w, c)
+        mu, act, roi = synth.phantom(w, c)
+        rois.append(roi)
         ctxs.append(Context(p, torch.from_numpy(mu.astype(np.float32))))
         evs.append(synth.generic_events(p, act, int(counts[c]), w.seed_events + c))
     sens = torch.stack([c.sensitivity(w.n_subsets) for c in ctxs]).contiguous()
@@ -316,6 +321,12 @@ def surrogate(args):
     ex_ms, ex_n = k_ex["k_row"]
     ex_terms, _ = plan.terms()
     ex_ach = ex_terms / (ex_ms * 1e-3)
+    # accuracy reference: the exact model's images after ROI_ITERS iterations
+    done = args.surrogate_steps + 2
+    roi_iters = max(ROI_ITERS, done)
+    if roi_iters > done:
+        plan.osem_graph(roi_iters - done, sens, lam)
+    lam_exact = lam.cpu().numpy().astype(np.float64)
 
     net = ctxs[0].mlp(seed=2)
     maps = synth.random_body_maps(p, 16, seed=41).astype(np.float32)
@@ -333,7 +344,27 @@ def surrogate(args):
     plan.osem_iter(1, sens, lam)
     k = plan.profile_read_kernels()
     plan.profile(False)
+    if roi_iters > done:
+        plan.osem_graph(roi_iters - done, sens, lam)
+    lam_sur = lam.cpu().numpy().astype(np.float64)
+    # the same iterations with the scatter term switched off (the network's
+    # output shifted by -100 in log space: a density below 1e-40), the method
+    # without a scatter model
+    theta, c0, _ = net.get_params()
+    off = ctxs[0].mlp(seed=0)
+    off.set_params(theta, c0 - 100.0, 0.0)
+    ctxs[0].set_scatter_model(off)
+    lam = lam0.clone()
+    plan.osem_graph(roi_iters, sens, lam)
+    lam_none = lam.cpu().numpy().astype(np.float64)
     ctxs[0].set_scatter_model(None)
+    # every patient's hot-region uptakes (FP64 sums on the host), each image
+    # after roi_iters iterations from the same start
+    def uptakes(x):
+        return np.array([[x[c][r].sum() for r in rois[c]] for c in range(w.n_cases)])
+    up_ex = uptakes(lam_exact)
+    rel = uptakes(lam_sur) / up_ex - 1.0
+    rel0 = uptakes(lam_none) / up_ex - 1.0
     mlp_ms, mlp_n = k["k_mlp_rows"]
     row_ms, row_n = k["k_row"]
     pairs = float(J) * Qm                            # (event, support pixel) pairs per iteration
@@ -354,6 +385,13 @@ def surrogate(args):
         "surrogate": {"value": J / sur_s, "s_per_iteration": sur_s,
                       "unscattered_kernel_ms_per_iteration": row_ms},
         "speedup": exact_s / sur_s,
+        "roi_uptake_vs_exact": {"iterations": roi_iters, "regions": int(rel.size),
+                                "surrogate": {"mean_rel": float(rel.mean()),
+                                              "mean_abs_rel": float(np.abs(rel).mean()),
+                                              "max_abs_rel": float(np.abs(rel).max())},
+                                "no_scatter_model": {"mean_rel": float(rel0.mean()),
+                                                     "mean_abs_rel": float(np.abs(rel0).mean()),
+                                                     "max_abs_rel": float(np.abs(rel0).max())}},
         "steps": args.surrogate_steps,
         "training": {"samples": int(16 * n_lab * Qm), "epochs": args.surrogate_epochs,
                      "batch": 8192, "seconds": train_s, "first_loss": losses[0],
