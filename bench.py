@@ -260,6 +260,48 @@ def three_d(steps):
             "setup_ms": setup}
 
 
+def scatter_resolution(ev, steps):
+    """The headline workload with the scatter modelled on coarser grids (the
+    lower-resolution scatter the paper's appendix on 3-D requirements
+    proposes): per scatter grid the iteration time and the hot-region
+    uptakes after ROI_ITERS iterations relative to the finest grid."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2305_17111_amd import Context, LmmewError, events_to_device
+
+    w = synth.CONFIGS["c2"]
+    mu, act, rois = synth.phantom(w)
+    dev = events_to_device(ev)
+    res, ups = {}, {}
+    for ns in (8, 16, 32):
+        p = synth.replace(w.params, ns=ns)
+        ctx = Context(p, torch.from_numpy(mu.astype(np.float32)))
+        try:
+            ctx.path_table(True)
+        except LmmewError:
+            pass
+        sens = ctx.sensitivity(w.n_subsets)
+        plan = ctx.plan(dev, w.n_subsets)
+        plan.autotune(use_cache=False)
+        lam = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+        s_it = _time_graph(plan, sens, lam, steps)
+        plan.osem_graph(ROI_ITERS - steps - 1, sens, lam)
+        x = lam.cpu().numpy().astype(np.float64)
+        ups[ns] = np.array([x[r].sum() for r in rois])
+        terms, _ = plan.terms()
+        res[ns] = {"scatter_cell_mm": 2 * p.R / ns, "s_per_iteration": s_it,
+                   "terms_per_iteration": terms}
+        del plan, ctx
+    for ns in res:
+        rel = ups[ns] / ups[32] - 1.0
+        res[ns]["roi_uptake_vs_finest"] = [float(v) for v in rel]
+    return {"workload": "c2 with scatter grids 8x8, 16x16, 32x32 (cells 32, 16, 8 mm); "
+                        f"uptakes of the hot regions after {ROI_ITERS} iterations",
+            "grids": {f"{ns}x{ns}": v for ns, v in res.items()}}
+
+
 def _time_graph(plan, sens, lam, steps):
     """Seconds per launch of a one-iteration graph (after one warmup launch)."""
     import torch
@@ -455,6 +497,8 @@ def main():
                     help="skip the continuous-position variant of the headline iterations")
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3-D single-scatter workload")
+    ap.add_argument("--no-scatter-grids", action="store_true",
+                    help="skip the headline workload on coarser scatter grids")
     ap.add_argument("--steps-3d", type=int, default=2)
     ap.add_argument("--no-path-table", action="store_true",
                     help="evaluate the scatter-path parameters inside the per-event kernel")
@@ -630,6 +674,8 @@ def main():
                                      "frac": ach_nt / PEAK_TERMS_PER_S,
                                      "frac_of_nonpacked_peak": ach_nt / NONPACKED_PEAK_TERMS_PER_S}
     del plan
+    if not args.no_scatter_grids:
+        out["scatter_resolution"] = scatter_resolution(ev, 2)
     if not args.no_3d:
         out["three_d"] = three_d(args.steps_3d)
     if not args.no_surrogate:
