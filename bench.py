@@ -45,8 +45,8 @@ NONPACKED_PEAK_TERMS_PER_S = 256 * 64 * 2.4e9 / 5.0
 # tile 16, without and with the path-parameter table (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE of these kernel versions, scaled by a 256 MiB copy kernel: fetch
 # x2.000, write x1.000)
-MEASURED_TRAFFIC = {("c2", 16, False): {"fetch": 58.7e6, "write": 81.5e6},
-                    ("c2", 16, True): {"fetch": 5229.3e6, "write": 81.5e6}}
+MEASURED_TRAFFIC = {("64x64_50k", 16, False): {"fetch": 58.7e6, "write": 81.5e6},
+                    ("64x64_50k", 16, True): {"fetch": 5229.3e6, "write": 81.5e6}}
 
 # iterations after which the 16-patient images of the exact model, the
 # surrogate and no scatter model are compared region by region
@@ -103,7 +103,7 @@ def batched(ctx, sens, args):
     import synth
     from paper_2305_17111_amd import events_to_device
 
-    w = synth.CONFIGS["c3"]
+    w = synth.CONFIGS["64x64_64cases"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     counts = synth.case_counts(w)
@@ -135,7 +135,7 @@ def batched(ctx, sens, args):
     lam0 = lam0.repeat(len(counts), 1).contiguous()
     Qp = (int(synth.fov_support(p).sum()) + 63) // 64 * 64
     cached = None if args.no_cached else cached_rows(plan, sens, lam0, J, Qp, args.batched_steps)
-    return {"workload": f"c3: {len(counts)} cases of the 64x64 workload, {J} events "
+    return {"workload": f"{len(counts)} cases of the 64x64 workload, {J} events "
                         f"({int(counts.min())}..{int(counts.max())} per case), {w.n_subsets} subsets",
             "value": J * args.batched_steps / el, "unit": "events*iterations/s",
             "s_per_iteration": el / args.batched_steps, "steps": args.batched_steps,
@@ -215,7 +215,7 @@ def three_d(steps):
     import synth
     from paper_2305_17111_amd import Context, events_to_device
 
-    w = synth.CONFIGS["c2_3d"]
+    w = synth.CONFIGS["64x64x16_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ev = synth.generic_events3(p, act, w.n_events, w.seed_events, poisson=w.poisson)
@@ -271,7 +271,7 @@ def scatter_resolution(ev, steps):
     import synth
     from paper_2305_17111_amd import Context, LmmewError, events_to_device
 
-    w = synth.CONFIGS["c2"]
+    w = synth.CONFIGS["64x64_50k"]
     mu, act, rois = synth.phantom(w)
     dev = events_to_device(ev)
     res, ups = {}, {}
@@ -297,8 +297,8 @@ def scatter_resolution(ev, steps):
     for ns in res:
         rel = ups[ns] / ups[32] - 1.0
         res[ns]["roi_uptake_vs_finest"] = [float(v) for v in rel]
-    return {"workload": "c2 with scatter grids 8x8, 16x16, 32x32 (cells 32, 16, 8 mm); "
-                        f"uptakes of the hot regions after {ROI_ITERS} iterations",
+    return {"workload": "64x64 workload with scatter grids 8x8, 16x16, 32x32 (cells 32, 16, "
+                        f"8 mm); uptakes of the hot regions after {ROI_ITERS} iterations",
             "grids": {f"{ns}x{ns}": v for ns, v in res.items()}}
 
 
@@ -318,12 +318,12 @@ def _time_graph(plan, sens, lam, steps):
 def surrogate(args):
     """Exact model vs the MLP scatter surrogate.
 
-    c5: 16 patients (own phantom and attenuation map each, uneven counts, 1M
-    events in total) in one plan, 16 subsets, each iteration one graph launch;
+    128x128: 16 patients (own phantom and attenuation map each, uneven counts,
+    1M events in total) in one plan, 16 subsets, each iteration one graph launch;
     the network is trained on the GPU on 10M samples of the exact scatter model
     drawn over 16 random water bodies (it has no attenuation-map input).
-    c1: the 16x16 workload the surrogate's accuracy is tested on (10
-    iterations as one graph launch)."""
+    16x16: the workload the surrogate's accuracy is tested on (10 iterations
+    as one graph launch)."""
     import numpy as np
     import torch
 
@@ -331,7 +331,7 @@ def surrogate(args):
     from paper_2305_17111_amd import Context, events_to_device, plan_maps
 
     out = {}
-    w = synth.CONFIGS["c5"]
+    w = synth.CONFIGS["128x128_16cases"]
     p = w.params
     counts = synth.case_counts(w)
     t = time.perf_counter()
@@ -411,8 +411,8 @@ def surrogate(args):
     row_ms, row_n = k["k_row"]
     pairs = float(J) * Qm                            # (event, support pixel) pairs per iteration
     flops = pairs * 2 * MLP_MAC_PER_PAIR / (mlp_ms * 1e-3)
-    out["c5_batched"] = {
-        "workload": f"c5: {w.n_cases} patients (own phantom and map) at {p.n}x{p.n}, "
+    out["128x128_16cases"] = {
+        "workload": f"{w.n_cases} patients (own phantom and map) at {p.n}x{p.n}, "
                     f"{p.pix:g} mm, scatter {p.ns}x{p.ns}, {p.nb} bins x {p.na} angles, "
                     f"{len(p.windows)} windows, {J} events ({int(counts.min())}..{int(counts.max())}"
                     f" per case), {w.n_subsets} subsets",
@@ -447,7 +447,7 @@ def surrogate(args):
     }
     del plan, ctxs, sens
 
-    w = synth.CONFIGS["c1"]
+    w = synth.CONFIGS["16x16_2k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ctx = Context(p, torch.from_numpy(mu.astype(np.float32)))
@@ -474,10 +474,10 @@ def surrogate(args):
         s_it = (time.perf_counter() - t0) / w.n_iters
         res[key] = {"value": w.n_events / s_it, "s_per_iteration": s_it}
     ctx.set_scatter_model(None)
-    out["c1"] = {"workload": workload_desc("c1", p, w.n_events, w.n_subsets),
-                 "unit": "events*iterations/s", **res,
-                 "training": {"samples": int(16 * 3000 * ctx.support_size), "epochs": 16,
-                              "seconds": train_s, "maps": "16 random water bodies"}}
+    out["16x16_2k"] = {"workload": workload_desc("16x16_2k", p, w.n_events, w.n_subsets),
+                       "unit": "events*iterations/s", **res,
+                       "training": {"samples": int(16 * 3000 * ctx.support_size), "epochs": 16,
+                                    "seconds": train_s, "maps": "16 random water bodies"}}
     return out
 
 
@@ -486,7 +486,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="64x64_50k")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")

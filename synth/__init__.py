@@ -82,34 +82,41 @@ class Workload:
     case_min: int = 0
     case_max: int = 0
     seed_cases: int = 0
+    own_phantom_per_case: bool = False
 
 
 CONFIGS = {
     # 16x16 at 4 mm, 8x8 scatter grid, 16 bins x 32 angles, EW1+EW2, 2000 events.
-    "c1": Workload("c1", SysParams(16, 4.0, 8, 16, 32, windows=(EW1, EW2)),
-                   2000, 4, 10, "disk2", 11, 12),
+    "16x16_2k": Workload("16x16_2k", SysParams(16, 4.0, 8, 16, 32, windows=(EW1, EW2)),
+                         2000, 4, 10, "disk2", 11, 12),
     # 64x64 at 4 mm, 32x32 scatter grid, 64 bins x 120 angles, EW1-3, ~50k events.
-    "c2": Workload("c2", SysParams(64, 4.0, 32, 64, 120, windows=(EW1, EW2, EW3)),
-                   50000, 8, 20, "ellipse3", 21, 22, poisson=True),
-    # 64 cases of the c2 geometry, per-case means uniform in [20k, 200k].
-    "c3": Workload("c3", SysParams(64, 4.0, 32, 64, 120, windows=(EW1, EW2, EW3)),
-                   0, 8, 20, "ellipse3", 21, 3100, poisson=True, n_cases=64,
-                   case_min=20000, case_max=200000, seed_cases=31),
+    "64x64_50k": Workload("64x64_50k", SysParams(64, 4.0, 32, 64, 120,
+                                                 windows=(EW1, EW2, EW3)),
+                          50000, 8, 20, "ellipse3", 21, 22, poisson=True),
+    # 64 cases of the 64x64 geometry, per-case means uniform in [20k, 200k].
+    "64x64_64cases": Workload("64x64_64cases", SysParams(64, 4.0, 32, 64, 120,
+                                                         windows=(EW1, EW2, EW3)),
+                              0, 8, 20, "ellipse3", 21, 3100, poisson=True, n_cases=64,
+                              case_min=20000, case_max=200000, seed_cases=31),
     # 128x128 at 2 mm, 64x64 scatter grid, 128 bins x 120 angles, EW1-3 + SW,
-    # 1M events over 16 uneven cases.
-    "c5": Workload("c5", SysParams(128, 2.0, 64, 128, 120, windows=(EW1, EW2, SW, EW3)),
-                   1000000, 16, 20, "ellipse3", 5200, 5300, poisson=False, n_cases=16,
-                   case_min=20000, case_max=200000, seed_cases=51),
+    # 1M events over 16 uneven cases, each with a phantom and attenuation map
+    # of its own.
+    "128x128_16cases": Workload("128x128_16cases", SysParams(128, 2.0, 64, 128, 120,
+                                                             windows=(EW1, EW2, SW, EW3)),
+                                1000000, 16, 20, "ellipse3", 5200, 5300, poisson=False,
+                                n_cases=16, case_min=20000, case_max=200000, seed_cases=51,
+                                own_phantom_per_case=True),
     # 3-D single scatter: 16x16x8 voxels of 4 mm, 8x8x4 scatter grid, 16x8 bins,
     # 16 angles, EW1+EW2, 600 events.
-    "c1_3d": Workload("c1_3d", SysParams(16, 4.0, 8, 16, 16, windows=(EW1, EW2), nz=8, nsz=4,
-                                         nbz=8),
-                      600, 4, 2, "disk2_3d", 11, 13),
+    "16x16x8_600": Workload("16x16x8_600", SysParams(16, 4.0, 8, 16, 16, windows=(EW1, EW2),
+                                                     nz=8, nsz=4, nbz=8),
+                            600, 4, 2, "disk2_3d", 11, 13),
     # 3-D: the 64x64 workload's slice geometry over 16 slices (256x256x64 mm),
     # 32x32x8 scatter grid, 64x16 bins, 120 angles, EW1-3, ~50k events.
-    "c2_3d": Workload("c2_3d", SysParams(64, 4.0, 32, 64, 120, windows=(EW1, EW2, EW3), nz=16,
-                                         nsz=8, nbz=16),
-                      50000, 8, 20, "ellipse3_3d", 21, 23, poisson=True),
+    "64x64x16_50k": Workload("64x64x16_50k", SysParams(64, 4.0, 32, 64, 120,
+                                                       windows=(EW1, EW2, EW3), nz=16, nsz=8,
+                                                       nbz=16),
+                             50000, 8, 20, "ellipse3_3d", 21, 23, poisson=True),
 }
 
 
@@ -350,7 +357,7 @@ def phantom(w: Workload, case: int = 0):
         return phantom_disk2_3d(w.params)
     if w.phantom == "ellipse3_3d":
         return phantom_ellipse3_3d(w.params, w.seed_phantom)
-    seed = w.seed_phantom + (case if w.name == "c5" else 0)
+    seed = w.seed_phantom + (case if w.own_phantom_per_case else 0)
     return phantom_ellipse3(w.params, seed)
 
 

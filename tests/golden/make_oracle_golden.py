@@ -4,14 +4,14 @@ Calls only the FP64 oracle (oracle/) and the seeded input generators (synth/).
 Every floating-point input is rounded to float32 first, exactly as the GPU path
 receives it, and the oracle then works in double precision on those values.
 
-    python tests/golden/make_oracle_golden.py c1        # ~1 min on 8 cores
-    python tests/golden/make_oracle_golden.py c2        # sampled rows + sensitivity
-    python tests/golden/make_oracle_golden.py c2iter    # one full iteration, 2000 events
-    python tests/golden/make_oracle_golden.py c5        # sampled rows at 128x128
-    python tests/golden/make_oracle_golden.py c1pos     # continuous positions, 16x16
-    python tests/golden/make_oracle_golden.py c2pos     # continuous positions, sampled rows
-    python tests/golden/make_oracle_golden.py c1_3d     # 3-D model, 16x16x8
-    python tests/golden/make_oracle_golden.py c2_3d     # 3-D model, sampled rows at 64x64x16
+    python tests/golden/make_oracle_golden.py small     # ~1 min on 8 cores
+    python tests/golden/make_oracle_golden.py rows64    # sampled rows + sensitivity
+    python tests/golden/make_oracle_golden.py iter64    # one full iteration, 2000 events
+    python tests/golden/make_oracle_golden.py rows128   # sampled rows at 128x128
+    python tests/golden/make_oracle_golden.py small_pos # continuous positions, 16x16
+    python tests/golden/make_oracle_golden.py pos64     # continuous positions, sampled rows
+    python tests/golden/make_oracle_golden.py small_3d  # 3-D model, 16x16x8
+    python tests/golden/make_oracle_golden.py rows64_3d # 3-D model, sampled rows at 64x64x16
 """
 import hashlib
 import os
@@ -40,8 +40,8 @@ def digest(ev):
     return h.hexdigest()
 
 
-def c1():
-    w = synth.CONFIGS["c1"]
+def small():
+    w = synth.CONFIGS["16x16_2k"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32 = f32(mu)
@@ -55,20 +55,20 @@ def c1():
     sens32 = f32(sens)          # the GPU run is checked against the oracle fed the same sens
     t = time.time()
     lam, hist, ll, sk = o.osem(evd, w.n_subsets, w.n_iters, lam0, sens32)
-    print("c1 osem", time.time() - t, "s")
+    print("small osem", time.time() - t, "s")
     act32 = f32(act)
     p_act = o.forward(evd, act32)
     rng = np.random.default_rng(1234)
     wts = f32(rng.uniform(0.5, 1.5, ev["bin"].size))
     bp = o.backproject(evd, wts)
-    np.savez_compressed(os.path.join(OUT, "c1_oracle.npz"), mu=mu32, act=act32,
+    np.savez_compressed(os.path.join(OUT, "16x16_2k_oracle.npz"), mu=mu32, act=act32,
                         support=o.support, bin=ev["bin"], angle=ev["angle"],
                         energy=ev["energy"], sens=sens, lam0=lam0, hist=hist, ll=ll,
                         skipped=sk, p_act=p_act, bp_w=wts, bp=bp)
 
 
-def c2():
-    w = synth.CONFIGS["c2"]
+def rows64():
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32, act32 = f32(mu), f32(act)
@@ -81,7 +81,7 @@ def c2():
            "energy": ev["energy"][idx].astype(np.float64)}
     t = time.time()
     p_act = o.forward(sub, act32)
-    print("c2 rows", time.time() - t, "s")
+    print("rows64 rows", time.time() - t, "s")
     qs = np.flatnonzero(o.support)
     pix = np.sort(rng.choice(qs, 16, replace=False))
     nsub = w.n_subsets
@@ -90,13 +90,13 @@ def c2():
     for k, q in enumerate(pix):
         for a in range(p.na):
             sens[a % nsub, k] += p.T * o.sens_qa(int(q), a)
-    print("c2 sens", time.time() - t, "s")
-    np.savez_compressed(os.path.join(OUT, "c2_oracle.npz"), digest=digest(ev), J=J, idx=idx,
+    print("rows64 sens", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "64x64_50k_oracle.npz"), digest=digest(ev), J=J, idx=idx,
                         p_act=p_act, pix=pix, sens=sens)
 
 
-def c2iter():
-    w = synth.CONFIGS["c2"]
+def iter64():
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32 = f32(mu)
@@ -107,13 +107,13 @@ def c2iter():
     lam0 = o.support.astype(np.float64)
     t = time.time()
     lam, hist, ll, sk = o.osem(evd, w.n_subsets, 1, lam0, f32(sens))
-    print("c2 iteration", time.time() - t, "s")
-    np.savez_compressed(os.path.join(OUT, "c2iter_oracle.npz"), digest=digest(ev), sens=sens,
+    print("iter64 iteration", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "64x64_50k_iter_oracle.npz"), digest=digest(ev), sens=sens,
                         lam0=lam0, hist=hist, ll=ll, skipped=sk)
 
 
-def c5():
-    w = synth.CONFIGS["c5"]
+def rows128():
+    w = synth.CONFIGS["128x128_16cases"]
     p = w.params
     mu, act, rois = synth.phantom(w, 0)
     mu32, act32 = f32(mu), f32(act)
@@ -125,8 +125,8 @@ def c5():
            "energy": ev["energy"][idx].astype(np.float64)}
     t = time.time()
     p_act = o.forward(sub, act32)
-    print("c5 rows", time.time() - t, "s")
-    np.savez_compressed(os.path.join(OUT, "c5_oracle.npz"), digest=digest(ev), idx=idx,
+    print("rows128 rows", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "128x128_16cases_oracle.npz"), digest=digest(ev), idx=idx,
                         p_act=p_act)
 
 
@@ -135,8 +135,8 @@ def below_R(u, p):
     return np.minimum(np.asarray(u, dtype=np.float32), np.nextafter(np.float32(p.R), np.float32(0)))
 
 
-def c1pos():
-    w = synth.CONFIGS["c1"]
+def small_pos():
+    w = synth.CONFIGS["16x16_2k"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32 = f32(mu)
@@ -151,18 +151,18 @@ def c1pos():
     lam0 = o.support.astype(np.float64)
     t = time.time()
     lam, hist, ll, sk = o.osem(evd, w.n_subsets, 2, lam0, f32(sens))
-    print("c1pos osem", time.time() - t, "s")
+    print("small_pos osem", time.time() - t, "s")
     p_act = o.forward(evd, f32(act))
     idx = np.arange(0, ev["angle"].size, 97)
     rows = np.stack([o.row_pos(evd["position"][j], evd["angle"][j], evd["energy"][j])
                      for j in idx])
-    np.savez_compressed(os.path.join(OUT, "c1pos_oracle.npz"), position=ev["position"],
+    np.savez_compressed(os.path.join(OUT, "16x16_2k_pos_oracle.npz"), position=ev["position"],
                         angle=ev["angle"], energy=ev["energy"], sens=sens, lam0=lam0,
                         hist=hist, ll=ll, skipped=sk, p_act=p_act, idx=idx, rows=rows)
 
 
-def c2pos():
-    w = synth.CONFIGS["c2"]
+def pos64():
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32, act32 = f32(mu), f32(act)
@@ -175,11 +175,11 @@ def c2pos():
            "energy": ev["energy"][idx].astype(np.float64)}
     t = time.time()
     p_act = o.forward(sub, act32)
-    print("c2pos rows", time.time() - t, "s")
+    print("pos64 rows", time.time() - t, "s")
     h = hashlib.sha256()
     for k in ("position", "angle", "energy"):
         h.update(np.ascontiguousarray(ev[k]).tobytes())
-    np.savez_compressed(os.path.join(OUT, "c2pos_oracle.npz"), digest=h.hexdigest(), J=J,
+    np.savez_compressed(os.path.join(OUT, "64x64_50k_pos_oracle.npz"), digest=h.hexdigest(), J=J,
                         idx=idx, p_act=p_act)
 
 
@@ -190,8 +190,8 @@ def digest3(ev):
     return h.hexdigest()
 
 
-def c1_3d():
-    w = synth.CONFIGS["c1_3d"]
+def small_3d():
+    w = synth.CONFIGS["16x16x8_600"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32, act32 = f32(mu), f32(act)
@@ -208,14 +208,14 @@ def c1_3d():
     idx = np.arange(0, ev["angle"].size, 50)
     rows = np.stack([o.row(evd["bin"][j], evd["bin_z"][j], evd["angle"][j], evd["energy"][j])
                      for j in idx])
-    print("c1_3d", time.time() - t, "s")
-    np.savez_compressed(os.path.join(OUT, "c1_3d_oracle.npz"), digest=digest3(ev), mu=mu32,
+    print("small_3d", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "16x16x8_600_oracle.npz"), digest=digest3(ev), mu=mu32,
                         act=act32, support=o.support, sens=sens, lam0=lam0, hist=hist, ll=ll,
                         skipped=sk, p_act=p_act, idx=idx, rows=rows)
 
 
-def c2_3d():
-    w = synth.CONFIGS["c2_3d"]
+def rows64_3d():
+    w = synth.CONFIGS["64x64x16_50k"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32, act32 = f32(mu), f32(act)
@@ -225,7 +225,7 @@ def c2_3d():
     idx = np.sort(rng.choice(J, 8, replace=False))
     t = time.time()
     o = oracle.Oracle3(p, mu32)
-    print("c2_3d tables", time.time() - t, "s")
+    print("rows64_3d tables", time.time() - t, "s")
     sub = {"bin": ev["bin"][idx], "bin_z": ev["bin_z"][idx], "angle": ev["angle"][idx],
            "energy": ev["energy"][idx].astype(np.float64)}
     p_act = o.forward(sub, act32)
@@ -236,8 +236,8 @@ def c2_3d():
     for k, q in enumerate(pix):
         for a in range(p.na):
             sens[a % nsub, k] += p.T * o.sens_qa(int(q), a)
-    print("c2_3d rows and sensitivity", time.time() - t, "s")
-    np.savez_compressed(os.path.join(OUT, "c2_3d_oracle.npz"), digest=digest3(ev), J=J,
+    print("rows64_3d rows and sensitivity", time.time() - t, "s")
+    np.savez_compressed(os.path.join(OUT, "64x64x16_50k_oracle.npz"), digest=digest3(ev), J=J,
                         idx=idx, p_act=p_act, pix=pix, sens=sens)
 
 

@@ -1,6 +1,6 @@
 """GPU parity of the 3-D single-scatter model (voxel grid of nz slices,
 coarse 3-D scatter grid, 2-D detector) through the C ABI.  Expected values
-come from tests/golden/make_oracle_golden.py (c1_3d, c2_3d), which calls only
+come from tests/golden/make_oracle_golden.py (small_3d, rows64_3d), which calls only
 the FP64 oracle (oracle/lmmew_oracle3.c) and the seeded generators.  The bar
 is the parity tests' 1e-4 relative error in max-norm and L2."""
 import hashlib
@@ -31,14 +31,14 @@ def _digest3(ev):
 
 
 @pytest.fixture(scope="module")
-def c1_3d():
+def small_3d():
     import torch
 
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2305_17111_amd as lm
 
-    g = np.load(os.path.join(GOLD, "c1_3d_oracle.npz"))
-    w = synth.CONFIGS["c1_3d"]
+    g = np.load(os.path.join(GOLD, "16x16x8_600_oracle.npz"))
+    w = synth.CONFIGS["16x16x8_600"]
     p = w.params
     ev = synth.generic_events3(p, synth.phantom(w)[1], w.n_events, w.seed_events)
     assert _digest3(ev) == str(g["digest"])
@@ -46,10 +46,10 @@ def c1_3d():
     return lm, w, g, ctx, lm.events_to_device(ev)
 
 
-def test_3d_sensitivity_rows_and_forward(c1_3d):
+def test_3d_sensitivity_rows_and_forward(small_3d):
     import torch
 
-    lm, w, g, ctx, ev = c1_3d
+    lm, w, g, ctx, ev = small_3d
     sens = ctx.sensitivity(w.n_subsets).cpu().numpy()
     mx, l2 = _rel(sens, g["sens"])
     assert mx < TOL and l2 < TOL, (mx, l2)
@@ -63,10 +63,10 @@ def test_3d_sensitivity_rows_and_forward(c1_3d):
     assert rel.max() < TOL, rel.max()
 
 
-def test_3d_osem_every_subiteration_and_graph(c1_3d):
+def test_3d_osem_every_subiteration_and_graph(small_3d):
     import torch
 
-    lm, w, g, ctx, ev = c1_3d
+    lm, w, g, ctx, ev = small_3d
     nsub = w.n_subsets
     sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
     lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
@@ -82,10 +82,10 @@ def test_3d_osem_every_subiteration_and_graph(c1_3d):
     assert torch.equal(graphed, lam)
 
 
-def test_3d_event_tiles_table_cached_and_batched(c1_3d):
+def test_3d_event_tiles_table_cached_and_batched(small_3d):
     import torch
 
-    lm, w, g, ctx, ev = c1_3d
+    lm, w, g, ctx, ev = small_3d
     nsub = w.n_subsets
     sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
     lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
@@ -128,10 +128,10 @@ def test_3d_event_tiles_table_cached_and_batched(c1_3d):
         assert torch.equal(lam, batched[c]), c
 
 
-def test_3d_maps_plan_equals_independent_plans(c1_3d):
+def test_3d_maps_plan_equals_independent_plans(small_3d):
     import torch
 
-    lm, w, g, ctx, ev = c1_3d
+    lm, w, g, ctx, ev = small_3d
     p = w.params
     mu2 = g["mu"].reshape(p.nz, -1).copy()
     mu2[:, : p.n * p.n // 2] *= 1.5                 # a second, different map
@@ -155,10 +155,10 @@ def test_3d_maps_plan_equals_independent_plans(c1_3d):
     assert not torch.equal(sens[0], sens[1])
 
 
-def test_3d_rejections(c1_3d):
+def test_3d_rejections(small_3d):
     import torch
 
-    lm, w, g, ctx, ev = c1_3d
+    lm, w, g, ctx, ev = small_3d
     p = w.params
     bad = {k: v.clone() for k, v in ev.items()}
     bad["bin_z"][5] = p.nbz
@@ -178,14 +178,14 @@ def test_3d_rejections(c1_3d):
         lm.Context(synth.replace(p, nsz=3), torch.from_numpy(g["mu"].astype(np.float32)))
 
 
-def test_c2_3d_sampled_rows_and_sensitivity_full_size():
+def test_64x64x16_sampled_rows_and_sensitivity_full_size():
     import torch
 
     import paper_2305_17111_amd as lm
 
-    path = os.path.join(GOLD, "c2_3d_oracle.npz")
+    path = os.path.join(GOLD, "64x64x16_50k_oracle.npz")
     g = np.load(path)
-    w = synth.CONFIGS["c2_3d"]
+    w = synth.CONFIGS["64x64x16_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ev = synth.generic_events3(p, act, w.n_events, w.seed_events, poisson=True)

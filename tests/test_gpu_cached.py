@@ -14,23 +14,23 @@ GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
-def c1():
+def small():
     import torch
 
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2305_17111_amd as lm
 
-    g = np.load(os.path.join(GOLD, "c1_oracle.npz"))
-    p = synth.CONFIGS["c1"].params
+    g = np.load(os.path.join(GOLD, "16x16_2k_oracle.npz"))
+    p = synth.CONFIGS["16x16_2k"].params
     ctx = lm.Context(p, torch.from_numpy(g["mu"].astype(np.float32)))
     ev = lm.events_to_device({"bin": g["bin"], "angle": g["angle"], "energy": g["energy"]})
     return lm, p, g, ctx, ev
 
 
-def test_cached_equals_matrix_free_eager_graph_and_stats(c1):
+def test_cached_equals_matrix_free_eager_graph_and_stats(small):
     import torch
 
-    lm, p, g, ctx, ev = c1
+    lm, p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
     plan = ctx.plan(ev, 4)
@@ -50,10 +50,10 @@ def test_cached_equals_matrix_free_eager_graph_and_stats(c1):
     assert torch.equal(a, d)
 
 
-def test_cached_batched_cases(c1):
+def test_cached_batched_cases(small):
     import torch
 
-    lm, p, g, ctx, ev = c1
+    lm, p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     n = ev["bin"].numel()
     offs = [0, 700, 1500, n]
@@ -67,10 +67,10 @@ def test_cached_batched_cases(c1):
     assert torch.equal(a, b)
 
 
-def test_cached_rows_follow_the_scatter_model(c1):
+def test_cached_rows_follow_the_scatter_model(small):
     import torch
 
-    lm, p, g, ctx, ev = c1
+    lm, p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     net = ctx.mlp(seed=3)
     net.fit(2000, epochs=1, batch=4096, lr=2e-3, floor_frac=3e-2, seed=1)
@@ -102,7 +102,7 @@ def test_cached_full_size_iteration():
 
     import paper_2305_17111_amd as lm
 
-    w = synth.CONFIGS["c2"]
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))

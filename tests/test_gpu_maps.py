@@ -11,13 +11,13 @@ TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
-def c1maps():
+def small_maps():
     import torch
 
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2305_17111_amd as lm
 
-    w = synth.CONFIGS["c1"]
+    w = synth.CONFIGS["16x16_2k"]
     p = w.params
     mu_disk, act, _ = synth.phantom(w)
     maps = [mu_disk] + list(synth.random_body_maps(p, 2, seed=5))
@@ -35,10 +35,10 @@ def _sens_stack(ctxs, nsub):
     return torch.stack([c.sensitivity(nsub) for c in ctxs]).contiguous()
 
 
-def test_maps_plan_equals_independent_plans(c1maps):
+def test_maps_plan_equals_independent_plans(small_maps):
     import torch
 
-    lm, p, act, maps, ctxs = c1maps
+    lm, p, act, maps, ctxs = small_maps
     counts = [700, 1900, 260]
     evs = [synth.generic_events(p, act, n, 900 + c) for c, n in enumerate(counts)]
     offs = np.concatenate([[0], np.cumsum(counts)]).tolist()
@@ -58,12 +58,12 @@ def test_maps_plan_equals_independent_plans(c1maps):
     assert not torch.equal(batched[1], batched[2])
 
 
-def test_maps_plan_matches_oracle_per_case(c1maps):
+def test_maps_plan_matches_oracle_per_case(small_maps):
     import torch
 
     import oracle
 
-    lm, p, act, maps, ctxs = c1maps
+    lm, p, act, maps, ctxs = small_maps
     evs, refs = [], []
     for c, m in enumerate(maps[:2]):
         orc = oracle.Oracle(p, m.astype(np.float32).astype(np.float64))
@@ -84,10 +84,10 @@ def test_maps_plan_matches_oracle_per_case(c1maps):
         assert np.linalg.norm(d) / np.linalg.norm(refs[c]) < TOL, c
 
 
-def test_maps_plan_with_surrogate_equals_independent(c1maps):
+def test_maps_plan_with_surrogate_equals_independent(small_maps):
     import torch
 
-    lm, p, act, maps, ctxs = c1maps
+    lm, p, act, maps, ctxs = small_maps
     net = ctxs[0].mlp(seed=4)
     net.fit(3000, epochs=1, batch=4096, lr=2e-3, floor_frac=3e-2, seed=1)
     theta, c0, fl = net.get_params()
@@ -114,10 +114,10 @@ def test_maps_plan_with_surrogate_equals_independent(c1maps):
             c.set_scatter_model(None)
 
 
-def test_maps_plan_rejects_other_systems(c1maps):
+def test_maps_plan_rejects_other_systems(small_maps):
     import torch
 
-    lm, p, act, maps, ctxs = c1maps
+    lm, p, act, maps, ctxs = small_maps
     other = lm.Context(synth.replace(p, fwhm0=3.0), torch.from_numpy(maps[0].astype(np.float32)))
     ev = lm.events_to_device(synth.generic_events(p, act, 50, 1))
     with pytest.raises(lm.LmmewError):

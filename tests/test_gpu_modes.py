@@ -23,7 +23,7 @@ def study():
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import oracle
 
-    w = synth.CONFIGS["c1"]
+    w = synth.CONFIGS["16x16_2k"]
     p = w.params
     mu, acts, rois = synth.disk2_objects(p, S, seed=101)
     mu32 = mu.astype(np.float32)

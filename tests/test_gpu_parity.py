@@ -50,46 +50,46 @@ def _digest(ev):
 
 
 @pytest.fixture(scope="module")
-def c1(lm):
+def small(lm):
     import torch
 
-    g = np.load(os.path.join(GOLD, "c1_oracle.npz"))
-    p = synth.CONFIGS["c1"].params
+    g = np.load(os.path.join(GOLD, "16x16_2k_oracle.npz"))
+    p = synth.CONFIGS["16x16_2k"].params
     ctx = lm.Context(p, torch.from_numpy(g["mu"].astype(np.float32)))
     ev = {"bin": g["bin"], "angle": g["angle"], "energy": g["energy"]}
     return p, g, ctx, _dev(ev)
 
 
-def test_c1_sensitivity(c1):
-    p, g, ctx, ev = c1
+def test_small_sensitivity(small):
+    p, g, ctx, ev = small
     sens = ctx.sensitivity(4).cpu().numpy()
     mx, l2 = _rel(sens, g["sens"])
     assert mx < TOL and l2 < TOL, (mx, l2)
 
 
-def test_c1_forward_every_event(c1):
+def test_small_forward_every_event(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     pj = ctx.forward(ev, torch.from_numpy(g["act"].astype(np.float32)).cuda()).cpu().numpy()
     rel = np.abs(pj - g["p_act"]) / g["p_act"]
     assert rel.max() < TOL, rel.max()
 
 
-def test_c1_backproject(c1):
+def test_small_backproject(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     out = ctx.backproject(ev, torch.from_numpy(g["bp_w"].astype(np.float32)).cuda()).cpu().numpy()
     mx, l2 = _rel(out, g["bp"])
     assert mx < TOL and l2 < TOL, (mx, l2)
     assert np.all(out[~g["support"]] == 0)
 
 
-def test_c1_osem_every_subiteration(c1):
+def test_small_osem_every_subiteration(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     nsub = 4
     sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
     lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
@@ -102,13 +102,13 @@ def test_c1_osem_every_subiteration(c1):
         assert mx < TOL and l2 < TOL, (k, mx, l2)
         assert sk == g["skipped"][k]
         assert ll == pytest.approx(g["ll"][k], rel=1e-5)
-    print("c1 worst relative error over 40 sub-iterations", worst)
+    print("small worst relative error over 40 sub-iterations", worst)
 
 
-def test_c1_end_to_end_with_gpu_sensitivity(c1):
+def test_small_end_to_end_with_gpu_sensitivity(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
     plan = ctx.plan(ev, 4)
@@ -117,10 +117,10 @@ def test_c1_end_to_end_with_gpu_sensitivity(c1):
     assert mx < TOL and l2 < TOL, (mx, l2)
 
 
-def test_c1_resume_is_bitwise_identical(c1):
+def test_small_resume_is_bitwise_identical(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     plan = ctx.plan(ev, 4)
     a = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
@@ -133,10 +133,10 @@ def test_c1_resume_is_bitwise_identical(c1):
     assert torch.equal(a, b)
 
 
-def test_c1_event_tiles_agree_and_runs_are_deterministic(c1):
+def test_small_event_tiles_agree_and_runs_are_deterministic(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
     plan = ctx.plan(ev, 4)
     outs = {}
@@ -155,10 +155,10 @@ def test_c1_event_tiles_agree_and_runs_are_deterministic(c1):
     assert np.abs(a - b).max() / np.abs(a).max() < 1e-5
 
 
-def test_batched_cases_equal_independent_runs(c1, lm):
+def test_batched_cases_equal_independent_runs(small, lm):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     rng = np.random.default_rng(3)
     n = ev["bin"].numel()
@@ -174,11 +174,11 @@ def test_batched_cases_equal_independent_runs(c1, lm):
         assert torch.equal(lam, batched[c])
 
 
-def test_c2_sampled_rows_at_full_size(lm):
+def test_64x64_sampled_rows_at_full_size(lm):
     import torch
 
-    g = np.load(os.path.join(GOLD, "c2_oracle.npz"))
-    w = synth.CONFIGS["c2"]
+    g = np.load(os.path.join(GOLD, "64x64_50k_oracle.npz"))
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ev = synth.generic_events(p, act, w.n_events, w.seed_events, poisson=True)
@@ -192,10 +192,10 @@ def test_c2_sampled_rows_at_full_size(lm):
     assert np.abs(got - g["sens"]).max() / np.abs(g["sens"]).max() < TOL
 
 
-def test_c2_count_conservation_full_size(lm):
+def test_64x64_count_conservation_full_size(lm):
     import torch
 
-    w = synth.CONFIGS["c2"]
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ev = synth.generic_events(p, act, w.n_events, w.seed_events, poisson=True)
@@ -211,12 +211,12 @@ def test_c2_count_conservation_full_size(lm):
         assert bool(torch.all(lam >= 0))
 
 
-def test_c2_one_full_iteration(lm):
+def test_64x64_one_full_iteration(lm):
     import torch
 
-    path = os.path.join(GOLD, "c2iter_oracle.npz")
+    path = os.path.join(GOLD, "64x64_50k_iter_oracle.npz")
     g = np.load(path)
-    w = synth.CONFIGS["c2"]
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ev = synth.generic_events(p, act, 2000, 23)
@@ -231,11 +231,11 @@ def test_c2_one_full_iteration(lm):
         assert mx < TOL and l2 < TOL, (k, mx, l2)
 
 
-def test_c5_sampled_rows_at_128(lm):
+def test_128x128_sampled_rows_at_128(lm):
     import torch
 
-    g = np.load(os.path.join(GOLD, "c5_oracle.npz"))
-    w = synth.CONFIGS["c5"]
+    g = np.load(os.path.join(GOLD, "128x128_16cases_oracle.npz"))
+    w = synth.CONFIGS["128x128_16cases"]
     p = w.params
     mu, act, _ = synth.phantom(w, 0)
     ev = synth.generic_events(p, act, 20000, 5300)
@@ -246,10 +246,10 @@ def test_c5_sampled_rows_at_128(lm):
     assert rel.max() < TOL, rel.max()
 
 
-def test_invalid_inputs_are_rejected(c1, lm):
+def test_invalid_inputs_are_rejected(small, lm):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     for key, val in (("bin", 16), ("angle", 32), ("energy", 110.0), ("energy", float("nan"))):
         bad = {k: v.clone() for k, v in ev.items()}
         bad[key][5] = val
@@ -268,10 +268,10 @@ def test_invalid_inputs_are_rejected(c1, lm):
         lm.Context(synth.replace(p, ns=5), torch.from_numpy(g["mu"].astype(np.float32)))
 
 
-def test_empty_and_single_event_lists(c1, lm):
+def test_empty_and_single_event_lists(small, lm):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     empty = {k: v[:0].contiguous() for k, v in ev.items()}
     assert ctx.forward(empty, sens[0]).numel() == 0
@@ -288,10 +288,10 @@ def test_empty_and_single_event_lists(c1, lm):
     assert float((s1[0].double() * lam.double()).sum()) == pytest.approx(1.0, rel=TOL)
 
 
-def test_graph_launch_equals_eager_and_replays(c1):
+def test_graph_launch_equals_eager_and_replays(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     plan = ctx.plan(ev, 4)
     lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
@@ -308,10 +308,10 @@ def test_graph_launch_equals_eager_and_replays(c1):
     assert mx < TOL and l2 < TOL
 
 
-def test_autotune_keeps_results(c1):
+def test_autotune_keeps_results(small):
     import torch
 
-    p, g, ctx, ev = c1
+    p, g, ctx, ev = small
     sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
     plan = ctx.plan(ev, 4)
     jt = plan.autotune(use_cache=False)
@@ -326,7 +326,7 @@ def test_autotune_keeps_results(c1):
 def test_batched_uneven_cases_in_one_graph(lm):
     import torch
 
-    w = synth.CONFIGS["c2"]
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))

@@ -1,7 +1,7 @@
 """GPU parity of events that carry a continuous lateral position (mm) instead
 of a detector bin: the collimator response becomes the Gaussian density at
 the position.  Expected values come from tests/golden/make_oracle_golden.py
-(c1pos, c2pos), which calls only the FP64 oracle and the seeded generators.
+(small_pos, pos64), which calls only the FP64 oracle and the seeded generators.
 The bar is the parity tests' 1e-4 relative error in max-norm and L2."""
 import hashlib
 import os
@@ -24,15 +24,15 @@ def _rel(got, ref):
 
 
 @pytest.fixture(scope="module")
-def c1pos():
+def small_pos():
     import torch
 
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2305_17111_amd as lm
 
-    g = np.load(os.path.join(GOLD, "c1pos_oracle.npz"))
-    mu = np.load(os.path.join(GOLD, "c1_oracle.npz"))["mu"]
-    p = synth.CONFIGS["c1"].params
+    g = np.load(os.path.join(GOLD, "16x16_2k_pos_oracle.npz"))
+    mu = np.load(os.path.join(GOLD, "16x16_2k_oracle.npz"))["mu"]
+    p = synth.CONFIGS["16x16_2k"].params
     ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
     ev = lm.events_to_device({"position": g["position"], "angle": g["angle"],
                               "energy": g["energy"]})
@@ -40,26 +40,26 @@ def c1pos():
     return lm, p, g, ctx, ev
 
 
-def test_position_rows_and_forward_match_oracle(c1pos):
+def test_position_rows_and_forward_match_oracle(small_pos):
     import torch
 
-    lm, p, g, ctx, ev = c1pos
+    lm, p, g, ctx, ev = small_pos
     rows = ctx.rows(ev, part=3).cpu().numpy()
     for k, j in enumerate(g["idx"]):
         mx, l2 = _rel(rows[j], g["rows"][k])
         assert mx < TOL and l2 < TOL, (j, mx, l2)
     # the context's model without a surrogate is the exact one
     assert np.array_equal(ctx.rows(ev, part=0).cpu().numpy(), rows)
-    act = np.load(os.path.join(GOLD, "c1_oracle.npz"))["act"]
+    act = np.load(os.path.join(GOLD, "16x16_2k_oracle.npz"))["act"]
     pj = ctx.forward(ev, torch.from_numpy(act.astype(np.float32)).cuda()).cpu().numpy()
     rel = np.abs(pj - g["p_act"]) / g["p_act"]
     assert rel.max() < TOL, rel.max()
 
 
-def test_position_osem_every_subiteration(c1pos):
+def test_position_osem_every_subiteration(small_pos):
     import torch
 
-    lm, p, g, ctx, ev = c1pos
+    lm, p, g, ctx, ev = small_pos
     nsub = g["sens"].shape[0]
     sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
     lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
@@ -76,10 +76,10 @@ def test_position_osem_every_subiteration(c1pos):
     assert torch.equal(graphed, lam)
 
 
-def test_position_event_tiles_table_and_cached_rows(c1pos):
+def test_position_event_tiles_table_and_cached_rows(small_pos):
     import torch
 
-    lm, p, g, ctx, ev = c1pos
+    lm, p, g, ctx, ev = small_pos
     nsub = g["sens"].shape[0]
     sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
     lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
@@ -109,10 +109,10 @@ def test_position_event_tiles_table_and_cached_rows(c1pos):
     plan.cache_rows(False)
 
 
-def test_position_batched_cases_equal_independent_runs(c1pos):
+def test_position_batched_cases_equal_independent_runs(small_pos):
     import torch
 
-    lm, p, g, ctx, ev = c1pos
+    lm, p, g, ctx, ev = small_pos
     n = ev["angle"].numel()
     offs = [0, 400, 1100, n]
     sens = ctx.sensitivity(4)
@@ -126,10 +126,10 @@ def test_position_batched_cases_equal_independent_runs(c1pos):
         assert torch.equal(lam, batched[c]), c
 
 
-def test_position_rejections(c1pos):
+def test_position_rejections(small_pos):
     import torch
 
-    lm, p, g, ctx, ev = c1pos
+    lm, p, g, ctx, ev = small_pos
     for val in (p.R, -p.R - 0.01, float("nan"), float("inf")):
         bad = {k: v.clone() for k, v in ev.items()}
         bad["position"][5] = val
@@ -161,13 +161,13 @@ def test_position_rejections(c1pos):
     assert bool(torch.isfinite(lam).all())
 
 
-def test_c2_position_sampled_rows_and_conservation_full_size():
+def test_64x64_position_sampled_rows_and_conservation_full_size():
     import torch
 
     import paper_2305_17111_amd as lm
 
-    g = np.load(os.path.join(GOLD, "c2pos_oracle.npz"))
-    w = synth.CONFIGS["c2"]
+    g = np.load(os.path.join(GOLD, "64x64_50k_pos_oracle.npz"))
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ev = synth.generic_events(p, act, w.n_events, w.seed_events, poisson=True)

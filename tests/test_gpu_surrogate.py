@@ -28,7 +28,7 @@ def env():
     import oracle
     import paper_2305_17111_amd as lm
 
-    w = synth.CONFIGS["c1"]
+    w = synth.CONFIGS["16x16_2k"]
     p = w.params
     mu, act, rois = synth.phantom(w)
     mu32 = mu.astype(np.float32)

@@ -14,14 +14,14 @@ TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
-def c1():
+def small():
     import torch
 
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2305_17111_amd as lm
 
-    g = np.load(os.path.join(GOLD, "c1_oracle.npz"))
-    p = synth.CONFIGS["c1"].params
+    g = np.load(os.path.join(GOLD, "16x16_2k_oracle.npz"))
+    p = synth.CONFIGS["16x16_2k"].params
     ctx = lm.Context(p, torch.from_numpy(g["mu"].astype(np.float32)))
     ev = lm.events_to_device({"bin": g["bin"], "angle": g["angle"], "energy": g["energy"]})
     return lm, p, g, ctx, ev
@@ -33,10 +33,10 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max(), np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_table_rows_and_osem_match_oracle(c1):
+def test_table_rows_and_osem_match_oracle(small):
     import torch
 
-    lm, p, g, ctx, ev = c1
+    lm, p, g, ctx, ev = small
     rows0 = ctx.rows(ev, part=3).cpu().numpy()
     ctx.path_table(True)
     try:
@@ -55,10 +55,10 @@ def test_table_rows_and_osem_match_oracle(c1):
         ctx.path_table(False)
 
 
-def test_table_graph_recaptures_when_the_table_goes(c1):
+def test_table_graph_recaptures_when_the_table_goes(small):
     import torch
 
-    lm, p, g, ctx, ev = c1
+    lm, p, g, ctx, ev = small
     sens = ctx.sensitivity(4)
     lam0 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
     plan = ctx.plan(ev, 4)
@@ -80,7 +80,7 @@ def test_table_full_size_iteration():
 
     import paper_2305_17111_amd as lm
 
-    w = synth.CONFIGS["c2"]
+    w = synth.CONFIGS["64x64_50k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
@@ -103,7 +103,7 @@ def test_table_in_plans_over_several_maps():
 
     import paper_2305_17111_amd as lm
 
-    w = synth.CONFIGS["c1"]
+    w = synth.CONFIGS["16x16_2k"]
     p = w.params
     mu, act, _ = synth.phantom(w)
     maps = [mu] + list(synth.random_body_maps(p, 2, seed=8))
