@@ -213,7 +213,9 @@ int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, fl
  * 3-D model by (case, angle, square block of the detector, bin_z, bin,
  * energy)) and
  * lays out the
- * work tiles and the per-subset scratch.  A plan holds one or more
+ * work tiles, the collimator-response factor of every (listed scatter point,
+ * event) pair of each tile (event-tile floats per listed point: 24 MB for 50k
+ * events at 64x64) and the per-subset scratch.  A plan holds one or more
  * independent cases (noise realisations or patients) that share the context's
  * attenuation map and sensitivity.
  *   ev            events of all cases, concatenated (device arrays).

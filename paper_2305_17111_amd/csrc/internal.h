@@ -14,6 +14,10 @@ namespace lmmew {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kPi = 3.14159265358979323846;
+// scatter-list entry .x: the point's index in its angle's list (low bits) and
+// the mask of the tile's groups of 16 events that its response reaches
+constexpr int kSlistGroupShift = 24;
+constexpr int kSlistPoint = (1 << kSlistGroupShift) - 1;
 constexpr float kPsfCut = 7.0f;    // collimator-response Gaussian dropped beyond 7 sigma
 
 // scatter surrogate network (6 -> 128 -> 128 -> 128 -> 1)
@@ -127,8 +131,13 @@ struct RowArgs {
     const float *ev_E;
     float *A;                // [rows][Qp]
     int mode;                // 0: all paths, 1: scattered paths only, 2: unscattered only
+    const float *pvt;        // [slist entry][event tile]: response factor of each listed
+                             // point for each event of its tile (0 past the tile's events)
 };
 hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st);
+// the response-factor table of the tiles of one subset (written to pvt)
+hipError_t launch_pv_table(const DevSys &S, const RowArgs &r, int event_tile, float *pvt,
+                           hipStream_t st);
 // collimator-response factors of every (angle, scatter point, bin); in 3-D also
 // every (angle, scatter point, axial bin) into respz (sz: scatter-point z by g_qs row)
 hipError_t launch_resp_table(const DevSys &S, const ScatA *sa, float *resp, const float *sz,

@@ -424,19 +424,18 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
 // One wavefront per work item: 64 support pixels (one per lane) x one tile of
 // up to JT events of a single angle, with JT accumulators a_jq per lane in
 // registers.  The tile carries the list of scatter points whose collimator
-// response reaches at least one of its events.  For each block of 16 listed
-// scatter points the wavefront computes the response factors of all
-// (scatter point, event) pairs, one group of JT/4 events per lane, and keeps
-// them in registers; in the pair loop v_readlane moves a factor into a scalar
-// register, so a zero factor skips its three exponentials with a uniform
-// branch.  For each listed scatter point every lane derives its pixel's path
-// parameters once and reuses them for all of the tile's events.
+// response reaches at least one of its events, each with the mask of its
+// groups of 16 events that the response reaches.  The response factors of
+// the listed (point, event) pairs come from the plan's table (k_pv_table)
+// through scalar loads, so they sit in scalar registers: a zero factor skips
+// the pair's exponentials with a uniform branch, and a group the point does
+// not reach is skipped whole.  For each listed point every lane reads or
+// derives its pixel's path parameters once and reuses them for all of the
+// tile's events.
 // ---------------------------------------------------------------------------
 template <int JT, int NW, bool TAB, bool D3>
 __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 {
-    constexpr int KC = 16;               // scatter points per response block
-    constexpr int TJ = JT / 4;           // events per lane in a response block
     // Work item p = (pixel block, tile) in block-major order.  Workgroups go to
     // the 8 XCDs round-robin by id, so XCD k runs ids k, k+8, ...: mapping them
     // to the k-th contiguous eighth of the items gives every XCD an equal share
@@ -524,124 +523,102 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 
     float Ej[JT];
 #pragma unroll
-    for (int j = 0; j < JT; ++j) Ej[j] = r.ev_E[T.e0 + min(j, last)];
+    for (int j = 0; j < JT; ++j) {
+        Ej[j] = r.ev_E[T.e0 + min(j, last)];
+    }
 
     float acc[JT];
 #pragma unroll
     for (int j = 0; j < JT; ++j) acc[j] = 0.f;
 
     const ScatA *sa = sab + (size_t)a * nsc;
-    const int kl = lane % KC, jg = lane / KC;
-    const int kend = (r.mode == 2) ? T.k0 : T.k1;     // unscattered only: no scatter loop
-    for (int lc0 = T.k0; lc0 < kend; lc0 += KC) {
-        // response factors of (listed scatter point lc0+kl, events jg*TJ .. jg*TJ+TJ-1):
-        // read from the map's [angle][point][bin] table for binned events, the
-        // density at the position otherwise
-        float pv[TJ];
-        {
-            const int l = lc0 + kl;
-            const int k = l < T.k1 ? r.slist[l].x : 0;
-            if (r.ev_u) {
-                const ScatA sp = sa[k];
+    // ptab: [angle][point][pixel][3 nw] -- a lane's 3 nw values are contiguous
+    const int pw = 3 * S.nw;
+    const float *pbase = TAB ? ptab + (size_t)a * nsc * S.Qp * pw + (size_t)i * pw : nullptr;
+    const size_t pstride = (size_t)S.Qp * pw;                  // one point of the angle
+    // A listed point's inputs: its response factors for the tile's events
+    // (scalar registers), and its path parameters from the table or what the
+    // kernel derives them from.  Two buffers alternate, so the next point's
+    // loads are in flight while the current one is evaluated, with no copies.
+    struct Pt {
+        int l;                         // scatter-list entry
+        unsigned gm;                   // groups of 16 events its response reaches
+        float pf[16];                  // response factors of the first 16 events
+        float A[NW], sw[NW], F[NW];    // table values
+        ScatA sp;                      // or: the point, its pixel path, its z
+        float gqs, zs;
+    };
+    auto load_pt = [&](int l, Pt &d) {
+        const int2 e = r.slist[l];
+        d.l = l;
+        d.gm = (unsigned)e.x >> kSlistGroupShift;
 #pragma unroll
-                for (int t = 0; t < TJ; ++t) {
-                    const int j = jg * TJ + t;
-                    const float z = (r.ev_u[T.e0 + min(j, last)] - sp.u) * sp.isig;
-                    pv[t] = (l < T.k1 && j < T.cnt) ? pdf_cut(z, sp.isig) : 0.f;
-                }
-            } else {
-                const float *rrow = resp + ((size_t)a * nsc + k) * S.nb;
-#pragma unroll
-                for (int t = 0; t < TJ; ++t) {
-                    const int j = jg * TJ + t;
-                    pv[t] = (l < T.k1 && j < T.cnt) ? rrow[r.ev_bin[T.e0 + min(j, last)]] : 0.f;
-                }
-                if (D3) {
-                    const float *zrow = respz + ((size_t)a * nsc + k) * S.nbz;
-#pragma unroll
-                    for (int t = 0; t < TJ; ++t) {
-                        const int j = jg * TJ + t;
-                        pv[t] *= zrow[r.ev_binz[T.e0 + min(j, last)]];
-                    }
-                }
-            }
-        }
-        const int kn = min(KC, T.k1 - lc0);
-        // the next listed point's data is loaded one iteration ahead, so the
-        // dependent loads (list entry, point, table values) overlap the work
-        // ptab: [angle][point][pixel][3 nw] -- a lane's 3 nw values are contiguous
-        const int pw = 3 * S.nw;
-        const float *pbase = TAB ? ptab + (size_t)a * nsc * S.Qp * pw + (size_t)i * pw : nullptr;
-        const size_t pstride = (size_t)S.Qp * pw;                  // one point of the angle
-        int2 en = r.slist[lc0];
-        ScatA spn{};
-        float gqn = 0.f, szn = 0.f;
-        float An[NW], sn[NW], Fn[NW];
+        for (int j = 0; j < 16; ++j) d.pf[j] = r.pvt[(size_t)l * JT + j];
+        const int k = e.x & kSlistPoint;
         if (TAB) {
-            const float *tp = pbase + (size_t)en.x * pstride;
+            const float *tp = pbase + (size_t)k * pstride;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                An[w] = tp[3 * w];
-                sn[w] = tp[3 * w + 1];
-                Fn[w] = tp[3 * w + 2];
+                d.A[w] = tp[3 * w];
+                d.sw[w] = tp[3 * w + 1];
+                d.F[w] = tp[3 * w + 2];
             }
         } else {
-            spn = sa[en.x];
-            gqn = g_qs[(size_t)en.y * S.Qp + i];
-            if (D3) szn = szs[en.y];
+            d.sp = sa[k];
+            d.gqs = g_qs[(size_t)e.y * S.Qp + i];
+            d.zs = D3 ? szs[e.y] : 0.f;
         }
-        for (int kk = 0; kk < kn; ++kk) {
-            float Aw[NW], sw[NW], Fw[NW];
-            if (TAB) {
+    };
+    auto run_pt = [&](const Pt &d) {
+        float Aw[NW], sw[NW], Fw[NW];
+        if (TAB) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    Aw[w] = An[w];
-                    sw[w] = sn[w];
-                    Fw[w] = Fn[w];
-                }
-                if (kk + 1 < kn) {
-                    en = r.slist[lc0 + kk + 1];
-                    const float *tp = pbase + (size_t)en.x * pstride;
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) {
-                        if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                        An[w] = tp[3 * w];
-                        sn[w] = tp[3 * w + 1];
-                        Fn[w] = tp[3 * w + 2];
-                    }
-                }
-            } else {
-                const ScatA sp = spn;
-                const float gqs = gqn, zs = szn;
-                if (kk + 1 < kn) {
-                    en = r.slist[lc0 + kk + 1];
-                    spn = sa[en.x];
-                    gqn = g_qs[(size_t)en.y * S.Qp + i];
-                    if (D3) szn = szs[en.y];
-                }
-                float Ep[NW];
-                scatter_params<NW, true, D3>(S, sp.x - xq, sp.y - yq, zs - zq, c, s, sp.lc, gqs,
-                                             sp.gsa, Aw, sw, Fw, Ep);
+            for (int w = 0; w < NW; ++w) {
+                Aw[w] = d.A[w];
+                sw[w] = d.sw[w];
+                Fw[w] = d.F[w];
             }
+        } else {
+            float Ep[NW];
+            scatter_params<NW, true, D3>(S, d.sp.x - xq, d.sp.y - yq, d.zs - zq, c, s, d.sp.lc,
+                                         d.gqs, d.sp.gsa, Aw, sw, Fw, Ep);
+        }
 #pragma unroll
-            for (int j = 0; j < JT; ++j) {
-                // factor bits in a scalar register: a scalar compare decides the branch
-                const int pbits =
-                    __builtin_amdgcn_readlane(__float_as_int(pv[j % TJ]), kk + KC * (j / TJ));
-                if (pbits != 0) {
-                    const float ps = __int_as_float(pbits);
+        for (int g = 0; g < JT / 16; ++g) {
+            if (JT > 16 && !((d.gm >> g) & 1u)) continue;
+            float pg[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                pg[t] = g == 0 ? d.pf[t] : r.pvt[(size_t)d.l * JT + 16 * g + t];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int j = 16 * g + t;
+                // a zero factor (response cut) skips the pair on a scalar compare
+                if (__float_as_int(pg[t]) != 0) {
                     float u = fmaf(sw[0], Ej[j], -Fw[0]);
-                    float t = fast_exp2(fmaf(-u, u, Aw[0]));
+                    float e = fast_exp2(fmaf(-u, u, Aw[0]));
 #pragma unroll
                     for (int w = 1; w < NW; ++w) {
                         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
                         u = fmaf(sw[w], Ej[j], -Fw[w]);
-                        t += fast_exp2(fmaf(-u, u, Aw[w]));
+                        e += fast_exp2(fmaf(-u, u, Aw[w]));
                     }
-                    acc[j] = fmaf(ps, t, acc[j]);
+                    acc[j] = fmaf(pg[t], e, acc[j]);
                 }
             }
+        }
+    };
+    const int kend = (r.mode == 2) ? T.k0 : T.k1;     // unscattered only: no scatter loop
+    if (T.k0 < kend) {
+        Pt d0, d1;
+        load_pt(T.k0, d0);
+        for (int l = T.k0; l < kend; l += 2) {
+            load_pt(min(l + 1, kend - 1), d1);
+            run_pt(d0);
+            if (l + 1 >= kend) break;
+            load_pt(min(l + 2, kend - 1), d0);
+            run_pt(d1);
         }
     }
 
@@ -651,6 +628,60 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
             r.A[(size_t)(T.e0 + j) * S.Qp + i] = valid ? prim[j * kWave + lane] + acc[j] : 0.f;
         }
     }
+}
+
+// Response factors of every (listed point, event) pair of each tile, built
+// with the tiles: the [angle][point][bin] table entry of binned events (times
+// the axial one in 3-D), the Gaussian density at a continuous position.  One
+// workgroup per tile.
+template <bool D3>
+__global__ __launch_bounds__(64) void k_pv_table(const DevSys S, const RowArgs r, int JT,
+                                                 float *pvt)
+{
+    const Tile T = r.tiles[blockIdx.x];
+    const float *resp = r.resp, *respz = r.respz;
+    const ScatA *sab = r.sa;
+    int nsc = S.nsc;
+    if (r.maps) {
+        const MapTab m = r.maps[T.ncase];
+        resp = m.resp;
+        respz = m.respz;
+        sab = m.sa;
+        nsc = m.nsc;
+    }
+    const int a = T.angle, last = T.cnt - 1;
+    const ScatA *sa = sab + (size_t)a * nsc;
+    const int n = (T.k1 - T.k0) * JT;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int l = T.k0 + t / JT, j = t % JT;
+        const int k = r.slist[l].x & kSlistPoint;
+        float v = 0.f;
+        if (r.ev_u) {
+            const ScatA sp = sa[k];
+            const float z = (r.ev_u[T.e0 + min(j, last)] - sp.u) * sp.isig;
+            v = j < T.cnt ? pdf_cut(z, sp.isig) : 0.f;
+        } else {
+            const float *rrow = resp + ((size_t)a * nsc + k) * S.nb;
+            v = j < T.cnt ? rrow[r.ev_bin[T.e0 + min(j, last)]] : 0.f;
+            if (D3) {
+                const float *zrow = respz + ((size_t)a * nsc + k) * S.nbz;
+                v *= zrow[r.ev_binz[T.e0 + min(j, last)]];
+            }
+        }
+        pvt[(size_t)l * JT + j] = v;
+    }
+}
+
+hipError_t launch_pv_table(const DevSys &S, const RowArgs &r, int event_tile, float *pvt,
+                           hipStream_t st)
+{
+    if (r.ntiles == 0) return hipSuccess;
+    if (S.nz > 0)
+        hipLaunchKernelGGL(k_pv_table<true>, dim3(r.ntiles), dim3(64), 0, st, S, r, event_tile, pvt);
+    else
+        hipLaunchKernelGGL(k_pv_table<false>, dim3(r.ntiles), dim3(64), 0, st, S, r, event_tile,
+                           pvt);
+    return hipGetLastError();
 }
 
 template <int JT, bool TAB, bool D3>

@@ -98,6 +98,7 @@ struct lmmew_plan {
     int64_t *d_perm = nullptr;
     Tile *d_tiles = nullptr;
     int2 *d_slist = nullptr;
+    float *d_pvt = nullptr;           // [slist entry][JT] response factors
     MapTab *d_maps = nullptr;
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
@@ -254,7 +255,7 @@ void free_plan(lmmew_plan *p)
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
     p->prof_ev.clear();
     dfree(p->d_bin); dfree(p->d_binz); dfree(p->d_u); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
-    dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
+    dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_pvt); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
     dfree(p->d_Acache);
@@ -300,6 +301,18 @@ std::pair<int, int> reached(const ScatA &e, const float *u, int first, int last)
     return {(int)(lo - u), (int)(hi - u)};
 }
 
+// Scatter-list entry .x: point index k and the mask of the tile's groups of 16
+// events that its response reaches.
+inline int slist_x(int k, unsigned gm) { return k | (int)(gm << kSlistGroupShift); }
+
+// Mask of the groups of 16 rows that rows [first, last) of a tile touch.
+inline unsigned group_span(int first, int last)
+{
+    unsigned gm = 0;
+    for (int g = first / 16; g <= (last - 1) / 16; ++g) gm |= 1u << g;
+    return gm;
+}
+
 // Builds tiles and chunks of a plan for the event tile size p->JT.
 void build_tiles(lmmew_plan *p)
 {
@@ -340,18 +353,21 @@ void build_tiles(lmmew_plan *p)
                     const int lo = c->rb_lo[ak], hi = c->rb_hi[ak];
                     const int lz = c->rbz_lo[ak], hz = c->rbz_hi[ak];
                     if (hi < bmin || lo > bmax || hz < zmin || lz > zmax) continue;
-                    bool any = false;
-                    for (int j = r; j < e && !any; ++j)
-                        any = p->bin[j] >= lo && p->bin[j] <= hi && p->binz[j] >= lz &&
-                              p->binz[j] <= hz;
-                    if (any) p->slist.push_back(make_int2(k, c->sa[ak].sidx));
+                    unsigned gm = 0;
+                    for (int j = r; j < e; ++j)
+                        if (p->bin[j] >= lo && p->bin[j] <= hi && p->binz[j] >= lz &&
+                            p->binz[j] <= hz)
+                            gm |= 1u << ((j - r) / 16);
+                    if (gm) p->slist.push_back(make_int2(slist_x(k, gm), c->sa[ak].sidx));
                 }
             } else if (p->cont) {
                 // scatter points whose density reaches some position of the tile
                 for (int k = 0; k < nsc; ++k) {
                     const ScatA &sp = c->sa[(size_t)a * nsc + k];
                     const std::pair<int, int> rr = reached(sp, p->u.data(), r, e);
-                    if (rr.first < rr.second) p->slist.push_back(make_int2(k, sp.sidx));
+                    if (rr.first < rr.second)
+                        p->slist.push_back(make_int2(
+                            slist_x(k, group_span(rr.first - r, rr.second - r)), sp.sidx));
                 }
             } else {
                 int bmin = p->bin[r], bmax = p->bin[r];
@@ -364,10 +380,14 @@ void build_tiles(lmmew_plan *p)
                     const size_t ak = (size_t)a * nsc + k;
                     const int lo = c->rb_lo[ak], hi = c->rb_hi[ak];
                     if (hi < bmin || lo > bmax) continue;
-                    // the tile's bins are sorted: is one of them inside [lo, hi]?
+                    // the tile's bins are sorted: the rows inside [lo, hi] are one run
                     const int *first = p->bin.data() + r, *lastp = p->bin.data() + e;
                     const int *it = std::lower_bound(first, lastp, lo);
-                    if (it != lastp && *it <= hi) p->slist.push_back(make_int2(k, c->sa[ak].sidx));
+                    const int *ie = std::upper_bound(it, lastp, hi);
+                    if (it != ie)
+                        p->slist.push_back(make_int2(
+                            slist_x(k, group_span((int)(it - first), (int)(ie - first))),
+                            c->sa[ak].sidx));
                 }
             }
             const int k1 = (int)p->slist.size();
@@ -406,6 +426,8 @@ void build_tiles(lmmew_plan *p)
     (void)na;
 }
 
+RowArgs row_args(const lmmew_ctx *ctx, const lmmew_plan *p, int s);
+
 int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
 {
     // a captured graph refers to the arrays about to be replaced
@@ -415,6 +437,7 @@ int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
     }
     dfree(p->d_tiles);
     dfree(p->d_slist);
+    dfree(p->d_pvt);
     dfree(p->d_chunks);
     dfree(p->d_case_chunk);
     dfree(p->d_part);
@@ -437,6 +460,14 @@ int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
                                    p->chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(p->d_case_chunk, p->case_chunk.data(),
                                p->case_chunk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    // response factors of the listed (point, event) pairs: JT floats per list entry
+    if (!p->slist.empty()) {
+        HIPCHK(ctx, dalloc(&p->d_pvt, p->slist.size() * (size_t)p->JT));
+        for (int s = 0; s < p->nsub; ++s) {
+            RowArgs r = row_args(ctx, p, s);
+            HIPCHK(ctx, launch_pv_table(ctx->S, r, p->JT, p->d_pvt, st));
+        }
+    }
     HIPCHK(ctx, hipStreamSynchronize(st));
     return LMMEW_OK;
 }
@@ -767,15 +798,10 @@ float *rows_of(lmmew_plan *p, int s)
     return p->d_Acache ? p->d_Acache + (size_t)p->subs[s].row0 * p->ctx->S.Qp : p->d_A;
 }
 
-int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
-             float *dst = nullptr)
+// Per-event kernel arguments of subset s (without output and mode).
+RowArgs row_args(const lmmew_ctx *ctx, const lmmew_plan *p, int s)
 {
     const lmmew_plan::Sub &sub = p->subs[s];
-    float *const out = dst ? dst : p->d_A;
-    const bool surrogate = (part == 0 && ctx->mlp != nullptr);
-    if (surrogate && p->cont)
-        return fail(ctx, LMMEW_EINVAL,
-                    "the scatter surrogate models binned events; these carry continuous positions");
     RowArgs r{};
     r.pix_xy = ctx->d_pix;
     r.dirs = ctx->d_dirs;
@@ -795,8 +821,22 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     r.ev_u = p->cont ? p->d_u + sub.row0 : nullptr;
     r.ev_binz = p->d_binz ? p->d_binz + sub.row0 : nullptr;
     r.ev_E = p->d_E + sub.row0;
+    return r;
+}
+
+int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
+             float *dst = nullptr)
+{
+    const lmmew_plan::Sub &sub = p->subs[s];
+    float *const out = dst ? dst : p->d_A;
+    const bool surrogate = (part == 0 && ctx->mlp != nullptr);
+    if (surrogate && p->cont)
+        return fail(ctx, LMMEW_EINVAL,
+                    "the scatter surrogate models binned events; these carry continuous positions");
+    RowArgs r = row_args(ctx, p, s);
     r.A = out;
     r.mode = surrogate ? 2 : (part == 3 ? 0 : part);
+    r.pvt = p->d_pvt;
     const bool prof = p->prof && sub.ntiles > 0;
     if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
     HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
@@ -987,6 +1027,8 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
                     smu.push_back(acc);
                 }
             }
+    if (sc.size() > (size_t)kSlistPoint)
+        return bail(fail(ctx, LMMEW_EINVAL, "too many scatter points (at most 2^24 - 1)"));
     const int nsc = (int)sc.size();
     // directions and per-angle scatter lists sorted by lateral coordinate
     ctx->dir_c.resize(na);
