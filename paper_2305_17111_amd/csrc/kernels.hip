@@ -487,38 +487,46 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const float xq = xy.x, yq = xy.y;
     const float zq = D3 ? r.pix_z[i] : 0.f;
 
-    // unscattered paths, staged in LDS (each row element is written once, at the end)
-    __shared__ float prim[JT * kWave];
-    {
-        const float dq = S.R - (xq * c + yq * s);
-        const float uq = -xq * s + yq * c;
-        const float isq = 1.f / ((S.fwhm0 + S.fslope * dq) * S.inv_fwhm_to_sigma);
-        const float gqa = g_qa[(size_t)a * S.Qp + i];
-        float Pp[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) Pp[w] = S.pp[w] * fast_exp2(-S.f[w] * gqa * kLog2e);
-        for (int j = 0; j < T.cnt; ++j) {
-            float ps = 0.f;
-            if (r.mode != 1) {
-                if (r.ev_u) {
-                    ps = pdf_cut((r.ev_u[T.e0 + j] - uq) * isq, isq);
-                } else {
-                    const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
-                    ps = psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
-                    if (D3) {
-                        const float lz = -S.Zh + (float)r.ev_binz[T.e0 + j] * S.dbz;
-                        ps *= psf_cut((lz + S.dbz - zq) * isq, (lz - zq) * isq);
-                    }
+    // Unscattered paths of event j at this lane's pixel (each row element is
+    // written once, at the end).  Tiles of 16 stage them in LDS before the
+    // scatter loop; larger tiles form them at the end, which keeps the LDS
+    // from limiting how many waves a SIMD holds.
+    const float dq = S.R - (xq * c + yq * s);
+    const float uq = -xq * s + yq * c;
+    const float isq = 1.f / ((S.fwhm0 + S.fslope * dq) * S.inv_fwhm_to_sigma);
+    auto prim_of = [&](int j, const float *Pp) {
+        float ps = 0.f;
+        if (r.mode != 1) {
+            if (r.ev_u) {
+                ps = pdf_cut((r.ev_u[T.e0 + j] - uq) * isq, isq);
+            } else {
+                const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
+                ps = psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
+                if (D3) {
+                    const float lz = -S.Zh + (float)r.ev_binz[T.e0 + j] * S.dbz;
+                    ps *= psf_cut((lz + S.dbz - zq) * isq, (lz - zq) * isq);
                 }
             }
-            float g = 0.f;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                g = fmaf(Pp[w], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gq[w]), j)), g);
-            }
-            prim[j * kWave + lane] = ps * g;
         }
+        float g = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+            g = fmaf(Pp[w], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gq[w]), j)), g);
+        }
+        return __fmul_rn(ps, g);
+    };
+    auto path_weights = [&](float *Pp) {
+        const float gqa = g_qa[(size_t)a * S.Qp + i];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) Pp[w] = S.pp[w] * fast_exp2(-S.f[w] * gqa * kLog2e);
+    };
+    constexpr bool kStage = JT <= 16;
+    __shared__ float prim[kStage ? JT * kWave : 1];
+    if (kStage) {
+        float Pp[NW];
+        path_weights(Pp);
+        for (int j = 0; j < T.cnt; ++j) prim[j * kWave + lane] = prim_of(j, Pp);
     }
 
     float Ej[JT];
@@ -622,10 +630,19 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         }
     }
 
+    if (kStage) {
 #pragma unroll
-    for (int j = 0; j < JT; ++j) {
-        if (j < T.cnt) {
-            r.A[(size_t)(T.e0 + j) * S.Qp + i] = valid ? prim[j * kWave + lane] + acc[j] : 0.f;
+        for (int j = 0; j < JT; ++j) {
+            if (j < T.cnt)
+                r.A[(size_t)(T.e0 + j) * S.Qp + i] = valid ? prim[j * kWave + lane] + acc[j] : 0.f;
+        }
+    } else {
+        float Pp[NW];
+        path_weights(Pp);
+#pragma unroll
+        for (int j = 0; j < JT; ++j) {
+            if (j < T.cnt)
+                r.A[(size_t)(T.e0 + j) * S.Qp + i] = valid ? prim_of(j, Pp) + acc[j] : 0.f;
         }
     }
 }
