@@ -418,6 +418,29 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
     }
 }
 
+// Global-address-space views of device pointers.  For generic (flat) loads
+// the compiler waits for every outstanding load before it uses any of them;
+// for global loads it waits only for those a value depends on.
+template <class T> using GPtr = const T __attribute__((address_space(1))) *;
+template <class T> __device__ __forceinline__ GPtr<T> global_ptr(const T *p)
+{
+    return (GPtr<T>)p;
+}
+
+__device__ __forceinline__ ScatA load_scat(GPtr<ScatA> p)
+{
+    ScatA v;
+    v.x = p->x;
+    v.y = p->y;
+    v.u = p->u;
+    v.isig = p->isig;
+    v.gsa = p->gsa;
+    v.lc = p->lc;
+    v.D = p->D;
+    v.sidx = p->sidx;
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // per-event system model (the hot path)
 //
@@ -451,21 +474,26 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const int i = bx * kWave + lane;
     const int a = T.angle;
     // attenuation tables of the tile's case
-    const float *g_qa = r.g_qa, *g_qs = r.g_qs, *ptab = r.ptab, *resp = r.resp;
-    const float *respz = r.respz, *szs = r.sz;
-    const ScatA *sab = r.sa;
+    const float *g_qa = r.g_qa, *g_qs_ = r.g_qs, *ptab_ = r.ptab, *resp = r.resp;
+    const float *respz = r.respz, *szs_ = r.sz;
+    const ScatA *sab_ = r.sa;
     int nsc = S.nsc;
     if (r.maps) {
         const MapTab m = r.maps[T.ncase];
         g_qa = m.g_qa;
-        g_qs = m.g_qs;
-        sab = m.sa;
-        ptab = m.ptab;
+        g_qs_ = m.g_qs;
+        sab_ = m.sa;
+        ptab_ = m.ptab;
         resp = m.resp;
         respz = m.respz;
-        szs = m.sz;
+        szs_ = m.sz;
         nsc = m.nsc;
     }
+    // Device tables are global memory: loads through global pointers let the
+    // compiler wait for the current point's loads only, not for the next
+    // point's as well (it must wait for every outstanding generic load).
+    const GPtr<float> g_qs = global_ptr(g_qs_), ptab = global_ptr(ptab_), szs = global_ptr(szs_);
+    const GPtr<ScatA> sab = global_ptr(sab_);
     const float2 dir = r.dirs[a];
     const float c = dir.x, s = dir.y;
     const bool valid = i < S.Qm;
@@ -539,19 +567,22 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
     for (int j = 0; j < JT; ++j) acc[j] = 0.f;
 
-    const ScatA *sa = sab + (size_t)a * nsc;
+    const GPtr<ScatA> sa = sab + (size_t)a * nsc;
     // ptab: [angle][point][pixel][3 nw] -- a lane's 3 nw values are contiguous
     const int pw = 3 * S.nw;
-    const float *pbase = TAB ? ptab + (size_t)a * nsc * S.Qp * pw + (size_t)i * pw : nullptr;
+    const GPtr<float> pbase = TAB ? ptab + (size_t)a * nsc * S.Qp * pw + (size_t)i * pw : nullptr;
     const size_t pstride = (size_t)S.Qp * pw;                  // one point of the angle
     // A listed point's inputs: its response factors for the tile's events
     // (scalar registers), and its path parameters from the table or what the
     // kernel derives them from.  Two buffers alternate, so the next point's
     // loads are in flight while the current one is evaluated, with no copies.
+    // The response factors are read as integer bits: their zero test is then a
+    // scalar compare (as a float test it becomes a vector class check per pair).
+    const int *pvb = reinterpret_cast<const int *>(r.pvt);
     struct Pt {
         int l;                         // scatter-list entry
         unsigned gm;                   // groups of 16 events its response reaches
-        float pf[16];                  // response factors of the first 16 events
+        int pf[16];                    // response factors of the first 16 events (bits)
         float A[NW], sw[NW], F[NW];    // table values
         ScatA sp;                      // or: the point, its pixel path, its z
         float gqs, zs;
@@ -561,10 +592,10 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         d.l = l;
         d.gm = (unsigned)e.x >> kSlistGroupShift;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) d.pf[j] = r.pvt[(size_t)l * JT + j];
+        for (int j = 0; j < 16; ++j) d.pf[j] = pvb[(size_t)l * JT + j];
         const int k = e.x & kSlistPoint;
         if (TAB) {
-            const float *tp = pbase + (size_t)k * pstride;
+            const GPtr<float> tp = pbase + (size_t)k * pstride;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
@@ -573,7 +604,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                 d.F[w] = tp[3 * w + 2];
             }
         } else {
-            d.sp = sa[k];
+            d.sp = load_scat(sa + k);
             d.gqs = g_qs[(size_t)e.y * S.Qp + i];
             d.zs = D3 ? szs[e.y] : 0.f;
         }
@@ -595,15 +626,15 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
         for (int g = 0; g < JT / 16; ++g) {
             if (JT > 16 && !((d.gm >> g) & 1u)) continue;
-            float pg[16];
+            int pg[16];
 #pragma unroll
             for (int t = 0; t < 16; ++t)
-                pg[t] = g == 0 ? d.pf[t] : r.pvt[(size_t)d.l * JT + 16 * g + t];
+                pg[t] = g == 0 ? d.pf[t] : pvb[(size_t)d.l * JT + 16 * g + t];
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
                 const int j = 16 * g + t;
                 // a zero factor (response cut) skips the pair on a scalar compare
-                if (__float_as_int(pg[t]) != 0) {
+                if (pg[t] != 0) {
                     float u = fmaf(sw[0], Ej[j], -Fw[0]);
                     float e = fast_exp2(fmaf(-u, u, Aw[0]));
 #pragma unroll
@@ -612,7 +643,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                         u = fmaf(sw[w], Ej[j], -Fw[w]);
                         e += fast_exp2(fmaf(-u, u, Aw[w]));
                     }
-                    acc[j] = fmaf(pg[t], e, acc[j]);
+                    acc[j] = fmaf(__int_as_float(pg[t]), e, acc[j]);
                 }
             }
         }
