@@ -209,11 +209,10 @@ int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, fl
                       hipStream_t stream);
 
 /* Prepares list-mode data for OSEM: validates every event, sorts each
- * subset's events by (case, angle, bin or position, energy) (stable; in the
- * 3-D model by (case, angle, square block of the detector, bin_z, bin,
- * energy)) and
- * lays out the
- * work tiles, the collimator-response factor of every (listed scatter point,
+ * subset's events by (case, angle, line mask, bin or position, energy)
+ * (stable; in the 3-D model by (case, angle, line mask, square block of the
+ * detector, bin_z, bin, energy); the line mask is defined at
+ * lmmew_plan_terms) and lays out the work tiles, the collimator-response factor of every (listed scatter point,
  * event) pair of each tile (event-tile floats per listed point: 24 MB for 50k
  * events at 64x64) and the per-subset scratch.  A plan holds one or more
  * independent cases (noise realisations or patients) that share the context's
@@ -326,9 +325,15 @@ int lmmew_plan_profile_read_kernels(lmmew_ctx *ctx, lmmew_plan *plan, double *ms
 /* Number of algorithmic terms one OSEM iteration of the plan evaluates in
  * the per-event system-model kernel: for every (event, support pixel) pair,
  * one term per line for the unscattered path and one per (line, scatter
- * point) whose collimator-response factor is not dropped (a scatter point
- * whose Gaussian response puts the event's bin beyond 7 standard
- * deviations contributes below 1.3e-12 of its peak and is skipped).
+ * point) that is not dropped.  Two cuts drop terms whose value is negligible:
+ * a scatter point whose Gaussian response puts the event's bin beyond 7
+ * standard deviations (below 1.3e-12 of its peak), and a line whose
+ * scattered photon cannot reach an energy near the event's: a line's
+ * scattered energy lies between E_w / (1 + 2 E_w / electron_keV) and E_w,
+ * and when the energy-resolution Gaussian at the event's energy is below
+ * 2^-40 of its peak for every energy in that range, the event keeps only
+ * the line's unscattered term (systems of up to three lines; with more, every
+ * line is kept).  The lines an event keeps form its line mask.
  *   out_terms      host: terms evaluated per iteration.
  *   out_full_terms host: terms of the unpruned model per iteration. */
 int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full_terms);

@@ -18,6 +18,12 @@ constexpr double kPi = 3.14159265358979323846;
 // the mask of the tile's groups of 16 events that its response reaches
 constexpr int kSlistGroupShift = 24;
 constexpr int kSlistPoint = (1 << kSlistGroupShift) - 1;
+// An event drops a line's scattered terms when their energy factor is below
+// 2^-kLineCutBits for every energy the scattered photon can have.  Tiles hold
+// events of one line mask; k_row is specialised per mask for up to
+// kMaskedLines lines (more lines keep every line).
+constexpr int kLineCutBits = 40;
+constexpr int kMaskedLines = 3;
 constexpr float kPsfCut = 7.0f;    // collimator-response Gaussian dropped beyond 7 sigma
 
 // scatter surrogate network (6 -> 128 -> 128 -> 128 -> 1)
@@ -79,7 +85,8 @@ struct Tile {
     int e0, cnt;
     int angle, ncase;
     int k0, k1;
-    int pad0, pad1;
+    int lmask;          // lines whose scattered terms its events keep (bit w: line w)
+    int pad;
 };
 
 // Chunk of consecutive rows of one case for the deterministic backprojection.

@@ -11,6 +11,8 @@
 
 #include <cmath>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace lmmew {
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(256) void k_tab3_sa(const DevSys S, const TabArgsD 
 // sqrt(log2(e) / (2 sigma'^2)), so that the energy factor of an event with
 // measured energy E is exp2(-(sw*E - Fw)^2).  The planar model's cell
 // interaction probability falls as 1/r, the 3-D model's (D3) as 1/r^2.
-template <int NW, bool NORM, bool D3 = false>
+template <int NW, bool NORM, bool D3 = false, unsigned LM = 0xFFu>
 __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float dy, float dz,
                                                float c, float s, float lc, float gqs, float gsa,
                                                float *Aw, float *sw, float *Fw, float *Ep)
@@ -400,6 +402,7 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+        if (!((LM >> w) & 1u)) continue;                  // line not needed
         // invP = E_w / E' = 1 + eps (1 - cos phi); rs = invP^(-1/2)
         const float invP = fmaf(S.eps[w], omc, 1.f);
         const float rs = fast_rsq(invP);
@@ -568,10 +571,11 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     for (int j = 0; j < JT; ++j) acc[j] = 0.f;
 
     const GPtr<ScatA> sa = sab + (size_t)a * nsc;
-    // ptab: [angle][point][pixel][3 nw] -- a lane's 3 nw values are contiguous
-    const int pw = 3 * S.nw;
-    const GPtr<float> pbase = TAB ? ptab + (size_t)a * nsc * S.Qp * pw + (size_t)i * pw : nullptr;
-    const size_t pstride = (size_t)S.Qp * pw;                  // one point of the angle
+    // ptab: [angle][point][line][pixel][3] -- a lane's 3 values of a line are
+    // contiguous, and a tile reads only the lines its events keep
+    const size_t lstride = (size_t)S.Qp * 3;                   // one line of a point
+    const GPtr<float> pbase = TAB ? ptab + (size_t)a * nsc * S.nw * lstride + (size_t)i * 3
+                                  : nullptr;
     // A listed point's inputs: its response factors for the tile's events
     // (scalar registers), and its path parameters from the table or what the
     // kernel derives them from.  Two buffers alternate, so the next point's
@@ -587,7 +591,8 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         ScatA sp;                      // or: the point, its pixel path, its z
         float gqs, zs;
     };
-    auto load_pt = [&](int l, Pt &d) {
+    auto load_pt = [&](int l, Pt &d, auto lmc) {
+        constexpr unsigned LM = decltype(lmc)::value;
         const int2 e = r.slist[l];
         d.l = l;
         d.gm = (unsigned)e.x >> kSlistGroupShift;
@@ -595,13 +600,14 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         for (int j = 0; j < 16; ++j) d.pf[j] = pvb[(size_t)l * JT + j];
         const int k = e.x & kSlistPoint;
         if (TAB) {
-            const GPtr<float> tp = pbase + (size_t)k * pstride;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-                d.A[w] = tp[3 * w];
-                d.sw[w] = tp[3 * w + 1];
-                d.F[w] = tp[3 * w + 2];
+                if (!((LM >> w) & 1u)) continue;
+                const GPtr<float> tp = pbase + ((size_t)k * S.nw + w) * lstride;
+                d.A[w] = tp[0];
+                d.sw[w] = tp[1];
+                d.F[w] = tp[2];
             }
         } else {
             d.sp = load_scat(sa + k);
@@ -609,7 +615,8 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
             d.zs = D3 ? szs[e.y] : 0.f;
         }
     };
-    auto run_pt = [&](const Pt &d) {
+    auto run_pt = [&](const Pt &d, auto lmc) {
+        constexpr unsigned LM = decltype(lmc)::value;
         float Aw[NW], sw[NW], Fw[NW];
         if (TAB) {
 #pragma unroll
@@ -620,8 +627,8 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
             }
         } else {
             float Ep[NW];
-            scatter_params<NW, true, D3>(S, d.sp.x - xq, d.sp.y - yq, d.zs - zq, c, s, d.sp.lc,
-                                         d.gqs, d.sp.gsa, Aw, sw, Fw, Ep);
+            scatter_params<NW, true, D3, LM>(S, d.sp.x - xq, d.sp.y - yq, d.zs - zq, c, s,
+                                             d.sp.lc, d.gqs, d.sp.gsa, Aw, sw, Fw, Ep);
         }
 #pragma unroll
         for (int g = 0; g < JT / 16; ++g) {
@@ -635,11 +642,13 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                 const int j = 16 * g + t;
                 // a zero factor (response cut) skips the pair on a scalar compare
                 if (pg[t] != 0) {
-                    float u = fmaf(sw[0], Ej[j], -Fw[0]);
-                    float e = fast_exp2(fmaf(-u, u, Aw[0]));
+                    constexpr int w0 = __builtin_ctz(LM);        // first kept line
+                    float u = fmaf(sw[w0], Ej[j], -Fw[w0]);
+                    float e = fast_exp2(fmaf(-u, u, Aw[w0]));
 #pragma unroll
-                    for (int w = 1; w < NW; ++w) {
+                    for (int w = w0 + 1; w < NW; ++w) {
                         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
+                        if (!((LM >> w) & 1u)) continue;
                         u = fmaf(sw[w], Ej[j], -Fw[w]);
                         e += fast_exp2(fmaf(-u, u, Aw[w]));
                     }
@@ -649,15 +658,32 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         }
     };
     const int kend = (r.mode == 2) ? T.k0 : T.k1;     // unscattered only: no scatter loop
-    if (T.k0 < kend) {
+    auto point_loop = [&](auto lmc) {
         Pt d0, d1;
-        load_pt(T.k0, d0);
+        load_pt(T.k0, d0, lmc);
         for (int l = T.k0; l < kend; l += 2) {
-            load_pt(min(l + 1, kend - 1), d1);
-            run_pt(d0);
+            load_pt(min(l + 1, kend - 1), d1, lmc);
+            run_pt(d0, lmc);
             if (l + 1 >= kend) break;
-            load_pt(min(l + 2, kend - 1), d0);
-            run_pt(d1);
+            load_pt(min(l + 2, kend - 1), d0, lmc);
+            run_pt(d1, lmc);
+        }
+    };
+    if (T.k0 < kend && T.lmask != 0) {
+        // one specialisation per line mask: the tile's events keep the same lines
+        constexpr unsigned kAll = (1u << NW) - 1u;
+        if constexpr (NW <= kMaskedLines) {
+            switch (T.lmask) {
+            case 1: if constexpr (kAll >= 1) point_loop(std::integral_constant<unsigned, 1>{}); break;
+            case 2: if constexpr (kAll >= 3) point_loop(std::integral_constant<unsigned, 2>{}); break;
+            case 3: if constexpr (kAll >= 3) point_loop(std::integral_constant<unsigned, 3>{}); break;
+            case 4: if constexpr (kAll >= 7) point_loop(std::integral_constant<unsigned, 4>{}); break;
+            case 5: if constexpr (kAll >= 7) point_loop(std::integral_constant<unsigned, 5>{}); break;
+            case 6: if constexpr (kAll >= 7) point_loop(std::integral_constant<unsigned, 6>{}); break;
+            default: point_loop(std::integral_constant<unsigned, kAll>{}); break;
+            }
+        } else {
+            point_loop(std::integral_constant<unsigned, 0xFFu>{});
         }
     }
 
@@ -807,13 +833,14 @@ __global__ __launch_bounds__(64) void k_path_table(const DevSys S, const float2 
     float Aw[NW], sw[NW], Fw[NW], Ep[NW];
     scatter_params<NW, true, D3>(S, sp.x - xy.x, sp.y - xy.y, dz, dir.x, dir.y, sp.lc, gqs,
                                  sp.gsa, Aw, sw, Fw, Ep);
-    float *tp = ptab + (((size_t)a * S.nsc + k) * S.Qp + i) * 3 * S.nw;
+    // [angle][point][line][pixel][3]
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-        tp[3 * w] = Aw[w];
-        tp[3 * w + 1] = sw[w];
-        tp[3 * w + 2] = Fw[w];
+        float *tp = ptab + ((((size_t)a * S.nsc + k) * S.nw + w) * S.Qp + i) * 3;
+        tp[0] = Aw[w];
+        tp[1] = sw[w];
+        tp[2] = Fw[w];
     }
 }
 

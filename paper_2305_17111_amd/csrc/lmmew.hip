@@ -76,6 +76,7 @@ struct lmmew_plan {
     std::vector<int> bin, ang, cas;   // sorted rows
     int *d_ang = nullptr;
     std::vector<float> E;
+    std::vector<int> lm;              // sorted rows: lines whose scattered terms are kept
     bool cont = false;                // events carry continuous positions (u), not bins
     std::vector<float> u;             // sorted rows: lateral position (mm) when cont
     std::vector<int> binz;            // 3-D: sorted rows: axial bins
@@ -301,6 +302,31 @@ std::pair<int, int> reached(const ScatA &e, const float *u, int first, int last)
     return {(int)(lo - u), (int)(hi - u)};
 }
 
+// Lines whose once-scattered terms an event of measured energy E keeps.  A
+// line's scattered photon reaches the detector with an energy between its
+// backscatter energy E_w / (1 + 2 E_w / m_e c^2) and E_w; the energy factor
+// of Eq. (7) at E is exp(-(E - E')^2 / (2 k E')) for scattered energy E'.
+// When that factor is below 2^-kLineCutBits for every reachable E', the
+// line's scattered terms are dropped for the event (its unscattered term is
+// always kept).  Systems with more than kMaskedLines lines keep every line.
+int line_mask(const lmmew_system &s, float Ef)
+{
+    const int all = (1 << s.n_lines) - 1;
+    if (s.n_lines > kMaskedLines) return all;
+    const double E = Ef;
+    const double fps = fwhm_per_sigma();
+    const double k = s.eres_frac * s.eres_frac * s.eres_ref_keV / (fps * fps);
+    const double cut = kLineCutBits * std::log(2.0);
+    int m = 0;
+    for (int w = 0; w < s.n_lines; ++w) {
+        const double Ew = s.line_keV[w];
+        const double Emin = Ew / (1.0 + 2.0 * Ew / s.electron_keV);
+        const double Ep = E < Emin ? Emin : (E > Ew ? Ew : E);   // closest reachable energy
+        if ((E - Ep) * (E - Ep) / (2.0 * k * Ep) <= cut) m |= 1 << w;
+    }
+    return m;
+}
+
 // Scatter-list entry .x: point index k and the mask of the tile's groups of 16
 // events that its response reaches.
 inline int slist_x(int k, unsigned gm) { return k | (int)(gm << kSlistGroupShift); }
@@ -336,7 +362,9 @@ void build_tiles(lmmew_plan *p)
             const int cs = p->cas[r], a = p->ang[r];
             const lmmew_ctx *c = p->maps.empty() ? p->ctx : p->maps[cs];
             const int nsc = c->S.nsc;
-            while (e < rend && e - r < p->JT && p->cas[e] == cs && p->ang[e] == a) ++e;
+            while (e < rend && e - r < p->JT && p->cas[e] == cs && p->ang[e] == a &&
+                   p->lm[e] == p->lm[r])
+                ++e;
             const int k0 = (int)p->slist.size();
             if (c->S.nz > 0) {
                 // 3-D: scatter points whose response reaches some (bin, axial bin)
@@ -398,6 +426,7 @@ void build_tiles(lmmew_plan *p)
             t.ncase = cs;
             t.k0 = k0;
             t.k1 = k1;
+            t.lmask = p->lm[r];
             p->tiles.push_back(t);
             r = e;
         }
@@ -598,6 +627,9 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
                 blk[j] = morton((uint32_t)(hb[j] / BU), (uint32_t)(hz[j] / BZ));
         }
     }
+    // lines whose scattered terms each event keeps; tiles hold one mask
+    std::vector<int> hm(n);
+    for (int64_t j = 0; j < n; ++j) hm[j] = line_mask(ctx->sys, he[j]);
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
@@ -605,6 +637,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         if (sx != sy) return sx < sy;
         if (casev[x] != casev[y]) return casev[x] < casev[y];
         if (ha[x] != ha[y]) return ha[x] < ha[y];
+        if (hm[x] != hm[y]) return hm[x] < hm[y];
         if (d3 && blk[x] != blk[y]) return blk[x] < blk[y];
         if (d3 && hz[x] != hz[y]) return hz[x] < hz[y];
         if (cont) {
@@ -620,6 +653,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     p->ang.resize(n);
     p->cas.resize(n);
     p->E.resize(n);
+    p->lm.resize(n);
     p->perm = order;
     for (int64_t r = 0; r < n; ++r) {
         const int64_t j = order[r];
@@ -631,6 +665,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         p->ang[r] = ha[j];
         p->cas[r] = casev[j];
         p->E[r] = he[j];
+        p->lm[r] = hm[j];
     }
     p->subs.assign(n_subsets, {});
     {
@@ -644,14 +679,16 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     }
     // algorithmic terms per iteration
     {
-        const double QW = (double)ctx->S.Qm * ctx->S.nw;
+        const double Qm = ctx->S.Qm, nw = ctx->S.nw, QW = Qm * nw;
         double t = 0;
         if (cont) {
-            // runs of one (case, angle) have ascending positions: count each
+            // runs of one (case, angle, line mask) have ascending positions: count each
             // scatter point's reached rows by bisection
             for (int64_t r = 0; r < n;) {
                 int64_t e = r;
-                while (e < n && p->cas[e] == p->cas[r] && p->ang[e] == p->ang[r]) ++e;
+                while (e < n && p->cas[e] == p->cas[r] && p->ang[e] == p->ang[r] &&
+                       p->lm[e] == p->lm[r])
+                    ++e;
                 const lmmew_ctx *c = p->maps.empty() ? ctx : p->maps[p->cas[r]];
                 double rel = 0;
                 for (int k = 0; k < c->S.nsc; ++k) {
@@ -659,7 +696,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
                         reached(c->sa[(size_t)p->ang[r] * c->S.nsc + k], p->u.data(), (int)r, (int)e);
                     rel += rr.second - rr.first;
                 }
-                t += QW * ((double)(e - r) + rel);
+                t += Qm * (nw * (double)(e - r) + rel * __builtin_popcount(p->lm[r]));
                 r = e;
             }
         } else {
@@ -672,7 +709,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
                 int &rc = rel_cache[m * per + ((size_t)p->ang[r] * s.n_bins + p->bin[r]) * nbz + bz];
                 if (rc < 0)
                     rc = relevant_scatter(m ? p->maps[m] : ctx, p->ang[r], p->bin[r], bz);
-                t += QW * (1.0 + rc);
+                t += Qm * (nw + (double)rc * __builtin_popcount(p->lm[r]));
             }
         }
         p->terms = t;
