@@ -213,7 +213,7 @@ int lmmew_backproject(lmmew_ctx *ctx, const lmmew_events *ev, const float *w, fl
  * (stable; in the 3-D model by (case, angle, line mask, square block of the
  * detector, bin_z, bin, energy); the line mask is defined at
  * lmmew_plan_terms) and lays out the work tiles, the collimator-response factor of every (listed scatter point,
- * event) pair of each tile (event-tile floats per listed point: 24 MB for 50k
+ * event) pair of each tile (event-tile floats per listed point: 35 MB for 50k
  * events at 64x64) and the per-subset scratch.  A plan holds one or more
  * independent cases (noise realisations or patients) that share the context's
  * attenuation map and sensitivity.
