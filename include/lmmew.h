@@ -338,6 +338,13 @@ int lmmew_plan_profile_read_kernels(lmmew_ctx *ctx, lmmew_plan *plan, double *ms
  *   out_full_terms host: terms of the unpruned model per iteration. */
 int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full_terms);
 
+/* The line mask of an event of measured energy energy_keV under system sys
+ * (host only, no device work): bit w is set when the event keeps line w's
+ * scattered terms (see lmmew_plan_terms).  Returns the mask (>= 0), or
+ * LMMEW_EINVAL for a NULL system, a line count outside 1..8 or a
+ * non-finite energy. */
+int lmmew_line_mask(const lmmew_system *sys, float energy_keV);
+
 /* ---------------------------------------------------------------------------
  * Per-event rows
  * ------------------------------------------------------------------------- */

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     Plan,
     Mlp,
     events_to_device,
+    line_mask,
     plan_maps,
     roi_metrics,
     system_from_params,

@@ -110,6 +110,7 @@ def _load():
         "lmmew_path_table_bytes": (i64, [vp]),
         "lmmew_roi_metrics": (i32, [vp, vp, i32, i32, i32, vp, vp, vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "lmmew_line_mask": (i32, [C.POINTER(_System), C.c_float]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -148,6 +149,16 @@ def system_from_params(p) -> _System:
         s.nz, s.ns_z, s.n_bins_z = nz, int(p.nsz), int(p.nbz)
         s.coll_solid_angle = float(p.domega)
     return s
+
+
+def line_mask(p, energy_keV):
+    """lmmew_line_mask: the lines (bit w: line w) whose scattered terms an event
+    of this measured energy keeps under system parameters p (host only)."""
+    s = system_from_params(p)
+    m = _load().lmmew_line_mask(C.byref(s), C.c_float(energy_keV))
+    if m < 0:
+        raise LmmewError(m, "lmmew_line_mask: invalid arguments")
+    return m
 
 
 def roi_metrics(est, truth):

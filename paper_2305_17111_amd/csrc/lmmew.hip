@@ -2175,6 +2175,13 @@ int lmmew_roi_uptake(lmmew_ctx *ctx, const float *lambda, int n_cases, const uin
     return LMMEW_OK;
 }
 
+int lmmew_line_mask(const lmmew_system *sys, float energy_keV)
+{
+    if (!sys || sys->n_lines < 1 || sys->n_lines > LMMEW_MAX_LINES || !std::isfinite(energy_keV))
+        return LMMEW_EINVAL;
+    return line_mask(*sys, energy_keV);
+}
+
 int lmmew_roi_metrics(const double *est, const double *truth, int S, int N, int K, double *enrmse,
                       double *bias, double *std_)
 {
