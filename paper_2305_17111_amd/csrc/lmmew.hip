@@ -304,8 +304,10 @@ std::pair<int, int> reached(const ScatA &e, const float *u, int first, int last)
 
 // Lines whose once-scattered terms an event of measured energy E keeps.  A
 // line's scattered photon reaches the detector with an energy between its
-// backscatter energy E_w / (1 + 2 E_w / m_e c^2) and E_w; the energy factor
-// of Eq. (7) at E is exp(-(E - E')^2 / (2 k E')) for scattered energy E'.
+// backscatter energy E_w / (1 + 2 E_w / m_e c^2) and E_w (Compton kinematics
+// of the scattered energies in Eq. (5)); the energy-resolution factor of
+// Eq. (3)'s event probability at E is exp(-(E - E')^2 / (2 k E')) for
+// scattered energy E' (variance k E', Sec. 3.1.2).
 // When that factor is below 2^-kLineCutBits for every reachable E', the
 // line's scattered terms are dropped for the event (its unscattered term is
 // always kept).  Systems with more than kMaskedLines lines keep every line.

@@ -1,10 +1,11 @@
 """The per-event line cut of the per-event kernel, checked on the host.
 
 An event of measured energy E keeps line w's once-scattered terms unless the
-energy-resolution Gaussian exp(-(E - E')^2 / (2 k E')) (Eq. (7), variance
-k E' with k = (eres_frac eres_ref / 2.3548)^2 / eres_ref) is below 2^-40 for
-every scattered energy E' the line can produce; Compton's relation (Eq. (6))
-puts E' between E_w / (1 + 2 E_w / m_e c^2) (backscatter) and E_w.  The
+energy-resolution Gaussian exp(-(E - E')^2 / (2 k E')) of its probability
+(Eq. (3); variance k E' with k = (eres_frac eres_ref / 2.3548)^2 / eres_ref,
+Sec. 3.1.2) is below 2^-40 for every scattered energy E' the line can
+produce; Compton kinematics puts the scattered energies of Eq. (5) between
+E_w / (1 + 2 E_w / m_e c^2) (backscatter) and E_w.  The
 library's mask (lmmew_line_mask, host code) is compared with a brute-force
 maximum of the Gaussian over a fine grid of scattering angles, away from the
 2^-40 boundary where the grid's own resolution decides."""
