@@ -65,6 +65,7 @@ struct DevSys {
     float nc[LMMEW_MAX_LINES];      // -0.5 log2(2 pi eres_k E_w)
     float gnorm[LMMEW_MAX_LINES];   // 1 / sqrt(2 pi eres_k E_w)
     float wlo[LMMEW_MAX_WINDOWS], whi[LMMEW_MAX_WINDOWS];
+    float sqck;                     // sqrt(log2(e) / (2 eres_k)): s_w = sqck / sqrt(E')
 };
 
 // Scatter point as seen from one angle (array [na][nsc], sorted by u).

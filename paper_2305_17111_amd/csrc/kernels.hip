@@ -573,8 +573,8 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     const GPtr<ScatA> sa = sab + (size_t)a * nsc;
     // ptab: [angle][point][line][pixel][3] -- a lane's 3 values of a line are
     // contiguous, and a tile reads only the lines its events keep
-    const size_t lstride = (size_t)S.Qp * 3;                   // one line of a point
-    const GPtr<float> pbase = TAB ? ptab + (size_t)a * nsc * S.nw * lstride + (size_t)i * 3
+    const size_t lstride = (size_t)S.Qp * 2;                   // one line of a point
+    const GPtr<float> pbase = TAB ? ptab + (size_t)a * nsc * S.nw * lstride + (size_t)i * 2
                                   : nullptr;
     // A listed point's inputs: its response factors for the tile's events
     // (scalar registers), and its path parameters from the table or what the
@@ -606,8 +606,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                 if (!((LM >> w) & 1u)) continue;
                 const GPtr<float> tp = pbase + ((size_t)k * S.nw + w) * lstride;
                 d.A[w] = tp[0];
-                d.sw[w] = tp[1];
-                d.F[w] = tp[2];
+                d.F[w] = tp[1];                   // the scattered energy E'
             }
         } else {
             d.sp = load_scat(sa + k);
@@ -621,9 +620,11 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         if (TAB) {
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
+                if (!((LM >> w) & 1u)) continue;
+                // s_w = sqrt(log2(e) / (2 k E')), F_w = s_w E'
                 Aw[w] = d.A[w];
-                sw[w] = d.sw[w];
-                Fw[w] = d.F[w];
+                sw[w] = S.sqck * fast_rsq(d.F[w]);
+                Fw[w] = sw[w] * d.F[w];
             }
         } else {
             float Ep[NW];
@@ -833,14 +834,13 @@ __global__ __launch_bounds__(64) void k_path_table(const DevSys S, const float2 
     float Aw[NW], sw[NW], Fw[NW], Ep[NW];
     scatter_params<NW, true, D3>(S, sp.x - xy.x, sp.y - xy.y, dz, dir.x, dir.y, sp.lc, gqs,
                                  sp.gsa, Aw, sw, Fw, Ep);
-    // [angle][point][line][pixel][3]
+    // [angle][point][line][pixel][2]: the log2 weight and the scattered energy
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
-        float *tp = ptab + ((((size_t)a * S.nsc + k) * S.nw + w) * S.Qp + i) * 3;
+        float *tp = ptab + ((((size_t)a * S.nsc + k) * S.nw + w) * S.Qp + i) * 2;
         tp[0] = Aw[w];
-        tp[1] = sw[w];
-        tp[2] = Fw[w];
+        tp[1] = Ep[w];
     }
 }
 

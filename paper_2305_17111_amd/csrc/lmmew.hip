@@ -1162,6 +1162,7 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     S.T = (float)s.T;
     const double k = s.eres_frac * s.eres_frac * s.eres_ref_keV / (fps * fps);
     S.eres_k = (float)k;
+    S.sqck = (float)std::sqrt(1.0 / std::log(2.0) / (2.0 * k));
     S.mu_pow = (float)s.mu_power;
     // r is clamped below: planar at the mean of 1/r over a disk of area hs^2,
     // 3-D where 1/r^2 equals its mean over a ball of volume hs^2 hz
@@ -1266,7 +1267,7 @@ int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t st)
         return LMMEW_OK;
     }
     if (ctx->d_ptab || ctx->S.nsc == 0) return LMMEW_OK;
-    const size_t n = (size_t)ctx->S.na * ctx->S.nsc * 3 * ctx->S.nw * ctx->S.Qp;
+    const size_t n = (size_t)ctx->S.na * ctx->S.nsc * 2 * ctx->S.nw * ctx->S.Qp;
     size_t fr = 0, tot = 0;
     HIPCHK(ctx, hipMemGetInfo(&fr, &tot));
     if (n * sizeof(float) + (size_t(1) << 30) > fr) {
@@ -1291,7 +1292,7 @@ int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t st)
 int64_t lmmew_path_table_bytes(const lmmew_ctx *ctx)
 {
     if (!ctx) return -1;
-    return (int64_t)ctx->S.na * ctx->S.nsc * 3 * ctx->S.nw * ctx->S.Qp * (int64_t)sizeof(float);
+    return (int64_t)ctx->S.na * ctx->S.nsc * 2 * ctx->S.nw * ctx->S.Qp * (int64_t)sizeof(float);
 }
 
 int lmmew_sensitivity(lmmew_ctx *ctx, int n_subsets, float *sens, hipStream_t st)

@@ -40,7 +40,7 @@ def test_table_rows_and_osem_match_oracle(small):
     rows0 = ctx.rows(ev, part=3).cpu().numpy()
     ctx.path_table(True)
     try:
-        assert ctx.path_table_bytes == p.na * 52 * 3 * 3 * 256 * 4   # 52 scatter points, 3 lines
+        assert ctx.path_table_bytes == p.na * 52 * 3 * 2 * 256 * 4   # 52 points, 3 lines, 2 values
         rows1 = ctx.rows(ev, part=3).cpu().numpy()
         mx, l2 = _rel(rows1, rows0)
         assert mx < 1e-6 and l2 < 1e-6, (mx, l2)
