@@ -433,6 +433,16 @@ void build_tiles(lmmew_plan *p)
             r = e;
         }
         sub.ntiles = (int)p->tiles.size() - sub.tile0;
+        // costliest tiles first: the launch's last work items are then cheap
+        // ones, which shortens the tail in which CUs run out of work
+        std::stable_sort(p->tiles.begin() + sub.tile0, p->tiles.end(),
+                         [](const Tile &x, const Tile &y) {
+                             const double cx = (double)(x.k1 - x.k0) * x.cnt *
+                                               (1 + 4 * __builtin_popcount(x.lmask));
+                             const double cy = (double)(y.k1 - y.k0) * y.cnt *
+                                               (1 + 4 * __builtin_popcount(y.lmask));
+                             return cx > cy;
+                         });
         // chunks: runs of <= kChunkRows rows of one case
         r = sub.row0;
         for (int cs = 0; cs < p->ncases; ++cs) {
