@@ -471,6 +471,9 @@ RowArgs row_args(const lmmew_ctx *ctx, const lmmew_plan *p, int s);
 
 int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
 {
+    // tiles and scatter-list entries are indexed with 32-bit integers
+    if (p->slist.size() > (size_t)INT32_MAX || p->tiles.size() > (size_t)INT32_MAX)
+        return fail(ctx, LMMEW_ENOMEM, "plan too large: more than 2^31 scatter-list entries");
     // a captured graph refers to the arrays about to be replaced
     if (p->gexec) {
         HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
