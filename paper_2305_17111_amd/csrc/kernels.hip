@@ -457,7 +457,9 @@ __device__ __forceinline__ ScatA load_scat(GPtr<ScatA> p)
 // the pair's exponentials with a uniform branch, and a group the point does
 // not reach is skipped whole.  For each listed point every lane reads or
 // derives its pixel's path parameters once and reuses them for all of the
-// tile's events.
+// tile's events.  A tile's events keep the same emission lines (the line
+// mask of the plan's line cut): the point loop is compiled once per mask,
+// so a tile evaluates, reads and exponentiates only its kept lines.
 // ---------------------------------------------------------------------------
 template <int JT, int NW, bool TAB, bool D3>
 __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
