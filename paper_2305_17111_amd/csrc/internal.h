@@ -141,8 +141,13 @@ struct RowArgs {
     int mode;                // 0: all paths, 1: scattered paths only, 2: unscattered only
     const float *pvt;        // [slist entry][event tile]: response factor of each listed
                              // point for each event of its tile (0 past the tile's events)
+    const float *psft;       // planar binned events: [na][nb][Qp] bin probabilities of the
+                             // unscattered paths, or NULL to form them in the kernel
 };
 hipError_t launch_row(const DevSys &S, const RowArgs &r, int event_tile, hipStream_t st);
+// bin probability of the unscattered path of every (angle, bin, support pixel)
+hipError_t launch_psf_table(const DevSys &S, const float2 *pix_xy, const float2 *dirs,
+                            float *psft, hipStream_t st);
 // the response-factor table of the tiles of one subset (written to pvt)
 hipError_t launch_pv_table(const DevSys &S, const RowArgs &r, int event_tile, float *pvt,
                            hipStream_t st);

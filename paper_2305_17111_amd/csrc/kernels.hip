@@ -530,7 +530,9 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     auto prim_of = [&](int j, const float *Pp) {
         float ps = 0.f;
         if (r.mode != 1) {
-            if (r.ev_u) {
+            if (!D3 && r.psft && !r.ev_u) {
+                ps = r.psft[((size_t)a * S.nb + r.ev_bin[T.e0 + j]) * S.Qp + i];
+            } else if (r.ev_u) {
                 ps = pdf_cut((r.ev_u[T.e0 + j] - uq) * isq, isq);
             } else {
                 const float lo = -S.R + (float)r.ev_bin[T.e0 + j] * S.db;
@@ -705,6 +707,30 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
                 r.A[(size_t)(T.e0 + j) * S.Qp + i] = valid ? prim_of(j, Pp) + acc[j] : 0.f;
         }
     }
+}
+
+// Bin probability of the unscattered path of every (angle, bin, support
+// pixel), the arithmetic of k_row's in-kernel formation: one lane per pixel.
+__global__ __launch_bounds__(64) void k_psf_table(const DevSys S, const float2 *pix_xy,
+                                                  const float2 *dirs, float *psft)
+{
+    const int i = blockIdx.x * kWave + threadIdx.x;
+    const int b = blockIdx.y, a = blockIdx.z;
+    const float2 xy = pix_xy[i], dir = dirs[a];
+    const float xq = xy.x, yq = xy.y, c = dir.x, s = dir.y;
+    const float dq = S.R - (xq * c + yq * s);
+    const float uq = -xq * s + yq * c;
+    const float isq = 1.f / ((S.fwhm0 + S.fslope * dq) * S.inv_fwhm_to_sigma);
+    const float lo = -S.R + (float)b * S.db;
+    psft[((size_t)a * S.nb + b) * S.Qp + i] = psf_cut((lo + S.db - uq) * isq, (lo - uq) * isq);
+}
+
+hipError_t launch_psf_table(const DevSys &S, const float2 *pix_xy, const float2 *dirs,
+                            float *psft, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_psf_table, dim3(S.Qp / kWave, S.nb, S.na), dim3(kWave), 0, st, S, pix_xy,
+                       dirs, psft);
+    return hipGetLastError();
 }
 
 // Response factors of every (listed point, event) pair of each tile, built

@@ -41,6 +41,7 @@ struct lmmew_ctx {
     hipStream_t cap_stream = nullptr; // private stream that graph captures are recorded on
     float *d_ptab = nullptr;          // scatter-path parameter table (lmmew_path_table) or NULL
     float *d_resp = nullptr;          // [na][nsc][nb] collimator-response factors
+    float *d_psft = nullptr;          // planar: [na][nb][Qp] unscattered bin probabilities
     float *d_respz = nullptr;         // 3-D: [na][nsc][nbz] axial response factors
     float *d_pixz = nullptr;          // 3-D: [Qp] voxel z
     double *d_pixzd = nullptr;        // 3-D: [Qp] voxel z (double, for the tables)
@@ -245,7 +246,7 @@ void free_ctx(lmmew_ctx *c)
     c->cap_stream = nullptr;
     dfree(c->d_pix); dfree(c->d_pixd); dfree(c->d_pixq); dfree(c->d_dirs); dfree(c->d_dirsd);
     dfree(c->d_scd); dfree(c->d_mu); dfree(c->d_gqa); dfree(c->d_gqs); dfree(c->d_sa);
-    dfree(c->d_Sqa); dfree(c->d_ptab); dfree(c->d_resp);
+    dfree(c->d_Sqa); dfree(c->d_ptab); dfree(c->d_resp); dfree(c->d_psft);
     dfree(c->d_respz); dfree(c->d_pixz); dfree(c->d_pixzd); dfree(c->d_scz); dfree(c->d_sczd);
 }
 
@@ -862,6 +863,7 @@ RowArgs row_args(const lmmew_ctx *ctx, const lmmew_plan *p, int s)
     r.sa = ctx->d_sa;
     r.resp = ctx->d_resp;
     r.respz = ctx->d_respz;
+    r.psft = ctx->d_psft;
     r.pix_z = ctx->d_pixz;
     r.sz = ctx->d_scz;
     r.maps = p->d_maps;
@@ -1251,6 +1253,13 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     CCHK(launch_tables_d(S, ctx->d_mu, ctx->d_pixd, ctx->d_pixzd, ctx->d_dirsd, ctx->d_scd,
                          ctx->d_sczd, ctx->d_gqa, ctx->d_gqs, ctx->d_sa, pix, R, st));
     CCHK(launch_resp_table(S, ctx->d_sa, ctx->d_resp, ctx->d_scz, ctx->d_respz, st));
+    // the unscattered paths' bin probabilities, read by the per-event kernel
+    // instead of two erfc per (event, pixel); kept to 2 GiB (larger systems
+    // form them in the kernel)
+    if (!d3 && (size_t)na * s.n_bins * Qp * sizeof(float) <= (size_t(2) << 30)) {
+        CCHK(dalloc(&ctx->d_psft, (size_t)na * s.n_bins * Qp));
+        CCHK(launch_psf_table(S, ctx->d_pix, ctx->d_dirs, ctx->d_psft, st));
+    }
     CCHK(hipStreamSynchronize(st));
 #undef CCHK
     *out = ctx;
