@@ -512,8 +512,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the whole reconstruction on a "
-              "single MI355X (see the design notes for how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the whole reconstruction on "
+              "a single MI355X (the design notes describe how it would shard)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
