@@ -165,13 +165,14 @@ int lmmew_destroy(lmmew_ctx *ctx);
 int64_t lmmew_support_size(const lmmew_ctx *ctx);
 
 /* Path-parameter table (optional): the event-independent part of every
- * once-scattered path of Eq. (3) -- for each (angle, scatter point, support
- * pixel) and line: the log2 path weight (attenuation along both legs,
- * Klein-Nishina, geometry, energy-Gaussian normalisation), s_w and F_w of the
- * energy factor exp2(-(s_w E - F_w)^2) -- evaluated once into device memory
- * owned by the context: n_angles x scatter points x 3 lines' worth x support
- * pixels x 4 bytes (lmmew_path_table_bytes; 11.7 GB at 64x64 with a 32x32
- * scatter grid and 3 lines).  With it the per-event kernel reads these values
+ * once-scattered path of Eq. (3) -- for each (angle, scatter point, line,
+ * support pixel): the log2 path weight (attenuation along both legs,
+ * Klein-Nishina, geometry, energy-Gaussian normalisation) and the scattered
+ * energy E', from which the kernel forms the energy factor
+ * exp2(-(s_w E - F_w)^2) with s_w = sqrt(log2(e) / (2 k E')), F_w = s_w E' --
+ * evaluated once into device memory owned by the context: n_angles x scatter
+ * points x lines x padded support pixels x 8 bytes (lmmew_path_table_bytes;
+ * 4.8 GB for the 64x64 workload's 508 scatter points and 3 lines).  With it the per-event kernel reads these values
  * instead of recomputing them for every tile of events; the rows are still
  * evaluated per event in every sub-iteration, and agree with the rows without
  * the table to rounding.  enable == 0 frees it.  Plans over several maps use
