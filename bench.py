@@ -45,8 +45,8 @@ NONPACKED_PEAK_TERMS_PER_S = 256 * 64 * 2.4e9 / 5.0
 # tile 16, without and with the path-parameter table (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE of these kernel versions, scaled by a 256 MiB copy kernel: fetch
 # x2.000, write x1.000)
-MEASURED_TRAFFIC = {("64x64_50k", 16, False): {"fetch": 458.7e6, "write": 81.5e6},
-                    ("64x64_50k", 16, True): {"fetch": 3427.1e6, "write": 81.5e6}}
+MEASURED_TRAFFIC = {("64x64_50k", 16, False): {"fetch": 458.9e6, "write": 81.5e6},
+                    ("64x64_50k", 16, True): {"fetch": 3449.8e6, "write": 81.5e6}}
 
 # iterations after which the 16-patient images of the exact model, the
 # surrogate and no scatter model are compared region by region

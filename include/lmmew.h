@@ -167,9 +167,10 @@ int64_t lmmew_support_size(const lmmew_ctx *ctx);
 /* Path-parameter table (optional): the event-independent part of every
  * once-scattered path of Eq. (3) -- for each (angle, scatter point, line,
  * support pixel): the log2 path weight (attenuation along both legs,
- * Klein-Nishina, geometry, energy-Gaussian normalisation) and the scattered
- * energy E', from which the kernel forms the energy factor
- * exp2(-(s_w E - F_w)^2) with s_w = sqrt(log2(e) / (2 k E')), F_w = s_w E' --
+ * Klein-Nishina, geometry, energy-Gaussian normalisation) and
+ * s_w = sqrt(log2(e) / (2 k E')) of the scattered energy E' (sigma'^2 = k E'),
+ * from which the kernel forms the energy factor exp2(-(s_w E - F_w)^2) with
+ * F_w = s_w E' = log2(e) / (2 k s_w) --
  * evaluated once into device memory owned by the context: n_angles x scatter
  * points x lines x padded support pixels x 8 bytes (lmmew_path_table_bytes;
  * 4.8 GB for the 64x64 workload's 508 scatter points and 3 lines).  With it the per-event kernel reads these values

@@ -575,11 +575,14 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     for (int j = 0; j < JT; ++j) acc[j] = 0.f;
 
     const GPtr<ScatA> sa = sab + (size_t)a * nsc;
-    // ptab: [angle][point][line][pixel][3] -- a lane's 3 values of a line are
-    // contiguous, and a tile reads only the lines its events keep
+    // ptab: [angle][point][line][pixel][2] -- a lane's 2 values of a line are
+    // contiguous, and a tile reads only the lines its events keep.  A line's
+    // address is a uniform base (scalar registers) plus the lane's fixed 32-bit
+    // byte offset, so the loads need no per-point vector address arithmetic.
     const size_t lstride = (size_t)S.Qp * 2;                   // one line of a point
-    const GPtr<float> pbase = TAB ? ptab + (size_t)a * nsc * S.nw * lstride + (size_t)i * 2
-                                  : nullptr;
+    const GPtr<float> pbase = TAB ? ptab + (size_t)a * nsc * S.nw * lstride : nullptr;
+    const unsigned pboff = (unsigned)i * (unsigned)sizeof(float2);
+    const float sqck2 = S.sqck * S.sqck;
     // A listed point's inputs: its response factors for the tile's events
     // (scalar registers), and its path parameters from the table or what the
     // kernel derives them from.  Two buffers alternate, so the next point's
@@ -591,7 +594,7 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
         int l;                         // scatter-list entry
         unsigned gm;                   // groups of 16 events its response reaches
         int pf[16];                    // response factors of the first 16 events (bits)
-        float A[NW], sw[NW], F[NW];    // table values
+        float A[NW], sw[NW];           // table values
         ScatA sp;                      // or: the point, its pixel path, its z
         float gqs, zs;
     };
@@ -608,9 +611,16 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
             for (int w = 0; w < NW; ++w) {
                 if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
                 if (!((LM >> w) & 1u)) continue;
-                const GPtr<float> tp = pbase + ((size_t)k * S.nw + w) * lstride;
-                d.A[w] = tp[0];
-                d.F[w] = tp[1];                   // the scattered energy E'
+                // the line's base stays opaque in scalar registers and the lane's
+                // 32-bit offset is widened at the load, so the compiler emits a
+                // scalar-base load instead of 64-bit vector address arithmetic
+                unsigned long long tb = (unsigned long long)(pbase + ((size_t)k * S.nw + w) * lstride);
+                unsigned off = pboff;
+                asm("" : "+s"(tb));
+                asm("" : "+v"(off));
+                const GPtr<float> v = (GPtr<float>)((GPtr<char>)tb + off);
+                d.A[w] = v[0];
+                d.sw[w] = v[1];
             }
         } else {
             d.sp = load_scat(sa + k);
@@ -625,10 +635,10 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 if (!((LM >> w) & 1u)) continue;
-                // s_w = sqrt(log2(e) / (2 k E')), F_w = s_w E'
+                // s_w = sqrt(log2(e) / (2 k E')), F_w = s_w E' = (log2(e) / (2 k)) / s_w
                 Aw[w] = d.A[w];
-                sw[w] = S.sqck * fast_rsq(d.F[w]);
-                Fw[w] = sw[w] * d.F[w];
+                sw[w] = d.sw[w];
+                Fw[w] = sqck2 * fast_rcp(d.sw[w]);
             }
         } else {
             float Ep[NW];
@@ -862,13 +872,14 @@ __global__ __launch_bounds__(64) void k_path_table(const DevSys S, const float2 
     float Aw[NW], sw[NW], Fw[NW], Ep[NW];
     scatter_params<NW, true, D3>(S, sp.x - xy.x, sp.y - xy.y, dz, dir.x, dir.y, sp.lc, gqs,
                                  sp.gsa, Aw, sw, Fw, Ep);
-    // [angle][point][line][pixel][2]: the log2 weight and the scattered energy
+    // [angle][point][line][pixel][2]: the log2 weight and s_w = sqrt(log2(e) / (2 k E'))
+    // of the scattered energy E' (the model's energy resolution, sigma'^2 = k E')
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         if (NW == LMMEW_MAX_LINES && w >= S.nw) break;
         float *tp = ptab + ((((size_t)a * S.nsc + k) * S.nw + w) * S.Qp + i) * 2;
         tp[0] = Aw[w];
-        tp[1] = Ep[w];
+        tp[1] = S.sqck * rsqrtf(Ep[w]);
     }
 }
 
