@@ -461,6 +461,24 @@ int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *mlp);
 int lmmew_roi_uptake(lmmew_ctx *ctx, const float *lambda, int n_cases, const uint8_t *masks,
                      int n_rois, double *out, hipStream_t stream);
 
+/* Largest n_cases * n_rois that lmmew_roi_uptake_noalloc accepts. */
+#define LMMEW_ROI_NOALLOC_MAX 65536
+
+/* lmmew_roi_uptake for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernel and the
+ * same results (bitwise), with the per-(case, region) sums staged in a static
+ * device array of LMMEW_ROI_NOALLOC_MAX doubles (512 KiB) that the library
+ * holds on every device it runs on until the process ends, instead of a
+ * buffer allocated per call.  The call allocates nothing and calls no
+ * allocating routine; it still synchronises the stream to copy the sums to
+ * out.  Every call on a device shares that device's array: calls that
+ * overlap on one device (other host threads or streams) race and must be
+ * serialised by the caller.
+ * Errors: EINVAL (as lmmew_roi_uptake, and n_cases * n_rois >
+ * LMMEW_ROI_NOALLOC_MAX), EDEVICE. */
+int lmmew_roi_uptake_noalloc(lmmew_ctx *ctx, const float *lambda, int n_cases,
+                             const uint8_t *masks, int n_rois, double *out, hipStream_t stream);
+
 /* Ensemble figures of merit of Sec. 3.1.4 over S object realisations x N
  * noise realisations (N >= 2) for K regions (host arrays, no device work):
  *   est    [S][N][K] estimated uptake, truth [S][K] true uptake (nonzero);

@@ -105,6 +105,7 @@ def _load():
                                                   C.POINTER(C.c_int64)]),
         "lmmew_support_size": (i64, [vp]),
         "lmmew_roi_uptake": (i32, [vp, vp, i32, vp, i32, vp, vp]),
+        "lmmew_roi_uptake_noalloc": (i32, [vp, vp, i32, vp, i32, vp, vp]),
         "lmmew_plan_cache_rows": (i32, [vp, vp, i32, vp]),
         "lmmew_path_table": (i32, [vp, i32, vp]),
         "lmmew_path_table_bytes": (i64, [vp]),
@@ -317,9 +318,10 @@ class Context:
     def lmmew_mlp_create(self, seed=0):
         return Mlp(self, seed)
 
-    def lmmew_roi_uptake(self, lam, masks):
+    def lmmew_roi_uptake(self, lam, masks, noalloc=False):
         """[n_cases, n_rois] FP64 host array of region sums of lam ([n_cases, Q] or [Q])
-        over masks ([n_rois, Q], nonzero = inside)."""
+        over masks ([n_rois, Q], nonzero = inside).  noalloc selects
+        lmmew_roi_uptake_noalloc (static device scratch, no allocation)."""
         import numpy as np
 
         lam = lam.contiguous()
@@ -327,9 +329,13 @@ class Context:
         nc = 1 if lam.dim() == 1 else lam.shape[0]
         nk = 1 if m.dim() == 1 else m.shape[0]
         out = np.zeros((nc, nk), np.float64)
-        self._check(_load().lmmew_roi_uptake(self._h, _ptr(lam), nc, _ptr(m), nk,
-                                             C.c_void_p(out.ctypes.data), _stream()))
+        fn = _load().lmmew_roi_uptake_noalloc if noalloc else _load().lmmew_roi_uptake
+        self._check(fn(self._h, _ptr(lam), nc, _ptr(m), nk, C.c_void_p(out.ctypes.data),
+                       _stream()))
         return out
+
+    def lmmew_roi_uptake_noalloc(self, lam, masks):
+        return self.lmmew_roi_uptake(lam, masks, noalloc=True)
 
     def lmmew_path_table(self, enable=True):
         """Builds (or frees) the context's scatter-path parameter table."""

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -966,6 +967,36 @@ int ensure_stats(lmmew_ctx *ctx, lmmew_plan *p, int count)
     return LMMEW_OK;
 }
 
+// Static device scratch of lmmew_roi_uptake_noalloc: the region sums before
+// their copy to the host.  Each device the library runs on holds its own copy
+// of the array (until the process ends); host code reaches it only through the
+// address hipGetSymbolAddress returns on that device, resolved once per device
+// with the device current (at context creation, or on the entry point's first
+// call there).
+static __device__ __align__(256) double roi_scratch[LMMEW_ROI_NOALLOC_MAX];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_roi_mu;
+double *g_roi_ptr[kMaxDevices] = {};
+
+hipError_t roi_scratch_ptr(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_roi_mu);
+    if (!g_roi_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(roi_scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_roi_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_roi_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1261,6 +1292,10 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
         CCHK(launch_psf_table(S, ctx->d_pix, ctx->d_dirs, ctx->d_psft, st));
     }
     CCHK(hipStreamSynchronize(st));
+    {
+        double *scr = nullptr;   // resolve the no-allocation scratch on this device once
+        CCHK(roi_scratch_ptr(&scr));
+    }
 #undef CCHK
     *out = ctx;
     return LMMEW_OK;
@@ -2180,6 +2215,30 @@ int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *m, int64_t n_label_events, int epoc
     dfree(feats);
     dfree(raw);
     return rc;
+}
+
+int lmmew_roi_uptake_noalloc(lmmew_ctx *ctx, const float *lambda, int n_cases,
+                             const uint8_t *masks, int n_rois, double *out, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (n_cases < 0 || n_rois < 0) return fail(ctx, LMMEW_EINVAL, "negative count");
+    if ((int64_t)n_cases * n_rois == 0) return LMMEW_OK;
+    if (!lambda || !masks || !out) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    if ((int64_t)n_cases * n_rois > LMMEW_ROI_NOALLOC_MAX)
+        return fail(ctx, LMMEW_EINVAL,
+                    "n_cases * n_rois = " + std::to_string((int64_t)n_cases * n_rois) +
+                        " exceeds the static scratch of " +
+                        std::to_string(LMMEW_ROI_NOALLOC_MAX) + " sums");
+    double *d = nullptr;
+    HIPCHK(ctx, roi_scratch_ptr(&d));
+    // every entry of the scratch that this call reads back is written by the
+    // kernel first (one workgroup per (case, region)), so nothing is cleared
+    hipError_t e = launch_roi_sums(lambda, n_cases, ctx->Q, masks, n_rois, d, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, d, sizeof(double) * n_cases * n_rois, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hipfail(ctx, e, "roi uptake (no allocation)");
+    return LMMEW_OK;
 }
 
 int lmmew_roi_uptake(lmmew_ctx *ctx, const float *lambda, int n_cases, const uint8_t *masks,
