@@ -158,7 +158,9 @@ const char *lmmew_last_error(const lmmew_ctx *ctx);
 int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *support,
                  hipStream_t stream, lmmew_ctx **out);
 
-/* Releases the context and everything it owns (waits for its work). */
+/* Releases the context and everything it owns.  Takes no stream: it waits
+ * for all work on the device (as freeing device memory does) before
+ * releasing anything. */
 int lmmew_destroy(lmmew_ctx *ctx);
 
 /* Number of support pixels (the pixels rows and labels cover), -1 for NULL. */
@@ -183,6 +185,18 @@ int64_t lmmew_support_size(const lmmew_ctx *ctx);
 int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t stream);
 int64_t lmmew_path_table_bytes(const lmmew_ctx *ctx);
 
+/* Unscattered bin-probability table (planar systems): the probability that
+ * the unscattered path from every support pixel lands in every detector bin
+ * at every angle (the position factor of Eq. (3) for n = 0), n_angles x
+ * n_bins x padded support pixels x 4 bytes, owned by the context.  It is
+ * built automatically on the context's first plan when it fits in 2 GiB and
+ * the allocation succeeds; otherwise, and after enable == 0, the per-event
+ * kernel forms each probability from two complementary error functions.
+ * Rows agree to rounding either way.  Synchronises the stream.  Returns 1
+ * when the table is in use after the call, 0 when not, or an error status
+ * (EINVAL, EDEVICE). */
+int lmmew_psf_table(lmmew_ctx *ctx, int enable, hipStream_t stream);
+
 /* Sensitivity image per subset: sens[s][q] = T * sum over the subset's
  * angles of the probability that a decay in pixel q is recorded (on the
  * detector and inside a window), unscattered or once scattered: the
@@ -202,8 +216,10 @@ int lmmew_sensitivity(lmmew_ctx *ctx, int n_subsets, float *sens, hipStream_t st
 int lmmew_forward(lmmew_ctx *ctx, const lmmew_events *ev, const float *lambda, float *p,
                   hipStream_t stream);
 
-/* Adjoint: out[q] = sum_j a_jq w[j] (events with w[j] = 0 contribute
- * nothing).
+/* Adjoint of lmmew_forward: out[q] = sum_j a_jq w[j] (events with w[j] = 0
+ * contribute nothing).  With w[j] = 1 / p_j over a subset's events,
+ * lambda[q] * out[q] is Algorithm 1's sumZbar[q]: the sum over the events of
+ * the expected path counts z-bar of Eq. (19), the numerator of Eq. (18).
  *   w        device [ev->n] float, input order.
  *   out      device [n*n] float, written.
  * Synchronises the stream once.  Errors as lmmew_forward. */
@@ -233,14 +249,20 @@ int lmmew_plan_create(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *cas
  * parameters and the support; they may differ in the map and hence in their
  * scatter points).  The plan belongs to ctxs[0]: pass ctxs[0] to the OSEM
  * calls, whose sens argument is then device [n_cases][n_subsets][n*n], case
- * c's block from lmmew_sensitivity(ctxs[c]).  The scatter model is ctxs[0]'s
- * (lmmew_set_scatter_model).  The contexts must outlive the plan.  Otherwise
+ * c's block from lmmew_sensitivity(ctxs[c]).  Scatter model: with no network
+ * selected on ctxs[0] every case uses the exact model (a network selected on
+ * another case's context is then an error, EINVAL at the OSEM call); with one
+ * selected, case c uses the network selected on ctxs[c], or ctxs[0]'s when
+ * ctxs[c] has none (lmmew_set_scatter_model), so that each patient may carry
+ * a network fitted to its own map.  The contexts must outlive the plan.  Otherwise
  * as lmmew_plan_create.  Errors: EINVAL (also for contexts with a different
  * system or support), ENOMEM, EDEVICE. */
 int lmmew_plan_create_maps(lmmew_ctx *const *ctxs, const lmmew_events *ev,
                            const int64_t *case_offsets, int n_cases, int n_subsets,
                            hipStream_t stream, lmmew_plan **out);
 
+/* Releases the plan (waits for all work on the device first, as
+ * lmmew_destroy). */
 int lmmew_plan_destroy(lmmew_plan *plan);
 
 /* Cached-row mode (a mode of its own, outside the paper's matrix-free
@@ -332,10 +354,11 @@ int lmmew_plan_profile_read_kernels(lmmew_ctx *ctx, lmmew_plan *plan, double *ms
  * standard deviations (below 1.3e-12 of its peak), and a line whose
  * scattered photon cannot reach an energy near the event's: a line's
  * scattered energy lies between E_w / (1 + 2 E_w / electron_keV) and E_w,
- * and when the energy-resolution Gaussian at the event's energy is below
- * 2^-40 of its peak for every energy in that range, the event keeps only
- * the line's unscattered term (systems of up to three lines; with more, every
- * line is kept).  The lines an event keeps form its line mask.
+ * and when the largest value of the energy-resolution Gaussian at the
+ * event's energy over that range is below 2^-40 of the largest such value
+ * over all lines, the event keeps only the line's unscattered term (the line
+ * with the largest value is always kept; systems of up to three lines, with
+ * more every line is kept).  The lines an event keeps form its line mask.
  *   out_terms      host: terms evaluated per iteration.
  *   out_full_terms host: terms of the unpruned model per iteration. */
 int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full_terms);
@@ -346,6 +369,20 @@ int lmmew_plan_terms(const lmmew_plan *plan, double *out_terms, double *out_full
  * LMMEW_EINVAL for a NULL system, a line count outside 1..8 or a
  * non-finite energy. */
 int lmmew_line_mask(const lmmew_system *sys, float energy_keV);
+
+/* Measured issue rate of the per-event kernel's instruction chains on the
+ * current device (the ceiling its roofline is reported against):
+ *   kind 0: algorithmic terms per second -- one energy-Gaussian factor of a
+ *           (line, path) pair of Eq. (3) at an event's energy, accumulated
+ *           with the event's collimator-response factor: two FMAs, one
+ *           exp2, one FMA, with the path parameters per lane and the event's
+ *           energy and factor uniform over the wavefront;
+ *   kind 1: FP32 fused multiply-adds per second (lane operations);
+ *   kind 2: exp2 evaluations per second (lane operations).
+ * 16 independent chains per lane, 8 waves per SIMD, 5 timed launches after
+ * one warm-up.  Allocates and frees a small buffer; synchronises the stream.
+ * Errors: EINVAL (kind outside 0..2, NULL rate), ENOMEM, EDEVICE. */
+int lmmew_calibrate(int kind, hipStream_t stream, double *rate);
 
 /* ---------------------------------------------------------------------------
  * Per-event rows
@@ -360,6 +397,20 @@ int lmmew_line_mask(const lmmew_system *sys, float energy_keV);
  *   rows  device [ev->n][n*n] float, written.
  * Synchronises the stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int lmmew_rows(lmmew_ctx *ctx, const lmmew_events *ev, int part, float *rows, hipStream_t stream);
+
+/* Rows of chosen events from one sub-iteration's system-model launch of a
+ * plan: the launch lmmew_osem_iter makes for subset `subset` (the plan's
+ * tiles, event tile, path table and the context's scatter model), written to
+ * the plan's scratch, then rows[k][q] = a_jq of input event events[k]
+ * (Eq. (3)) over the n*n grid (zero off the support).  For parity tests of
+ * the rows at full size, in the configuration the OSEM iterations use.
+ *   events  host int64 [n]: input indices (as given to lmmew_plan_create) of
+ *           events of that subset.
+ *   rows    device [n][n*n] float, written.
+ * Synchronises the stream.  Errors: EINVAL (an event outside the subset or
+ * out of range), ENOMEM, EDEVICE. */
+int lmmew_plan_rows(lmmew_ctx *ctx, lmmew_plan *plan, int subset, const int64_t *events,
+                    int64_t n, float *rows, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Scatter surrogate (an extension beyond the paper)
@@ -427,7 +478,10 @@ int lmmew_scatter_labels(lmmew_ctx *ctx, int64_t n_events, uint64_t seed, float 
 
 /* Fits the network to given labels: floor = floor_frac x mean of raw, c0 =
  * mean of log(raw + floor), targets log(raw + floor) - c0, then
- * lmmew_mlp_train (seeded with seed).  feats, raw: device, n rows, as written
+ * lmmew_mlp_train (seeded with seed).  floor_frac == 0 keeps the network's
+ * current floor and c0 (fine-tuning a fitted network, e.g. one whose
+ * parameters were copied with lmmew_mlp_set_params, on labels of another
+ * map); EINVAL if it has none.  feats, raw: device, n rows, as written
  * by lmmew_scatter_labels of this or any context with the same system (so a
  * network can be trained on labels of several attenuation maps; the batch
  * shuffle mixes them).  Synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */

@@ -8,6 +8,7 @@ is missing.
 """
 from .binding import (  # noqa: F401
     LmmewError,
+    calibrate,
     Context,
     Plan,
     Mlp,

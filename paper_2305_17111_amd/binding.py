@@ -112,6 +112,9 @@ def _load():
         "lmmew_roi_metrics": (i32, [vp, vp, i32, i32, i32, vp, vp, vp]),
         "lmmew_plan_profile_read": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "lmmew_line_mask": (i32, [C.POINTER(_System), C.c_float]),
+        "lmmew_calibrate": (i32, [i32, vp, C.POINTER(C.c_double)]),
+        "lmmew_plan_rows": (i32, [vp, vp, i32, vp, i64, vp, vp]),
+        "lmmew_psf_table": (i32, [vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -160,6 +163,16 @@ def line_mask(p, energy_keV):
     if m < 0:
         raise LmmewError(m, "lmmew_line_mask: invalid arguments")
     return m
+
+
+def calibrate(kind):
+    """lmmew_calibrate: measured rate on the current device of the per-event
+    kernel's term chain (kind 0, terms/s), FP32 FMA (1) or exp2 (2), per second."""
+    rate = C.c_double(0.0)
+    rc = _load().lmmew_calibrate(int(kind), _stream(), C.byref(rate))
+    if rc != 0:
+        raise LmmewError(rc, _load().lmmew_status_string(rc).decode())
+    return rate.value
 
 
 def roi_metrics(est, truth):
@@ -341,6 +354,16 @@ class Context:
         """Builds (or frees) the context's scatter-path parameter table."""
         self._check(_load().lmmew_path_table(self._h, int(bool(enable)), _stream()))
 
+    def lmmew_psf_table(self, enable=True):
+        """Builds (or frees, and stops building) the unscattered bin-probability
+        table; returns whether it is in use."""
+        rc = _load().lmmew_psf_table(self._h, int(bool(enable)), _stream())
+        if rc < 0:
+            self._check(rc)
+        return bool(rc)
+
+    psf_table = lmmew_psf_table
+
     @property
     def path_table_bytes(self):
         return int(_load().lmmew_path_table_bytes(self._h))
@@ -456,9 +479,22 @@ class Plan:
         self.ctx._check(_load().lmmew_plan_cache_rows(self.ctx._h, self._h, int(bool(enable)),
                                                       _stream()))
 
+    def lmmew_plan_rows(self, subset, events):
+        """Rows [len(events), n*n] of the given input events (all of subset `subset`)
+        from that sub-iteration's system-model launch."""
+        import numpy as np
+
+        idx = np.ascontiguousarray(events, dtype=np.int64)
+        rows = torch.empty((idx.size, self.ctx.Q), device="cuda", dtype=torch.float32)
+        self.ctx._check(_load().lmmew_plan_rows(self.ctx._h, self._h, int(subset),
+                                                C.c_void_p(idx.ctypes.data), int(idx.size),
+                                                _ptr(rows), _stream()))
+        return rows
+
     osem_graph = lmmew_osem_graph
     autotune = lmmew_autotune
     cache_rows = lmmew_plan_cache_rows
+    rows = lmmew_plan_rows
 
     def set_event_tile(self, jt):
         self.ctx._check(_load().lmmew_plan_set_event_tile(self.ctx._h, self._h, int(jt), _stream()))

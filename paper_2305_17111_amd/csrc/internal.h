@@ -122,8 +122,9 @@ struct RowArgs {
     const float *g_qs;
     const ScatA *sa;
     const MapTab *maps;      // [ncases] tables per case, or NULL (g_qa, g_qs, sa, S.nsc)
-    const float *ptab;       // scatter-path parameters [na][nsc][Qp][3 nw] (per line: log2
-                             // weight, s_w, F_w), or NULL to evaluate them in the kernel
+    const float *ptab;       // scatter-path parameters [na][nsc][nw][Qp][2] (per line and
+                             // pixel: log2 weight A_w, s_w; the kernel derives F_w =
+                             // log2(e) / (2 k s_w)), or NULL to evaluate them in the kernel
     const float *resp;       // [na][nsc][nb] collimator-response factor of scatter point k
                              // (angle's sorted order) for bin b, 0 beyond 7 sigma
     const float *respz;      // 3-D: [na][nsc][nbz] the same for the axial bin
@@ -228,6 +229,9 @@ hipError_t launch_scatter_out(const float *src, const int64_t *perm, int64_t n, 
                               hipStream_t st);
 hipError_t launch_rows_out(const DevSys &S, const float *A, int rows, const int64_t *perm,
                            const int *pixq, int Q, float *out, hipStream_t st);
+// out[k][pixq[i]] = A[ridx[k]][i] for k < n (rows picked from the subset scratch)
+hipError_t launch_rows_pick(const DevSys &S, const float *A, const int *ridx, int n,
+                            const int *pixq, int Q, float *out, hipStream_t st);
 hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float *dst,
                            hipStream_t st);
 hipError_t launch_roi_sums(const float *lam, int C, int Q, const uint8_t *masks, int K,

@@ -1173,6 +1173,15 @@ __global__ __launch_bounds__(256) void k_rows_out(const DevSys S, const float *A
     out[perm[e] * Q + pixq[i]] = A[(long)e * S.Qp + i];
 }
 
+__global__ __launch_bounds__(256) void k_rows_pick(const DevSys S, const float *A, const int *ridx,
+                                                   int n, const int *pixq, int Q, float *out)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)n * S.Qm) return;
+    const int k = (int)(t / S.Qm), i = (int)(t % S.Qm);
+    out[(long)k * Q + pixq[i]] = A[(long)ridx[k] * S.Qp + i];
+}
+
 __global__ __launch_bounds__(256) void k_gather_w(const float *w, const int64_t *perm, int64_t n,
                                                   float *dst)
 {
@@ -1277,6 +1286,16 @@ hipError_t launch_rows_out(const DevSys &S, const float *A, int rows, const int6
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rows_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S, A, rows,
                        perm, pixq, Q, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_pick(const DevSys &S, const float *A, const int *ridx, int n,
+                            const int *pixq, int Q, float *out, hipStream_t st)
+{
+    const long m = (long)n * S.Qm;
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rows_pick, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, S, A,
+                       ridx, n, pixq, Q, out);
     return hipGetLastError();
 }
 

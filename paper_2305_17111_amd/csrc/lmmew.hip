@@ -43,6 +43,7 @@ struct lmmew_ctx {
     float *d_ptab = nullptr;          // scatter-path parameter table (lmmew_path_table) or NULL
     float *d_resp = nullptr;          // [na][nsc][nb] collimator-response factors
     float *d_psft = nullptr;          // planar: [na][nb][Qp] unscattered bin probabilities
+    bool psft_off = false;            // the table is disabled (lmmew_psf_table) or did not fit
     float *d_respz = nullptr;         // 3-D: [na][nsc][nbz] axial response factors
     float *d_pixz = nullptr;          // 3-D: [Qp] voxel z
     double *d_pixzd = nullptr;        // 3-D: [Qp] voxel z (double, for the tables)
@@ -90,6 +91,7 @@ struct lmmew_plan {
     };
     std::vector<Sub> subs;
     std::vector<int> case_chunk;      // [nsub][ncases+1], chunk index relative to the subset
+    std::vector<int> case_rows;       // [nsub][ncases+1], row index relative to the subset
     std::vector<Tile> tiles;
     std::vector<int2> slist;          // scatter list entries of all tiles: (point, table row)
     std::vector<Chunk> chunks;
@@ -115,7 +117,7 @@ struct lmmew_plan {
     // captured OSEM sequence (lmmew_osem_graph) and the arguments it was captured with
     hipGraphExec_t gexec = nullptr;
     int g_iters = -1, g_jt = 0, g_gen = -1;
-    const float *g_cache = nullptr, *g_tab = nullptr;
+    const float *g_cache = nullptr, *g_tab = nullptr, *g_psft = nullptr;
     const float *g_sens = nullptr;
     float *g_lambda = nullptr;
     // optional timing of the per-event kernel launches (HIP events on the caller's stream)
@@ -310,9 +312,12 @@ std::pair<int, int> reached(const ScatA &e, const float *u, int first, int last)
 // of the scattered energies in Eq. (5)); the energy-resolution factor of
 // Eq. (3)'s event probability at E is exp(-(E - E')^2 / (2 k E')) for
 // scattered energy E' (variance k E', Sec. 3.1.2).
-// When that factor is below 2^-kLineCutBits for every reachable E', the
-// line's scattered terms are dropped for the event (its unscattered term is
-// always kept).  Systems with more than kMaskedLines lines keep every line.
+// A line's largest factor over its reachable E' is compared with the largest
+// over all lines: when it is below 2^-kLineCutBits of that, the line's
+// scattered terms are dropped for the event (its unscattered term is always
+// kept, and the line with the largest factor is always kept, so an energy far
+// from every line's reach keeps its nearest line instead of none).  Systems
+// with more than kMaskedLines lines keep every line.
 int line_mask(const lmmew_system &s, float Ef)
 {
     const int all = (1 << s.n_lines) - 1;
@@ -321,13 +326,17 @@ int line_mask(const lmmew_system &s, float Ef)
     const double fps = fwhm_per_sigma();
     const double k = s.eres_frac * s.eres_frac * s.eres_ref_keV / (fps * fps);
     const double cut = kLineCutBits * std::log(2.0);
-    int m = 0;
+    double x[LMMEW_MAX_LINES], xmin = INFINITY;
     for (int w = 0; w < s.n_lines; ++w) {
         const double Ew = s.line_keV[w];
         const double Emin = Ew / (1.0 + 2.0 * Ew / s.electron_keV);
         const double Ep = E < Emin ? Emin : (E > Ew ? Ew : E);   // closest reachable energy
-        if ((E - Ep) * (E - Ep) / (2.0 * k * Ep) <= cut) m |= 1 << w;
+        x[w] = (E - Ep) * (E - Ep) / (2.0 * k * Ep);             // -log of the largest factor
+        xmin = std::min(xmin, x[w]);
     }
+    int m = 0;
+    for (int w = 0; w < s.n_lines; ++w)
+        if (x[w] - xmin <= cut) m |= 1 << w;
     return m;
 }
 
@@ -530,6 +539,30 @@ bool same_system(const lmmew_ctx *a, const lmmew_ctx *b)
 int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st);
 
 // maps: NULL, or the context of each of the n_cases cases (maps[0] == ctx)
+// The unscattered paths' bin probabilities ([na][nb][Qp], planar systems),
+// read by the per-event kernel instead of two erfc per (event, pixel).  Built
+// on the first plan of a context (so that the contexts of the other patients
+// of a plan over several maps, whose tables the kernel does not read, never
+// hold one), kept to 2 GiB; when it does not fit, or when it is disabled, the
+// kernel forms the probabilities itself.
+int ensure_psft(lmmew_ctx *ctx, hipStream_t st)
+{
+    if (ctx->d_psft || ctx->psft_off || ctx->sys.nz > 0) return LMMEW_OK;
+    const size_t n = (size_t)ctx->S.na * ctx->S.nb * ctx->S.Qp;
+    if (n * sizeof(float) > (size_t(2) << 30)) {
+        ctx->psft_off = true;
+        return LMMEW_OK;
+    }
+    if (dalloc(&ctx->d_psft, n) != hipSuccess) {
+        (void)hipGetLastError();          // clear the allocation failure; fall back
+        ctx->d_psft = nullptr;
+        ctx->psft_off = true;
+        return LMMEW_OK;
+    }
+    HIPCHK(ctx, launch_psf_table(ctx->S, ctx->d_pix, ctx->d_dirs, ctx->d_psft, st));
+    return LMMEW_OK;
+}
+
 int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offsets, int n_cases,
               int n_subsets, hipStream_t st, lmmew_plan **out, lmmew_ctx *const *maps = nullptr)
 {
@@ -555,6 +588,10 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     if (n_cases < 1) return fail(ctx, LMMEW_EINVAL, "n_cases must be >= 1");
     const int64_t n = ev->n;
     if (n > ((int64_t)1 << 31) - 1) return fail(ctx, LMMEW_EINVAL, "too many events");
+    {
+        const int rp = ensure_psft(ctx, st);
+        if (rp != LMMEW_OK) return rp;
+    }
     std::vector<int64_t> off(n_cases + 1);
     if (case_offsets) {
         for (int c = 0; c <= n_cases; ++c) off[c] = case_offsets[c];
@@ -692,6 +729,18 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
             while (r < n && p->ang[r] % n_subsets == sidx) ++r;
             p->subs[sidx].rows = (int)r - p->subs[sidx].row0;
             p->max_rows = std::max(p->max_rows, p->subs[sidx].rows);
+        }
+        // rows of each case within each subset (a subset's rows are sorted by case)
+        p->case_rows.assign((size_t)n_subsets * (n_cases + 1), 0);
+        for (int sidx = 0; sidx < n_subsets; ++sidx) {
+            const lmmew_plan::Sub &sb = p->subs[sidx];
+            int *cr = p->case_rows.data() + (size_t)sidx * (n_cases + 1);
+            int rr = 0;
+            for (int c = 0; c < n_cases; ++c) {
+                cr[c] = rr;
+                while (rr < sb.rows && p->cas[sb.row0 + rr] == c) ++rr;
+            }
+            cr[n_cases] = rr;
         }
     }
     // algorithmic terms per iteration
@@ -879,12 +928,34 @@ RowArgs row_args(const lmmew_ctx *ctx, const lmmew_plan *p, int s)
     return r;
 }
 
+// Scatter network of case c: its own context's selection in a plan over
+// several maps, else the plan context's.
+const lmmew_mlp *case_model(const lmmew_ctx *ctx, const lmmew_plan *p, int c)
+{
+    if (!p->maps.empty() && p->maps[c]->mlp) return p->maps[c]->mlp;
+    return ctx->mlp;
+}
+
+// Changes whenever the scatter model of any case of the plan changes.
+int plan_model_gen(const lmmew_ctx *ctx, const lmmew_plan *p)
+{
+    int g = ctx->model_gen;
+    for (size_t c = 1; c < p->maps.size(); ++c) g += p->maps[c]->model_gen;
+    return g;
+}
+
 int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
              float *dst = nullptr)
 {
     const lmmew_plan::Sub &sub = p->subs[s];
     float *const out = dst ? dst : p->d_A;
     const bool surrogate = (part == 0 && ctx->mlp != nullptr);
+    if (part == 0 && !ctx->mlp)
+        for (size_t c = 1; c < p->maps.size(); ++c)
+            if (p->maps[c]->mlp)
+                return fail(ctx, LMMEW_EINVAL,
+                            "a case's context selects a scatter network but the plan's context "
+                            "does not");
     if (surrogate && p->cont)
         return fail(ctx, LMMEW_EINVAL,
                     "the scatter surrogate models binned events; these carry continuous positions");
@@ -897,21 +968,32 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
     if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
     if (surrogate) {
-        const lmmew_mlp *m = ctx->mlp;
-        MlpRowArgs a{};
-        a.pix_xy = ctx->d_pix;
-        a.dirs = ctx->d_dirs;
-        a.ev_bin = p->d_bin + sub.row0;
-        a.ev_ang = p->d_ang + sub.row0;
-        a.ev_E = p->d_E + sub.row0;
-        a.rows = sub.rows;
-        a.A = out;
-        a.P = m->P;
-        a.c0 = (float)m->c0;
-        a.floor_ = (float)m->floor_;
+        // one launch per run of consecutive cases that share a network (the
+        // whole subset when every case uses the plan context's)
         const bool profm = p->prof && sub.rows > 0;
         if (profm) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
-        HIPCHK(ctx, mlp_rows(ctx->S, a, st));
+        const int *cr = p->case_rows.data() + (size_t)s * (p->ncases + 1);
+        for (int c0 = 0; c0 < p->ncases;) {
+            const lmmew_mlp *m = case_model(ctx, p, c0);
+            int c1 = c0 + 1;
+            while (c1 < p->ncases && case_model(ctx, p, c1) == m) ++c1;
+            const int r0 = cr[c0], r1 = cr[c1];
+            if (r1 > r0) {
+                MlpRowArgs a{};
+                a.pix_xy = ctx->d_pix;
+                a.dirs = ctx->d_dirs;
+                a.ev_bin = p->d_bin + sub.row0 + r0;
+                a.ev_ang = p->d_ang + sub.row0 + r0;
+                a.ev_E = p->d_E + sub.row0 + r0;
+                a.rows = r1 - r0;
+                a.A = out + (size_t)r0 * ctx->S.Qp;
+                a.P = m->P;
+                a.c0 = (float)m->c0;
+                a.floor_ = (float)m->floor_;
+                HIPCHK(ctx, mlp_rows(ctx->S, a, st));
+            }
+            c0 = c1;
+        }
         if (profm) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
     }
     return LMMEW_OK;
@@ -1284,13 +1366,6 @@ int lmmew_create(const lmmew_system *sys, const float *mu85, const uint8_t *supp
     CCHK(launch_tables_d(S, ctx->d_mu, ctx->d_pixd, ctx->d_pixzd, ctx->d_dirsd, ctx->d_scd,
                          ctx->d_sczd, ctx->d_gqa, ctx->d_gqs, ctx->d_sa, pix, R, st));
     CCHK(launch_resp_table(S, ctx->d_sa, ctx->d_resp, ctx->d_scz, ctx->d_respz, st));
-    // the unscattered paths' bin probabilities, read by the per-event kernel
-    // instead of two erfc per (event, pixel); kept to 2 GiB (larger systems
-    // form them in the kernel)
-    if (!d3 && (size_t)na * s.n_bins * Qp * sizeof(float) <= (size_t(2) << 30)) {
-        CCHK(dalloc(&ctx->d_psft, (size_t)na * s.n_bins * Qp));
-        CCHK(launch_psf_table(S, ctx->d_pix, ctx->d_dirs, ctx->d_psft, st));
-    }
     CCHK(hipStreamSynchronize(st));
     {
         double *scr = nullptr;   // resolve the no-allocation scratch on this device once
@@ -1317,7 +1392,7 @@ int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t st)
     if (!ctx) return LMMEW_EINVAL;
     if (!enable) {
         if (ctx->d_ptab) {
-            HIPCHK(ctx, hipDeviceSynchronize());
+            HIPCHK(ctx, hipStreamSynchronize(st));
             dfree(ctx->d_ptab);
             ctx->d_ptab = nullptr;
         }
@@ -1344,6 +1419,25 @@ int lmmew_path_table(lmmew_ctx *ctx, int enable, hipStream_t st)
     }
     ctx->d_ptab = t;
     return LMMEW_OK;
+}
+
+int lmmew_psf_table(lmmew_ctx *ctx, int enable, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!enable) {
+        if (ctx->d_psft) {
+            HIPCHK(ctx, hipStreamSynchronize(st));
+            dfree(ctx->d_psft);
+            ctx->d_psft = nullptr;
+        }
+        ctx->psft_off = true;
+        return LMMEW_OK;
+    }
+    ctx->psft_off = false;
+    const int rc = ensure_psft(ctx, st);
+    if (rc != LMMEW_OK) return rc;
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return ctx->d_psft ? 1 : 0;
 }
 
 int64_t lmmew_path_table_bytes(const lmmew_ctx *ctx)
@@ -1474,8 +1568,8 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
         if (rm != LMMEW_OK) return rm;
     }
     if (!p->gexec || p->g_iters != n_iters || p->g_sens != sens || p->g_lambda != lambda ||
-        p->g_jt != p->JT || p->g_gen != ctx->model_gen || p->g_cache != p->d_Acache ||
-        p->g_tab != plan_ptab(ctx, p)) {
+        p->g_jt != p->JT || p->g_gen != plan_model_gen(ctx, p) || p->g_cache != p->d_Acache ||
+        p->g_tab != plan_ptab(ctx, p) || p->g_psft != ctx->d_psft) {
         if (p->gexec) {
             HIPCHK(ctx, hipGraphExecDestroy(p->gexec));
             p->gexec = nullptr;
@@ -1508,9 +1602,10 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
         p->g_sens = sens;
         p->g_lambda = lambda;
         p->g_jt = p->JT;
-        p->g_gen = ctx->model_gen;
+        p->g_gen = plan_model_gen(ctx, p);
         p->g_cache = p->d_Acache;
         p->g_tab = plan_ptab(ctx, p);
+        p->g_psft = ctx->d_psft;
     }
     HIPCHK(ctx, hipGraphLaunch(p->gexec, st));
     return LMMEW_OK;
@@ -1573,7 +1668,7 @@ int lmmew_plan_cache_rows(lmmew_ctx *ctx, lmmew_plan *p, int enable, hipStream_t
         return rc;
     }
     p->d_Acache = c;
-    p->cache_gen = ctx->model_gen;
+    p->cache_gen = plan_model_gen(ctx, p);
     return LMMEW_OK;
 }
 
@@ -1733,7 +1828,7 @@ static int osem_run(lmmew_ctx *ctx, lmmew_plan *p, int first_subset, int count, 
 {
     const int K = count;
     const bool want = stats != nullptr;
-    if (p->d_Acache && p->cache_gen != ctx->model_gen)
+    if (p->d_Acache && p->cache_gen != plan_model_gen(ctx, p))
         return fail(ctx, LMMEW_EINVAL,
                     "cached rows are stale: the scatter model changed (cache them again)");
     if (K > 0) {
@@ -1919,6 +2014,41 @@ int lmmew_rows(lmmew_ctx *ctx, const lmmew_events *ev, int part, float *rows, hi
     return rc;
 }
 
+int lmmew_plan_rows(lmmew_ctx *ctx, lmmew_plan *p, int subset, const int64_t *events, int64_t n,
+                    float *rows, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!p || p->ctx != ctx) return fail(ctx, LMMEW_EINVAL, "plan of another context");
+    if (subset < 0 || subset >= p->nsub) return fail(ctx, LMMEW_EINVAL, "subset out of range");
+    if (n < 0 || (n > 0 && (!events || !rows))) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    if (n == 0) return LMMEW_OK;
+    const lmmew_plan::Sub &sub = p->subs[subset];
+    std::vector<int> inv(p->n, -1);   // input index -> row within the subset
+    for (int r = 0; r < sub.rows; ++r) inv[p->perm[sub.row0 + r]] = r;
+    std::vector<int> ridx(n);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t j = events[k];
+        if (j < 0 || j >= p->n || inv[j] < 0)
+            return fail(ctx, LMMEW_EINVAL, "event " + std::to_string((long long)j) +
+                                               " is not in subset " + std::to_string(subset));
+        ridx[k] = inv[j];
+    }
+    int rc = run_rows(ctx, p, subset, st);
+    if (rc != LMMEW_OK) return rc;
+    int *d_idx = nullptr;
+    hipError_t e = dalloc(&d_idx, (size_t)n);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_idx, ridx.data(), n * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(rows, 0, (size_t)n * ctx->Q * sizeof(float), st);
+    if (e == hipSuccess)
+        e = launch_rows_pick(ctx->S, p->d_A, d_idx, (int)n, ctx->d_pixq, ctx->Q, rows, st);
+    const hipError_t e2 = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = e2;
+    dfree(d_idx);
+    if (e != hipSuccess) return hipfail(ctx, e, "plan rows");
+    return LMMEW_OK;
+}
+
 int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
 {
     if (!ctx || !out) return LMMEW_EINVAL;
@@ -1960,7 +2090,7 @@ int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
     MCHK(hipMemset(m->m1, 0, sizeof(float) * kMlpParams));
     MCHK(hipMemset(m->m2, 0, sizeof(float) * kMlpParams));
     MCHK(mlp_refresh(m->P, m->W2b, m->W3b, nullptr));
-    MCHK(hipDeviceSynchronize());
+    MCHK(hipStreamSynchronize(nullptr));   // the copies and the refresh ran on the null stream
 #undef MCHK
     *out = m;
     return LMMEW_OK;
@@ -1998,7 +2128,7 @@ int lmmew_mlp_set_params(lmmew_mlp *m, const float *params, double c0, double fl
     HIPCHK(ctx, hipMemset(m->m1, 0, sizeof(float) * kMlpParams));
     HIPCHK(ctx, hipMemset(m->m2, 0, sizeof(float) * kMlpParams));
     HIPCHK(ctx, mlp_refresh(m->P, m->W2b, m->W3b, nullptr));
-    HIPCHK(ctx, hipDeviceSynchronize());
+    HIPCHK(ctx, hipStreamSynchronize(nullptr));   // the copies and the refresh ran on the null stream
     m->step = 0;
     m->c0 = c0;
     m->floor_ = floor_;
@@ -2169,11 +2299,23 @@ int lmmew_mlp_fit_labels(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const
                          uint64_t seed, double *epoch_loss, hipStream_t st)
 {
     if (!ctx || !m || m->ctx != ctx) return LMMEW_EINVAL;
-    if (!(floor_frac > 0)) return fail(ctx, LMMEW_EINVAL, "floor_frac must be > 0");
+    const bool keep = floor_frac == 0.0;
+    if (!(floor_frac > 0) && !keep) return fail(ctx, LMMEW_EINVAL, "floor_frac must be >= 0");
+    if (keep && !(m->floor_ > 0))
+        return fail(ctx, LMMEW_EINVAL, "floor_frac 0 keeps the network's floor, which is unset");
     if (n <= 0 || !feats || !raw) return fail(ctx, LMMEW_EINVAL, "bad arguments");
     float *tgt = nullptr;
     HIPCHK(ctx, dalloc(&tgt, n));
     int rc = LMMEW_OK;
+    if (keep) {
+        const hipError_t e = mlp_targets(raw, n, (float)m->floor_, (float)m->c0, tgt, st);
+        if (e != hipSuccess) rc = hipfail(ctx, e, "targets");
+        if (rc == LMMEW_OK)
+            rc = lmmew_mlp_train(ctx, m, feats, tgt, n, batch, epochs, lr, seed ^ 0x5eedull,
+                                 epoch_loss, st);
+        dfree(tgt);
+        return rc;
+    }
     // floor = floor_frac x mean density, c0 = mean of log(density + floor)
     std::vector<float> h(n);
     hipError_t e = hipMemcpyAsync(h.data(), raw, sizeof(float) * n, hipMemcpyDeviceToHost, st);

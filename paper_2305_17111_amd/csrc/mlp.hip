@@ -390,12 +390,26 @@ __device__ __forceinline__ unsigned gelu_pair(float a, float b, const unsigned *
 {
     const h2 z = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b));
     const unsigned bits = __builtin_bit_cast(unsigned, z);
-    const unsigned e0 = tab[(bits >> 6) & 0x3FFu], e1 = tab[bits >> 22];
-    const h2 dz = z - __builtin_bit_cast(h2, bits & 0xFFC0FFC0u);
-    // (value, slope) of the two entries -> (value0, value1), (slope0, slope1)
-    const h2 G = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x05040100u));
-    const h2 D = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x07060302u));
-    return __builtin_bit_cast(unsigned, __builtin_elementwise_fma(D, dz, G));
+    // the entries' own arguments z_k (low 6 bits of each half cleared); an
+    // entry's byte offset is its index times 4, i.e. bits 4..15 of z_k's low
+    // half (one bit-field extract) and bits 20..31 of its high half (one
+    // shift).  The opaque copy keeps the compiler from re-deriving the offsets
+    // from `bits` with a shift and a mask each.
+    unsigned zk = bits & 0xFFC0FFC0u;
+    asm volatile("" : "+v"(zk));
+    const unsigned o0 = __builtin_amdgcn_ubfe(zk, 4, 12), o1 = zk >> 20;
+    const char *t = reinterpret_cast<const char *>(tab);
+    const unsigned e0 = *reinterpret_cast<const unsigned *>(t + o0);
+    const unsigned e1 = *reinterpret_cast<const unsigned *>(t + o1);
+    const h2 dz = z - __builtin_bit_cast(h2, zk);
+    // entry = (value, slope): one mixed-precision FMA per half takes value,
+    // slope and offset from their FP16 halves (operand selects), evaluates in
+    // FP32 and writes its half of the result (no byte permutes)
+    const h2 E0 = __builtin_bit_cast(h2, e0), E1 = __builtin_bit_cast(h2, e1);
+    h2 r;
+    r.x = (_Float16)fmaf((float)E0.y, (float)dz.x, (float)E0.x);
+    r.y = (_Float16)fmaf((float)E1.y, (float)dz.y, (float)E1.x);
+    return __builtin_bit_cast(unsigned, r);
 }
 
 // four 32-bit words (FP16 pairs) as an MFMA operand fragment
