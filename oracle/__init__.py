@@ -100,11 +100,11 @@ _S3 = C.POINTER(_Sys3)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
+        build(force=False)            # compiles when missing or older than the sources
         L = C.CDLL(_LIB)
         sig = {
             "or_threads": (C.c_int, []),
+            "or_set_threads": (None, [C.c_int]),
             "or_angle_dir": (None, [C.c_int, C.c_int, _D, _D]),
             "or_segment_integral": (C.c_double, [_D, C.c_int, C.c_double, C.c_double,
                                                  C.c_double, C.c_double, C.c_double]),
@@ -128,6 +128,7 @@ def lib():
             "or_event_row_pos": (None, [_G, C.c_double, C.c_int, C.c_double, _D]),
             "or_sens_qa": (C.c_double, [_G, C.c_int, C.c_int]),
             "or_sensitivity": (None, [_G, C.c_int, _D]),
+            "or_sensitivity_subset": (None, [_G, C.c_int, C.c_int, _D]),
             "or_sample_masses": (C.c_long, [_G, _D, _D]),
             "or_check_events": (C.c_int, [_G, C.c_long, _I, _D, _I, _D]),
             "or_forward": (None, [_G, C.c_long, _I, _D, _I, _D, _D, _D]),
@@ -194,6 +195,11 @@ def make_sys(p) -> _Sys:
 def threads():
     """OpenMP threads the oracle uses."""
     return int(lib().or_threads())
+
+
+def set_threads(n):
+    """Threads the oracle's OpenMP loops use from now on."""
+    lib().or_set_threads(int(n))
 
 
 def angle_dir(a, na):
@@ -334,6 +340,12 @@ class Oracle:
     def sensitivity(self, nsub):
         out = np.zeros((int(nsub), self.Q))
         lib().or_sensitivity(C.byref(self._g), int(nsub), _dp(out))
+        return out
+
+    def sensitivity_subset(self, nsub, s):
+        """Row s of sensitivity(nsub), computed alone."""
+        out = np.zeros(self.Q)
+        lib().or_sensitivity_subset(C.byref(self._g), int(nsub), int(s), _dp(out))
         return out
 
     # -- events

@@ -26,6 +26,16 @@ int or_threads(void)
 #endif
 }
 
+/* Sets the threads the OpenMP loops of this library use (n >= 1). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* FWHM of a Gaussian in units of its standard deviation: 2 sqrt(2 ln 2). */
 static double fwhm_per_sigma(void) { return 2.0 * sqrt(2.0 * log(2.0)); }
 
@@ -498,6 +508,21 @@ void or_sensitivity(const or_geom *G, int nsub, double *sens)
         if (!G->support[q]) continue;
         for (int a = 0; a < na; ++a)
             sens[(size_t)(a % nsub) * G->Q + q] += G->S.T * or_sens_qa(G, q, a);
+    }
+}
+
+/* One subset's row of or_sensitivity: T * sum over the angles a with
+ * a mod nsub == s of the pixel sensitivity (the denominator of Eq. (18) for
+ * that subset alone). */
+void or_sensitivity_subset(const or_geom *G, int nsub, int s, double *sens_s)
+{
+    int na = G->S.na;
+    memset(sens_s, 0, sizeof(double) * (size_t)G->Q);
+#pragma omp parallel for schedule(dynamic)
+    for (int q = 0; q < G->Q; ++q) {
+        if (!G->support[q]) continue;
+        for (int a = s; a < na; a += nsub)
+            sens_s[q] += G->S.T * or_sens_qa(G, q, a);
     }
 }
 

@@ -70,6 +70,7 @@ typedef struct {
 } or_geom;
 
 int    or_threads(void);
+void   or_set_threads(int n);
 
 /* ---- physics and geometry primitives ---------------------------------- */
 void   or_angle_dir(int a, int na, double *c, double *s);
@@ -98,6 +99,7 @@ void   or_event_row_pos(const or_geom *G, double u, int a, double Ehat, double *
 void   or_event_row_scatter(const or_geom *G, int b, int a, double Ehat, double *row);
 double or_sens_qa(const or_geom *G, int q, int a);
 void   or_sensitivity(const or_geom *G, int nsub, double *sens);
+void   or_sensitivity_subset(const or_geom *G, int nsub, int s, double *sens_s);
 long   or_sample_masses(const or_geom *G, const double *lambda, double *mass);
 
 /* ---- list-mode OSEM ----------------------------------------------------- */

@@ -8,6 +8,7 @@ receives it, and the oracle then works in double precision on those values.
     python tests/golden/make_oracle_golden.py rows64    # sampled rows + sensitivity
     python tests/golden/make_oracle_golden.py iter64    # one full iteration, 2000 events
     python tests/golden/make_oracle_golden.py rows128   # sampled rows at 128x128
+    python tests/golden/make_oracle_golden.py maps128   # one sub-iteration, two patients' maps
     python tests/golden/make_oracle_golden.py small_pos # continuous positions, 16x16
     python tests/golden/make_oracle_golden.py pos64     # continuous positions, sampled rows
     python tests/golden/make_oracle_golden.py small_3d  # 3-D model, 16x16x8
@@ -81,6 +82,8 @@ def rows64():
            "energy": ev["energy"][idx].astype(np.float64)}
     t = time.time()
     p_act = o.forward(sub, act32)
+    rows = np.stack([o.row(int(b), int(a), float(E))
+                     for b, a, E in zip(sub["bin"], sub["angle"], sub["energy"])])
     print("rows64 rows", time.time() - t, "s")
     qs = np.flatnonzero(o.support)
     pix = np.sort(rng.choice(qs, 16, replace=False))
@@ -92,7 +95,7 @@ def rows64():
             sens[a % nsub, k] += p.T * o.sens_qa(int(q), a)
     print("rows64 sens", time.time() - t, "s")
     np.savez_compressed(os.path.join(OUT, "64x64_50k_oracle.npz"), digest=digest(ev), J=J, idx=idx,
-                        p_act=p_act, pix=pix, sens=sens)
+                        p_act=p_act, rows=rows, pix=pix, sens=sens)
 
 
 def iter64():
@@ -125,9 +128,37 @@ def rows128():
            "energy": ev["energy"][idx].astype(np.float64)}
     t = time.time()
     p_act = o.forward(sub, act32)
+    rows = np.stack([o.row(int(b), int(a), float(E))
+                     for b, a, E in zip(sub["bin"], sub["angle"], sub["energy"])])
     print("rows128 rows", time.time() - t, "s")
     np.savez_compressed(os.path.join(OUT, "128x128_16cases_oracle.npz"), digest=digest(ev), idx=idx,
-                        p_act=p_act)
+                        p_act=p_act, rows=rows)
+
+
+def maps128():
+    """One sub-iteration (subset 0 of 16) of a plan over two patients of the
+    128x128 workload, each with its own attenuation map: the first 150 events
+    of subset 0 in each patient's event list."""
+    w = synth.CONFIGS["128x128_16cases"]
+    p = w.params
+    nsub, per = w.n_subsets, 150
+    out = {}
+    for c in (0, 1):
+        _, mu, act, _, ev = synth.workload_inputs(w.name, c)
+        sel = np.flatnonzero(ev["angle"] % nsub == 0)[:per]
+        sub = {"bin": ev["bin"][sel], "angle": ev["angle"][sel], "energy": ev["energy"][sel]}
+        evd = {"bin": sub["bin"], "angle": sub["angle"], "energy": sub["energy"].astype(np.float64)}
+        t = time.time()
+        o = oracle.Oracle(p, f32(mu))
+        sens = np.zeros((nsub, o.Q))
+        sens[0] = o.sensitivity_subset(nsub, 0)
+        print("maps128 case", c, "tables + sensitivity", time.time() - t, "s")
+        lam0 = o.support.astype(np.float64)
+        lam, hist, ll, sk = o.osem(evd, nsub, 1, lam0, f32(sens))
+        print("maps128 case", c, "sub-iteration", time.time() - t, "s")
+        out.update({f"sel{c}": sel, f"digest{c}": digest(ev), f"sens{c}": sens[0],
+                    f"lam0_{c}": lam0, f"lam1_{c}": hist[0], f"ll{c}": ll[0], f"skipped{c}": sk[0]})
+    np.savez_compressed(os.path.join(OUT, "128x128_maps_subiter_oracle.npz"), **out)
 
 
 def below_R(u, p):

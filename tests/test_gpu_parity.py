@@ -346,3 +346,63 @@ def test_batched_uneven_cases_in_one_graph(lm):
         single.set_event_tile(plan.event_tile)
         single.osem_iter(2, sens, lam)
         assert torch.equal(lam, batched[c]), c
+
+
+def test_small_osem_with_unscattered_probabilities_in_kernel(lm):
+    """The per-event kernel forming the unscattered paths' bin probabilities
+    itself (the table disabled, as when it would not fit) against the oracle,
+    every sub-iteration; and the table re-enabled gives the same images to
+    rounding."""
+    import torch
+
+    g = np.load(os.path.join(GOLD, "16x16_2k_oracle.npz"))
+    p = synth.CONFIGS["16x16_2k"].params
+    ctx = lm.Context(p, torch.from_numpy(g["mu"].astype(np.float32)))
+    assert ctx.psf_table(False) is False
+    ev = _dev({"bin": g["bin"], "angle": g["angle"], "energy": g["energy"]})
+    sens = torch.from_numpy(g["sens"].astype(np.float32)).cuda()
+    lam = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    plan = ctx.plan(ev, 4)
+    for k in range(g["hist"].shape[0]):
+        plan.osem_subiter(k % 4, sens, lam)
+        mx, l2 = _rel(lam.cpu().numpy(), g["hist"][k])
+        assert mx < TOL and l2 < TOL, (k, mx, l2)
+    assert ctx.psf_table(True) is True
+    lam2 = torch.from_numpy(g["lam0"].astype(np.float32)).cuda()
+    ctx.plan(ev, 4).osem_iter(10, sens, lam2)
+    d = (lam2 - lam).abs().max().item() / lam.abs().max().item()
+    assert d < 1e-5, d
+
+
+def test_rows_of_events_far_from_every_line(lm, oracle_mod):
+    """Events in a window below every line's scattered range (30-34 keV with
+    lines at 85/154/270 keV: every line's Gaussian factor is below 2^-40 of
+    its peak at every reachable scattered energy) keep the nearest line's
+    scattered terms, since the line cut is relative to the event's largest
+    line factor; their rows (about 1e-18, still normal FP32 numbers) match the
+    oracle's, which keeps every term."""
+    import math
+
+    import torch
+
+    from paper_2305_17111_amd import line_mask
+
+    p = synth.SysParams(16, 4.0, 8, 16, 16, windows=((30.0, 34.0), synth.EW1))
+    k = (p.eres_frac * p.eres_ref / (2.0 * math.sqrt(2.0 * math.log(2.0)))) ** 2 / p.eres_ref
+    emin = p.lines[0] / (1.0 + 2.0 * p.lines[0] / p.me)
+    mu, act, _ = synth.phantom_disk2(p)
+    mu32 = np.asarray(mu, np.float32)
+    o = oracle_mod.Oracle(p, mu32.astype(np.float64))
+    ctx = lm.Context(p, torch.from_numpy(mu32))
+    ev = {"bin": np.array([5, 8, 10, 7], np.int16), "angle": np.array([0, 3, 9, 14], np.int16),
+          "energy": np.array([30.5, 32.0, 33.8, 80.0], np.float32)}
+    for E in ev["energy"][:3]:
+        assert (emin - E) ** 2 / (2 * k * emin) > 40 * math.log(2.0)   # beyond the absolute cut
+        assert line_mask(p, float(E)) == 0b001
+    rows = ctx.rows(_dev(ev)).cpu().numpy().astype(np.float64)
+    for j in range(4):
+        ref = o.row(int(ev["bin"][j]), int(ev["angle"][j]), float(ev["energy"][j]))
+        m = np.abs(ref).max()
+        assert m > 1e-30
+        err = np.abs(rows[j] - ref)
+        assert np.all(err <= 1e-4 * np.abs(ref) + 1e-7 * m), (j, (err / (np.abs(ref) + 1e-7 * m)).max())

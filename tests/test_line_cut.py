@@ -39,19 +39,39 @@ def _max_exponent_margin(p, E, w):
 
 
 def test_line_mask_matches_brute_force_over_scattering_angles():
+    """A line is kept when its largest Gaussian factor is within 2^-40 of the
+    largest over the event's lines."""
     from paper_2305_17111_amd import line_mask
 
     p = synth.CONFIGS["64x64_50k"].params
     checked = 0
-    for E in np.linspace(60.0, 310.0, 501):
+    for E in np.linspace(20.0, 420.0, 801):
         m = line_mask(p, float(np.float32(E)))
-        for w in range(len(p.lines)):
-            x = _max_exponent_margin(p, float(np.float32(E)), w)
-            if abs(x - CUT) < 0.05:
+        xs = [_max_exponent_margin(p, float(np.float32(E)), w) for w in range(len(p.lines))]
+        for w, x in enumerate(xs):
+            rel = x - min(xs)
+            if abs(rel - CUT) < 0.05:
                 continue                      # the grid decides at the boundary
-            assert bool((m >> w) & 1) == (x <= CUT), (E, w, x, m)
+            assert bool((m >> w) & 1) == (rel <= CUT), (E, w, x, m)
             checked += 1
-    assert checked > 1400
+        assert m != 0, E                      # some line's scattered terms are always kept
+    assert checked > 2300
+
+
+def test_line_mask_far_from_every_line_keeps_the_nearest():
+    """An in-window energy far outside every line's reachable scattered range
+    (a 10-20 keV window with these lines) keeps the line whose range is nearest
+    instead of dropping every scattered term."""
+    from paper_2305_17111_amd import line_mask
+
+    p = synth.SysParams(16, 4.0, 8, 16, 16, windows=((10.0, 20.0),))
+    for E in (10.0, 15.0, 20.0):
+        xs = [_max_exponent_margin(p, E, w) for w in range(3)]
+        assert min(xs) > CUT                  # beyond the absolute cut for every line
+        m = line_mask(p, E)
+        assert m & (1 << int(np.argmin(xs))), (E, m)
+    # and above every line
+    assert line_mask(p, 400.0) & 0b100
 
 
 def test_line_mask_on_the_windows():
