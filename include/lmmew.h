@@ -495,6 +495,23 @@ int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, int64_t n_label_events, int ep
                   double lr, double floor_frac, uint64_t seed, double *epoch_loss,
                   hipStream_t stream);
 
+/* Factor on the scatter network's density for this context's cases
+ * (default 1): in a plan over several maps case c takes ctxs[c]'s factor,
+ * otherwise every case takes the plan context's.  It calibrates a network
+ * with no attenuation-map input to one patient's map (lmmew_scatter_scale_fit).
+ * Errors: EINVAL (scale not positive and finite). */
+int lmmew_set_scatter_scale(lmmew_ctx *ctx, double scale);
+
+/* The factor that matches the network's total once-scattered density to the
+ * exact model's over the given events on this context's map: *scale =
+ * sum_j sum_q exact scattered a_jq / sum_j sum_q network density_jq (sums over
+ * every support pixel, FP64), for example over a sample of one patient's own
+ * recorded events.  mlp: a network of this context or of one with the same
+ * system and support (it need not be selected).  Synchronises the stream.  Errors: EINVAL (no events,
+ * continuous positions, NULL), ENUMERIC (a sum vanishes), ENOMEM, EDEVICE. */
+int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, const lmmew_events *ev,
+                            double *scale, hipStream_t stream);
+
 /* Selects the scatter model that lmmew_osem_iter/_subiter/_graph,
  * lmmew_forward and lmmew_backproject use for this context: NULL for the
  * exact model, or a network of this context (kept by pointer: it must stay

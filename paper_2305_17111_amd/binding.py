@@ -115,6 +115,8 @@ def _load():
         "lmmew_calibrate": (i32, [i32, vp, C.POINTER(C.c_double)]),
         "lmmew_plan_rows": (i32, [vp, vp, i32, vp, i64, vp, vp]),
         "lmmew_psf_table": (i32, [vp, i32, vp]),
+        "lmmew_set_scatter_scale": (i32, [vp, C.c_double]),
+        "lmmew_scatter_scale_fit": (i32, [vp, vp, C.POINTER(_Events), C.POINTER(C.c_double), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -327,6 +329,20 @@ class Context:
     def lmmew_set_scatter_model(self, mlp):
         self._check(_load().lmmew_set_scatter_model(self._h, mlp._h if mlp is not None else None))
         self._scatter_model = mlp
+
+    def lmmew_set_scatter_scale(self, scale):
+        self._check(_load().lmmew_set_scatter_scale(self._h, float(scale)))
+
+    def lmmew_scatter_scale_fit(self, mlp, ev):
+        """Exact over network once-scattered density summed over the events' rows."""
+        e = _events(ev)
+        out = C.c_double()
+        self._check(_load().lmmew_scatter_scale_fit(self._h, mlp._h, C.byref(e), C.byref(out),
+                                                    _stream()))
+        return out.value
+
+    set_scatter_scale = lmmew_set_scatter_scale
+    scatter_scale_fit = lmmew_scatter_scale_fit
 
     def lmmew_mlp_create(self, seed=0):
         return Mlp(self, seed)

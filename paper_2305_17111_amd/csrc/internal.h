@@ -234,6 +234,8 @@ hipError_t launch_rows_pick(const DevSys &S, const float *A, const int *ridx, in
                             const int *pixq, int Q, float *out, hipStream_t st);
 hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float *dst,
                            hipStream_t st);
+// out[0] = sum of x[0..n) in FP64 (fixed order: deterministic)
+hipError_t launch_sum(const float *x, long n, double *out, hipStream_t st);
 hipError_t launch_roi_sums(const float *lam, int C, int Q, const uint8_t *masks, int K,
                            double *out, hipStream_t st);
 
@@ -253,6 +255,8 @@ struct MlpRowArgs {
     float *A;
     const float *P;                    // fp32 parameters
     float c0, floor_;
+    const int *ev_case;                // rows' cases (with case_scale), or NULL
+    const float *case_scale;           // [cases] factor on the density, or NULL (1)
 };
 hipError_t mlp_gemm(const unsigned short *A, long sai, long sak, const unsigned short *B, long sbk,
                     long sbj, float *C, long ldc, int M, int N, int K, hipStream_t st);

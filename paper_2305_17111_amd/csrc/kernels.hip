@@ -1341,6 +1341,27 @@ __global__ __launch_bounds__(256) void k_roi_sums(const float *lam, int Q, const
     if (threadIdx.x == 0) out[(size_t)c * K + k] = red[0];
 }
 
+// FP64 sum of n floats by one workgroup in a fixed order (setup-time use).
+__global__ __launch_bounds__(1024) void k_sum_f64(const float *x, long n, double *out)
+{
+    __shared__ double red[1024];
+    double acc = 0.0;
+    for (long i = threadIdx.x; i < n; i += 1024) acc += (double)x[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t launch_sum(const float *x, long n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(1024), 0, st, x, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_roi_sums(const float *lam, int C, int Q, const uint8_t *masks, int K,
                            double *out, hipStream_t st)
 {

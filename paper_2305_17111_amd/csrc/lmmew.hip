@@ -50,6 +50,7 @@ struct lmmew_ctx {
     float *d_scz = nullptr;           // 3-D: [nsc] scatter-point z
     double *d_sczd = nullptr;         // 3-D: [nsc] scatter-point z (double)
     lmmew_mlp *mlp = nullptr;         // scatter surrogate used by OSEM (NULL: exact model)
+    float scatter_scale = 1.f;        // factor on the surrogate's density for this map's cases
     int model_gen = 0;                // bumped whenever the scatter model changes
 };
 
@@ -109,6 +110,8 @@ struct lmmew_plan {
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
     float *d_Acache = nullptr;        // [n][Qp] rows of every subset (lmmew_plan_cache_rows) or NULL
     float *d_lamc = nullptr;          // [ncases][Qp] support copy of the current images
+    float *d_cscale = nullptr;        // [ncases] surrogate density factor of each case
+    std::vector<float> cscale;        // what d_cscale holds
     int cache_gen = -1;               // scatter-model generation the cached rows were computed with
     double *d_logp = nullptr, *d_ll = nullptr;
     float *d_part = nullptr, *d_comp = nullptr;
@@ -265,6 +268,7 @@ void free_plan(lmmew_plan *p)
     dfree(p->d_maps);
     dfree(p->d_Acache);
     dfree(p->d_lamc);
+    dfree(p->d_cscale);
 }
 
 bool in_window(const lmmew_system &s, float e)
@@ -812,6 +816,7 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     PCHK(dalloc(&p->d_logp, n));
     PCHK(dalloc(&p->d_A, (size_t)std::max(p->max_rows, 1) * Qp));
     PCHK(dalloc(&p->d_lamc, (size_t)n_cases * Qp));
+    PCHK(dalloc(&p->d_cscale, (size_t)n_cases));
     if (n > 0) {
         if (d3)
             PCHK(hipMemcpyAsync(p->d_binz, p->binz.data(), n * sizeof(int), hipMemcpyHostToDevice,
@@ -827,8 +832,8 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         PCHK(hipMemcpyAsync(p->d_perm, p->perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice,
                             st));
     }
-    if (!p->maps.empty()) {
-        PCHK(dalloc(&p->d_maps, n_cases));
+    if (!p->maps.empty()) PCHK(dalloc(&p->d_maps, n_cases));
+    {
         const int rm = sync_maps(ctx, p, st);
         if (rm != LMMEW_OK) return fin(rm);
     }
@@ -857,9 +862,20 @@ hipError_t prof_mark(lmmew_ctx *, lmmew_plan *p, int kind, hipStream_t st)
 // (exact, or unscattered + surrogate when a surrogate is set), 1 exact
 // scattered paths only, 2 unscattered only, 3 exact (ignoring the surrogate).
 // Uploads the per-case tables of a plan over several maps when they changed
-// (a context's path-parameter table may be built or freed after the plan).
+// (a context's path-parameter table may be built or freed after the plan),
+// and the surrogate's per-case density factors.
 int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
 {
+    // the surrogate's density factor of every case (lmmew_set_scatter_scale)
+    std::vector<float> cs(p->ncases);
+    for (int c = 0; c < p->ncases; ++c)
+        cs[c] = (p->maps.empty() ? ctx : p->maps[c])->scatter_scale;
+    if (cs != p->cscale) {
+        HIPCHK(ctx, hipMemcpyAsync(p->d_cscale, cs.data(), cs.size() * sizeof(float),
+                                   hipMemcpyHostToDevice, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        p->cscale = cs;
+    }
     if (p->maps.empty()) return LMMEW_OK;
     std::vector<MapTab> mt(p->ncases);
     for (int c = 0; c < p->ncases; ++c) {
@@ -990,6 +1006,8 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
                 a.P = m->P;
                 a.c0 = (float)m->c0;
                 a.floor_ = (float)m->floor_;
+                a.ev_case = p->d_case + sub.row0 + r0;
+                a.case_scale = p->d_cscale;
                 HIPCHK(ctx, mlp_rows(ctx->S, a, st));
             }
             c0 = c1;
@@ -2033,7 +2051,8 @@ int lmmew_plan_rows(lmmew_ctx *ctx, lmmew_plan *p, int subset, const int64_t *ev
                                                " is not in subset " + std::to_string(subset));
         ridx[k] = inv[j];
     }
-    int rc = run_rows(ctx, p, subset, st);
+    int rc = sync_maps(ctx, p, st);
+    if (rc == LMMEW_OK) rc = run_rows(ctx, p, subset, st);
     if (rc != LMMEW_OK) return rc;
     int *d_idx = nullptr;
     hipError_t e = dalloc(&d_idx, (size_t)n);
@@ -2439,6 +2458,75 @@ int lmmew_roi_metrics(const double *est, const double *truth, int S, int N, int 
         if (bias) bias[k] = b_sum / ((double)S * N);
         if (std_) std_[k] = s_sum / S;
     }
+    return LMMEW_OK;
+}
+
+int lmmew_set_scatter_scale(lmmew_ctx *ctx, double scale)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!(scale > 0) || !std::isfinite(scale))
+        return fail(ctx, LMMEW_EINVAL, "scatter scale must be positive and finite");
+    if ((float)scale != ctx->scatter_scale) {
+        ctx->scatter_scale = (float)scale;
+        ctx->model_gen++;
+    }
+    return LMMEW_OK;
+}
+
+int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev, double *scale,
+                            hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!m || !scale || !ev) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    if (m->ctx != ctx && !same_system(ctx, m->ctx))
+        return fail(ctx, LMMEW_EINVAL, "network of a context with another system or support");
+    if (ev->n < 1) return fail(ctx, LMMEW_EINVAL, "no events");
+    if (ev->position_mm) return fail(ctx, LMMEW_EINVAL, "the surrogate models binned events");
+    lmmew_plan *pl = nullptr;
+    int rc = make_plan(ctx, ev, nullptr, 1, subsets_for_budget(ctx, ev->n), st, &pl);
+    if (rc != LMMEW_OK) return rc;
+    double *d_sum = nullptr;
+    hipError_t e = dalloc(&d_sum, 2 * (size_t)pl->nsub);
+    for (int s = 0; s < pl->nsub && e == hipSuccess && rc == LMMEW_OK; ++s) {
+        const lmmew_plan::Sub &sub = pl->subs[s];
+        rc = run_rows(ctx, pl, s, st, 1);                         // exact scattered paths
+        if (rc != LMMEW_OK) break;
+        e = launch_sum(pl->d_A, (long)sub.rows * ctx->S.Qp, d_sum + 2 * s, st);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(pl->d_A, 0, (size_t)sub.rows * ctx->S.Qp * sizeof(float), st);
+        if (e == hipSuccess) {
+            MlpRowArgs a{};                                        // the network alone
+            a.pix_xy = ctx->d_pix;
+            a.dirs = ctx->d_dirs;
+            a.ev_bin = pl->d_bin + sub.row0;
+            a.ev_ang = pl->d_ang + sub.row0;
+            a.ev_E = pl->d_E + sub.row0;
+            a.rows = sub.rows;
+            a.A = pl->d_A;
+            a.P = m->P;
+            a.c0 = (float)m->c0;
+            a.floor_ = (float)m->floor_;
+            e = mlp_rows(ctx->S, a, st);
+        }
+        if (e == hipSuccess) e = launch_sum(pl->d_A, (long)sub.rows * ctx->S.Qp, d_sum + 2 * s + 1, st);
+    }
+    std::vector<double> h(2 * (size_t)pl->nsub, 0.0);
+    if (e == hipSuccess && rc == LMMEW_OK)
+        e = hipMemcpyAsync(h.data(), d_sum, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    const hipError_t e2 = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = e2;
+    dfree(d_sum);
+    lmmew_plan_destroy(pl);
+    if (rc != LMMEW_OK) return rc;
+    if (e != hipSuccess) return hipfail(ctx, e, "scatter scale fit");
+    double ex = 0.0, net = 0.0;
+    for (int s = 0; 2 * s < (int)h.size(); ++s) {
+        ex += h[2 * s];
+        net += h[2 * s + 1];
+    }
+    if (!(net > 0) || !(ex > 0) || !std::isfinite(ex / net))
+        return fail(ctx, LMMEW_ENUMERIC, "scattered densities vanish for these events");
+    *scale = ex / net;
     return LMMEW_OK;
 }
 

@@ -500,6 +500,7 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
         const int bin = a.ev_bin[e];
         const float2 dir = a.dirs[a.ev_ang[e]];
         const float E = a.ev_E[e];
+        const float sc = a.case_scale ? a.case_scale[a.ev_case[e]] : 1.f;
 
         // first-layer B fragments: group 0 (xh, 1, 1), group 1 (xl, 0, 0),
         // group 2 (xh, 0, 0), group 3 zero
@@ -589,7 +590,7 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             y += __shfl_xor(y, 32, 64);
             if (g == 0 && ip[p] < S.Qm) {
                 const float v = fmaxf(__expf(y + b4 + a.c0) - a.floor_, 0.f);
-                a.A[(long)e * S.Qp + ip[p]] += v;
+                a.A[(long)e * S.Qp + ip[p]] += v * sc;
             }
         }
     }
