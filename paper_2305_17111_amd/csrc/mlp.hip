@@ -359,15 +359,15 @@ __device__ __forceinline__ v8h load_frag_h(const float *P, int off, int f)
 
 // GELU of two values by linear interpolation in an FP16 table.  Entry k of
 // kGeluTab is indexed by the top 10 bits of an FP16 encoding (sign, exponent,
-// top 4 mantissa bits): for z_k, the value whose encoding is k << 6, it holds
-// GELU(z_k) and the slope of the chord to the next entry, as an FP16 pair.
-// A value z in the entry's interval gets GELU(z_k) + slope (z - z_k), where
-// z - z_k is exact.  Over every finite FP16 input the result is within
-// 1.9e-3 of the exact GELU (2 FP16 ulps at z near 2.7; the interpolation part
-// is below 2e-4), against 9.7e-4 for rounding the exact value to FP16 once;
-// beyond |z| = 16 the chords are exactly z and 0.  It replaces the two exp2
-// and two reciprocals per pair on the quarter-rate transcendental unit by two
-// LDS reads and a few full-rate instructions.
+// top 4 mantissa bits): z_k, the value whose encoding is k << 6, starts the
+// entry's interval, and the entry holds the chord from (z_k, GELU(z_k)) to the
+// next entry's point as intercept and slope, an FP16 pair: a value z in the
+// interval gets intercept + slope z, one FMA.  Over every finite FP16 input
+// the result is within 2.1e-3 of the exact GELU (two FP16 ulps near z = 2.8,
+// mostly the FP16 rounding of the stored intercept; rounding the exact value
+// once costs up to 9.7e-4); beyond |z| = 16 the chords are exactly z and 0.
+// It replaces the two exp2 and two reciprocals per pair on the quarter-rate
+// transcendental unit by two LDS reads and a few full-rate instructions.
 constexpr int kGeluTab = 1024;
 
 // fills the table (one entry per call) from the FP32 gelu()
@@ -379,37 +379,31 @@ __device__ __forceinline__ unsigned gelu_table_entry(int k)
     const float g0 = gelu(z0);
     float sl = (gelu(z1) - g0) / (z1 - z0);
     if (!__builtin_isfinite(z1) || !__builtin_isfinite(sl)) sl = z0 > 0.f ? 1.f : 0.f;
-    const h2 v = {(_Float16)g0, (_Float16)sl};
+    const h2 v = {(_Float16)fmaf(-sl, z0, g0), (_Float16)sl};
     return __builtin_bit_cast(unsigned, v);
 }
 
 // two FP32 accumulators -> FP16 pair (round toward zero) -> GELU, as the
 // 32-bit encoding of the FP16 pair; tab must sit at LDS address 0 so that an
-// entry's address is just its index times 4
+// entry's byte offset is just its index times 4
 __device__ __forceinline__ unsigned gelu_pair(float a, float b, const unsigned *tab)
 {
     const h2 z = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b));
     const unsigned bits = __builtin_bit_cast(unsigned, z);
-    // the entries' own arguments z_k (low 6 bits of each half cleared); an
-    // entry's byte offset is its index times 4, i.e. bits 4..15 of z_k's low
-    // half (one bit-field extract) and bits 20..31 of its high half (one
-    // shift).  The opaque copy keeps the compiler from re-deriving the offsets
-    // from `bits` with a shift and a mask each.
+    // With the low 6 bits of each half cleared, an entry's byte offset is bits
+    // 4..15 of the low half (one bit-field extract) and bits 20..31 of the high
+    // half (one shift).  The opaque copy keeps the compiler from re-deriving
+    // the offsets from `bits` with a shift and a mask each.
     unsigned zk = bits & 0xFFC0FFC0u;
     asm volatile("" : "+v"(zk));
     const unsigned o0 = __builtin_amdgcn_ubfe(zk, 4, 12), o1 = zk >> 20;
     const char *t = reinterpret_cast<const char *>(tab);
     const unsigned e0 = *reinterpret_cast<const unsigned *>(t + o0);
     const unsigned e1 = *reinterpret_cast<const unsigned *>(t + o1);
-    const h2 dz = z - __builtin_bit_cast(h2, zk);
-    // entry = (value, slope): one mixed-precision FMA per half takes value,
-    // slope and offset from their FP16 halves (operand selects), evaluates in
-    // FP32 and writes its half of the result (no byte permutes)
-    const h2 E0 = __builtin_bit_cast(h2, e0), E1 = __builtin_bit_cast(h2, e1);
-    h2 r;
-    r.x = (_Float16)fmaf((float)E0.y, (float)dz.x, (float)E0.x);
-    r.y = (_Float16)fmaf((float)E1.y, (float)dz.y, (float)E1.x);
-    return __builtin_bit_cast(unsigned, r);
+    // (intercept, slope) of the two entries -> (intercept0, intercept1), (slope0, slope1)
+    const h2 I = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x05040100u));
+    const h2 D = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x07060302u));
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_fma(D, z, I));
 }
 
 // four 32-bit words (FP16 pairs) as an MFMA operand fragment
@@ -519,40 +513,67 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             x1[p][6] = one;
             x1[p][7] = one;
         }
+        // Every layer is software-pipelined by one output block: the MFMAs of
+        // block ib are issued before the GELUs of block ib - 1, whose
+        // accumulators they no longer touch, so the matrix unit works on one
+        // block while the vector unit activates the previous one.
+        //
         // layer 1 (bf16 hi/lo MFMA): output block ib = units 16 ib + 4g + t ->
         // item 4 (ib & 1) + t of chunk ib / 2, GELU from the table
         unsigned h1[kRowGroups][4][4];            // FP16 pairs: items 2t, 2t + 1 of chunk c
+        v4f pend[kRowGroups];                     // accumulators awaiting their GELU
 #pragma unroll
-        for (int ib = 0; ib < 8; ++ib) {
-            const v8bf w = w1[(ib * 4 + g) * 16 + r];
+        for (int ib = 0; ib <= 8; ++ib) {
+            v4f acc[kRowGroups];
+            if (ib < 8) {
+                const v8bf w = w1[(ib * 4 + g) * 16 + r];
 #pragma unroll
-            for (int p = 0; p < kRowGroups; ++p) {
-                const v4f acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    w, x1[p], v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-                h1[p][ib >> 1][2 * (ib & 1) + 0] = gelu_pair(acc[0], acc[1], sTab);
-                h1[p][ib >> 1][2 * (ib & 1) + 1] = gelu_pair(acc[2], acc[3], sTab);
+                for (int p = 0; p < kRowGroups; ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        w, x1[p], v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            }
+            if (ib > 0) {
+                const int jb = ib - 1;
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p) {
+                    h1[p][jb >> 1][2 * (jb & 1) + 0] = gelu_pair(pend[p][0], pend[p][1], sTab);
+                    h1[p][jb >> 1][2 * (jb & 1) + 1] = gelu_pair(pend[p][2], pend[p][3], sTab);
+                }
+            }
+            if (ib < 8) {
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p) pend[p] = acc[p];
             }
         }
         // layer 2 (fp16 MFMA, fp32 accumulation from the bias)
         unsigned h2v[kRowGroups][4][4];
 #pragma unroll
-        for (int ib = 0; ib < 8; ++ib) {
-            const float4 b = bb[(16 * ib + 4 * g) >> 2];
+        for (int ib = 0; ib <= 8; ++ib) {
             v4f acc[kRowGroups];
+            if (ib < 8) {
+                const float4 b = bb[(16 * ib + 4 * g) >> 2];
 #pragma unroll
-            for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
+                for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const v8h w = w2[frag_index(ib, c, g, r)];
+                for (int c = 0; c < 4; ++c) {
+                    const v8h w = w2[frag_index(ib, c, g, r)];
 #pragma unroll
-                for (int p = 0; p < kRowGroups; ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h1[p][c]), acc[p],
-                                                                   0, 0, 0);
+                    for (int p = 0; p < kRowGroups; ++p)
+                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h1[p][c]),
+                                                                       acc[p], 0, 0, 0);
+                }
             }
+            if (ib > 0) {
+                const int jb = ib - 1;
 #pragma unroll
-            for (int p = 0; p < kRowGroups; ++p) {
-                h2v[p][ib >> 1][2 * (ib & 1) + 0] = gelu_pair(acc[p][0], acc[p][1], sTab);
-                h2v[p][ib >> 1][2 * (ib & 1) + 1] = gelu_pair(acc[p][2], acc[p][3], sTab);
+                for (int p = 0; p < kRowGroups; ++p) {
+                    h2v[p][jb >> 1][2 * (jb & 1) + 0] = gelu_pair(pend[p][0], pend[p][1], sTab);
+                    h2v[p][jb >> 1][2 * (jb & 1) + 1] = gelu_pair(pend[p][2], pend[p][3], sTab);
+                }
+            }
+            if (ib < 8) {
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p) pend[p] = acc[p];
             }
         }
         // layer 3 and the output unit (FP16 pairs dotted with w4, FP32 sum)
@@ -560,27 +581,36 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
 #pragma unroll
         for (int p = 0; p < kRowGroups; ++p) part[p] = 0.f;
 #pragma unroll
-        for (int ib = 0; ib < 8; ++ib) {
-            const float4 b = bb[H / 4 + ((16 * ib + 4 * g) >> 2)];
-            const f2p wa = __builtin_bit_cast(f2p, w4[(16 * ib + 4 * g) >> 1]);
-            const f2p wb = __builtin_bit_cast(f2p, w4[((16 * ib + 4 * g) >> 1) + 1]);
+        for (int ib = 0; ib <= 8; ++ib) {
             v4f acc[kRowGroups];
+            if (ib < 8) {
+                const float4 b = bb[H / 4 + ((16 * ib + 4 * g) >> 2)];
 #pragma unroll
-            for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
+                for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const v8h w = w3[frag_index(ib, c, g, r)];
+                for (int c = 0; c < 4; ++c) {
+                    const v8h w = w3[frag_index(ib, c, g, r)];
 #pragma unroll
-                for (int p = 0; p < kRowGroups; ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h2v[p][c]), acc[p],
-                                                                   0, 0, 0);
+                    for (int p = 0; p < kRowGroups; ++p)
+                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h2v[p][c]),
+                                                                       acc[p], 0, 0, 0);
+                }
             }
+            if (ib > 0) {
+                const int jb = ib - 1;
+                const f2p wa = __builtin_bit_cast(f2p, w4[(16 * jb + 4 * g) >> 1]);
+                const f2p wb = __builtin_bit_cast(f2p, w4[((16 * jb + 4 * g) >> 1) + 1]);
 #pragma unroll
-            for (int p = 0; p < kRowGroups; ++p) {
-                const unsigned lo = gelu_pair(acc[p][0], acc[p][1], sTab);
-                const unsigned hi = gelu_pair(acc[p][2], acc[p][3], sTab);
-                part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, lo), wa, part[p], false);
-                part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, hi), wb, part[p], false);
+                for (int p = 0; p < kRowGroups; ++p) {
+                    const unsigned lo = gelu_pair(pend[p][0], pend[p][1], sTab);
+                    const unsigned hi = gelu_pair(pend[p][2], pend[p][3], sTab);
+                    part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, lo), wa, part[p], false);
+                    part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, hi), wb, part[p], false);
+                }
+            }
+            if (ib < 8) {
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p) pend[p] = acc[p];
             }
         }
 #pragma unroll
