@@ -440,6 +440,9 @@ int lmmew_plan_rows(lmmew_ctx *ctx, lmmew_plan *plan, int subset, const int64_t 
  * The surrogate models the planar system: EINVAL for a 3-D context (as for
  * lmmew_scatter_labels). */
 int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out);
+/* Releases the network (waits for all work on the device first).  Its
+ * context may have been destroyed before it: lmmew_destroy detaches the
+ * context's networks, which then only accept lmmew_mlp_destroy. */
 int lmmew_mlp_destroy(lmmew_mlp *mlp);
 
 /* Host copies of the FP32 parameters (NULL to skip) and the output shift c0

@@ -134,6 +134,9 @@ struct RowArgs {
     const int2 *slist;       // scatter list entries of the tiles: (point in the angle's
                              // sorted list, row of the point in the g_qs table)
     int ntiles;
+    const int *case_tiles;   // [ncases+1]: the tiles of case c are [case_tiles[c],
+                             // case_tiles[c+1]) (tiles are grouped by case), or NULL
+    int ncases;
     const int *ev_bin;       // sorted rows of this subset: detector bins (NULL for positions)
     const int *ev_binz;      // 3-D: sorted rows: axial bins
     const float *ev_u;       // sorted rows: continuous lateral positions (mm), or NULL (bins)

@@ -464,17 +464,30 @@ __device__ __forceinline__ ScatA load_scat(GPtr<ScatA> p)
 template <int JT, int NW, bool TAB, bool D3>
 __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
 {
-    // Work item p = (pixel block, tile) in block-major order.  Workgroups go to
-    // the 8 XCDs round-robin by id, so XCD k runs ids k, k+8, ...: mapping them
-    // to the k-th contiguous eighth of the items gives every XCD an equal share
-    // made of few pixel blocks, whose table columns then stay in its L2.
+    // Work item p = (case, pixel block, tile of the case): case-major, then
+    // block-major.  Workgroups go to the 8 XCDs round-robin by id, so XCD k
+    // runs ids k, k+8, ...: mapping them to the k-th contiguous eighth of the
+    // items gives every XCD an equal share made of few cases and pixel blocks,
+    // so the tiles an XCD runs at one time read one map's tables for few
+    // pixel blocks, which then stay in its L2.
     const int nb = S.Qp / kWave;
     const int W = nb * r.ntiles;
     const int per = (W + 7) >> 3;
-    const int p = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    int p = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     if (p >= W) return;
-    const int bx = p / r.ntiles;
-    const Tile T = r.tiles[p - bx * r.ntiles];
+    int t0 = 0, nt = r.ntiles;
+    if (r.case_tiles) {
+        int cc = 0;
+        nt = r.case_tiles[1];
+        while (p >= nb * nt) {        // the items of case cc are nb * nt
+            p -= nb * nt;
+            if (++cc >= r.ncases) return;
+            t0 = r.case_tiles[cc];
+            nt = r.case_tiles[cc + 1] - t0;
+        }
+    }
+    const int bx = p / nt;
+    const Tile T = r.tiles[t0 + p - bx * nt];
     const int lane = threadIdx.x;
     const int i = bx * kWave + lane;
     const int a = T.angle;

@@ -51,6 +51,7 @@ struct lmmew_ctx {
     double *d_sczd = nullptr;         // 3-D: [nsc] scatter-point z (double)
     lmmew_mlp *mlp = nullptr;         // scatter surrogate used by OSEM (NULL: exact model)
     float scatter_scale = 1.f;        // factor on the surrogate's density for this map's cases
+    std::vector<lmmew_mlp *> nets;    // networks created on this context (detached when it goes)
     int model_gen = 0;                // bumped whenever the scatter model changes
 };
 
@@ -93,6 +94,7 @@ struct lmmew_plan {
     std::vector<Sub> subs;
     std::vector<int> case_chunk;      // [nsub][ncases+1], chunk index relative to the subset
     std::vector<int> case_rows;       // [nsub][ncases+1], row index relative to the subset
+    std::vector<int> case_tiles;      // [nsub][ncases+1], tile index relative to the subset
     std::vector<Tile> tiles;
     std::vector<int2> slist;          // scatter list entries of all tiles: (point, table row)
     std::vector<Chunk> chunks;
@@ -100,6 +102,7 @@ struct lmmew_plan {
     double terms = 0, full_terms = 0;
     // device
     int *d_bin = nullptr, *d_binz = nullptr, *d_case = nullptr, *d_case_chunk = nullptr;
+    int *d_case_tiles = nullptr;
     float *d_E = nullptr, *d_u = nullptr;
     int64_t *d_perm = nullptr;
     Tile *d_tiles = nullptr;
@@ -262,7 +265,7 @@ void free_plan(lmmew_plan *p)
     p->gexec = nullptr;
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
     p->prof_ev.clear();
-    dfree(p->d_bin); dfree(p->d_binz); dfree(p->d_u); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_E); dfree(p->d_perm);
+    dfree(p->d_bin); dfree(p->d_binz); dfree(p->d_u); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_case_tiles); dfree(p->d_E); dfree(p->d_perm);
     dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_pvt); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
@@ -364,6 +367,7 @@ void build_tiles(lmmew_plan *p)
     p->slist.clear();
     p->chunks.clear();
     p->case_chunk.assign((size_t)p->nsub * (p->ncases + 1), 0);
+    p->case_tiles.assign((size_t)p->nsub * (p->ncases + 1), 0);
     p->max_chunks = 0;
     for (int s = 0; s < p->nsub; ++s) {
         lmmew_plan::Sub &sub = p->subs[s];
@@ -448,16 +452,29 @@ void build_tiles(lmmew_plan *p)
             r = e;
         }
         sub.ntiles = (int)p->tiles.size() - sub.tile0;
-        // costliest tiles first: the launch's last work items are then cheap
-        // ones, which shortens the tail in which CUs run out of work
+        // Each case's tiles together (the per-event kernel walks the work
+        // items case by case, so that the tiles it runs at one time share one
+        // map's tables in the L2), costliest first within a case: the launch's
+        // last work items are then cheap ones, which shortens the tail in
+        // which CUs run out of work.
         std::stable_sort(p->tiles.begin() + sub.tile0, p->tiles.end(),
                          [](const Tile &x, const Tile &y) {
+                             if (x.ncase != y.ncase) return x.ncase < y.ncase;
                              const double cx = (double)(x.k1 - x.k0) * x.cnt *
                                                (1 + 4 * __builtin_popcount(x.lmask));
                              const double cy = (double)(y.k1 - y.k0) * y.cnt *
                                                (1 + 4 * __builtin_popcount(y.lmask));
                              return cx > cy;
                          });
+        {
+            int *ct = &p->case_tiles[(size_t)s * (p->ncases + 1)];
+            int t = 0;
+            for (int c = 0; c < p->ncases; ++c) {
+                ct[c] = t;
+                while (t < sub.ntiles && p->tiles[sub.tile0 + t].ncase == c) ++t;
+            }
+            ct[p->ncases] = t;
+        }
         // chunks: runs of <= kChunkRows rows of one case
         r = sub.row0;
         for (int cs = 0; cs < p->ncases; ++cs) {
@@ -499,12 +516,14 @@ int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
     dfree(p->d_pvt);
     dfree(p->d_chunks);
     dfree(p->d_case_chunk);
+    dfree(p->d_case_tiles);
     dfree(p->d_part);
     dfree(p->d_comp);
     HIPCHK(ctx, dalloc(&p->d_tiles, p->tiles.size()));
     HIPCHK(ctx, dalloc(&p->d_slist, p->slist.size()));
     HIPCHK(ctx, dalloc(&p->d_chunks, p->chunks.size()));
     HIPCHK(ctx, dalloc(&p->d_case_chunk, p->case_chunk.size()));
+    HIPCHK(ctx, dalloc(&p->d_case_tiles, p->case_tiles.size()));
     const size_t total_chunks = std::max<size_t>(p->chunks.size(), 1);
     HIPCHK(ctx, dalloc(&p->d_part, total_chunks * ctx->S.Qp));
     HIPCHK(ctx, dalloc(&p->d_comp, total_chunks * ctx->S.Qp));
@@ -519,6 +538,8 @@ int upload_tiles(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
                                    p->chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(p->d_case_chunk, p->case_chunk.data(),
                                p->case_chunk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_case_tiles, p->case_tiles.data(),
+                               p->case_tiles.size() * sizeof(int), hipMemcpyHostToDevice, st));
     // response factors of the listed (point, event) pairs: JT floats per list entry
     if (!p->slist.empty()) {
         HIPCHK(ctx, dalloc(&p->d_pvt, p->slist.size() * (size_t)p->JT));
@@ -937,6 +958,8 @@ RowArgs row_args(const lmmew_ctx *ctx, const lmmew_plan *p, int s)
     r.tiles = p->d_tiles + sub.tile0;
     r.slist = p->d_slist;
     r.ntiles = sub.ntiles;
+    r.case_tiles = p->d_case_tiles + (size_t)s * (p->ncases + 1);
+    r.ncases = p->ncases;
     r.ev_bin = p->cont ? nullptr : p->d_bin + sub.row0;
     r.ev_u = p->cont ? p->d_u + sub.row0 : nullptr;
     r.ev_binz = p->d_binz ? p->d_binz + sub.row0 : nullptr;
@@ -1398,6 +1421,11 @@ int lmmew_destroy(lmmew_ctx *ctx)
 {
     if (!ctx) return LMMEW_EINVAL;
     (void)hipDeviceSynchronize();
+    // networks of this context may outlive it (their destroy call must then
+    // not touch it): detach them
+    for (lmmew_mlp *m : ctx->nets) m->ctx = nullptr;
+    ctx->nets.clear();
+    ctx->mlp = nullptr;
     free_ctx(ctx);
     delete ctx;
     return LMMEW_OK;
@@ -2111,6 +2139,7 @@ int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
     MCHK(mlp_refresh(m->P, m->W2b, m->W3b, nullptr));
     MCHK(hipStreamSynchronize(nullptr));   // the copies and the refresh ran on the null stream
 #undef MCHK
+    ctx->nets.push_back(m);
     *out = m;
     return LMMEW_OK;
 }
@@ -2119,9 +2148,13 @@ int lmmew_mlp_destroy(lmmew_mlp *m)
 {
     if (!m) return LMMEW_EINVAL;
     (void)hipDeviceSynchronize();
-    if (m->ctx && m->ctx->mlp == m) {
-        m->ctx->mlp = nullptr;
-        m->ctx->model_gen++;
+    if (m->ctx) {
+        std::vector<lmmew_mlp *> &v = m->ctx->nets;
+        v.erase(std::remove(v.begin(), v.end(), m), v.end());
+        if (m->ctx->mlp == m) {
+            m->ctx->mlp = nullptr;
+            m->ctx->model_gen++;
+        }
     }
     free_mlp(m);
     delete m;
@@ -2141,7 +2174,7 @@ int lmmew_mlp_get_params(const lmmew_mlp *m, float *params, double *c0, double *
 
 int lmmew_mlp_set_params(lmmew_mlp *m, const float *params, double c0, double floor_)
 {
-    if (!m || !params) return LMMEW_EINVAL;
+    if (!m || !params || !m->ctx) return LMMEW_EINVAL;   // NULL, or detached from its context
     lmmew_ctx *ctx = m->ctx;
     HIPCHK(ctx, hipMemcpy(m->P, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemset(m->m1, 0, sizeof(float) * kMlpParams));
@@ -2478,7 +2511,7 @@ int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev
 {
     if (!ctx) return LMMEW_EINVAL;
     if (!m || !scale || !ev) return fail(ctx, LMMEW_EINVAL, "NULL argument");
-    if (m->ctx != ctx && !same_system(ctx, m->ctx))
+    if (!m->ctx || (m->ctx != ctx && !same_system(ctx, m->ctx)))
         return fail(ctx, LMMEW_EINVAL, "network of a context with another system or support");
     if (ev->n < 1) return fail(ctx, LMMEW_EINVAL, "no events");
     if (ev->position_mm) return fail(ctx, LMMEW_EINVAL, "the surrogate models binned events");

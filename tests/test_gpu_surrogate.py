@@ -308,5 +308,37 @@ def test_surrogate_region_bias_at_128x128():
     rel = uptakes(lam) / up_ex - 1.0
     print(f"128x128 surrogate region bias: mean {rel.mean():+.4f}, mean |.| "
           f"{np.abs(rel).mean():.4f}, max |.| {np.abs(rel).max():.4f} over {rel.size} regions")
+    ctxs[0].set_scatter_model(None)
     assert abs(rel.mean()) <= 0.01
     assert np.abs(rel).max() < 0.15
+
+
+def test_context_destroyed_before_its_network():
+    """A network may outlive its context (lmmew_mlp_destroy after
+    lmmew_destroy, the order a garbage collector may take): the context
+    detaches its networks, which are then only freed."""
+    import torch
+
+    import paper_2305_17111_amd as lm
+
+    p = synth.CONFIGS["64x64_50k"].params
+    mu, _, _ = synth.phantom(synth.CONFIGS["64x64_50k"])
+    for order in ("ctx_first", "net_first"):
+        ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+        nets = [ctx.mlp(seed=s) for s in (1, 2)]
+        ctx.set_scatter_model(nets[0])
+        if order == "ctx_first":
+            ctx.close()
+            for n in nets:
+                n.close()
+        else:
+            for n in nets:
+                n.close()
+            ctx.close()
+    ctx = lm.Context(p, torch.from_numpy(mu.astype(np.float32)))
+    net = ctx.mlp(seed=3)
+    ctx.set_scatter_model(net)
+    ctx.close()
+    with pytest.raises(Exception):
+        net.set_params(np.zeros(lm.Mlp.NPARAM, np.float32))
+    net.close()
