@@ -135,7 +135,8 @@ struct RowArgs {
                              // sorted list, row of the point in the g_qs table)
     int ntiles;
     const int *case_tiles;   // [ncases+1]: the tiles of case c are [case_tiles[c],
-                             // case_tiles[c+1]) (tiles are grouped by case), or NULL
+                             // case_tiles[c+1]) (tiles are grouped by case): work items
+                             // case-major; or NULL: block-major over all tiles
     int ncases;
     const int *ev_bin;       // sorted rows of this subset: detector bins (NULL for positions)
     const int *ev_binz;      // 3-D: sorted rows: axial bins

@@ -477,14 +477,13 @@ __global__ __launch_bounds__(64) void k_row(const DevSys S, const RowArgs r)
     if (p >= W) return;
     int t0 = 0, nt = r.ntiles;
     if (r.case_tiles) {
-        int cc = 0;
-        nt = r.case_tiles[1];
-        while (p >= nb * nt) {        // the items of case cc are nb * nt
-            p -= nb * nt;
-            if (++cc >= r.ncases) return;
-            t0 = r.case_tiles[cc];
-            nt = r.case_tiles[cc + 1] - t0;
-        }
+        // The items of case c are [nb * case_tiles[c], nb * case_tiles[c+1]),
+        // so item p belongs to the case of tile p / nb (tiles are grouped by
+        // case): three dependent loads, whatever the number of cases.
+        const int c = r.tiles[p / nb].ncase;
+        t0 = r.case_tiles[c];
+        nt = r.case_tiles[c + 1] - t0;
+        p -= nb * t0;
     }
     const int bx = p / nt;
     const Tile T = r.tiles[t0 + p - bx * nt];

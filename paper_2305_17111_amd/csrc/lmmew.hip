@@ -1001,6 +1001,10 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     RowArgs r = row_args(ctx, p, s);
     r.A = out;
     r.mode = surrogate ? 2 : (part == 3 ? 0 : part);
+    // Without scattered paths a tile reads no map's scatter tables; its
+    // pixel block's unscattered tables are shared by every case, so the
+    // block-major order over all tiles keeps those in the L2 instead.
+    if (r.mode == 2) r.case_tiles = nullptr;
     r.pvt = p->d_pvt;
     const bool prof = p->prof && sub.ntiles > 0;
     if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));

@@ -335,7 +335,9 @@ __global__ __launch_bounds__(256) void k_targets(const float *raw, long n, float
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerWG = 32;
 constexpr int kRowGroups = 2;                  // 16-pixel groups per wavefront
-constexpr int kPixPerWG = 4 * 16 * kRowGroups; // 128
+constexpr int kWaves = 4;                      // wavefronts per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kPixPerWG = kWaves * 16 * kRowGroups;
 constexpr int kFrag = 8 * 4 * 4 * 16;          // A fragments per hidden layer: (ib, c, g, r)
 constexpr int kFrag1 = 8 * 4 * 16;             // first layer: (ib, g, r)
 
@@ -383,27 +385,45 @@ __device__ __forceinline__ unsigned gelu_table_entry(int k)
     return __builtin_bit_cast(unsigned, v);
 }
 
-// two FP32 accumulators -> FP16 pair (round toward zero) -> GELU, as the
-// 32-bit encoding of the FP16 pair; tab must sit at LDS address 0 so that an
-// entry's byte offset is just its index times 4
-__device__ __forceinline__ unsigned gelu_pair(float a, float b, const unsigned *tab)
+// GELU of two FP32 accumulators in two steps, so that the table reads can be
+// issued well before their results are used.  gelu_fetch: the FP16 pair
+// (round toward zero) and its two table entries; tab must sit at LDS address 0
+// so that an entry's byte offset is just its index times 4.
+struct GeluFetch {
+    h2 z;
+    unsigned e0, e1;
+};
+
+__device__ __forceinline__ GeluFetch gelu_fetch(float a, float b, const unsigned *tab)
 {
-    const h2 z = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b));
-    const unsigned bits = __builtin_bit_cast(unsigned, z);
+    GeluFetch f;
+    f.z = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b));
     // With the low 6 bits of each half cleared, an entry's byte offset is bits
     // 4..15 of the low half (one bit-field extract) and bits 20..31 of the high
     // half (one shift).  The opaque copy keeps the compiler from re-deriving
-    // the offsets from `bits` with a shift and a mask each.
-    unsigned zk = bits & 0xFFC0FFC0u;
+    // the offsets from the pair with a shift and a mask each.
+    unsigned zk = __builtin_bit_cast(unsigned, f.z) & 0xFFC0FFC0u;
     asm volatile("" : "+v"(zk));
     const unsigned o0 = __builtin_amdgcn_ubfe(zk, 4, 12), o1 = zk >> 20;
     const char *t = reinterpret_cast<const char *>(tab);
-    const unsigned e0 = *reinterpret_cast<const unsigned *>(t + o0);
-    const unsigned e1 = *reinterpret_cast<const unsigned *>(t + o1);
+    f.e0 = *reinterpret_cast<const unsigned *>(t + o0);
+    f.e1 = *reinterpret_cast<const unsigned *>(t + o1);
+    return f;
+}
+
+// gelu_finish: intercept + slope z per half, as the 32-bit encoding of the
+// FP16 pair of GELUs
+__device__ __forceinline__ unsigned gelu_finish(const GeluFetch &f)
+{
     // (intercept, slope) of the two entries -> (intercept0, intercept1), (slope0, slope1)
-    const h2 I = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x05040100u));
-    const h2 D = __builtin_bit_cast(h2, __builtin_amdgcn_perm(e1, e0, 0x07060302u));
-    return __builtin_bit_cast(unsigned, __builtin_elementwise_fma(D, z, I));
+    const h2 I = __builtin_bit_cast(h2, __builtin_amdgcn_perm(f.e1, f.e0, 0x05040100u));
+    const h2 D = __builtin_bit_cast(h2, __builtin_amdgcn_perm(f.e1, f.e0, 0x07060302u));
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_fma(D, f.z, I));
+}
+
+__device__ __forceinline__ unsigned gelu_pair(float a, float b, const unsigned *tab)
+{
+    return gelu_finish(gelu_fetch(a, b, tab));
 }
 
 // four 32-bit words (FP16 pairs) as an MFMA operand fragment
@@ -440,7 +460,7 @@ __device__ __forceinline__ uint4 load_frag1(const float *P, int f)
     return make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
 }
 
-__global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowArgs a)
+__global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const MlpRowArgs a)
 {
     // one LDS buffer (77 KB, two workgroups per CU): the GELU table at address
     // 0, then the weight fragments, biases and output weights
@@ -452,23 +472,23 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
     float4 *const sB = reinterpret_cast<float4 *>(sW3 + kFrag);          // b2, b3
     h2 *const sW4 = reinterpret_cast<h2 *>(sB + 2 * H / 4);              // w4 in fp16 pairs
 
-    for (int f = threadIdx.x; f < kFrag; f += 256) {
+    for (int f = threadIdx.x; f < kFrag; f += kThreads) {
         sW2[f] = load_frag_h(a.P, kOffW2, f);
         sW3[f] = load_frag_h(a.P, kOffW3, f);
     }
-    for (int f = threadIdx.x; f < kFrag1; f += 256) sW1[f] = load_frag1(a.P, f);
-    for (int t = threadIdx.x; t < H / 4; t += 256) {
+    for (int f = threadIdx.x; f < kFrag1; f += kThreads) sW1[f] = load_frag1(a.P, f);
+    for (int t = threadIdx.x; t < H / 4; t += kThreads) {
         sB[t] = reinterpret_cast<const float4 *>(a.P + kOffB2)[t];
         sB[H / 4 + t] = reinterpret_cast<const float4 *>(a.P + kOffB3)[t];
     }
-    for (int t = threadIdx.x; t < H / 2; t += 256) {
+    for (int t = threadIdx.x; t < H / 2; t += kThreads) {
         h2 w;
         w.x = (_Float16)a.P[kOffW4 + 2 * t];
         w.y = (_Float16)a.P[kOffW4 + 2 * t + 1];
         sW4[t] = w;
     }
     const float b4 = a.P[kOffB4];
-    for (int k = threadIdx.x; k < kGeluTab; k += 256) sTab[k] = gelu_table_entry(k);
+    for (int k = threadIdx.x; k < kGeluTab; k += kThreads) sTab[k] = gelu_table_entry(k);
     __syncthreads();
 
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
@@ -516,7 +536,10 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
         // Every layer is software-pipelined by one output block: the MFMAs of
         // block ib are issued before the GELUs of block ib - 1, whose
         // accumulators they no longer touch, so the matrix unit works on one
-        // block while the vector unit activates the previous one.
+        // block while the vector unit activates the previous one.  In the
+        // hidden layers the GELU table reads of block ib - 1 are issued before
+        // block ib's MFMAs and used after them, and the weight fragments and
+        // bias of block ib + 1 are read from LDS while block ib runs.
         //
         // layer 1 (bf16 hi/lo MFMA): output block ib = units 16 ib + 4g + t ->
         // item 4 (ib & 1) + t of chunk ib / 2, GELU from the table
@@ -547,16 +570,35 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
         }
         // layer 2 (fp16 MFMA, fp32 accumulation from the bias)
         unsigned h2v[kRowGroups][4][4];
+        v8h wc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) wc[c] = w2[frag_index(0, c, g, r)];
+        float4 bc = bb[(4 * g) >> 2];
 #pragma unroll
         for (int ib = 0; ib <= 8; ++ib) {
             v4f acc[kRowGroups];
+            GeluFetch gf[kRowGroups][2];
+            v8h wn[4];
+            float4 bn;
+            if (ib + 1 < 8) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wn[c] = w2[frag_index(ib + 1, c, g, r)];
+                bn = bb[(16 * (ib + 1) + 4 * g) >> 2];
+            }
+            if (ib > 0) {
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p) {
+                    gf[p][0] = gelu_fetch(pend[p][0], pend[p][1], sTab);
+                    gf[p][1] = gelu_fetch(pend[p][2], pend[p][3], sTab);
+                }
+            }
             if (ib < 8) {
-                const float4 b = bb[(16 * ib + 4 * g) >> 2];
+                const float4 b = bc;
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const v8h w = w2[frag_index(ib, c, g, r)];
+                    const v8h w = wc[c];
 #pragma unroll
                     for (int p = 0; p < kRowGroups; ++p)
                         acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h1[p][c]),
@@ -567,13 +609,18 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
                 const int jb = ib - 1;
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p) {
-                    h2v[p][jb >> 1][2 * (jb & 1) + 0] = gelu_pair(pend[p][0], pend[p][1], sTab);
-                    h2v[p][jb >> 1][2 * (jb & 1) + 1] = gelu_pair(pend[p][2], pend[p][3], sTab);
+                    h2v[p][jb >> 1][2 * (jb & 1) + 0] = gelu_finish(gf[p][0]);
+                    h2v[p][jb >> 1][2 * (jb & 1) + 1] = gelu_finish(gf[p][1]);
                 }
             }
             if (ib < 8) {
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p) pend[p] = acc[p];
+            }
+            if (ib + 1 < 8) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wc[c] = wn[c];
+                bc = bn;
             }
         }
         // layer 3 and the output unit (FP16 pairs dotted with w4, FP32 sum)
@@ -581,15 +628,33 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
 #pragma unroll
         for (int p = 0; p < kRowGroups; ++p) part[p] = 0.f;
 #pragma unroll
+        for (int c = 0; c < 4; ++c) wc[c] = w3[frag_index(0, c, g, r)];
+        bc = bb[H / 4 + ((4 * g) >> 2)];
+#pragma unroll
         for (int ib = 0; ib <= 8; ++ib) {
             v4f acc[kRowGroups];
+            GeluFetch gf[kRowGroups][2];
+            v8h wn[4];
+            float4 bn;
+            if (ib + 1 < 8) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wn[c] = w3[frag_index(ib + 1, c, g, r)];
+                bn = bb[H / 4 + ((16 * (ib + 1) + 4 * g) >> 2)];
+            }
+            if (ib > 0) {
+#pragma unroll
+                for (int p = 0; p < kRowGroups; ++p) {
+                    gf[p][0] = gelu_fetch(pend[p][0], pend[p][1], sTab);
+                    gf[p][1] = gelu_fetch(pend[p][2], pend[p][3], sTab);
+                }
+            }
             if (ib < 8) {
-                const float4 b = bb[H / 4 + ((16 * ib + 4 * g) >> 2)];
+                const float4 b = bc;
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p) acc[p] = v4f{b.x, b.y, b.z, b.w};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const v8h w = w3[frag_index(ib, c, g, r)];
+                    const v8h w = wc[c];
 #pragma unroll
                     for (int p = 0; p < kRowGroups; ++p)
                         acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, frag_of(h2v[p][c]),
@@ -602,8 +667,8 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
                 const f2p wb = __builtin_bit_cast(f2p, w4[((16 * jb + 4 * g) >> 1) + 1]);
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p) {
-                    const unsigned lo = gelu_pair(pend[p][0], pend[p][1], sTab);
-                    const unsigned hi = gelu_pair(pend[p][2], pend[p][3], sTab);
+                    const unsigned lo = gelu_finish(gf[p][0]);
+                    const unsigned hi = gelu_finish(gf[p][1]);
                     part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, lo), wa, part[p], false);
                     part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, hi), wb, part[p], false);
                 }
@@ -611,6 +676,11 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const DevSys S, const MlpRowAr
             if (ib < 8) {
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p) pend[p] = acc[p];
+            }
+            if (ib + 1 < 8) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wc[c] = wn[c];
+                bc = bn;
             }
         }
 #pragma unroll
@@ -766,7 +836,7 @@ hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
         b.ev_E += r0;
         b.A += (long)r0 * S.Qp;
         hipLaunchKernelGGL(k_mlp_rows, dim3(nblk(S.Qp, kPixPerWG), nblk(b.rows, kRowsPerWG)),
-                           dim3(256), 0, st, S, b);
+                           dim3(kThreads), 0, st, S, b);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
