@@ -72,7 +72,7 @@ def measured_traffic(profile, source):
         return None, f"{profile} missing"
     kv = {}
     for line in open(path):
-        m = re.match(r"^\s*([a-z_]+):\s*(\S+)\s*$", line)
+        m = re.match(r"^\s*([a-z0-9_]+):\s*(\S+)\s*$", line)
         if m:
             kv[m.group(1)] = m.group(2)
     want = _sha256(os.path.join(ROOT, "paper_2305_17111_amd", "csrc", source))
