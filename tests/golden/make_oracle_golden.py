@@ -13,6 +13,7 @@ receives it, and the oracle then works in double precision on those values.
     python tests/golden/make_oracle_golden.py pos64     # continuous positions, sampled rows
     python tests/golden/make_oracle_golden.py small_3d  # 3-D model, 16x16x8
     python tests/golden/make_oracle_golden.py rows64_3d # 3-D model, sampled rows at 64x64x16
+                                                         # (~10 min on 8 cores)
 """
 import hashlib
 import os
@@ -267,9 +268,27 @@ def rows64_3d():
     for k, q in enumerate(pix):
         for a in range(p.na):
             sens[a % nsub, k] += p.T * o.sens_qa(int(q), a)
-    print("rows64_3d rows and sensitivity", time.time() - t, "s")
+    print("rows64_3d p_j and sensitivity", time.time() - t, "s")
+    # the sampled events' whole rows (every voxel), two minutes each: one
+    # process per row, forked after the tables are built (they are shared)
+    global _ROW3
+    _ROW3 = (o, sub)
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(4) as pool:
+        rows = np.stack(pool.map(_row3, range(idx.size)))
+    assert np.allclose(rows @ act32.ravel().astype(np.float64), p_act, rtol=1e-12)
+    print("rows64_3d rows", time.time() - t, "s")
     np.savez_compressed(os.path.join(OUT, "64x64x16_50k_oracle.npz"), digest=digest3(ev), J=J,
-                        idx=idx, p_act=p_act, pix=pix, sens=sens)
+                        idx=idx, p_act=p_act, pix=pix, sens=sens, rows=rows.astype(np.float32))
+
+
+_ROW3 = None
+
+
+def _row3(k):
+    o, sub = _ROW3
+    return o.row(int(sub["bin"][k]), int(sub["bin_z"][k]), int(sub["angle"][k]),
+                 float(sub["energy"][k]))
 
 
 if __name__ == "__main__":
