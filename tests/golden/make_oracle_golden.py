@@ -207,12 +207,15 @@ def pos64():
            "energy": ev["energy"][idx].astype(np.float64)}
     t = time.time()
     p_act = o.forward(sub, act32)
+    rows = np.stack([o.row_pos(sub["position"][j], sub["angle"][j], sub["energy"][j])
+                     for j in range(idx.size)])
+    assert np.allclose(rows @ act32.astype(np.float64), p_act, rtol=1e-12)
     print("pos64 rows", time.time() - t, "s")
     h = hashlib.sha256()
     for k in ("position", "angle", "energy"):
         h.update(np.ascontiguousarray(ev[k]).tobytes())
     np.savez_compressed(os.path.join(OUT, "64x64_50k_pos_oracle.npz"), digest=h.hexdigest(), J=J,
-                        idx=idx, p_act=p_act)
+                        idx=idx, p_act=p_act, rows=rows)
 
 
 def digest3(ev):

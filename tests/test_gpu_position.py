@@ -161,7 +161,7 @@ def test_position_rejections(small_pos):
     assert bool(torch.isfinite(lam).all())
 
 
-def test_64x64_position_sampled_rows_and_conservation_full_size():
+def test_64x64_position_rows_elementwise_and_conservation_full_size():
     import torch
 
     import paper_2305_17111_amd as lm
@@ -180,9 +180,34 @@ def test_64x64_position_sampled_rows_and_conservation_full_size():
     pj = ctx.forward(evd, torch.from_numpy(act.astype(np.float32)).cuda()).cpu().numpy()
     rel = np.abs(pj[g["idx"]] - g["p_act"]) / g["p_act"]
     assert rel.max() < TOL, rel.max()
-    # count conservation of every sub-iteration (holds for any row scale)
+    # whole rows of the sampled events from the plan's sub-iteration launches,
+    # with and without the path table, at every event tile: element by element,
+    # |gpu - oracle| <= 1e-4 |oracle| + 1e-7 max_q oracle on the support (the
+    # density is cut beyond 7 standard deviations, R20/R24), 0 off it
     sens = ctx.sensitivity(w.n_subsets)
     plan = ctx.plan(evd, w.n_subsets)
+    support = synth.fov_support(p).ravel()
+    ref = g["rows"]
+    for table in (False, True):
+        ctx.path_table(table)
+        for jt in (16, 32, 64):
+            plan.set_event_tile(jt)
+            rows = {}
+            for s in range(w.n_subsets):
+                sel = [int(j) for j in g["idx"] if int(ev["angle"][j]) % w.n_subsets == s]
+                if sel:
+                    for j, r in zip(sel, plan.rows(s, sel).cpu().numpy()):
+                        rows[j] = r
+            for k, j in enumerate(g["idx"]):
+                x, r = rows[int(j)].astype(np.float64), ref[k]
+                assert np.all(x[~support] == 0), (table, jt, k)
+                m = np.abs(r[support]).max()
+                err = np.abs(x[support] - r[support])
+                assert np.all(err <= TOL * np.abs(r[support]) + 1e-7 * m), (
+                    table, jt, k, float((err / (np.abs(r[support]) + 1e-7 * m)).max()))
+    ctx.path_table(False)
+    plan.set_event_tile(16)
+    # count conservation of every sub-iteration (holds for any row scale)
     lam = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
     for s in range(w.n_subsets):
         sk, _ = plan.osem_subiter(s, sens, lam, stats=True)
