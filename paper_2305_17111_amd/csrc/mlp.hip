@@ -30,9 +30,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-typedef __fp16 f2p __attribute__((ext_vector_type(2)));
-
-extern "C" __device__ _Float16 __ocml_exp2_f16(_Float16);
 
 constexpr int H = kMlpHidden;
 
@@ -332,6 +329,10 @@ __global__ __launch_bounds__(256) void k_targets(const float *raw, long n, float
 // bf16 high and low parts, x = xh + xl, W = Wh + Wl, and the chunk carries
 // xh.Wh (group 0), xl.Wh (group 1) and xh.Wl (group 2); the dropped xl.Wl is
 // below 2^-16 of each product, so the first layer keeps about FP32 accuracy.
+// The hidden layers run on v_mfma_f32_16x16x32_f16.  The output unit is one
+// FP16 MFMA per completed 32-unit chunk of the last hidden layer, with w4 in
+// row 0 of the A fragment: row 0 of the result is the unit's sum, already in
+// the lanes that write the pixels.
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerWG = 32;
 constexpr int kRowGroups = 2;                  // 16-pixel groups per wavefront
@@ -463,14 +464,14 @@ __device__ __forceinline__ uint4 load_frag1(const float *P, int f)
 __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const MlpRowArgs a)
 {
     // one LDS buffer (77 KB, two workgroups per CU): the GELU table at address
-    // 0, then the weight fragments, biases and output weights
-    __shared__ uint4 lds[kGeluTab / 4 + kFrag1 + 2 * kFrag + 2 * H / 4 + H / 8];
+    // 0, then the weight fragments and biases (the output weights sit in
+    // registers, see w4f)
+    __shared__ uint4 lds[kGeluTab / 4 + kFrag1 + 2 * kFrag + 2 * H / 4];
     unsigned *const sTab = reinterpret_cast<unsigned *>(lds);            // 4 KB
     uint4 *const sW1 = lds + kGeluTab / 4;                               // 8 KB, bf16
     v8h *const sW2 = reinterpret_cast<v8h *>(sW1 + kFrag1);               // 32 KB, fp16
     v8h *const sW3 = sW2 + kFrag;                                        // 32 KB, fp16
     float4 *const sB = reinterpret_cast<float4 *>(sW3 + kFrag);          // b2, b3
-    h2 *const sW4 = reinterpret_cast<h2 *>(sB + 2 * H / 4);              // w4 in fp16 pairs
 
     for (int f = threadIdx.x; f < kFrag; f += kThreads) {
         sW2[f] = load_frag_h(a.P, kOffW2, f);
@@ -480,12 +481,6 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
     for (int t = threadIdx.x; t < H / 4; t += kThreads) {
         sB[t] = reinterpret_cast<const float4 *>(a.P + kOffB2)[t];
         sB[H / 4 + t] = reinterpret_cast<const float4 *>(a.P + kOffB3)[t];
-    }
-    for (int t = threadIdx.x; t < H / 2; t += kThreads) {
-        h2 w;
-        w.x = (_Float16)a.P[kOffW4 + 2 * t];
-        w.y = (_Float16)a.P[kOffW4 + 2 * t + 1];
-        sW4[t] = w;
     }
     const float b4 = a.P[kOffB4];
     for (int k = threadIdx.x; k < kGeluTab; k += kThreads) sTab[k] = gelu_table_entry(k);
@@ -499,6 +494,17 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
         ip[p] = blockIdx.x * kPixPerWG + wv * 16 * kRowGroups + 16 * p + r;
         xy[p] = a.pix_xy[min(ip[p], S.Qp - 1)];
     }
+    // Output unit as MFMA: A fragment of chunk c holds w4 in row 0 (the lanes
+    // with r = 0) and zeros elsewhere, in the item order of the B fragments
+    // (input units 32c + 4g + {0..3}, 32c + 16 + 4g + {0..3}); row 0 of the
+    // result, in the lanes with g = 0, is then the sum over the 128 units.
+    v8h w4f[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            w4f[c][t] = r == 0 ? (_Float16)a.P[kOffW4 + 32 * c + 16 * (t >> 2) + 4 * g + (t & 3)]
+                               : (_Float16)0.f;
     const int e0 = blockIdx.y * kRowsPerWG, e1 = min(e0 + kRowsPerWG, a.rows);
     for (int e = e0; e < e1; ++e) {
         // An opaque zero offset keeps the weight reads inside the row loop:
@@ -506,7 +512,6 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
         int off = 0;
         asm volatile("" : "+v"(off));
         const float4 *bb = sB + off;
-        const h2 *w4 = sW4 + off;
         const v8bf *w1 = reinterpret_cast<const v8bf *>(sW1) + off;
         const v8h *w2 = sW2 + off;
         const v8h *w3 = sW3 + off;
@@ -623,10 +628,11 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
                 bc = bn;
             }
         }
-        // layer 3 and the output unit (FP16 pairs dotted with w4, FP32 sum)
-        float part[kRowGroups];
+        // layer 3 and the output unit (an MFMA per completed 32-unit chunk)
+        v4f yacc[kRowGroups];
+        unsigned h3[kRowGroups][4];               // the chunk being completed
 #pragma unroll
-        for (int p = 0; p < kRowGroups; ++p) part[p] = 0.f;
+        for (int p = 0; p < kRowGroups; ++p) yacc[p] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < 4; ++c) wc[c] = w3[frag_index(0, c, g, r)];
         bc = bb[H / 4 + ((4 * g) >> 2)];
@@ -663,14 +669,17 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
             }
             if (ib > 0) {
                 const int jb = ib - 1;
-                const f2p wa = __builtin_bit_cast(f2p, w4[(16 * jb + 4 * g) >> 1]);
-                const f2p wb = __builtin_bit_cast(f2p, w4[((16 * jb + 4 * g) >> 1) + 1]);
 #pragma unroll
                 for (int p = 0; p < kRowGroups; ++p) {
-                    const unsigned lo = gelu_finish(gf[p][0]);
-                    const unsigned hi = gelu_finish(gf[p][1]);
-                    part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, lo), wa, part[p], false);
-                    part[p] = __builtin_amdgcn_fdot2(__builtin_bit_cast(f2p, hi), wb, part[p], false);
+                    h3[p][2 * (jb & 1) + 0] = gelu_finish(gf[p][0]);
+                    h3[p][2 * (jb & 1) + 1] = gelu_finish(gf[p][1]);
+                }
+                if (jb & 1) {
+#pragma unroll
+                    for (int p = 0; p < kRowGroups; ++p)
+                        yacc[p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4f[jb >> 1],
+                                                                        frag_of(h3[p]), yacc[p],
+                                                                        0, 0, 0);
                 }
             }
             if (ib < 8) {
@@ -685,9 +694,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
         }
 #pragma unroll
         for (int p = 0; p < kRowGroups; ++p) {
-            float y = part[p];
-            y += __shfl_xor(y, 16, 64);
-            y += __shfl_xor(y, 32, 64);
+            const float y = yacc[p][0];
             if (g == 0 && ip[p] < S.Qm) {
                 const float v = fmaxf(__expf(y + b4 + a.c0) - a.floor_, 0.f);
                 a.A[(long)e * S.Qp + ip[p]] += v * sc;
