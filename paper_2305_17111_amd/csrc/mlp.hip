@@ -433,6 +433,15 @@ __device__ __forceinline__ v8h frag_of(const unsigned *w)
     return __builtin_bit_cast(v8h, make_uint4(w[0], w[1], w[2], w[3]));
 }
 
+// two FP32 values rounded to BF16 (nearest even) as one 32-bit pair, a in
+// the low half
+__device__ __forceinline__ unsigned bf16_pair(float a, float b)
+{
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f2v){a, b}, b2v));
+}
+
 __device__ __forceinline__ unsigned pack2(unsigned short a, unsigned short b)
 {
     return (unsigned)a | ((unsigned)b << 16);
@@ -487,6 +496,10 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
     __syncthreads();
 
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    // first-layer input split per lane group (see the B fragments below)
+    const float keep = g == 3 ? 0.f : 1.f;
+    const float lo_sign = g == 1 ? -1.f : 0.f;
+    const unsigned ones = g == 0 ? bf16_pair(1.f, 1.f) : 0u;
     int ip[kRowGroups];
     float2 xy[kRowGroups];
 #pragma unroll
@@ -522,21 +535,25 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
         const float sc = a.case_scale ? a.case_scale[a.ev_case[e]] : 1.f;
 
         // first-layer B fragments: group 0 (xh, 1, 1), group 1 (xl, 0, 0),
-        // group 2 (xh, 0, 0), group 3 zero
+        // group 2 (xh, 0, 0), group 3 zero.  With x scaled by keep (0 in
+        // group 3), a lane rounds x + lo_sign * xh to BF16: xh in groups 0 and
+        // 2, xl = x - xh (exact in FP32) in group 1; two inputs per conversion.
         v8bf x1[kRowGroups];
 #pragma unroll
         for (int p = 0; p < kRowGroups; ++p) {
             float f[kMlpIn];
             pair_features(S, xy[p], bin, dir, E, f);
+            unsigned wd[4];
 #pragma unroll
-            for (int d = 0; d < kMlpIn; ++d) {
-                const __bf16 hi = (__bf16)f[d];
-                const __bf16 lo = (__bf16)(f[d] - (float)hi);
-                x1[p][d] = g == 1 ? lo : (g == 3 ? (__bf16)0.f : hi);
+            for (int d = 0; d < kMlpIn; d += 2) {
+                const float x0 = f[d] * keep, x1v = f[d + 1] * keep;
+                const unsigned hp = bf16_pair(x0, x1v);
+                const float h0 = __builtin_bit_cast(float, hp << 16);
+                const float h1 = __builtin_bit_cast(float, hp & 0xFFFF0000u);
+                wd[d >> 1] = bf16_pair(fmaf(h0, lo_sign, x0), fmaf(h1, lo_sign, x1v));
             }
-            const __bf16 one = g == 0 ? (__bf16)1.f : (__bf16)0.f;
-            x1[p][6] = one;
-            x1[p][7] = one;
+            wd[3] = ones;
+            x1[p] = __builtin_bit_cast(v8bf, make_uint4(wd[0], wd[1], wd[2], wd[3]));
         }
         // Every layer is software-pipelined by one output block: the MFMAs of
         // block ib are issued before the GELUs of block ib - 1, whose
