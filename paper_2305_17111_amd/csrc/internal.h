@@ -249,7 +249,7 @@ struct MlpWork {             // activations of one training batch
     float *part, *split;               // reduction partials: [M/256][8][128], [64][128][128]
     double *dsum;
     unsigned short *H1b, *H2b, *dZb;
-    const unsigned short *W2b, *W3b;   // bf16 [in][out]
+    const unsigned short *W2b, *W3b;   // bf16 [in][out], then the transpose [out][in]
 };
 struct MlpRowArgs {
     const float2 *pix_xy, *dirs;
@@ -262,8 +262,6 @@ struct MlpRowArgs {
     const int *ev_case;                // rows' cases (with case_scale), or NULL
     const float *case_scale;           // [cases] factor on the density, or NULL (1)
 };
-hipError_t mlp_gemm(const unsigned short *A, long sai, long sak, const unsigned short *B, long sbk,
-                    long sbj, float *C, long ldc, int M, int N, int K, hipStream_t st);
 hipError_t mlp_forward_batch(const MlpWork &w, const float *P, const float *feats, const int *idx,
                              int M, const float *tgt, hipStream_t st);
 hipError_t mlp_backward_batch(const MlpWork &w, const float *P, int M, float *G, hipStream_t st);

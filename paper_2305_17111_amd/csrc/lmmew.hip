@@ -58,7 +58,8 @@ struct lmmew_ctx {
 struct lmmew_mlp {
     lmmew_ctx *ctx = nullptr;
     float *P = nullptr, *G = nullptr, *m1 = nullptr, *m2 = nullptr;   // [kMlpParams]
-    unsigned short *W2b = nullptr, *W3b = nullptr;   // bf16 copies [in][out] for training
+    unsigned short *W2b = nullptr, *W3b = nullptr;   // bf16 copies for training: [in][out],
+                                                     // then the transpose [out][in]
     double c0 = 0.0, floor_ = 0.0;    // target = log(density + floor) - c0
     int step = 0;                     // Adam step count
     // training workspace for batches of up to cap samples
@@ -2123,8 +2124,8 @@ int lmmew_mlp_create(lmmew_ctx *ctx, uint64_t seed, lmmew_mlp **out)
     MCHK(dalloc(&m->G, kMlpParams));
     MCHK(dalloc(&m->m1, kMlpParams));
     MCHK(dalloc(&m->m2, kMlpParams));
-    MCHK(dalloc(&m->W2b, kMlpHidden * kMlpHidden));
-    MCHK(dalloc(&m->W3b, kMlpHidden * kMlpHidden));
+    MCHK(dalloc(&m->W2b, 2 * kMlpHidden * kMlpHidden));
+    MCHK(dalloc(&m->W3b, 2 * kMlpHidden * kMlpHidden));
     MCHK(dalloc(&m->dloss, 1));
     // Glorot-uniform weights, zero biases, from a counter-based generator
     std::vector<float> P(kMlpParams, 0.f);

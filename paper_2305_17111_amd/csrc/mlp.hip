@@ -25,7 +25,6 @@
 
 namespace lmmew {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
@@ -65,33 +64,112 @@ __device__ __forceinline__ float gelu_prime(float z)
 }
 
 // ---------------------------------------------------------------------------
-// generic GEMM: C[i][j] = sum_k A(i,k) B(k,j), A(i,k) = A[i*sai + k*sak],
-// B(k,j) = B[k*sbk + j*sbj] (bf16), C fp32 with row stride ldc.
-// One wavefront per 16x16 output tile; M, N, K multiples of 16.
+// training GEMMs on v_mfma_f32_16x16x32_bf16 (bf16 operands, FP32 results)
+//
+// Operand fragments: lane (g, r) of a wavefront supplies row r of A and
+// column r of B at the contraction indices 32 kc + 8 g + {0..7} of chunk kc,
+// 16 contiguous bytes when the contraction index is the fastest one; lane
+// (g, r) receives D[4 g + t][r], t = 0..3.
 // ---------------------------------------------------------------------------
-// With gridDim.z > 1 the K range is split: slice z covers [z*K/Z, (z+1)*K/Z)
-// and writes C + z * cstride (partials summed afterwards in slice order).
-__global__ __launch_bounds__(64) void k_gemm(const unsigned short *A, long sai, long sak,
-                                             const unsigned short *B, long sbk, long sbj,
-                                             float *C, long ldc, int K, long cstride)
+constexpr int kPitch = H + 8;          // LDS row pitch in bf16 (272 B): the 16-byte
+                                       // reads of a wavefront's 16 rows spread over the banks
+
+// C[m][j] = sum_k A[m][k] Bt[j][k] for m < M, j, k < 128 (A, Bt row-major with
+// rows of 128; C row stride ldc).  Workgroup: 4 wavefronts x 16 rows; Bt is
+// staged in LDS once per workgroup, each wavefront keeps its rows' A
+// fragments in registers and runs 8 column tiles x 4 chunks of MFMAs.
+constexpr int kNtRows = 64;
+__global__ __launch_bounds__(256) void k_gemm_nt(const unsigned short *A,
+                                                 const unsigned short *Bt, float *C, long ldc,
+                                                 int M)
 {
-    const int l = threadIdx.x, r = l & 15, g = l >> 4;
-    const long i0 = (long)blockIdx.y * 16, j0 = (long)blockIdx.x * 16;
-    const int kz = K / gridDim.z;
-    C += blockIdx.z * cstride;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = blockIdx.z * kz; k0 < (int)(blockIdx.z + 1) * kz; k0 += 16) {
-        v4s a, b;
+    __shared__ uint4 sB[H * kPitch / 8];                           // 34 KB
+    for (int c = threadIdx.x; c < H * (H / 8); c += 256)
+        sB[(c >> 4) * (kPitch / 8) + (c & 15)] = reinterpret_cast<const uint4 *>(Bt)[c];
+    __syncthreads();
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    const long m0 = (long)blockIdx.x * kNtRows + 16 * w;
+    if (m0 >= M) return;                                           // M is a multiple of 16
+    const uint4 *arow = reinterpret_cast<const uint4 *>(A + (m0 + r) * H);
+    v8bf a[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const long k = k0 + 4 * g + t;
-            a[t] = (short)A[(i0 + r) * sai + k * sak];
-            b[t] = (short)B[k * sbk + (j0 + r) * sbj];
+    for (int kc = 0; kc < 4; ++kc) a[kc] = __builtin_bit_cast(v8bf, arow[4 * kc + g]);
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            const v8bf b = __builtin_bit_cast(v8bf, sB[(16 * jt + r) * (kPitch / 8) + 4 * kc + g]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc], b, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) C[(i0 + 4 * g + t) * ldc + j0 + r] = acc[t];
+        for (int t = 0; t < 4; ++t) C[(m0 + 4 * g + t) * ldc + 16 * jt + r] = acc[t];
+    }
+}
+
+// Weight gradient with the batch as the contraction: part[z][i][o] = sum over
+// the samples m of slice z of X[m][i] D[m][o] (X, D row-major [M][128]).
+// Workgroup z runs its slice in blocks of 128 samples: each block is staged in
+// LDS transposed ([unit][sample], zero past M), then wavefront w accumulates
+// the 2 x 8 output tiles of rows 32 w .. 32 w + 31 in registers.
+constexpr int kWgBlock = 128;
+__global__ __launch_bounds__(256) void k_gemm_wgrad(const unsigned short *X,
+                                                    const unsigned short *D, int M, int per,
+                                                    float *part)
+{
+    __shared__ unsigned short sX[H * kPitch], sD[H * kPitch];     // 2 x 34 KB
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    v4f acc[2][8];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot) acc[u][ot] = v4f{0.f, 0.f, 0.f, 0.f};
+    const long z0 = (long)blockIdx.x * per;
+    for (int b0 = 0; b0 < per; b0 += kWgBlock) {
+        for (int c = threadIdx.x; c < kWgBlock * (H / 8); c += 256) {
+            const int m = c >> 4, u0 = (c & 15) * 8;
+            const long row = z0 + b0 + m;
+            uint4 vx = make_uint4(0u, 0u, 0u, 0u), vd = vx;
+            if (row < M) {
+                vx = reinterpret_cast<const uint4 *>(X + row * H)[c & 15];
+                vd = reinterpret_cast<const uint4 *>(D + row * H)[c & 15];
+            }
+            const unsigned px[4] = {vx.x, vx.y, vx.z, vx.w}, pd[4] = {vd.x, vd.y, vd.z, vd.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sX[(u0 + 2 * q) * kPitch + m] = (unsigned short)(px[q] & 0xFFFFu);
+                sX[(u0 + 2 * q + 1) * kPitch + m] = (unsigned short)(px[q] >> 16);
+                sD[(u0 + 2 * q) * kPitch + m] = (unsigned short)(pd[q] & 0xFFFFu);
+                sD[(u0 + 2 * q + 1) * kPitch + m] = (unsigned short)(pd[q] >> 16);
+            }
+        }
+        __syncthreads();
+        const uint4 *qx = reinterpret_cast<const uint4 *>(sX);
+        const uint4 *qd = reinterpret_cast<const uint4 *>(sD);
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            v8bf a[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                a[u] = __builtin_bit_cast(v8bf, qx[(16 * (2 * w + u) + r) * (kPitch / 8) + 4 * kc + g]);
+#pragma unroll
+            for (int ot = 0; ot < 8; ++ot) {
+                const v8bf b = __builtin_bit_cast(v8bf, qd[(16 * ot + r) * (kPitch / 8) + 4 * kc + g]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[u][ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b, acc[u][ot], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    float *out = part + (size_t)blockIdx.x * H * H;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                out[(16 * (2 * w + u) + 4 * g + t) * H + 16 * ot + r] = acc[u][ot][t];
 }
 
 // ---------------------------------------------------------------------------
@@ -253,13 +331,18 @@ __global__ __launch_bounds__(256) void k_adam(float *P, const float *G, float *m
 }
 
 // bf16 copies of W2, W3, row-major [in][out], for the training GEMMs
+// bf16 copies of W2 and W3 for training: [in][out], then the transpose [out][in]
 __global__ __launch_bounds__(256) void k_refresh_bf16(const float *P, unsigned short *W2b,
                                                       unsigned short *W3b)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= H * H) return;
-    W2b[t] = f2bf(P[kOffW2 + t]);
-    W3b[t] = f2bf(P[kOffW3 + t]);
+    const int i = t / H, o = t % H;
+    const unsigned short w2 = f2bf(P[kOffW2 + t]), w3 = f2bf(P[kOffW3 + t]);
+    W2b[t] = w2;
+    W3b[t] = w3;
+    W2b[H * H + o * H + i] = w2;
+    W3b[H * H + o * H + i] = w3;
 }
 
 // ---------------------------------------------------------------------------
@@ -725,23 +808,23 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const DevSys S, const Mlp
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t mlp_gemm(const unsigned short *A, long sai, long sak, const unsigned short *B, long sbk,
-                    long sbj, float *C, long ldc, int M, int N, int K, hipStream_t st)
+// C[m][j] = sum_k A[m][k] Bt[j][k], M rows (a multiple of 16)
+static hipError_t mlp_gemm_nt(const unsigned short *A, const unsigned short *Bt, float *C, int M,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gemm, dim3(N / 16, M / 16, 1), dim3(64), 0, st, A, sai, sak, B, sbk, sbj,
-                       C, ldc, K, 0L);
+    hipLaunchKernelGGL(k_gemm_nt, dim3(nblk(M, kNtRows)), dim3(256), 0, st, A, Bt, C, (long)H, M);
     return hipGetLastError();
 }
 
-// weight gradient [128][128] with the batch dimension as K: split-K over up to
-// 64 slices of >= 256 samples, then an ordered sum of the slices
-static hipError_t mlp_gemm_wgrad(const unsigned short *A, const unsigned short *B, int M, float *out,
+// weight gradient [128][128] with the batch dimension as the contraction: at
+// most 64 slices of whole 128-sample blocks, then an ordered sum of the slices
+static hipError_t mlp_gemm_wgrad(const unsigned short *X, const unsigned short *D, int M, float *out,
                                  float *scratch, hipStream_t st)
 {
-    int nz = 1;
-    while (nz < 64 && M % (nz * 2 * 16) == 0 && M / (nz * 2) >= 256) nz *= 2;
-    hipLaunchKernelGGL(k_gemm, dim3(H / 16, H / 16, nz), dim3(64), 0, st, A, 1L, (long)H, B,
-                       (long)H, 1L, scratch, (long)H, M, (long)H * H);
+    const int blocks = (M + kWgBlock - 1) / kWgBlock;
+    const int per = ((blocks + 63) / 64) * kWgBlock;               // samples per slice
+    const int nz = (M + per - 1) / per;
+    hipLaunchKernelGGL(k_gemm_wgrad, dim3(nz), dim3(256), 0, st, X, D, M, per, scratch);
     hipLaunchKernelGGL(k_split_sum, dim3(H * H / 256), dim3(256), 0, st, scratch, nz, out);
     return hipGetLastError();
 }
@@ -762,11 +845,11 @@ hipError_t mlp_forward_batch(const MlpWork &w, const float *P, const float *feat
     const long n = (long)M * H;
     hipLaunchKernelGGL(k_mlp_l1, dim3(nblk(n, 256)), dim3(256), 0, st, feats, idx, M, P, w.X,
                        w.Z1, w.H1b);
-    hipError_t e = mlp_gemm(w.H1b, H, 1, w.W2b, H, 1, w.Z2, H, M, H, H, st);
+    hipError_t e = mlp_gemm_nt(w.H1b, w.W2b + H * H, w.Z2, M, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bias_gelu, dim3(nblk(n, 256)), dim3(256), 0, st, w.Z2, P + kOffB2, n,
                        w.H2b, (float *)nullptr);
-    e = mlp_gemm(w.H2b, H, 1, w.W3b, H, 1, w.Z3, H, M, H, H, st);
+    e = mlp_gemm_nt(w.H2b, w.W3b + H * H, w.Z3, M, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bias_gelu, dim3(nblk(n, 256)), dim3(256), 0, st, w.Z3, P + kOffB3, n,
                        (unsigned short *)nullptr, w.H3);
@@ -790,7 +873,7 @@ hipError_t mlp_backward_batch(const MlpWork &w, const float *P, int M, float *G,
     if (e != hipSuccess) return e;
     e = mlp_colsums(w.dZ, nullptr, nullptr, M, w.part, G + kOffB3, nullptr, nullptr, st);
     if (e != hipSuccess) return e;
-    e = mlp_gemm(w.dZb, H, 1, w.W3b, 1, H, w.dH, H, M, H, H, st);
+    e = mlp_gemm_nt(w.dZb, w.W3b, w.dH, M, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gelu_back, dim3(nblk(n, 256)), dim3(256), 0, st, w.dH, w.Z2, n, w.dZ,
                        w.dZb);
@@ -799,7 +882,7 @@ hipError_t mlp_backward_batch(const MlpWork &w, const float *P, int M, float *G,
     if (e != hipSuccess) return e;
     e = mlp_colsums(w.dZ, nullptr, nullptr, M, w.part, G + kOffB2, nullptr, nullptr, st);
     if (e != hipSuccess) return e;
-    e = mlp_gemm(w.dZb, H, 1, w.W2b, 1, H, w.dH, H, M, H, H, st);
+    e = mlp_gemm_nt(w.dZb, w.W2b, w.dH, M, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gelu_back, dim3(nblk(n, 256)), dim3(256), 0, st, w.dH, w.Z1, n, w.dZ,
                        (unsigned short *)nullptr);
