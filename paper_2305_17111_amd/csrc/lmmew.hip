@@ -2247,47 +2247,68 @@ int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const floa
     int rc = mlp_workspace(ctx, m, batch);
     if (rc != LMMEW_OK) return rc;
     const int64_t nb = n / batch;
-    int *d_perm = nullptr;
+    // Two permutation buffers on each side: the host shuffles epoch ep + 1's
+    // order while the device still runs epoch ep (before refilling a host
+    // buffer it waits only for the copy made from it two epochs earlier), and
+    // the batch losses of every epoch are read back once at the end.
+    int *d_perm[2] = {nullptr, nullptr};
     double *d_losses = nullptr;
-    HIPCHK(ctx, dalloc(&d_perm, n));
-    if (dalloc(&d_losses, nb) != hipSuccess) {
-        dfree(d_perm);
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    auto release = [&]() {
+        dfree(d_perm[0]);
+        dfree(d_perm[1]);
+        dfree(d_losses);
+        for (hipEvent_t &v : copied)
+            if (v) (void)hipEventDestroy(v);
+    };
+    if (dalloc(&d_perm[0], n) != hipSuccess || dalloc(&d_perm[1], n) != hipSuccess ||
+        dalloc(&d_losses, (size_t)std::max(epochs, 1) * nb) != hipSuccess ||
+        hipEventCreateWithFlags(&copied[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&copied[1], hipEventDisableTiming) != hipSuccess) {
+        release();
         return fail(ctx, LMMEW_ENOMEM, "training buffers");
     }
-    std::vector<int> perm(n);
-    std::vector<double> losses(nb);
+    std::vector<int> perm[2] = {std::vector<int>(n), std::vector<int>(n)};
     uint64_t rs = seed;
     const MlpWork w = mlp_work(m);
     hipError_t e = hipSuccess;
     for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
-        for (int64_t t = 0; t < n; ++t) perm[t] = (int)t;
+        const int k = ep & 1;
+        if (ep >= 2) e = hipEventSynchronize(copied[k]);       // epoch ep - 2's copy is done
+        std::vector<int> &pv = perm[k];
+        for (int64_t t = 0; t < n; ++t) pv[t] = (int)t;
         for (int64_t t = n - 1; t > 0; --t) {          // Fisher-Yates
             const int64_t j = (int64_t)(splitmix64(rs) % (uint64_t)(t + 1));
-            std::swap(perm[t], perm[j]);
+            std::swap(pv[t], pv[j]);
         }
-        e = hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_perm[k], pv.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(copied[k], st);
         for (int64_t b = 0; b < nb && e == hipSuccess; ++b) {
-            const int *idx = d_perm + b * batch;
+            const int *idx = d_perm[k] + b * batch;
             e = mlp_forward_batch(w, m->P, feats, idx, batch, target, st);
             if (e == hipSuccess) e = mlp_backward_batch(w, m->P, batch, m->G, st);
-            if (e == hipSuccess) e = mlp_loss(w, batch, d_losses + b, st);
+            if (e == hipSuccess) e = mlp_loss(w, batch, d_losses + (size_t)ep * nb + b, st);
             // cosine decay of the step size from lr to lr/10 over the run
             const double prog = (double)(ep * nb + b) / std::max<double>(1.0, (double)epochs * nb);
             lr = lr0 * (0.1 + 0.9 * 0.5 * (1.0 + std::cos(kPi * prog)));
             if (e == hipSuccess) e = mlp_adam(m->P, m->G, m->m1, m->m2, (float)lr, ++m->step, st);
             if (e == hipSuccess) e = mlp_refresh(m->P, m->W2b, m->W3b, st);
         }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(losses.data(), d_losses, sizeof(double) * nb, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e == hipSuccess && epoch_loss) {
+    }
+    std::vector<double> losses((size_t)epochs * nb);
+    if (e == hipSuccess && epochs > 0)
+        e = hipMemcpyAsync(losses.data(), d_losses, sizeof(double) * losses.size(),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && epoch_loss) {
+        for (int ep = 0; ep < epochs; ++ep) {
             double sum = 0.0;
-            for (double v : losses) sum += v;
+            for (int64_t b = 0; b < nb; ++b) sum += losses[(size_t)ep * nb + b];
             epoch_loss[ep] = sum / ((double)nb * batch);
         }
     }
-    dfree(d_perm);
-    dfree(d_losses);
+    release();
     if (e != hipSuccess) return hipfail(ctx, e, "training");
     ctx->model_gen++;
     return LMMEW_OK;
