@@ -255,7 +255,8 @@ def headline(args, sections, out):
         "dtype": "f32",
         "data": "synthetic (seeded phantoms and generic list-mode events; random-init "
                 "surrogate trained on the exact model's labels)",
-        "config": {"workload": desc, "model": "exact", "events": J, "patients": w.n_cases,
+        "system_model": "exact (the surrogate's figures are under \"surrogate\")",
+        "config": {"workload": desc, "events": J, "patients": w.n_cases,
                    "subsets": w.n_subsets, "iterations_per_step": 1, "event_tile": jt,
                    "pixels_in_support": Qm},
         "roofline": {
