@@ -256,15 +256,22 @@ __global__ __launch_bounds__(128) void k_colsum_part(const float *a, const float
                                                      const float *X, int M, float *part)
 {
     const int u = threadIdx.x;
-    const int m0 = blockIdx.x * kRedRows, m1 = min(m0 + kRedRows, M);
+    const int m0 = blockIdx.x * kRedRows, n = min(kRedRows, M - m0);
+    // the chunk's column is read first (all loads in flight together), then
+    // summed row by row in order
+    float v[kRedRows];
+#pragma unroll
+    for (int i = 0; i < kRedRows; ++i) v[i] = i < n ? a[(long)(m0 + i) * H + u] : 0.f;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int m = m0; m < m1; ++m) {
-        const float v = a[(long)m * H + u];
-        acc[0] += v;
-        if (s) acc[1] = fmaf(v, s[m], acc[1]);
+#pragma unroll
+    for (int i = 0; i < kRedRows; ++i) {
+        if (i >= n) break;
+        acc[0] += v[i];
+        if (s) acc[1] = fmaf(v[i], s[m0 + i], acc[1]);
         if (X) {
 #pragma unroll
-            for (int d = 0; d < kMlpIn; ++d) acc[2 + d] = fmaf(X[(long)m * kMlpIn + d], v, acc[2 + d]);
+            for (int d = 0; d < kMlpIn; ++d)
+                acc[2 + d] = fmaf(X[(long)(m0 + i) * kMlpIn + d], v[i], acc[2 + d]);
         }
     }
 #pragma unroll
@@ -296,7 +303,15 @@ __global__ __launch_bounds__(256) void k_split_sum(const float *part, int nz, fl
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= H * H) return;
     float acc = 0.f;
-    for (int z = 0; z < nz; ++z) acc += part[(long)z * H * H + t];
+    int z = 0;
+    for (; z + 8 <= nz; z += 8) {                       // eight loads in flight, then in order
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[(long)(z + q) * H * H + t];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q];
+    }
+    for (; z < nz; ++z) acc += part[(long)z * H * H + t];
     out[t] = acc;
 }
 
@@ -304,7 +319,15 @@ __global__ __launch_bounds__(256) void k_sum(const float *v, int n, double *out)
 {
     __shared__ double red[256];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
+    int i = threadIdx.x;
+    for (; i + 7 * 256 < n; i += 8 * 256) {              // eight loads in flight, then in order
+        float x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = v[i + q * 256];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += x[q];
+    }
+    for (; i < n; i += 256) acc += v[i];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
