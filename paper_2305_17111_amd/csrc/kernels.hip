@@ -1004,39 +1004,62 @@ __device__ __forceinline__ void neumaier(float &sum, float &cmp, float v)
 // ahead; the four compensated partials are combined in a fixed order.
 __global__ __launch_bounds__(256) void k_back(const DevSys S, const BackArgs b)
 {
-    __shared__ float ps[4][kWave], pc[4][kWave];
+    // Four consecutive pixels per lane (16-byte row loads), 256 per
+    // workgroup; each pixel's rows are summed in the same order as with one
+    // pixel per lane: wave wv takes rows r0 + wv, r0 + wv + 4, ... and the
+    // four partials are combined in wave order.
+    __shared__ float4 ps[4][kWave], pc[4][kWave];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int i = blockIdx.x * kWave + lane;
+    const int i = (blockIdx.x * kWave + lane) * 4;
+    const bool act = i < S.Qp;                 // Qp is a multiple of 64, not of 256
     const Chunk ch = b.chunks[blockIdx.y];
-    float sum = 0.f, cmp = 0.f;
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f), cmp = sum;
+    auto add = [&](const float4 &v, float w) {
+        neumaier(sum.x, cmp.x, v.x * w);
+        neumaier(sum.y, cmp.y, v.y * w);
+        neumaier(sum.z, cmp.z, v.z * w);
+        neumaier(sum.w, cmp.w, v.w * w);
+    };
+    auto row = [&](int e) {
+        return act ? *reinterpret_cast<const float4 *>(b.A + (size_t)e * S.Qp + i)
+                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
     int e = ch.r0 + wv;
     for (; e + 12 < ch.r1; e += 16) {
-        float v[4], w[4];
+        float4 v[4];
+        float w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             w[k] = b.wt[e + 4 * k];
-            v[k] = b.A[(size_t)(e + 4 * k) * S.Qp + i];
+            v[k] = row(e + 4 * k);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (w[k] != 0.f) neumaier(sum, cmp, v[k] * w[k]);
+            if (w[k] != 0.f) add(v[k], w[k]);
     }
     for (; e < ch.r1; e += 4) {
         const float w = b.wt[e];
-        if (w != 0.f) neumaier(sum, cmp, b.A[(size_t)e * S.Qp + i] * w);
+        if (w != 0.f) add(row(e), w);
     }
     ps[wv][lane] = sum;
     pc[wv][lane] = cmp;
     __syncthreads();
-    if (wv == 0) {
-        float s0 = ps[0][lane], c0 = pc[0][lane];
+    if (wv == 0 && act) {
+        float4 s0 = ps[0][lane], c0 = pc[0][lane];
 #pragma unroll
         for (int k = 1; k < 4; ++k) {
-            neumaier(s0, c0, ps[k][lane]);
-            c0 += pc[k][lane];
+            const float4 s1 = ps[k][lane], c1 = pc[k][lane];
+            neumaier(s0.x, c0.x, s1.x);
+            neumaier(s0.y, c0.y, s1.y);
+            neumaier(s0.z, c0.z, s1.z);
+            neumaier(s0.w, c0.w, s1.w);
+            c0.x += c1.x;
+            c0.y += c1.y;
+            c0.z += c1.z;
+            c0.w += c1.w;
         }
-        b.part[(size_t)blockIdx.y * S.Qp + i] = s0;
-        b.comp[(size_t)blockIdx.y * S.Qp + i] = c0;
+        *reinterpret_cast<float4 *>(b.part + (size_t)blockIdx.y * S.Qp + i) = s0;
+        *reinterpret_cast<float4 *>(b.comp + (size_t)blockIdx.y * S.Qp + i) = c0;
     }
 }
 
@@ -1242,7 +1265,8 @@ hipError_t launch_forward(const DevSys &S, const FwdArgs &f, hipStream_t st)
 hipError_t launch_back(const DevSys &S, const BackArgs &b, hipStream_t st)
 {
     if (b.nchunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_back, dim3(S.Qp / kWave, b.nchunks), dim3(256), 0, st, S, b);
+    hipLaunchKernelGGL(k_back, dim3((S.Qp + 4 * kWave - 1) / (4 * kWave), b.nchunks), dim3(256), 0,
+                       st, S, b);
     return hipGetLastError();
 }
 
