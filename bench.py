@@ -280,6 +280,10 @@ def headline(args, sections, out):
         "model_terms_per_iteration": {"evaluated": terms, "unpruned": full_terms},
     })
     setup_total = dict(setup)
+    if "cached" in sections:
+        # not the headline: the rows of every subset computed once (52 GB at
+        # this size), the iterations then read them (HBM-bound)
+        out["cached_rows"] = cached_rows(plan, sens, lam0, J, Qp, K)
 
     if "surrogate" in sections and args.surrogate_untrained:
         # inference cost only (a random-init network; for profiling runs)
