@@ -499,11 +499,19 @@ int lmmew_mlp_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, int64_t n_label_events, int ep
                   hipStream_t stream);
 
 /* Factor on the scatter network's density for this context's cases
- * (default 1): in a plan over several maps case c takes ctxs[c]'s factor,
- * otherwise every case takes the plan context's.  It calibrates a network
- * with no attenuation-map input to one patient's map (lmmew_scatter_scale_fit).
+ * (default 1), the same for every energy window: in a plan over several maps
+ * case c takes ctxs[c]'s factors, otherwise every case takes the plan
+ * context's.  It calibrates a network with no attenuation-map input to one
+ * patient's map (lmmew_scatter_scale_fit).
  * Errors: EINVAL (scale not positive and finite). */
 int lmmew_set_scatter_scale(lmmew_ctx *ctx, double scale);
+
+/* As lmmew_set_scatter_scale with one factor per energy window: an event's
+ * density takes the factor of the first window (in the system's order) that
+ * holds its energy.  scales: host array of n_windows factors, n_windows the
+ * system's window count.  Errors: EINVAL (NULL, another count, a factor not
+ * positive and finite). */
+int lmmew_set_scatter_scale_windows(lmmew_ctx *ctx, const double *scales, int n_windows);
 
 /* The factor that matches the network's total once-scattered density to the
  * exact model's over the given events on this context's map: *scale =
@@ -514,6 +522,17 @@ int lmmew_set_scatter_scale(lmmew_ctx *ctx, double scale);
  * continuous positions, NULL), ENUMERIC (a sum vanishes), ENOMEM, EDEVICE. */
 int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *mlp, const lmmew_events *ev,
                             double *scale, hipStream_t stream);
+
+/* The factors of lmmew_scatter_scale_fit for each energy window: scales[w] =
+ * the exact model's once-scattered density summed over the rows of the given
+ * events whose energy lies in window w (the first that holds it) / the
+ * network's over the same rows (FP64, every support pixel).  A window whose
+ * events are absent, or whose sums vanish, takes the factor over all the
+ * events.  scales: host array of n_windows, the system's window count.
+ * Synchronises the stream.  Errors: as lmmew_scatter_scale_fit, and EINVAL
+ * for another count. */
+int lmmew_scatter_scale_fit_windows(lmmew_ctx *ctx, lmmew_mlp *mlp, const lmmew_events *ev,
+                                    double *scales, int n_windows, hipStream_t stream);
 
 /* Selects the scatter model that lmmew_osem_iter/_subiter/_graph,
  * lmmew_forward and lmmew_backproject use for this context: NULL for the

@@ -116,6 +116,8 @@ def _load():
         "lmmew_plan_rows": (i32, [vp, vp, i32, vp, i64, vp, vp]),
         "lmmew_psf_table": (i32, [vp, i32, vp]),
         "lmmew_set_scatter_scale": (i32, [vp, C.c_double]),
+        "lmmew_set_scatter_scale_windows": (i32, [vp, vp, i32]),
+        "lmmew_scatter_scale_fit_windows": (i32, [vp, vp, C.POINTER(_Events), vp, i32, vp]),
         "lmmew_scatter_scale_fit": (i32, [vp, vp, C.POINTER(_Events), C.POINTER(C.c_double), vp]),
     }
     for name, (res, args) in sig.items():
@@ -341,8 +343,27 @@ class Context:
                                                     _stream()))
         return out.value
 
+    def lmmew_set_scatter_scale_windows(self, scales):
+        import numpy as np
+
+        v = np.ascontiguousarray(scales, np.float64)
+        self._check(_load().lmmew_set_scatter_scale_windows(self._h, C.c_void_p(v.ctypes.data),
+                                                            int(v.size)))
+
+    def lmmew_scatter_scale_fit_windows(self, mlp, ev):
+        """lmmew_scatter_scale_fit per energy window (numpy array, one per window)."""
+        import numpy as np
+
+        e = _events(ev)
+        out = np.zeros(len(self.params.windows), np.float64)
+        self._check(_load().lmmew_scatter_scale_fit_windows(
+            self._h, mlp._h, C.byref(e), C.c_void_p(out.ctypes.data), int(out.size), _stream()))
+        return out
+
     set_scatter_scale = lmmew_set_scatter_scale
     scatter_scale_fit = lmmew_scatter_scale_fit
+    set_scatter_scale_windows = lmmew_set_scatter_scale_windows
+    scatter_scale_fit_windows = lmmew_scatter_scale_fit_windows
 
     def lmmew_mlp_create(self, seed=0):
         return Mlp(self, seed)

@@ -240,6 +240,8 @@ hipError_t launch_gather_w(const float *w, const int64_t *perm, int64_t n, float
                            hipStream_t st);
 // out[0] = sum of x[0..n) in FP64 (fixed order: deterministic)
 hipError_t launch_sum(const float *x, long n, double *out, hipStream_t st);
+// out[r] = sum of row r of A [rows][Qp] in FP64, in a fixed order
+hipError_t launch_row_sums(const float *A, int rows, int Qp, double *out, hipStream_t st);
 hipError_t launch_roi_sums(const float *lam, int C, int Q, const uint8_t *masks, int K,
                            double *out, hipStream_t st);
 
@@ -259,8 +261,8 @@ struct MlpRowArgs {
     float *A;
     const float *P;                    // fp32 parameters
     float c0, floor_;
-    const int *ev_case;                // rows' cases (with case_scale), or NULL
-    const float *case_scale;           // [cases] factor on the density, or NULL (1)
+    const int *ev_scale;               // rows' entries of case_scale, or NULL
+    const float *case_scale;           // [cases][windows] factor on the density, or NULL (1)
 };
 hipError_t mlp_forward_batch(const MlpWork &w, const float *P, const float *feats, const int *idx,
                              int M, const float *tgt, hipStream_t st);

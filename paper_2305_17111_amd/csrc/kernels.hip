@@ -1398,6 +1398,27 @@ hipError_t launch_sum(const float *x, long n, double *out, hipStream_t st)
     return hipGetLastError();
 }
 
+// FP64 sum of every row of A [rows][Qp]: one wavefront per row, the lanes'
+// strided partial sums, then a butterfly over the wavefront (a fixed order).
+__global__ __launch_bounds__(256) void k_row_sums(const float *A, int rows, int Qp, double *out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (r >= rows) return;
+    const float *row = A + (size_t)r * Qp;
+    double acc = 0.0;
+    for (int q = lane; q < Qp; q += kWave) acc += (double)row[q];
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) out[r] = acc;
+}
+
+hipError_t launch_row_sums(const float *A, int rows, int Qp, double *out, hipStream_t st)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_sums, dim3((rows + 3) / 4), dim3(256), 0, st, A, rows, Qp, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_roi_sums(const float *lam, int C, int Q, const uint8_t *masks, int K,
                            double *out, hipStream_t st)
 {

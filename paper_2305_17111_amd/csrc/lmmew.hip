@@ -50,7 +50,8 @@ struct lmmew_ctx {
     float *d_scz = nullptr;           // 3-D: [nsc] scatter-point z
     double *d_sczd = nullptr;         // 3-D: [nsc] scatter-point z (double)
     lmmew_mlp *mlp = nullptr;         // scatter surrogate used by OSEM (NULL: exact model)
-    float scatter_scale = 1.f;        // factor on the surrogate's density for this map's cases
+    // factor on the surrogate's density for this map's cases, per energy window
+    float scatter_scale[LMMEW_MAX_WINDOWS] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
     std::vector<lmmew_mlp *> nets;    // networks created on this context (detached when it goes)
     int model_gen = 0;                // bumped whenever the scatter model changes
 };
@@ -114,8 +115,10 @@ struct lmmew_plan {
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
     float *d_Acache = nullptr;        // [n][Qp] rows of every subset (lmmew_plan_cache_rows) or NULL
     float *d_lamc = nullptr;          // [ncases][Qp] support copy of the current images
-    float *d_cscale = nullptr;        // [ncases] surrogate density factor of each case
+    float *d_cscale = nullptr;        // [ncases][nwin] surrogate density factor of each case
+                                      // and energy window
     std::vector<float> cscale;        // what d_cscale holds
+    int *d_sidx = nullptr;            // sorted rows: entry of d_cscale (case * nwin + window)
     int cache_gen = -1;               // scatter-model generation the cached rows were computed with
     double *d_logp = nullptr, *d_ll = nullptr;
     float *d_part = nullptr, *d_comp = nullptr;
@@ -273,6 +276,7 @@ void free_plan(lmmew_plan *p)
     dfree(p->d_Acache);
     dfree(p->d_lamc);
     dfree(p->d_cscale);
+    dfree(p->d_sidx);
 }
 
 bool in_window(const lmmew_system &s, float e)
@@ -281,6 +285,15 @@ bool in_window(const lmmew_system &s, float e)
     for (int k = 0; k < s.n_windows; ++k)
         if (e >= (float)s.win_lo_keV[k] && e <= (float)s.win_hi_keV[k]) return true;
     return false;
+}
+
+// The first window that holds energy e (the same comparisons as in_window;
+// 0 for an energy in none).
+int window_of(const lmmew_system &s, float e)
+{
+    for (int k = 0; k < s.n_windows; ++k)
+        if (e >= (float)s.win_lo_keV[k] && e <= (float)s.win_hi_keV[k]) return k;
+    return 0;
 }
 
 // Relevant (not pruned) scatter points of one event: those whose collimator
@@ -838,7 +851,8 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
     PCHK(dalloc(&p->d_logp, n));
     PCHK(dalloc(&p->d_A, (size_t)std::max(p->max_rows, 1) * Qp));
     PCHK(dalloc(&p->d_lamc, (size_t)n_cases * Qp));
-    PCHK(dalloc(&p->d_cscale, (size_t)n_cases));
+    PCHK(dalloc(&p->d_cscale, (size_t)n_cases * ctx->S.nwin));
+    PCHK(dalloc(&p->d_sidx, n));
     if (n > 0) {
         if (d3)
             PCHK(hipMemcpyAsync(p->d_binz, p->binz.data(), n * sizeof(int), hipMemcpyHostToDevice,
@@ -851,6 +865,11 @@ int make_plan(lmmew_ctx *ctx, const lmmew_events *ev, const int64_t *case_offset
         PCHK(hipMemcpyAsync(p->d_ang, p->ang.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_case, p->cas.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(p->d_E, p->E.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+        std::vector<int> sidx(n);
+        for (int64_t r = 0; r < n; ++r)
+            sidx[r] = p->cas[r] * ctx->S.nwin + window_of(ctx->sys, p->E[r]);
+        PCHK(hipMemcpyAsync(p->d_sidx, sidx.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        PCHK(hipStreamSynchronize(st));
         PCHK(hipMemcpyAsync(p->d_perm, p->perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice,
                             st));
     }
@@ -888,10 +907,13 @@ hipError_t prof_mark(lmmew_ctx *, lmmew_plan *p, int kind, hipStream_t st)
 // and the surrogate's per-case density factors.
 int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
 {
-    // the surrogate's density factor of every case (lmmew_set_scatter_scale)
-    std::vector<float> cs(p->ncases);
+    // the surrogate's density factor of every case and window
+    // (lmmew_set_scatter_scale, lmmew_set_scatter_scale_windows)
+    const int nwin = ctx->S.nwin;
+    std::vector<float> cs((size_t)p->ncases * nwin);
     for (int c = 0; c < p->ncases; ++c)
-        cs[c] = (p->maps.empty() ? ctx : p->maps[c])->scatter_scale;
+        for (int w = 0; w < nwin; ++w)
+            cs[(size_t)c * nwin + w] = (p->maps.empty() ? ctx : p->maps[c])->scatter_scale[w];
     if (cs != p->cscale) {
         HIPCHK(ctx, hipMemcpyAsync(p->d_cscale, cs.data(), cs.size() * sizeof(float),
                                    hipMemcpyHostToDevice, st));
@@ -1034,7 +1056,7 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
                 a.P = m->P;
                 a.c0 = (float)m->c0;
                 a.floor_ = (float)m->floor_;
-                a.ev_case = p->d_case + sub.row0 + r0;
+                a.ev_scale = p->d_sidx + sub.row0 + r0;
                 a.case_scale = p->d_cscale;
                 HIPCHK(ctx, mlp_rows(ctx->S, a, st));
             }
@@ -2525,18 +2547,41 @@ int lmmew_set_scatter_scale(lmmew_ctx *ctx, double scale)
     if (!ctx) return LMMEW_EINVAL;
     if (!(scale > 0) || !std::isfinite(scale))
         return fail(ctx, LMMEW_EINVAL, "scatter scale must be positive and finite");
-    if ((float)scale != ctx->scatter_scale) {
-        ctx->scatter_scale = (float)scale;
-        ctx->model_gen++;
+    bool changed = false;
+    for (int w = 0; w < ctx->S.nwin; ++w) {
+        changed |= (float)scale != ctx->scatter_scale[w];
+        ctx->scatter_scale[w] = (float)scale;
     }
+    if (changed) ctx->model_gen++;
     return LMMEW_OK;
 }
 
-int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev, double *scale,
-                            hipStream_t st)
+int lmmew_set_scatter_scale_windows(lmmew_ctx *ctx, const double *scales, int n_windows)
 {
     if (!ctx) return LMMEW_EINVAL;
-    if (!m || !scale || !ev) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    if (!scales || n_windows != ctx->S.nwin)
+        return fail(ctx, LMMEW_EINVAL, "one scale per energy window of the system");
+    for (int w = 0; w < n_windows; ++w)
+        if (!(scales[w] > 0) || !std::isfinite(scales[w]))
+            return fail(ctx, LMMEW_EINVAL, "scatter scale must be positive and finite");
+    bool changed = false;
+    for (int w = 0; w < n_windows; ++w) {
+        changed |= (float)scales[w] != ctx->scatter_scale[w];
+        ctx->scatter_scale[w] = (float)scales[w];
+    }
+    if (changed) ctx->model_gen++;
+    return LMMEW_OK;
+}
+
+}  // extern "C"
+
+// The exact model's and the network's once-scattered densities summed over
+// every support pixel of the given events' rows, per energy window of the
+// events (FP64; a row's sum in a fixed order, rows added in plan order).
+static int scale_sums(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev, double *ex,
+                      double *net, hipStream_t st)
+{
+    if (!m || !ev) return fail(ctx, LMMEW_EINVAL, "NULL argument");
     if (!m->ctx || (m->ctx != ctx && !same_system(ctx, m->ctx)))
         return fail(ctx, LMMEW_EINVAL, "network of a context with another system or support");
     if (ev->n < 1) return fail(ctx, LMMEW_EINVAL, "no events");
@@ -2544,15 +2589,19 @@ int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev
     lmmew_plan *pl = nullptr;
     int rc = make_plan(ctx, ev, nullptr, 1, subsets_for_budget(ctx, ev->n), st, &pl);
     if (rc != LMMEW_OK) return rc;
-    double *d_sum = nullptr;
-    hipError_t e = dalloc(&d_sum, 2 * (size_t)pl->nsub);
+    const int Qp = ctx->S.Qp;
+    double *d_rs = nullptr;
+    hipError_t e = dalloc(&d_rs, 2 * (size_t)std::max(pl->max_rows, 1));
+    std::vector<double> h(2 * (size_t)std::max(pl->max_rows, 1));
+    for (int w = 0; w < ctx->S.nwin; ++w) ex[w] = net[w] = 0.0;
     for (int s = 0; s < pl->nsub && e == hipSuccess && rc == LMMEW_OK; ++s) {
         const lmmew_plan::Sub &sub = pl->subs[s];
+        if (sub.rows == 0) continue;
         rc = run_rows(ctx, pl, s, st, 1);                         // exact scattered paths
         if (rc != LMMEW_OK) break;
-        e = launch_sum(pl->d_A, (long)sub.rows * ctx->S.Qp, d_sum + 2 * s, st);
+        e = launch_row_sums(pl->d_A, sub.rows, Qp, d_rs, st);
         if (e == hipSuccess)
-            e = hipMemsetAsync(pl->d_A, 0, (size_t)sub.rows * ctx->S.Qp * sizeof(float), st);
+            e = hipMemsetAsync(pl->d_A, 0, (size_t)sub.rows * Qp * sizeof(float), st);
         if (e == hipSuccess) {
             MlpRowArgs a{};                                        // the network alone
             a.pix_xy = ctx->d_pix;
@@ -2567,25 +2616,67 @@ int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev
             a.floor_ = (float)m->floor_;
             e = mlp_rows(ctx->S, a, st);
         }
-        if (e == hipSuccess) e = launch_sum(pl->d_A, (long)sub.rows * ctx->S.Qp, d_sum + 2 * s + 1, st);
+        if (e == hipSuccess) e = launch_row_sums(pl->d_A, sub.rows, Qp, d_rs + sub.rows, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.data(), d_rs, 2 * (size_t)sub.rows * sizeof(double),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess)
+            for (int r = 0; r < sub.rows; ++r) {
+                const int w = window_of(ctx->sys, pl->E[sub.row0 + r]);
+                ex[w] += h[r];
+                net[w] += h[sub.rows + r];
+            }
     }
-    std::vector<double> h(2 * (size_t)pl->nsub, 0.0);
-    if (e == hipSuccess && rc == LMMEW_OK)
-        e = hipMemcpyAsync(h.data(), d_sum, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
     const hipError_t e2 = hipStreamSynchronize(st);
     if (e == hipSuccess) e = e2;
-    dfree(d_sum);
+    dfree(d_rs);
     lmmew_plan_destroy(pl);
     if (rc != LMMEW_OK) return rc;
     if (e != hipSuccess) return hipfail(ctx, e, "scatter scale fit");
-    double ex = 0.0, net = 0.0;
-    for (int s = 0; 2 * s < (int)h.size(); ++s) {
-        ex += h[2 * s];
-        net += h[2 * s + 1];
+    return LMMEW_OK;
+}
+
+extern "C" {
+
+int lmmew_scatter_scale_fit(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev, double *scale,
+                            hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!scale) return fail(ctx, LMMEW_EINVAL, "NULL argument");
+    double ex[LMMEW_MAX_WINDOWS], net[LMMEW_MAX_WINDOWS];
+    const int rc = scale_sums(ctx, m, ev, ex, net, st);
+    if (rc != LMMEW_OK) return rc;
+    double x = 0.0, y = 0.0;
+    for (int w = 0; w < ctx->S.nwin; ++w) {
+        x += ex[w];
+        y += net[w];
     }
-    if (!(net > 0) || !(ex > 0) || !std::isfinite(ex / net))
+    if (!(y > 0) || !(x > 0) || !std::isfinite(x / y))
         return fail(ctx, LMMEW_ENUMERIC, "scattered densities vanish for these events");
-    *scale = ex / net;
+    *scale = x / y;
+    return LMMEW_OK;
+}
+
+int lmmew_scatter_scale_fit_windows(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev,
+                                    double *scales, int n_windows, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (!scales || n_windows != ctx->S.nwin)
+        return fail(ctx, LMMEW_EINVAL, "one scale per energy window of the system");
+    double ex[LMMEW_MAX_WINDOWS], net[LMMEW_MAX_WINDOWS];
+    const int rc = scale_sums(ctx, m, ev, ex, net, st);
+    if (rc != LMMEW_OK) return rc;
+    double x = 0.0, y = 0.0;
+    for (int w = 0; w < n_windows; ++w) {
+        x += ex[w];
+        y += net[w];
+    }
+    if (!(y > 0) || !(x > 0) || !std::isfinite(x / y))
+        return fail(ctx, LMMEW_ENUMERIC, "scattered densities vanish for these events");
+    for (int w = 0; w < n_windows; ++w)
+        scales[w] = (ex[w] > 0 && net[w] > 0 && std::isfinite(ex[w] / net[w])) ? ex[w] / net[w]
+                                                                              : x / y;
     return LMMEW_OK;
 }
 

@@ -643,7 +643,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
         const int bin = a.ev_bin[e];
         const float2 dir = a.dirs[a.ev_ang[e]];
         const float E = a.ev_E[e];
-        const float sc = a.case_scale ? a.case_scale[a.ev_case[e]] : 1.f;
+        const float sc = a.case_scale ? a.case_scale[a.ev_scale[e]] : 1.f;
 
         // first-layer B fragments: group 0 (xh, 1, 1), group 1 (xl, 0, 0),
         // group 2 (xh, 0, 0), group 3 zero.  With x scaled by keep (0 in

@@ -257,10 +257,69 @@ def test_scatter_scale_multiplies_the_network_density(env, trained):
         ctx.set_scatter_model(None)
 
 
+def test_scatter_scale_per_window(env, trained):
+    """lmmew_set_scatter_scale_windows multiplies the surrogate's density of
+    each event by its energy window's factor; equal factors are
+    lmmew_set_scatter_scale; lmmew_scatter_scale_fit_windows returns each
+    window's ratio of the exact scattered density to the network's, and the
+    factor over all events for a window without events."""
+    lm, p, act, rois, ctx, orc = env
+    net, _ = trained
+    rng = np.random.default_rng(10)
+    n = 12
+    E = np.concatenate([rng.uniform(*p.windows[0], n), rng.uniform(*p.windows[1], n)])
+    ev_h = {"bin": rng.integers(0, p.nb, 2 * n).astype(np.int16),
+            "angle": rng.integers(0, p.na, 2 * n).astype(np.int16),
+            "energy": E.astype(np.float32)}
+    ev = _dev(lm, ev_h)
+    ctx.set_scatter_model(net)
+    try:
+        prim = ctx.rows(ev, part=2).double()
+        full1 = ctx.rows(ev, part=0).double()
+        ctx.set_scatter_scale_windows([2.5, 0.5])
+        full2 = ctx.rows(ev, part=0).double()
+        sur1, sur2 = full1 - prim, full2 - prim
+        tol = 4 * 2.0 ** -24 * (prim.abs() + full1.abs() + full2.abs())
+        f = torch_col([2.5] * n + [0.5] * n)
+        assert bool(((sur2 - f * sur1).abs() <= 2.5 * tol + 1e-6 * sur2.abs()).all())
+        ctx.set_scatter_scale_windows([1.7, 1.7])
+        a = ctx.rows(ev, part=0)
+        ctx.set_scatter_scale(1.7)
+        b = ctx.rows(ev, part=0)
+        assert bool((a == b).all())
+        ctx.set_scatter_scale(1.0)
+        exact = ctx.rows(ev, part=1).double()
+        k = ctx.scatter_scale_fit_windows(net, ev)
+        for w, sl in enumerate((slice(0, n), slice(n, 2 * n))):
+            ref = float(exact[sl].sum() / sur1[sl].sum())
+            bound = float(tol[sl].sum() / sur1[sl].sum()) + 1e-5
+            assert abs(k[w] / ref - 1) <= bound, (w, k[w], ref, bound)
+        # events of window 0 only: its factor and the fallback of window 1 are
+        # both the factor over all of them
+        ev0 = _dev(lm, {q: v[:n] for q, v in ev_h.items()})
+        k0 = ctx.scatter_scale_fit_windows(net, ev0)
+        kall = ctx.scatter_scale_fit(net, ev0)
+        assert k0[0] == kall and k0[1] == kall
+        with pytest.raises(lm.LmmewError):
+            ctx.set_scatter_scale_windows([1.0])
+        with pytest.raises(lm.LmmewError):
+            ctx.set_scatter_scale_windows([1.0, -1.0])
+    finally:
+        ctx.set_scatter_scale(1.0)
+        ctx.set_scatter_model(None)
+
+
+def torch_col(v):
+    import torch
+
+    return torch.tensor(v, dtype=torch.float64, device="cuda")[:, None]
+
+
 def test_surrogate_region_bias_at_128x128():
     """The 128x128 workload (16 patients with their own maps, 1M events, 16
     subsets): the network trained on random water bodies, its density scaled
-    per patient by lmmew_scatter_scale_fit over 256 of the patient's events,
+    per patient by lmmew_scatter_scale_fit over 256 of the patient's events
+    (then per patient and energy window by lmmew_scatter_scale_fit_windows),
     reconstructs the 48 hot-region uptakes after 10 iterations within 1 % of
     the exact model on average (the largest single region is reported)."""
     import torch
@@ -308,9 +367,21 @@ def test_surrogate_region_bias_at_128x128():
     rel = uptakes(lam) / up_ex - 1.0
     print(f"128x128 surrogate region bias: mean {rel.mean():+.4f}, mean |.| "
           f"{np.abs(rel).mean():.4f}, max |.| {np.abs(rel).max():.4f} over {rel.size} regions")
+    # the same with one factor per energy window
+    for c in range(w.n_cases):
+        e = evs[c]
+        idx = np.linspace(0, e["bin"].size - 1, 256).astype(np.int64)
+        k = ctxs[c].scatter_scale_fit_windows(net, lm.events_to_device(
+            {q: e[q][idx] for q in ("bin", "angle", "energy")}))
+        ctxs[c].set_scatter_scale_windows(k)
+    lam = lam0.clone()
+    plan.osem_graph(10, sens, lam)
+    relw = uptakes(lam) / up_ex - 1.0
+    print(f"  per window: mean {relw.mean():+.4f}, mean |.| {np.abs(relw).mean():.4f}, "
+          f"max |.| {np.abs(relw).max():.4f}")
     ctxs[0].set_scatter_model(None)
-    assert abs(rel.mean()) <= 0.01
-    assert np.abs(rel).max() < 0.15
+    assert abs(rel.mean()) <= 0.01 and abs(relw.mean()) <= 0.01
+    assert np.abs(rel).max() < 0.15 and np.abs(relw).max() < 0.15
 
 
 def test_context_destroyed_before_its_network():
