@@ -408,16 +408,22 @@ __device__ __forceinline__ void scatter_params(const DevSys &S, float dx, float 
         const float rs = fast_rsq(invP);
         const float P = rs * rs;
         const float l2i = fast_log2(invP);
-        const float lK = fast_log2(P + invP - sin2) - 2.f * l2i;
-        const float fE = S.f[w] * fast_exp2(S.mu_pow * l2i);
-        const float att = (S.f[w] * gqs + fE * gsa) * kLog2e;
-        float A = base + S.lsc[w] + lK - att;
-        if (NORM) A += S.nc[w] + 0.5f * l2i;
+        // Klein-Nishina: log2(P + 1/P - sin^2) - 2 log2(invP), the normalised
+        // Gaussian's 0.5 log2(invP) folded into the same FMA
+        const float lkn = fast_log2(fmaf(rs, rs, invP) - sin2);
+        // attenuation (log2 units): f_w log2(e) gqs on the way in, and on the
+        // way out f(E') log2(e) gsa with f(E') = f_w invP^p, as one exp2 whose
+        // exponent carries log2(f_w log2(e)) (the same for every point)
+        const float ea = fast_exp2(fmaf(S.mu_pow, l2i, fast_log2(S.f[w] * kLog2e)));
+        float A = fmaf(l2i, NORM ? -1.5f : -2.f, base + (NORM ? S.lsc[w] + S.nc[w] : S.lsc[w]));
+        A += lkn;
+        A = fmaf(-(S.f[w] * kLog2e), gqs, A);
+        A = fmaf(-ea, gsa, A);
         Aw[w] = A;
         Ep[w] = S.E[w] * P;
         // sqrt(c0 * invP) = sqc0 * invP * rs ;  F = sqrt(c) * E' = sqc0 * E_w * rs
         sw[w] = S.sqc0[w] * invP * rs;
-        Fw[w] = S.sqc0[w] * S.E[w] * rs;
+        Fw[w] = (S.sqc0[w] * S.E[w]) * rs;
     }
 }
 
