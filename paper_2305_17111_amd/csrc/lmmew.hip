@@ -10,6 +10,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -2269,10 +2270,12 @@ int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const floa
     int rc = mlp_workspace(ctx, m, batch);
     if (rc != LMMEW_OK) return rc;
     const int64_t nb = n / batch;
-    // Two permutation buffers on each side: the host shuffles epoch ep + 1's
-    // order while the device still runs epoch ep (before refilling a host
-    // buffer it waits only for the copy made from it two epochs earlier), and
-    // the batch losses of every epoch are read back once at the end.
+    // Two permutation buffers on each side: a worker thread shuffles epoch
+    // ep + 1's order while this thread enqueues epoch ep (before refilling a
+    // host buffer it waits only for the copy made from it two epochs
+    // earlier), so the device does not wait for the shuffle once the stream's
+    // queue is full; the batch losses of every epoch are read back once at
+    // the end.
     int *d_perm[2] = {nullptr, nullptr};
     double *d_losses = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr};
@@ -2292,20 +2295,37 @@ int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const floa
     }
     std::vector<int> perm[2] = {std::vector<int>(n), std::vector<int>(n)};
     uint64_t rs = seed;
+    // the epochs' orders, in sequence from one generator (Fisher-Yates)
+    auto shuffle = [&rs, n](std::vector<int> *pv) {
+        for (int64_t t = 0; t < n; ++t) (*pv)[t] = (int)t;
+        for (int64_t t = n - 1; t > 0; --t) {
+            const int64_t j = (int64_t)(splitmix64(rs) % (uint64_t)(t + 1));
+            std::swap((*pv)[t], (*pv)[j]);
+        }
+    };
+    std::thread worker;
+    auto finish = [&worker]() {
+        if (worker.joinable()) worker.join();
+    };
+    if (epochs > 0) shuffle(&perm[0]);
     const MlpWork w = mlp_work(m);
     hipError_t e = hipSuccess;
     for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
         const int k = ep & 1;
-        if (ep >= 2) e = hipEventSynchronize(copied[k]);       // epoch ep - 2's copy is done
-        std::vector<int> &pv = perm[k];
-        for (int64_t t = 0; t < n; ++t) pv[t] = (int)t;
-        for (int64_t t = n - 1; t > 0; --t) {          // Fisher-Yates
-            const int64_t j = (int64_t)(splitmix64(rs) % (uint64_t)(t + 1));
-            std::swap(pv[t], pv[j]);
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_perm[k], pv.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+        finish();                                       // epoch ep's order is ready
+        e = hipMemcpyAsync(d_perm[k], perm[k].data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipEventRecord(copied[k], st);
+        if (e == hipSuccess && ep + 1 < epochs) {
+            // the other host buffer was last copied at the start of epoch ep - 1
+            if (ep >= 1) e = hipEventSynchronize(copied[k ^ 1]);
+            if (e == hipSuccess) {
+                try {
+                    worker = std::thread(shuffle, &perm[k ^ 1]);
+                } catch (...) {
+                    shuffle(&perm[k ^ 1]);              // no thread: shuffle here
+                }
+            }
+        }
         for (int64_t b = 0; b < nb && e == hipSuccess; ++b) {
             const int *idx = d_perm[k] + b * batch;
             e = mlp_forward_batch(w, m->P, feats, idx, batch, target, st);
@@ -2318,6 +2338,7 @@ int lmmew_mlp_train(lmmew_ctx *ctx, lmmew_mlp *m, const float *feats, const floa
             if (e == hipSuccess) e = mlp_refresh(m->P, m->W2b, m->W3b, st);
         }
     }
+    finish();
     std::vector<double> losses((size_t)epochs * nb);
     if (e == hipSuccess && epochs > 0)
         e = hipMemcpyAsync(losses.data(), d_losses, sizeof(double) * losses.size(),
