@@ -194,3 +194,15 @@ def test_128x128_two_patient_maps_one_subiteration(lm):
         for c in (0, 1):
             mx, l2 = _rel(lam_j[c].cpu().numpy(), g[f"lam1_{c}"])
             assert mx < TOL and l2 < TOL, (jt, c, mx, l2)
+    # the same sub-iteration from cached rows (every subset's rows computed
+    # once): equal to the matrix-free one bitwise, so to the oracle as above
+    lam_mf = lam.clone()
+    plan.osem_subiter(0, sens, lam_mf)
+    plan.cache_rows(True)
+    try:
+        lam_c = lam.clone()
+        sk, ll = plan.osem_subiter(0, sens, lam_c, stats=True)
+        assert sk == int(g["skipped0"]) + int(g["skipped1"])
+        assert bool((lam_c == lam_mf).all())
+    finally:
+        plan.cache_rows(False)
