@@ -13,6 +13,11 @@ scaled per patient to the exact model's total over a sample of the patient's
 events) with its region-uptake bias against the exact model.  Setup (attenuation tables, sensitivities, event
 plan, autotuning, surrogate training) is timed separately in `setup_s`.
 
+The surrogate is also reported with the network evaluated at nodes every 2 and
+every 4 pixels, the support pixels interpolated bilinearly (`surrogate_grid2`,
+`surrogate_grid4`; each refitted per patient and window, with its own timing and
+region bias).
+
 Beside them (`extras`): the 64x64 workload (50k events, 8 subsets) with the
 path-parameter table, 64 batched cases of it, continuous positions, the
 cached-row mode (a different mode, never the headline), coarser scatter grids,
@@ -311,27 +316,6 @@ def headline(args, sections, out):
         lam = lam0.clone()
         plan.osem_graph(roi_iters, sens, lam)
         up_shared = uptakes(lam.cpu().numpy().astype(np.float64))
-        # per patient and energy window: the factor that matches the network's
-        # total scattered density to the exact model's over a sample of the
-        # patient's own events (the network has no attenuation-map input)
-        t = time.perf_counter()
-        kappa = []
-        for c in range(w.n_cases):
-            e = evs[c]
-            idx = np.linspace(0, e["bin"].size - 1, args.calib_events).astype(np.int64)
-            sub = events_to_device({k: e[k][idx] for k in ("bin", "angle", "energy")})
-            kappa.append(ctxs[c].scatter_scale_fit_windows(net, sub))
-            ctxs[c].set_scatter_scale_windows(kappa[-1])
-        torch.cuda.synchronize()
-        calib_s = time.perf_counter() - t
-        lam = lam0.clone()
-        el_s, ks = _timed_iterations(plan, sens, lam, W, K)
-        assert bool(torch.isfinite(lam).all())
-        if roi_iters > W + K:
-            plan.osem_graph(roi_iters - W - K, sens, lam)
-        up_sur = uptakes(lam.cpu().numpy().astype(np.float64))
-        for c in range(w.n_cases):
-            ctxs[c].set_scatter_scale(1.0)
         # the same iterations with the scatter term switched off (the network's
         # output shifted by -100 in log space: a density below 1e-40): the
         # method without a scatter model
@@ -341,49 +325,86 @@ def headline(args, sections, out):
         lam = lam0.clone()
         plan.osem_graph(roi_iters, sens, lam)
         up_none = uptakes(lam.cpu().numpy().astype(np.float64))
-        ctxs[0].set_scatter_model(None)
-        rel = up_sur / up_ex - 1.0
-        mlp_ms, mlp_n = ks["k_mlp_rows"]
-        prim_ms, _ = ks["k_row"]
-        pairs = float(J) * Qm
-        flops = pairs * 2 * MLP_MAC_PER_PAIR * K / (mlp_ms * 1e-3)
+        ctxs[0].set_scatter_model(net)
         mm, mm_src = measured_traffic("k_mlp_rows_128x128_16cases_hbm_traffic.md", "mlp.hip")
-        out["surrogate"] = {
-            "value": J * K / el_s, "unit": "events*iterations/s",
-            "ms_per_step": 1e3 * el_s / K, "s_per_iteration": el_s / K,
-            "speedup_vs_exact": el / el_s,
-            "roi_uptake_vs_exact": {
-                "iterations": roi_iters, "regions": int(rel.size),
-                "calibrated_per_patient_window": _bias(rel),
-                "bias_within_1pct": bool(abs(rel.mean()) <= 0.01),
-                "per_patient_mean_rel": [float(v) for v in rel.mean(1)],
-                "uncalibrated": _bias(up_shared / up_ex - 1.0),
-                "no_scatter_model": _bias(up_none / up_ex - 1.0)},
-            "roofline": {
-                "bound": "mfma", "kernel": "k_mlp_rows (surrogate inference, all patients' "
-                                           "launches of a subset)",
-                "achieved": flops / 1e12, "peak": PEAK_BF16_FLOPS / 1e12, "unit": "TFLOP/s",
-                "frac": flops / PEAK_BF16_FLOPS,
-                "traffic": (mm["fetch"] + mm["write"]) if mm else None,
-                "traffic_source": mm_src,
-                "flop_per_pair": 2 * MLP_MAC_PER_PAIR, "gelu_per_pair": MLP_GELU_PER_PAIR,
-                "pairs_per_s": pairs * K / (mlp_ms * 1e-3),
-                "avg_ms_per_subset": mlp_ms / mlp_n, "subsets_timed": mlp_n},
-            "unscattered_kernel_ms_per_iteration": prim_ms / K,
-            "training": {"pretrain": {"samples": int(16 * n_lab * Qm),
-                                      "epochs": args.surrogate_epochs, "batch": 8192,
-                                      "seconds": pretrain_s, "first_loss": losses[0],
-                                      "last_loss": losses[-1],
-                                      "maps": "16 random water bodies"},
-                         "calibration": {"events_per_patient": args.calib_events,
-                                         "seconds": calib_s,
-                                         "scales_per_window": [[float(v) for v in k]
-                                                               for k in kappa],
-                                         "what": "exact / network scattered density summed "
-                                                 "over the rows of the sampled events of "
-                                                 "each energy window"}},
-        }
-        setup_total["surrogate_training"] = pretrain_s + calib_s
+        calib_total = 0.0
+        for gi, grid in enumerate(args.surrogate_grids):
+            net.set_grid(grid)
+            nodes = net.grid_nodes()
+            # per patient and energy window: the factor that matches the
+            # network's total scattered density to the exact model's over a
+            # sample of the patient's own events (the network has no
+            # attenuation-map input); fitted on the network as evaluated
+            t = time.perf_counter()
+            kappa = []
+            for c in range(w.n_cases):
+                e = evs[c]
+                idx = np.linspace(0, e["bin"].size - 1, args.calib_events).astype(np.int64)
+                sub = events_to_device({k: e[k][idx] for k in ("bin", "angle", "energy")})
+                kappa.append(ctxs[c].scatter_scale_fit_windows(net, sub))
+                ctxs[c].set_scatter_scale_windows(kappa[-1])
+            torch.cuda.synchronize()
+            calib_s = time.perf_counter() - t
+            calib_total += calib_s
+            lam = lam0.clone()
+            el_s, ks = _timed_iterations(plan, sens, lam, W, K)
+            assert bool(torch.isfinite(lam).all())
+            if roi_iters > W + K:
+                plan.osem_graph(roi_iters - W - K, sens, lam)
+            up_sur = uptakes(lam.cpu().numpy().astype(np.float64))
+            for c in range(w.n_cases):
+                ctxs[c].set_scatter_scale(1.0)
+            rel = up_sur / up_ex - 1.0
+            mlp_ms, mlp_n = ks["k_mlp_rows"]
+            prim_ms, _ = ks["k_row"]
+            pairs = float(J) * nodes
+            flops = pairs * 2 * MLP_MAC_PER_PAIR * K / (mlp_ms * 1e-3)
+            entry = {
+                "value": J * K / el_s, "unit": "events*iterations/s",
+                "ms_per_step": 1e3 * el_s / K, "s_per_iteration": el_s / K,
+                "speedup_vs_exact": el / el_s,
+                "evaluation_grid": {
+                    "spacing_pixels": grid, "positions_per_row": nodes,
+                    "what": "network at every support pixel" if grid == 1 else
+                            f"network at nodes every {grid} pixels ({grid * p.pix:g} mm), "
+                            "support pixels interpolated bilinearly"},
+                "roi_uptake_vs_exact": {
+                    "iterations": roi_iters, "regions": int(rel.size),
+                    "calibrated_per_patient_window": _bias(rel),
+                    "bias_within_1pct": bool(abs(rel.mean()) <= 0.01),
+                    "per_patient_mean_rel": [float(v) for v in rel.mean(1)]},
+                "roofline": {
+                    "bound": "mfma",
+                    "kernel": "k_mlp_rows (surrogate inference, all patients' launches of a "
+                              "subset" + (")" if grid == 1 else
+                                         "; with the node interpolation k_coarse_interp)"),
+                    "achieved": flops / 1e12, "peak": PEAK_BF16_FLOPS / 1e12,
+                    "unit": "TFLOP/s", "frac": flops / PEAK_BF16_FLOPS,
+                    "traffic": (mm["fetch"] + mm["write"]) if (mm and grid == 1) else None,
+                    "traffic_source": mm_src if grid == 1 else "not measured for this grid",
+                    "flop_per_pair": 2 * MLP_MAC_PER_PAIR, "gelu_per_pair": MLP_GELU_PER_PAIR,
+                    "pairs_per_s": pairs * K / (mlp_ms * 1e-3),
+                    "avg_ms_per_subset": mlp_ms / mlp_n, "subsets_timed": mlp_n},
+                "unscattered_kernel_ms_per_iteration": prim_ms / K,
+                "calibration": {"events_per_patient": args.calib_events, "seconds": calib_s,
+                                "scales_per_window": [[float(v) for v in k] for k in kappa],
+                                "what": "exact / network scattered density summed over the "
+                                        "rows of the sampled events of each energy window"},
+            }
+            if gi == 0:
+                entry["roi_uptake_vs_exact"]["uncalibrated"] = _bias(up_shared / up_ex - 1.0)
+                entry["roi_uptake_vs_exact"]["no_scatter_model"] = _bias(up_none / up_ex - 1.0)
+                entry["training"] = {"pretrain": {
+                    "samples": int(16 * n_lab * Qm), "epochs": args.surrogate_epochs,
+                    "batch": 8192, "seconds": pretrain_s, "first_loss": losses[0],
+                    "last_loss": losses[-1], "maps": "16 random water bodies"}}
+                out["surrogate"] = entry
+            else:
+                entry["training"] = "the network of \"surrogate\""
+                out[f"surrogate_grid{grid}"] = entry
+        net.set_grid(1)
+        ctxs[0].set_scatter_model(None)
+        setup_total["surrogate_training"] = pretrain_s + calib_total
     out["setup_s"] = setup_total
     if "cpu" in sections:
         out["cpu_baseline"] = cpu_baseline(p, mus[0], evs[0])
@@ -713,6 +734,9 @@ def main():
     ap.add_argument("--steps-64", type=int, default=10)
     ap.add_argument("--steps-3d", type=int, default=2)
     ap.add_argument("--surrogate-epochs", type=int, default=8)
+    ap.add_argument("--surrogate-grids", default="1,2,4",
+                    help="evaluation grids of the surrogate (node spacing in pixels), the "
+                         "first reported as \"surrogate\", the others beside it")
     ap.add_argument("--calib-events", type=int, default=256,
                     help="events per patient for the surrogate's per-patient scale")
     ap.add_argument("--surrogate-untrained", action="store_true",
@@ -733,6 +757,10 @@ def main():
     unknown = sections - set(SECTIONS)
     if unknown:
         print(f"unknown sections: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    args.surrogate_grids = [int(g) for g in args.surrogate_grids.split(",") if g]
+    if not args.surrogate_grids or not all(1 <= g <= 8 for g in args.surrogate_grids):
+        print("--surrogate-grids: node spacings of 1 to 8 pixels", file=sys.stderr)
         sys.exit(2)
 
     import torch

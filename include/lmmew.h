@@ -542,6 +542,29 @@ int lmmew_scatter_scale_fit_windows(lmmew_ctx *ctx, lmmew_mlp *mlp, const lmmew_
  * EINVAL. */
 int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *mlp);
 
+/* Where OSEM, lmmew_forward, lmmew_backproject, lmmew_rows and the scale
+ * fits evaluate this network (an extension of the surrogate: the paper
+ * evaluates its scatter model on a grid coarser than the object's, Sec. 5 and
+ * the appendix on 3-D requirements, and the scatter density varies slowly
+ * over a pixel).  grid = 1 (the default): at every support pixel.  grid =
+ * g in 2..8: at nodes placed on the centres of the pixels (g u, g v) for
+ * every node any support pixel needs; a support pixel (ix, iy) takes the
+ * bilinear interpolation of the four nodes around it, (ix / g, iy / g) and
+ * the next ones in x and y (integer division), with weights from
+ * fx = (ix mod g) / g and fy = (iy mod g) / g.  The density factors
+ * (lmmew_set_scatter_scale*) apply to the node values.  About 1/g^2 of the
+ * network evaluations; rows change by the interpolation error only.  Plans
+ * using the network keep a node-value scratch of their largest subset's rows
+ * times the node count (about Qm / g^2 floats per row), allocated on first
+ * use.  Synchronises the device (the old node tables may still be read).
+ * Errors: EINVAL (NULL, a network whose context was destroyed, grid outside
+ * 1..8), EDEVICE/ENOMEM. */
+int lmmew_mlp_set_grid(lmmew_mlp *mlp, int grid);
+
+/* Number of positions at which the network is evaluated per event row: the
+ * node count with a coarse grid, else the support size.  EINVAL for NULL. */
+int lmmew_mlp_grid_nodes(const lmmew_mlp *mlp);
+
 /* ---------------------------------------------------------------------------
  * Figures of merit for regional uptake (Sec. 3.1.4)
  * ------------------------------------------------------------------------- */

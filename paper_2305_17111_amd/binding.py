@@ -90,6 +90,8 @@ def _load():
         "lmmew_mlp_destroy": (i32, [vp]),
         "lmmew_mlp_get_params": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lmmew_mlp_set_params": (i32, [vp, vp, C.c_double, C.c_double]),
+        "lmmew_mlp_set_grid": (i32, [vp, i32]),
+        "lmmew_mlp_grid_nodes": (i32, [vp]),
         "lmmew_mlp_forward": (i32, [vp, vp, vp, i64, vp, vp]),
         "lmmew_mlp_grad": (i32, [vp, vp, vp, vp, i64, vp, C.POINTER(C.c_double), vp]),
         "lmmew_mlp_train": (i32, [vp, vp, vp, vp, i64, i32, i32, C.c_double, C.c_uint64,
@@ -612,6 +614,17 @@ class Mlp:
         assert p.size == self.NPARAM
         self.ctx._check(_load().lmmew_mlp_set_params(self._h, C.c_void_p(p.ctypes.data),
                                                      float(c0), float(floor)))
+
+    def set_grid(self, grid):
+        """Evaluate the network at nodes every `grid` pixels in OSEM and the
+        row calls, support pixels interpolated bilinearly (1: every pixel)."""
+        self.ctx._check(_load().lmmew_mlp_set_grid(self._h, int(grid)))
+
+    def grid_nodes(self):
+        """Positions per event row at which the network is evaluated."""
+        n = _load().lmmew_mlp_grid_nodes(self._h)
+        self.ctx._check(min(n, 0))
+        return n
 
     def forward(self, feats):
         feats = feats.contiguous()

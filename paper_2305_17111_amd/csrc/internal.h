@@ -263,7 +263,15 @@ struct MlpRowArgs {
     float c0, floor_;
     const int *ev_scale;               // rows' entries of case_scale, or NULL
     const float *case_scale;           // [cases][windows] factor on the density, or NULL (1)
+    int npix;                          // positions evaluated: pix_xy[0, npix)
+    int ld;                            // row stride of A (floats)
+    int assign;                        // 1: A = density (coarse nodes); 0: A += density
 };
+// Rows' scattered densities at the support pixels by bilinear interpolation of
+// the network's values at the coarse nodes (lmmew_set_scatter_grid):
+// A[e][q] += sum_k w[q].k * C[e][idx[q].k] for the Qm support pixels of rows rows.
+hipError_t launch_coarse_interp(const DevSys &S, const float *C, int ldc, const int4 *idx,
+                                const float4 *w, int rows, float *A, hipStream_t st);
 hipError_t mlp_forward_batch(const MlpWork &w, const float *P, const float *feats, const int *idx,
                              int M, const float *tgt, hipStream_t st);
 hipError_t mlp_backward_batch(const MlpWork &w, const float *P, int M, float *G, hipStream_t st);

@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -64,6 +66,14 @@ struct lmmew_mlp {
                                                      // then the transpose [out][in]
     double c0 = 0.0, floor_ = 0.0;    // target = log(density + floor) - c0
     int step = 0;                     // Adam step count
+    // Evaluation grid in OSEM (lmmew_mlp_set_grid): nodes every `grid` pixels
+    // of the context's support, support pixels interpolated bilinearly
+    // (grid 1: the network at every support pixel, no node tables).
+    int grid = 1;
+    int ncn = 0, ldc = 0;             // nodes; row stride of the node values (multiple of 64)
+    float2 *d_cnode = nullptr;        // [ldc] node positions (padding repeats the last node)
+    int4 *d_cidx = nullptr;           // [Qp] a support pixel's four nodes
+    float4 *d_cw = nullptr;           // [Qp] their bilinear weights
     // training workspace for batches of up to cap samples
     int cap = 0;
     float *X = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *H3 = nullptr, *dZ = nullptr,
@@ -114,6 +124,8 @@ struct lmmew_plan {
     MapTab *d_maps = nullptr;
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
+    float *d_C = nullptr;             // network values at the coarse nodes of a subset's rows
+    size_t C_cap = 0;                 // floats in d_C
     float *d_Acache = nullptr;        // [n][Qp] rows of every subset (lmmew_plan_cache_rows) or NULL
     float *d_lamc = nullptr;          // [ncases][Qp] support copy of the current images
     float *d_cscale = nullptr;        // [ncases][nwin] surrogate density factor of each case
@@ -272,6 +284,7 @@ void free_plan(lmmew_plan *p)
     p->prof_ev.clear();
     dfree(p->d_bin); dfree(p->d_binz); dfree(p->d_u); dfree(p->d_ang); dfree(p->d_case); dfree(p->d_case_chunk); dfree(p->d_case_tiles); dfree(p->d_E); dfree(p->d_perm);
     dfree(p->d_tiles); dfree(p->d_slist); dfree(p->d_pvt); dfree(p->d_chunks); dfree(p->d_A); dfree(p->d_p); dfree(p->d_wt);
+    dfree(p->d_C);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
     dfree(p->d_Acache);
@@ -1007,6 +1020,53 @@ int plan_model_gen(const lmmew_ctx *ctx, const lmmew_plan *p)
     return g;
 }
 
+// The node-value scratch a sub-iteration's surrogate rows need: the largest
+// subset's rows times the widest node row of the networks the plan's cases
+// use (none when every network is evaluated at the support pixels).  Sized
+// outside graph captures (lmmew_osem_graph calls it before capturing).
+int coarse_scratch(lmmew_ctx *ctx, lmmew_plan *p)
+{
+    size_t need = 0;
+    for (int c = 0; c < p->ncases; ++c) {
+        const lmmew_mlp *m = case_model(ctx, p, c);
+        if (m && m->grid > 1) need = std::max(need, (size_t)std::max(p->max_rows, 1) * m->ldc);
+    }
+    if (need <= p->C_cap) return LMMEW_OK;
+    dfree(p->d_C);
+    p->d_C = nullptr;
+    p->C_cap = 0;
+    HIPCHK(ctx, dalloc(&p->d_C, need));
+    p->C_cap = need;
+    return LMMEW_OK;
+}
+
+// The network's scattered densities of a.rows rows (a holds the events, the
+// parameters and the density factors) added to out [rows][Qp]: evaluated at
+// every support pixel, or, with a coarse grid, at the network's nodes into
+// C [rows][ldc] and interpolated from there.
+hipError_t net_rows(const lmmew_ctx *ctx, const lmmew_mlp *m, MlpRowArgs a, float *out, float *C,
+                    hipStream_t st)
+{
+    if (m->grid <= 1) {
+        a.pix_xy = ctx->d_pix;
+        a.npix = ctx->S.Qm;
+        a.ld = ctx->S.Qp;
+        a.assign = 0;
+        a.A = out;
+        return mlp_rows(ctx->S, a, st);
+    }
+    if (!C) return hipErrorInvalidValue;
+    a.pix_xy = m->d_cnode;
+    a.npix = m->ncn;
+    a.ld = m->ldc;
+    a.assign = 1;
+    a.A = C;
+    hipError_t e = mlp_rows(ctx->S, a, st);
+    if (e == hipSuccess)
+        e = launch_coarse_interp(ctx->S, C, m->ldc, m->d_cidx, m->d_cw, a.rows, out, st);
+    return e;
+}
+
 int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
              float *dst = nullptr)
 {
@@ -1040,6 +1100,10 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
         const bool profm = p->prof && sub.rows > 0;
         if (profm) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
         const int *cr = p->case_rows.data() + (size_t)s * (p->ncases + 1);
+        {
+            const int rc = coarse_scratch(ctx, p);
+            if (rc != LMMEW_OK) return rc;
+        }
         for (int c0 = 0; c0 < p->ncases;) {
             const lmmew_mlp *m = case_model(ctx, p, c0);
             int c1 = c0 + 1;
@@ -1047,19 +1111,19 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
             const int r0 = cr[c0], r1 = cr[c1];
             if (r1 > r0) {
                 MlpRowArgs a{};
-                a.pix_xy = ctx->d_pix;
                 a.dirs = ctx->d_dirs;
                 a.ev_bin = p->d_bin + sub.row0 + r0;
                 a.ev_ang = p->d_ang + sub.row0 + r0;
                 a.ev_E = p->d_E + sub.row0 + r0;
                 a.rows = r1 - r0;
-                a.A = out + (size_t)r0 * ctx->S.Qp;
                 a.P = m->P;
                 a.c0 = (float)m->c0;
                 a.floor_ = (float)m->floor_;
                 a.ev_scale = p->d_sidx + sub.row0 + r0;
                 a.case_scale = p->d_cscale;
-                HIPCHK(ctx, mlp_rows(ctx->S, a, st));
+                // runs follow each other on the stream: each reuses the
+                // node-value scratch from its start
+                HIPCHK(ctx, net_rows(ctx, m, a, out + (size_t)r0 * ctx->S.Qp, p->d_C, st));
             }
             c0 = c1;
         }
@@ -1641,6 +1705,10 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
         const int rm = sync_maps(ctx, p, st);
         if (rm != LMMEW_OK) return rm;
     }
+    if (!p->d_Acache && ctx->mlp) {
+        const int rc = coarse_scratch(ctx, p);   // no allocation inside the capture
+        if (rc != LMMEW_OK) return rc;
+    }
     if (!p->gexec || p->g_iters != n_iters || p->g_sens != sens || p->g_lambda != lambda ||
         p->g_jt != p->JT || p->g_gen != plan_model_gen(ctx, p) || p->g_cache != p->d_Acache ||
         p->g_tab != plan_ptab(ctx, p) || p->g_psft != ctx->d_psft) {
@@ -2018,6 +2086,7 @@ void free_mlp(lmmew_mlp *m)
     dfree(m->X); dfree(m->Z1); dfree(m->Z2); dfree(m->Z3); dfree(m->H3); dfree(m->dZ); dfree(m->dH);
     dfree(m->y); dfree(m->dy); dfree(m->sq); dfree(m->H1b); dfree(m->H2b); dfree(m->dZb);
     dfree(m->idx); dfree(m->dloss); dfree(m->part); dfree(m->split); dfree(m->dsum);
+    dfree(m->d_cnode); dfree(m->d_cidx); dfree(m->d_cw);
 }
 
 int mlp_workspace(lmmew_ctx *ctx, lmmew_mlp *m, int M)
@@ -2612,7 +2681,9 @@ static int scale_sums(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev, doub
     if (rc != LMMEW_OK) return rc;
     const int Qp = ctx->S.Qp;
     double *d_rs = nullptr;
+    float *d_C = nullptr;
     hipError_t e = dalloc(&d_rs, 2 * (size_t)std::max(pl->max_rows, 1));
+    if (e == hipSuccess && m->grid > 1) e = dalloc(&d_C, (size_t)std::max(pl->max_rows, 1) * m->ldc);
     std::vector<double> h(2 * (size_t)std::max(pl->max_rows, 1));
     for (int w = 0; w < ctx->S.nwin; ++w) ex[w] = net[w] = 0.0;
     for (int s = 0; s < pl->nsub && e == hipSuccess && rc == LMMEW_OK; ++s) {
@@ -2625,17 +2696,15 @@ static int scale_sums(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev, doub
             e = hipMemsetAsync(pl->d_A, 0, (size_t)sub.rows * Qp * sizeof(float), st);
         if (e == hipSuccess) {
             MlpRowArgs a{};                                        // the network alone
-            a.pix_xy = ctx->d_pix;
             a.dirs = ctx->d_dirs;
             a.ev_bin = pl->d_bin + sub.row0;
             a.ev_ang = pl->d_ang + sub.row0;
             a.ev_E = pl->d_E + sub.row0;
             a.rows = sub.rows;
-            a.A = pl->d_A;
             a.P = m->P;
             a.c0 = (float)m->c0;
             a.floor_ = (float)m->floor_;
-            e = mlp_rows(ctx->S, a, st);
+            e = net_rows(ctx, m, a, pl->d_A, d_C, st);
         }
         if (e == hipSuccess) e = launch_row_sums(pl->d_A, sub.rows, Qp, d_rs + sub.rows, st);
         if (e == hipSuccess)
@@ -2652,6 +2721,7 @@ static int scale_sums(lmmew_ctx *ctx, lmmew_mlp *m, const lmmew_events *ev, doub
     const hipError_t e2 = hipStreamSynchronize(st);
     if (e == hipSuccess) e = e2;
     dfree(d_rs);
+    dfree(d_C);
     lmmew_plan_destroy(pl);
     if (rc != LMMEW_OK) return rc;
     if (e != hipSuccess) return hipfail(ctx, e, "scatter scale fit");
@@ -2707,6 +2777,82 @@ int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *m)
     ctx->mlp = m;
     ctx->model_gen++;
     return LMMEW_OK;
+}
+
+int lmmew_mlp_set_grid(lmmew_mlp *m, int grid)
+{
+    if (!m || !m->ctx) return LMMEW_EINVAL;
+    lmmew_ctx *ctx = m->ctx;
+    if (grid < 1 || grid > 8) return fail(ctx, LMMEW_EINVAL, "grid must be 1 to 8 pixels");
+    if (grid == m->grid) return LMMEW_OK;
+    // kernels still reading the old tables finish before they are replaced
+    HIPCHK(ctx, hipDeviceSynchronize());
+    dfree(m->d_cnode); dfree(m->d_cidx); dfree(m->d_cw);
+    m->d_cnode = nullptr;
+    m->d_cidx = nullptr;
+    m->d_cw = nullptr;
+    m->ncn = m->ldc = 0;
+    m->grid = 1;
+    ctx->model_gen++;
+    if (grid == 1) return LMMEW_OK;
+    // Node (u, v) sits at the centre of pixel (grid u, grid v); support pixel
+    // (ix, iy) lies in the cell of nodes (ix / grid, iy / grid) and the next
+    // ones, at fractions fx = (ix mod grid) / grid, fy likewise.  Only nodes
+    // with a non-zero weight are kept, numbered row by row; a zero-weight
+    // corner names the cell's first node.
+    const int n = ctx->sys.n, Qm = ctx->S.Qm, Qp = ctx->S.Qp;
+    const double pix = ctx->sys.pixel_mm, R = ctx->R;
+    std::map<std::pair<int, int>, int> id;                         // (v, u) -> node
+    std::vector<std::array<std::pair<int, int>, 4>> corner(Qm);
+    std::vector<float4> w(Qp, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int i = 0; i < Qm; ++i) {
+        const int q = ctx->pixq[i], ix = q % n, iy = q / n;
+        const int u0 = ix / grid, v0 = iy / grid;
+        const double fx = (double)(ix - grid * u0) / grid, fy = (double)(iy - grid * v0) / grid;
+        const double wk[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+        const std::pair<int, int> ck[4] = {{v0, u0}, {v0, u0 + 1}, {v0 + 1, u0}, {v0 + 1, u0 + 1}};
+        for (int k = 0; k < 4; ++k) {
+            corner[i][k] = wk[k] > 0 ? ck[k] : ck[0];
+            if (wk[k] > 0) id.emplace(ck[k], 0);
+        }
+        w[i] = make_float4((float)wk[0], (float)wk[1], (float)wk[2], (float)wk[3]);
+    }
+    const int ncn = (int)id.size();
+    const int ldc = (ncn + kWave - 1) / kWave * kWave;
+    std::vector<float2> node(ldc);
+    int k = 0;
+    for (auto &kv : id) {
+        kv.second = k;
+        node[k++] = make_float2((float)((grid * kv.first.second + 0.5) * pix - R),
+                                (float)((grid * kv.first.first + 0.5) * pix - R));
+    }
+    for (int j = ncn; j < ldc; ++j) node[j] = node[ncn - 1];
+    std::vector<int4> idx(Qp, make_int4(0, 0, 0, 0));
+    for (int i = 0; i < Qm; ++i)
+        idx[i] = make_int4(id[corner[i][0]], id[corner[i][1]], id[corner[i][2]], id[corner[i][3]]);
+    hipError_t e = dalloc(&m->d_cnode, ldc);
+    if (e == hipSuccess) e = dalloc(&m->d_cidx, Qp);
+    if (e == hipSuccess) e = dalloc(&m->d_cw, Qp);
+    if (e == hipSuccess) e = hipMemcpy(m->d_cnode, node.data(), ldc * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_cidx, idx.data(), Qp * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_cw, w.data(), Qp * sizeof(float4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dfree(m->d_cnode); dfree(m->d_cidx); dfree(m->d_cw);
+        m->d_cnode = nullptr;
+        m->d_cidx = nullptr;
+        m->d_cw = nullptr;
+        return hipfail(ctx, e, "surrogate node tables");
+    }
+    m->grid = grid;
+    m->ncn = ncn;
+    m->ldc = ldc;
+    return LMMEW_OK;
+}
+
+int lmmew_mlp_grid_nodes(const lmmew_mlp *m)
+{
+    if (!m) return LMMEW_EINVAL;
+    return m->grid > 1 ? m->ncn : (m->ctx ? m->ctx->S.Qm : LMMEW_EINVAL);
 }
 
 }  // extern "C"

@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
     for (int p = 0; p < kRowGroups; ++p) {
         ip[p] = blockIdx.x * kPixPerWG + wv * 16 * kRowGroups + 16 * p + r;
-        xy[p] = a.pix_xy[min(ip[p], S.Qp - 1)];
+        xy[p] = a.pix_xy[min(ip[p], a.npix - 1)];
     }
     // Output unit as MFMA: A fragment of chunk c holds w4 in row 0 (the lanes
     // with r = 0) and zeros elsewhere, in the item order of the B fragments
@@ -823,9 +823,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
         for (int p = 0; p < kRowGroups; ++p) {
             const float y = yacc[p][0];
-            if (g == 0 && ip[p] < S.Qm) {
+            if (g == 0 && ip[p] < a.npix) {
                 const float v = fmaxf(__expf(y + b4 + a.c0) - a.floor_, 0.f);
-                a.A[(long)e * S.Qp + ip[p]] += v * sc;
+                float *const out = a.A + (long)e * a.ld + ip[p];
+                if (a.assign)
+                    *out = v * sc;
+                else
+                    *out += v * sc;
             }
         }
     }
@@ -961,6 +965,7 @@ hipError_t mlp_targets(const float *raw, long n, float floor_, float c0, float *
 
 hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
 {
+    if (a.npix < 1 || a.ld < a.npix) return hipErrorInvalidValue;
     // grid.y is limited to 65535 workgroups: launch in slices of rows
     constexpr int kSlice = 32768 * kRowsPerWG;
     for (int r0 = 0; r0 < a.rows; r0 += kSlice) {
@@ -969,8 +974,8 @@ hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
         b.ev_bin += r0;
         b.ev_ang += r0;
         b.ev_E += r0;
-        b.A += (long)r0 * S.Qp;
-        hipLaunchKernelGGL(k_mlp_rows, dim3(nblk(S.Qp, kPixPerWG), nblk(b.rows, kRowsPerWG)),
+        b.A += (long)r0 * a.ld;
+        hipLaunchKernelGGL(k_mlp_rows, dim3(nblk(a.npix, kPixPerWG), nblk(b.rows, kRowsPerWG)),
                            dim3(kThreads), 0, st, S, b);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

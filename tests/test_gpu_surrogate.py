@@ -164,6 +164,85 @@ def test_inference_kernel_matches_network(env, trained):
         assert mx <= 2e-2 and l2 <= 1e-2, (name, mx, l2)
 
 
+def _features(p, ev, j, x, y):
+    R, db = p.R, p.fov / p.nb
+    th = 2 * np.pi * ev["angle"][j] / p.na
+    c, s = np.cos(th), np.sin(th)
+    uq, dq = -x * s + y * c, R - (x * c + y * s)
+    ub = -R + (ev["bin"][j] + 0.5) * db
+    return [(ub - uq) / R, dq / R, uq / R, c, s, (ev["energy"][j] - 180.0) / 120.0]
+
+
+@pytest.mark.parametrize("grid", [2, 3])
+def test_coarse_grid_rows_interpolate_the_network(env, trained, grid):
+    """lmmew_mlp_set_grid: the scattered part of the surrogate's rows equals the
+    bilinear interpolation of the FP64 network at the nodes around each support
+    pixel, nodes and weights derived here from the definition in the header
+    (node (u, v) at the centre of pixel (g u, g v); pixel (ix, iy) between
+    nodes (ix // g, iy // g) and the next ones, fractions (ix % g) / g).  A
+    grid of 3 on the 16-pixel side also needs nodes beyond the last pixel.
+    Same bar as the kernel at every pixel (2 % max, 1 % L2 of the density);
+    the node count is exact; back at grid 1 the rows are bitwise those of the
+    network at every pixel."""
+    from oracle import mlp_ref
+
+    lm, p, act, rois, ctx, orc = env
+    net, _ = trained
+    ev = orc.sample_events(act, 10, seed=7)
+    ev["energy"] = ev["energy"].astype(np.float32)
+    d = _dev(lm, ev)
+    ctx.set_scatter_model(net)
+    full0 = ctx.rows(d, part=0).cpu().numpy()
+    net.set_grid(grid)
+    try:
+        sur = ctx.rows(d, part=0).cpu().numpy()
+        nodes = net.grid_nodes()
+    finally:
+        net.set_grid(1)
+    full1 = ctx.rows(d, part=0).cpu().numpy()
+    ctx.set_scatter_model(None)
+    prim = ctx.rows(d, part=2).cpu().numpy()
+    assert np.array_equal(full0, full1)
+
+    qs = np.flatnonzero(orc.support)
+    n = p.n
+    stencil, used = [], set()
+    for q in qs:
+        ix, iy = q % n, q // n
+        u0, v0 = ix // grid, iy // grid
+        fx, fy = (ix % grid) / grid, (iy % grid) / grid
+        corners = [((u0, v0), (1 - fx) * (1 - fy)), ((u0 + 1, v0), fx * (1 - fy)),
+                   ((u0, v0 + 1), (1 - fx) * fy), ((u0 + 1, v0 + 1), fx * fy)]
+        corners = [(k, wk) for k, wk in corners if wk > 0]
+        used.update(k for k, _ in corners)
+        stencil.append(corners)
+    assert nodes == len(used)
+    node = sorted(used)
+    pos = {k: ((grid * k[0] + 0.5) * p.pix - p.R, (grid * k[1] + 0.5) * p.pix - p.R)
+           for k in node}
+    theta, c0, fl = net.get_params()
+    want = np.zeros((10, qs.size))
+    for j in range(10):
+        feats = np.array([_features(p, ev, j, *pos[k]) for k in node], np.float64)
+        y_ref, _ = mlp_ref.forward(theta.astype(np.float64), feats)
+        dens = dict(zip(node, np.maximum(np.exp(y_ref + c0) - fl, 0)))
+        want[j] = [sum(wk * dens[k] for k, wk in st) for st in stencil]
+    got = (sur - prim)[:, qs]
+    mx = np.abs(got - want).max() / want.max()
+    l2 = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"grid {grid}: {nodes} nodes for {qs.size} pixels; max {mx:.3e} L2 {l2:.3e}")
+    assert mx <= 2e-2 and l2 <= 1e-2, (mx, l2)
+
+
+def test_coarse_grid_rejects_bad_spacing(env, trained):
+    lm, p, act, rois, ctx, orc = env
+    net, _ = trained
+    for g in (0, 9, -1):
+        with pytest.raises(lm.LmmewError):
+            net.set_grid(g)
+    assert net.grid_nodes() == ctx.support_size
+
+
 def test_surrogate_roi_bias_and_gain(env):
     """Trained on random water-ellipse attenuation maps (the network has no
     map input), used on the disk phantom it never saw."""
@@ -379,9 +458,23 @@ def test_surrogate_region_bias_at_128x128():
     relw = uptakes(lam) / up_ex - 1.0
     print(f"  per window: mean {relw.mean():+.4f}, mean |.| {np.abs(relw).mean():.4f}, "
           f"max |.| {np.abs(relw).max():.4f}")
+    # the network at nodes every 2 pixels, refitted per window
+    net.set_grid(2)
+    for c in range(w.n_cases):
+        e = evs[c]
+        idx = np.linspace(0, e["bin"].size - 1, 256).astype(np.int64)
+        k = ctxs[c].scatter_scale_fit_windows(net, lm.events_to_device(
+            {q: e[q][idx] for q in ("bin", "angle", "energy")}))
+        ctxs[c].set_scatter_scale_windows(k)
+    lam = lam0.clone()
+    plan.osem_graph(10, sens, lam)
+    relg = uptakes(lam) / up_ex - 1.0
+    net.set_grid(1)
+    print(f"  per window, nodes every 2 pixels: mean {relg.mean():+.4f}, mean |.| "
+          f"{np.abs(relg).mean():.4f}, max |.| {np.abs(relg).max():.4f}")
     ctxs[0].set_scatter_model(None)
-    assert abs(rel.mean()) <= 0.01 and abs(relw.mean()) <= 0.01
-    assert np.abs(rel).max() < 0.15 and np.abs(relw).max() < 0.15
+    assert abs(rel.mean()) <= 0.01 and abs(relw.mean()) <= 0.01 and abs(relg.mean()) <= 0.01
+    assert max(np.abs(v).max() for v in (rel, relw, relg)) < 0.15
 
 
 def test_context_destroyed_before_its_network():
