@@ -291,13 +291,16 @@ def headline(args, sections, out):
         out["cached_rows"] = cached_rows(plan, sens, lam0, J, Qp, K)
 
     if "surrogate" in sections and args.surrogate_untrained:
-        # inference cost only (a random-init network; for profiling runs)
+        # inference cost only (a random-init network on the first of the
+        # evaluation grids; for profiling runs)
         net = ctxs[0].mlp(seed=2)
+        net.set_grid(args.surrogate_grids[0])
         ctxs[0].set_scatter_model(net)
         lam = lam0.clone()
         el_s, ks = _timed_iterations(plan, sens, lam, W, K)
         mlp_ms, mlp_n = ks["k_mlp_rows"]
         out["surrogate"] = {"untrained": True, "value": J * K / el_s,
+                            "evaluation_grid": args.surrogate_grids[0],
                             "s_per_iteration": el_s / K, "avg_ms_per_subset": mlp_ms / mlp_n}
         ctxs[0].set_scatter_model(None)
     elif "surrogate" in sections:

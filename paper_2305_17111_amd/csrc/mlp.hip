@@ -963,6 +963,49 @@ hipError_t mlp_targets(const float *raw, long n, float floor_, float c0, float *
     return hipGetLastError();
 }
 
+// Scattered densities of the surrogate at the support pixels from its values
+// at the coarse nodes: A[e][q] += w.x C[e][i.x] + w.y C[e][i.y] + w.z C[e][i.z]
+// + w.w C[e][i.w], with the four bilinear weights and nodes of pixel q.  A
+// thread keeps its pixel's stencil for kInterpRows rows; a row's nodes sit
+// close together in C, so the gathers of neighbouring pixels share cache lines.
+constexpr int kInterpRows = 32;
+
+__global__ __launch_bounds__(256) void k_coarse_interp(const DevSys S, const float *__restrict__ C,
+                                                       int ldc, const int4 *__restrict__ idx,
+                                                       const float4 *__restrict__ w, int rows,
+                                                       float *__restrict__ A)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= S.Qm) return;
+    const int4 n = idx[q];
+    const float4 f = w[q];
+    const int e0 = blockIdx.y * kInterpRows, e1 = min(e0 + kInterpRows, rows);
+    for (int e = e0; e < e1; ++e) {
+        const float *c = C + (size_t)e * ldc;
+        float v = f.x * c[n.x];
+        v = fmaf(f.y, c[n.y], v);
+        v = fmaf(f.z, c[n.z], v);
+        v = fmaf(f.w, c[n.w], v);
+        A[(size_t)e * S.Qp + q] += v;
+    }
+}
+
+hipError_t launch_coarse_interp(const DevSys &S, const float *C, int ldc, const int4 *idx,
+                                const float4 *w, int rows, float *A, hipStream_t st)
+{
+    // grid.y is limited to 65535 workgroups: launch in slices of rows
+    constexpr int kSlice = 32768 * kInterpRows;
+    for (int r0 = 0; r0 < rows; r0 += kSlice) {
+        const int n = rows - r0 < kSlice ? rows - r0 : kSlice;
+        hipLaunchKernelGGL(k_coarse_interp, dim3((S.Qm + 255) / 256, (n + kInterpRows - 1) / kInterpRows),
+                           dim3(256), 0, st, S, C + (size_t)r0 * ldc, ldc, idx, w, n,
+                           A + (size_t)r0 * S.Qp);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
 {
     if (a.npix < 1 || a.ld < a.npix) return hipErrorInvalidValue;
