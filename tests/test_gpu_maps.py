@@ -114,6 +114,39 @@ def test_maps_plan_with_surrogate_equals_independent(small_maps):
             c.set_scatter_model(None)
 
 
+def test_maps_plan_with_coarse_grid_networks_equals_independent(small_maps):
+    """Cases whose networks are evaluated on different coarse grids (2 and 3
+    pixels, R28) in one graph-captured plan: each case reconstructs bitwise
+    as in a plan of its own context."""
+    import torch
+
+    lm, p, act, maps, ctxs = small_maps
+    net = ctxs[0].mlp(seed=4)
+    net.fit(3000, epochs=1, batch=4096, lr=2e-3, floor_frac=3e-2, seed=1)
+    theta, c0, fl = net.get_params()
+    own = ctxs[1].mlp(seed=0)
+    own.set_params(theta, c0, fl)
+    net.set_grid(2)
+    own.set_grid(3)
+    counts = [500, 700]
+    evs = [synth.generic_events(p, act, n, 970 + c) for c, n in enumerate(counts)]
+    offs = [0, counts[0], sum(counts)]
+    sens = _sens_stack(ctxs[:2], 4)
+    lam0 = torch.from_numpy(synth.fov_support(p).astype(np.float32)).cuda()
+    batched = lam0.repeat(2, 1).contiguous()
+    ctxs[0].set_scatter_model(net)
+    ctxs[1].set_scatter_model(own)
+    try:
+        lm.plan_maps(ctxs[:2], lm.events_to_device(_cat(evs)), 4, offs).osem_graph(2, sens, batched)
+        for c, e in enumerate(evs):
+            lam = lam0.clone()
+            ctxs[c].plan(lm.events_to_device(e), 4).osem_iter(2, sens[c], lam)
+            assert torch.equal(lam, batched[c]), c
+    finally:
+        for c in ctxs:
+            c.set_scatter_model(None)
+
+
 def test_maps_plan_rejects_other_systems(small_maps):
     import torch
 

@@ -279,7 +279,12 @@ def test_surrogate_roi_bias_and_gain(env):
     assert np.all(np.abs(bias_none[:2]) >= 0.05), bias_none
 
 
-def test_surrogate_graph_equals_eager(env, trained):
+@pytest.mark.parametrize("grid", [1, 2])
+def test_surrogate_graph_equals_eager(env, trained, grid):
+    """One captured graph equals eager iterations, also with the network on a
+    coarse grid (its node-value scratch is sized before the capture); a new
+    grid after the capture is picked up by the next graph launch; cached
+    rows of the same model give the same iterations."""
     import torch
 
     lm, p, act, rois, ctx, orc = env
@@ -289,12 +294,26 @@ def test_surrogate_graph_equals_eager(env, trained):
     sens = ctx.sensitivity(4)
     ctx.set_scatter_model(net)
     plan = ctx.plan(d, 4)
-    a = torch.from_numpy(orc.support.astype(np.float32)).cuda()
-    b = a.clone()
-    plan.osem_iter(3, sens, a)
-    plan.osem_graph(3, sens, b)
-    ctx.set_scatter_model(None)
-    assert torch.equal(a, b)
+    net.set_grid(grid)
+    try:
+        a = torch.from_numpy(orc.support.astype(np.float32)).cuda()
+        lam0 = a.clone()
+        b, c = a.clone(), a.clone()
+        plan.osem_iter(3, sens, a)
+        plan.osem_graph(3, sens, b)
+        plan.cache_rows(True)
+        plan.osem_iter(3, sens, c)
+        plan.cache_rows(False)
+        assert torch.equal(a, b) and torch.equal(a, c)
+        if grid > 1:
+            net.set_grid(3)
+            e, f = lam0.clone(), lam0.clone()
+            plan.osem_iter(3, sens, e)
+            plan.osem_graph(3, sens, f)
+            assert torch.equal(e, f) and not torch.equal(e, a)
+    finally:
+        net.set_grid(1)
+        ctx.set_scatter_model(None)
 
 
 def test_scatter_scale_multiplies_the_network_density(env, trained):
