@@ -19,6 +19,7 @@
 // fragment (see k_mlp_rows).
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 
 #include "internal.h"
@@ -419,7 +420,8 @@ __global__ __launch_bounds__(256) void k_targets(const float *raw, long n, float
 // fused inference: for every (row e, support pixel i) of a subset, add the
 // surrogate's once-scattered density max(exp(y + c0) - floor, 0) to A[e][i].
 //
-// Workgroup: 8 wavefronts, 256 pixels, kRowsPerWG rows; two workgroups per CU
+// Workgroup: 8 wavefronts, each with its own task of 32 positions x kRowsPerWG
+// rows (consecutive tasks of a flat list); two workgroups per CU
 // (the LDS holds two copies of the network) and at most 128 VGPRs, so that four
 // wavefronts share every SIMD and one's vector work fills the gaps of another's
 // matrix work (9 % faster than two per SIMD with 145 VGPRs and no spill; the
@@ -448,7 +450,6 @@ constexpr int kRowsPerWG = 32;
 constexpr int kRowGroups = 2;                  // 16-pixel groups per wavefront
 constexpr int kWaves = 8;                      // wavefronts per workgroup
 constexpr int kThreads = 64 * kWaves;
-constexpr int kPixPerWG = kWaves * 16 * kRowGroups;
 constexpr int kFrag = 8 * 4 * 4 * 16;          // A fragments per hidden layer: (ib, c, g, r)
 constexpr int kFrag1 = 8 * 4 * 16;             // first layer: (ib, g, r)
 
@@ -611,11 +612,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     const float keep = g == 3 ? 0.f : 1.f;
     const float lo_sign = g == 1 ? -1.f : 0.f;
     const unsigned ones = g == 0 ? bf16_pair(1.f, 1.f) : 0u;
+    // A wavefront's task: one block of 32 positions of one block of rows, from
+    // a flat list (row block major) shared by the workgroups, so that only the
+    // last position block of each row block carries padding.  The tasks past
+    // the end of the list (in the last workgroup) return; no barrier follows.
+    const int npb = (a.npix + 16 * kRowGroups - 1) / (16 * kRowGroups);
+    const int task = (int)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(wv);
+    const int rb = task / npb, pb = task - rb * npb;
+    if (rb * kRowsPerWG >= a.rows) return;
     int ip[kRowGroups];
     float2 xy[kRowGroups];
 #pragma unroll
     for (int p = 0; p < kRowGroups; ++p) {
-        ip[p] = blockIdx.x * kPixPerWG + wv * 16 * kRowGroups + 16 * p + r;
+        ip[p] = pb * 16 * kRowGroups + 16 * p + r;
         xy[p] = a.pix_xy[min(ip[p], a.npix - 1)];
     }
     // Output unit as MFMA: A fragment of chunk c holds w4 in row 0 (the lanes
@@ -629,7 +638,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
         for (int t = 0; t < 8; ++t)
             w4f[c][t] = r == 0 ? (_Float16)a.P[kOffW4 + 32 * c + 16 * (t >> 2) + 4 * g + (t & 3)]
                                : (_Float16)0.f;
-    const int e0 = blockIdx.y * kRowsPerWG, e1 = min(e0 + kRowsPerWG, a.rows);
+    const int e0 = rb * kRowsPerWG, e1 = min(e0 + kRowsPerWG, a.rows);
     for (int e = e0; e < e1; ++e) {
         // An opaque zero offset keeps the weight reads inside the row loop:
         // hoisted, they would take 512 registers and leave one wavefront per SIMD.
@@ -1009,7 +1018,8 @@ hipError_t launch_coarse_interp(const DevSys &S, const float *C, int ldc, const 
 hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
 {
     if (a.npix < 1 || a.ld < a.npix) return hipErrorInvalidValue;
-    // grid.y is limited to 65535 workgroups: launch in slices of rows
+    // slices of at most 2^20 rows keep a launch's task count (position blocks
+    // x row blocks) far inside the grid's range
     constexpr int kSlice = 32768 * kRowsPerWG;
     for (int r0 = 0; r0 < a.rows; r0 += kSlice) {
         MlpRowArgs b = a;
@@ -1018,8 +1028,9 @@ hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
         b.ev_ang += r0;
         b.ev_E += r0;
         b.A += (long)r0 * a.ld;
-        hipLaunchKernelGGL(k_mlp_rows, dim3(nblk(a.npix, kPixPerWG), nblk(b.rows, kRowsPerWG)),
-                           dim3(kThreads), 0, st, S, b);
+        const long tasks = (long)nblk(a.npix, 16 * kRowGroups) * nblk(b.rows, kRowsPerWG);
+        if (tasks + kWaves > INT_MAX) return hipErrorInvalidValue;   // 32-bit task index
+        hipLaunchKernelGGL(k_mlp_rows, dim3(nblk(tasks, kWaves)), dim3(kThreads), 0, st, S, b);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
