@@ -18,6 +18,10 @@ every 4 pixels, the support pixels interpolated bilinearly (`surrogate_grid2`,
 `surrogate_grid4`; each refitted per patient and window, with its own timing and
 region bias).
 
+Also beside them: the exact model with its scattered part evaluated at node
+pixels every 2 pixels and interpolated (`exact_pixel_grid2`, an approximation
+with its own region bias against the exact model).
+
 Beside them (`extras`): the 64x64 workload (50k events, 8 subsets) with the
 path-parameter table, 64 batched cases of it, continuous positions, the
 cached-row mode (a different mode, never the headline), coarser scatter grids,
@@ -55,7 +59,7 @@ PEAK_BF16_FLOPS = 2.5e15
 PEAK_HBM_BYTES_PER_S = 8.0e12
 
 SECTIONS = ("exact", "surrogate", "cpu", "calib", "64x64", "batched", "positions", "cached",
-            "scatter_grids", "three_d", "small_surrogate")
+            "scatter_grids", "three_d", "small_surrogate", "pixel_grid")
 
 
 def workload_desc(name, p, J, nsub):
@@ -241,7 +245,7 @@ def headline(args, sections, out):
     assert bool(torch.isfinite(lam).all())
     row_ms, row_n = k["k_row"]
     achieved = terms * K / (row_ms * 1e-3)
-    compare = "surrogate" in sections and not args.surrogate_untrained
+    compare = ("surrogate" in sections and not args.surrogate_untrained) or "pixel_grid" in sections
     if compare and roi_iters > W + K:
         plan.osem_graph(roi_iters - W - K, sens, lam)
     up_ex = uptakes(lam.cpu().numpy().astype(np.float64))
@@ -285,6 +289,23 @@ def headline(args, sections, out):
         "model_terms_per_iteration": {"evaluated": terms, "unpruned": full_terms},
     })
     setup_total = dict(setup)
+    if "pixel_grid" in sections:
+        # the exact model with its scattered part at node pixels every 2
+        # pixels, interpolated (an approximation; not the headline)
+        for c in ctxs:
+            c.set_scatter_pixel_grid(2)
+        lam = lam0.clone()
+        el_g, _ = _timed_iterations(plan, sens, lam, W, K)
+        if roi_iters > W + K:
+            plan.osem_graph(roi_iters - W - K, sens, lam)
+        rel_g = uptakes(lam.cpu().numpy().astype(np.float64)) / up_ex - 1.0
+        out["exact_pixel_grid2"] = {
+            "value": J * K / el_g, "unit": "events*iterations/s", "s_per_iteration": el_g / K,
+            "speedup_vs_exact": el / el_g,
+            "what": "exact model, scattered part at node pixels every 2 pixels, interpolated",
+            "roi_uptake_vs_exact": {"iterations": roi_iters, **_bias(rel_g)}}
+        for c in ctxs:
+            c.set_scatter_pixel_grid(1)
     if "cached" in sections:
         # not the headline: the rows of every subset computed once (52 GB at
         # this size), the iterations then read them (HBM-bound)

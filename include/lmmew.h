@@ -565,6 +565,33 @@ int lmmew_mlp_set_grid(lmmew_mlp *mlp, int grid);
  * node count with a coarse grid, else the support size.  EINVAL for NULL. */
 int lmmew_mlp_grid_nodes(const lmmew_mlp *mlp);
 
+/* Scatter at a coarser pixel resolution for the exact model (the paper's
+ * conclusion and its appendix on 3-D requirements name scatter at a coarser
+ * resolution as the way to cut the once-scattered term's cost; Eq. (5)).
+ * grid = 1 (the default): the scattered part of every row a_jq (Eq. (3)-(5))
+ * at every support pixel.  grid = g in 2..8 (planar model): the scattered
+ * part is evaluated only at node pixels and interpolated; the unscattered
+ * part stays at every support pixel, and the sensitivity is unchanged.
+ * Support pixel (ix, iy) takes the bilinear combination of the pixels
+ * (g u0, g v0), (g u0 + g, g v0), (g u0, g v0 + g), (g u0 + g, g v0 + g),
+ * u0 = ix / g, v0 = iy / g (integer division), with weights from
+ * fx = (ix mod g) / g and fy = (iy mod g) / g; corners outside the support
+ * or the grid are dropped and the remaining weights renormalised (a pixel
+ * with no corner in the support keeps its own value).  A node pixel's value
+ * is the one the full-resolution model gives it.  Applies to every row the
+ * context's exact model produces: OSEM, lmmew_forward, lmmew_backproject,
+ * lmmew_rows (parts 0, 1, 3), the surrogate's labels and scale fits.  In a
+ * plan over several maps every context needs the same grid.  Plans keep a
+ * node-value scratch of their largest subset's rows times the node count.
+ * Synchronises the device (the old node tables may still be read) and the
+ * stream.  Errors: EINVAL (NULL, grid outside 1..8, grid > 1 in 3-D),
+ * ENOMEM, EDEVICE. */
+int lmmew_set_scatter_pixel_grid(lmmew_ctx *ctx, int grid, hipStream_t stream);
+
+/* Pixels at which the exact scattered part is evaluated per event row: the
+ * node count with a coarse grid, else the support size.  EINVAL for NULL. */
+int lmmew_scatter_pixel_grid_nodes(const lmmew_ctx *ctx);
+
 /* ---------------------------------------------------------------------------
  * Figures of merit for regional uptake (Sec. 3.1.4)
  * ------------------------------------------------------------------------- */

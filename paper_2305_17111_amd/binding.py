@@ -91,6 +91,8 @@ def _load():
         "lmmew_mlp_get_params": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lmmew_mlp_set_params": (i32, [vp, vp, C.c_double, C.c_double]),
         "lmmew_mlp_set_grid": (i32, [vp, i32]),
+        "lmmew_set_scatter_pixel_grid": (i32, [vp, i32, vp]),
+        "lmmew_scatter_pixel_grid_nodes": (i32, [vp]),
         "lmmew_mlp_grid_nodes": (i32, [vp]),
         "lmmew_mlp_forward": (i32, [vp, vp, vp, i64, vp, vp]),
         "lmmew_mlp_grad": (i32, [vp, vp, vp, vp, i64, vp, C.POINTER(C.c_double), vp]),
@@ -316,6 +318,16 @@ class Context:
             out = torch.empty((e.n, self.Q), device="cuda", dtype=torch.float32)
         self._check(_load().lmmew_rows(self._h, C.byref(e), int(part), _ptr(out), _stream()))
         return out
+
+    def set_scatter_pixel_grid(self, grid):
+        """Exact model: scattered part at node pixels every `grid` pixels,
+        interpolated to the support (1: every pixel)."""
+        self._check(_load().lmmew_set_scatter_pixel_grid(self._h, int(grid), _stream()))
+
+    def scatter_pixel_grid_nodes(self):
+        n = _load().lmmew_scatter_pixel_grid_nodes(self._h)
+        self._check(min(n, 0))
+        return n
 
     @property
     def support_size(self):

@@ -57,6 +57,15 @@ struct lmmew_ctx {
     float scatter_scale[LMMEW_MAX_WINDOWS] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
     std::vector<lmmew_mlp *> nets;    // networks created on this context (detached when it goes)
     int model_gen = 0;                // bumped whenever the scatter model changes
+    // The exact model's scattered part evaluated at node pixels every xgrid
+    // pixels and interpolated (lmmew_set_scatter_pixel_grid; 1: every pixel).
+    int xgrid = 1;
+    int xncn = 0, xldc = 0;           // node pixels; row stride of the node values
+    float2 *d_xnode = nullptr;        // [xldc] node positions (support pixels)
+    int4 *d_xidx = nullptr;           // [Qp] a support pixel's nodes (node indices)
+    float4 *d_xw = nullptr;           // [Qp] their weights
+    float *d_xgqa = nullptr;          // [na][xldc] pixel -> detector integrals at the nodes
+    float *d_xgqs = nullptr;          // [nsc][xldc] pixel -> scatter point integrals at the nodes
 };
 
 struct lmmew_mlp {
@@ -122,6 +131,8 @@ struct lmmew_plan {
     int2 *d_slist = nullptr;
     float *d_pvt = nullptr;           // [slist entry][JT] response factors
     MapTab *d_maps = nullptr;
+    MapTab *d_xmaps = nullptr;        // the cases' node tables (lmmew_set_scatter_pixel_grid)
+    std::vector<MapTab> xmaptab;      // what d_xmaps holds
     Chunk *d_chunks = nullptr;
     float *d_A = nullptr, *d_p = nullptr, *d_wt = nullptr;
     float *d_C = nullptr;             // network values at the coarse nodes of a subset's rows
@@ -274,6 +285,7 @@ void free_ctx(lmmew_ctx *c)
     dfree(c->d_scd); dfree(c->d_mu); dfree(c->d_gqa); dfree(c->d_gqs); dfree(c->d_sa);
     dfree(c->d_Sqa); dfree(c->d_ptab); dfree(c->d_resp); dfree(c->d_psft);
     dfree(c->d_respz); dfree(c->d_pixz); dfree(c->d_pixzd); dfree(c->d_scz); dfree(c->d_sczd);
+    dfree(c->d_xnode); dfree(c->d_xidx); dfree(c->d_xw); dfree(c->d_xgqa); dfree(c->d_xgqs);
 }
 
 void free_plan(lmmew_plan *p)
@@ -287,6 +299,7 @@ void free_plan(lmmew_plan *p)
     dfree(p->d_C);
     dfree(p->d_logp); dfree(p->d_ll); dfree(p->d_part); dfree(p->d_comp); dfree(p->d_nskip);
     dfree(p->d_maps);
+    dfree(p->d_xmaps);
     dfree(p->d_Acache);
     dfree(p->d_lamc);
     dfree(p->d_cscale);
@@ -935,6 +948,32 @@ int sync_maps(lmmew_ctx *ctx, lmmew_plan *p, hipStream_t st)
         p->cscale = cs;
     }
     if (p->maps.empty()) return LMMEW_OK;
+    if (ctx->xgrid > 1) {
+        // the cases' node tables for the exact scattered part at the nodes
+        std::vector<MapTab> xt(p->ncases);
+        for (int c = 0; c < p->ncases; ++c) {
+            const lmmew_ctx *m = p->maps[c];
+            if (m->xgrid != ctx->xgrid)
+                return fail(ctx, LMMEW_EINVAL,
+                            "every context of the plan needs the plan context's scatter pixel grid");
+            xt[c].g_qa = m->d_xgqa;
+            xt[c].g_qs = m->d_xgqs;
+            xt[c].sa = m->d_sa;
+            xt[c].ptab = nullptr;
+            xt[c].resp = m->d_resp;
+            xt[c].respz = m->d_respz;
+            xt[c].sz = m->d_scz;
+            xt[c].nsc = m->S.nsc;
+        }
+        if (!p->d_xmaps) HIPCHK(ctx, dalloc(&p->d_xmaps, (size_t)p->ncases));
+        if (xt.size() != p->xmaptab.size() ||
+            std::memcmp(xt.data(), p->xmaptab.data(), xt.size() * sizeof(MapTab)) != 0) {
+            HIPCHK(ctx, hipMemcpyAsync(p->d_xmaps, xt.data(), xt.size() * sizeof(MapTab),
+                                       hipMemcpyHostToDevice, st));
+            HIPCHK(ctx, hipStreamSynchronize(st));
+            p->xmaptab = xt;
+        }
+    }
     std::vector<MapTab> mt(p->ncases);
     for (int c = 0; c < p->ncases; ++c) {
         const lmmew_ctx *m = p->maps[c];
@@ -1031,6 +1070,7 @@ int coarse_scratch(lmmew_ctx *ctx, lmmew_plan *p)
         const lmmew_mlp *m = case_model(ctx, p, c);
         if (m && m->grid > 1) need = std::max(need, (size_t)std::max(p->max_rows, 1) * m->ldc);
     }
+    if (ctx->xgrid > 1) need = std::max(need, (size_t)std::max(p->max_rows, 1) * ctx->xldc);
     if (need <= p->C_cap) return LMMEW_OK;
     dfree(p->d_C);
     p->d_C = nullptr;
@@ -1085,6 +1125,44 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     RowArgs r = row_args(ctx, p, s);
     r.A = out;
     r.mode = surrogate ? 2 : (part == 3 ? 0 : part);
+    if (!surrogate && r.mode != 2 && ctx->xgrid > 1) {
+        // The exact scattered part at the node pixels, interpolated to every
+        // support pixel; the unscattered part at every support pixel.
+        if (!p->maps.empty() && p->xmaptab.size() != (size_t)p->ncases)
+            return fail(ctx, LMMEW_EINVAL, "the plan's node tables are not set up");
+        {
+            const int rc = coarse_scratch(ctx, p);
+            if (rc != LMMEW_OK) return rc;
+        }
+        r.pvt = p->d_pvt;
+        const bool prof = p->prof && sub.ntiles > 0;
+        if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
+        if (r.mode == 1) {
+            HIPCHK(ctx, hipMemsetAsync(out, 0, (size_t)sub.rows * ctx->S.Qp * sizeof(float), st));
+        } else {
+            RowArgs u = r;
+            u.mode = 2;
+            u.case_tiles = nullptr;
+            HIPCHK(ctx, launch_row(ctx->S, u, p->JT, st));
+        }
+        RowArgs x = r;
+        x.mode = 1;
+        x.pix_xy = ctx->d_xnode;
+        x.g_qa = ctx->d_xgqa;
+        x.g_qs = ctx->d_xgqs;
+        x.psft = nullptr;
+        x.ptab = nullptr;
+        x.maps = p->maps.empty() ? nullptr : p->d_xmaps;
+        x.A = p->d_C;
+        DevSys Sx = ctx->S;
+        Sx.Qm = ctx->xncn;
+        Sx.Qp = ctx->xldc;
+        HIPCHK(ctx, launch_row(Sx, x, p->JT, st));
+        HIPCHK(ctx, launch_coarse_interp(ctx->S, p->d_C, ctx->xldc, ctx->d_xidx, ctx->d_xw,
+                                         sub.rows, out, st));
+        if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
+        return LMMEW_OK;
+    }
     // Without scattered paths a tile reads no map's scatter tables; its
     // pixel block's unscattered tables are shared by every case, so the
     // block-major order over all tiles keeps those in the L2 instead.
@@ -1705,7 +1783,7 @@ int lmmew_osem_graph(lmmew_ctx *ctx, lmmew_plan *p, int n_iters, const float *se
         const int rm = sync_maps(ctx, p, st);
         if (rm != LMMEW_OK) return rm;
     }
-    if (!p->d_Acache && ctx->mlp) {
+    if (!p->d_Acache && (ctx->mlp || ctx->xgrid > 1)) {
         const int rc = coarse_scratch(ctx, p);   // no allocation inside the capture
         if (rc != LMMEW_OK) return rc;
     }
@@ -2847,6 +2925,138 @@ int lmmew_mlp_set_grid(lmmew_mlp *m, int grid)
     m->ncn = ncn;
     m->ldc = ldc;
     return LMMEW_OK;
+}
+
+int lmmew_set_scatter_pixel_grid(lmmew_ctx *ctx, int grid, hipStream_t st)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    if (grid < 1 || grid > 8) return fail(ctx, LMMEW_EINVAL, "grid must be 1 to 8 pixels");
+    if (grid > 1 && ctx->S.nz > 0)
+        return fail(ctx, LMMEW_EINVAL, "the scatter pixel grid is for the planar model");
+    if (grid == ctx->xgrid) return LMMEW_OK;
+    // kernels still reading the old node tables finish before they go
+    HIPCHK(ctx, hipDeviceSynchronize());
+    dfree(ctx->d_xnode); dfree(ctx->d_xidx); dfree(ctx->d_xw); dfree(ctx->d_xgqa); dfree(ctx->d_xgqs);
+    ctx->d_xnode = nullptr;
+    ctx->d_xidx = nullptr;
+    ctx->d_xw = nullptr;
+    ctx->d_xgqa = nullptr;
+    ctx->d_xgqs = nullptr;
+    ctx->xncn = ctx->xldc = 0;
+    ctx->xgrid = 1;
+    ctx->model_gen++;
+    if (grid == 1) return LMMEW_OK;
+    // Support pixel (ix, iy) lies in the cell of the pixels (g u0, g v0),
+    // (g u0 + g, g v0), (g u0, g v0 + g), (g u0 + g, g v0 + g), u0 = ix / g,
+    // v0 = iy / g, with bilinear weights from fx = (ix mod g) / g, fy likewise.
+    // Corners outside the support (or the grid) are dropped and the remaining
+    // weights renormalised; a pixel with no corner in the support is its own
+    // node.  The nodes are the support pixels some stencil names, in support
+    // order.
+    const int n = ctx->sys.n, Qm = ctx->S.Qm, Qp = ctx->S.Qp;
+    const double pix = ctx->sys.pixel_mm, R = ctx->R;
+    std::vector<int> sidx((size_t)n * n, -1);
+    for (int i = 0; i < Qm; ++i) sidx[ctx->pixq[i]] = i;
+    std::vector<std::array<int, 4>> cn(Qm);
+    std::vector<std::array<double, 4>> cw(Qm);
+    std::vector<char> used(Qm, 0);
+    for (int i = 0; i < Qm; ++i) {
+        const int q = ctx->pixq[i], ix = q % n, iy = q / n;
+        const int u0 = ix / grid, v0 = iy / grid;
+        const double fx = (double)(ix - grid * u0) / grid, fy = (double)(iy - grid * v0) / grid;
+        const double wk[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+        double sum = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            const int cx = grid * (u0 + (k & 1)), cy = grid * (v0 + (k >> 1));
+            const int c = (cx < n && cy < n && wk[k] > 0) ? sidx[(size_t)cy * n + cx] : -1;
+            cn[i][k] = c;
+            cw[i][k] = c >= 0 ? wk[k] : 0.0;
+            sum += cw[i][k];
+        }
+        if (sum > 0) {
+            for (int k = 0; k < 4; ++k) cw[i][k] /= sum;
+        } else {
+            cn[i] = {i, -1, -1, -1};
+            cw[i] = {1.0, 0.0, 0.0, 0.0};
+        }
+        for (int k = 0; k < 4; ++k)
+            if (cn[i][k] >= 0) used[cn[i][k]] = 1;
+    }
+    std::vector<int> node_of(Qm, -1), nodes;
+    for (int i = 0; i < Qm; ++i)
+        if (used[i]) {
+            node_of[i] = (int)nodes.size();
+            nodes.push_back(i);
+        }
+    const int ncn = (int)nodes.size();
+    const int ldc = (ncn + kWave - 1) / kWave * kWave;
+    std::vector<double2> pos_d(ldc);
+    std::vector<float2> pos_f(ldc);
+    for (int k = 0; k < ldc; ++k) {
+        const int q = ctx->pixq[nodes[std::min(k, ncn - 1)]];
+        const double x = ((q % n) + 0.5) * pix - R, y = ((q / n) + 0.5) * pix - R;
+        pos_d[k] = make_double2(x, y);
+        pos_f[k] = make_float2((float)x, (float)y);
+    }
+    std::vector<int4> idx(Qp, make_int4(0, 0, 0, 0));
+    std::vector<float4> w(Qp, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int i = 0; i < Qm; ++i) {
+        int k4[4];
+        for (int k = 0; k < 4; ++k) k4[k] = cn[i][k] >= 0 ? node_of[cn[i][k]] : 0;
+        // a dropped corner names a kept node with weight 0
+        const int first = cn[i][0] >= 0 ? k4[0] : (cn[i][1] >= 0 ? k4[1] : (cn[i][2] >= 0 ? k4[2] : k4[3]));
+        for (int k = 0; k < 4; ++k)
+            if (cn[i][k] < 0) k4[k] = first;
+        idx[i] = make_int4(k4[0], k4[1], k4[2], k4[3]);
+        w[i] = make_float4((float)cw[i][0], (float)cw[i][1], (float)cw[i][2], (float)cw[i][3]);
+    }
+    // the node pixels' attenuation integrals, by the same kernels and inputs
+    // as the context's own tables
+    DevSys Sx = ctx->S;
+    Sx.Qm = ncn;
+    Sx.Qp = ldc;
+    const int na = ctx->S.na, nsc = std::max(ctx->S.nsc, 1);
+    double2 *d_pd = nullptr;
+    ScatA *d_sa = nullptr;
+    hipError_t e = dalloc(&ctx->d_xnode, ldc);
+    if (e == hipSuccess) e = dalloc(&ctx->d_xidx, Qp);
+    if (e == hipSuccess) e = dalloc(&ctx->d_xw, Qp);
+    if (e == hipSuccess) e = dalloc(&ctx->d_xgqa, (size_t)na * ldc);
+    if (e == hipSuccess) e = dalloc(&ctx->d_xgqs, (size_t)nsc * ldc);
+    if (e == hipSuccess) e = dalloc(&d_pd, ldc);
+    if (e == hipSuccess) e = dalloc(&d_sa, (size_t)na * nsc);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_xnode, pos_f.data(), ldc * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_xidx, idx.data(), Qp * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_xw, w.data(), Qp * sizeof(float4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_pd, pos_d.data(), ldc * sizeof(double2), hipMemcpyHostToDevice);
+    // the scatter-point entries are updated in place by the table kernels: a copy
+    if (e == hipSuccess)
+        e = hipMemcpy(d_sa, ctx->d_sa, (size_t)na * nsc * sizeof(ScatA), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess)
+        e = launch_tables_d(Sx, ctx->d_mu, d_pd, nullptr, ctx->d_dirsd, ctx->d_scd, nullptr,
+                            ctx->d_xgqa, ctx->d_xgqs, d_sa, pix, R, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(d_pd);
+    dfree(d_sa);
+    if (e != hipSuccess) {
+        dfree(ctx->d_xnode); dfree(ctx->d_xidx); dfree(ctx->d_xw); dfree(ctx->d_xgqa); dfree(ctx->d_xgqs);
+        ctx->d_xnode = nullptr;
+        ctx->d_xidx = nullptr;
+        ctx->d_xw = nullptr;
+        ctx->d_xgqa = nullptr;
+        ctx->d_xgqs = nullptr;
+        return hipfail(ctx, e, "scatter pixel grid tables");
+    }
+    ctx->xgrid = grid;
+    ctx->xncn = ncn;
+    ctx->xldc = ldc;
+    return LMMEW_OK;
+}
+
+int lmmew_scatter_pixel_grid_nodes(const lmmew_ctx *ctx)
+{
+    if (!ctx) return LMMEW_EINVAL;
+    return ctx->xgrid > 1 ? ctx->xncn : ctx->S.Qm;
 }
 
 int lmmew_mlp_grid_nodes(const lmmew_mlp *m)
