@@ -147,9 +147,39 @@ def test_iterations_graph_cached_and_maps(env):
         ctx.set_scatter_pixel_grid(1)
 
 
+def test_continuous_positions(env):
+    """Events with continuous positions: the scattered part at node pixels
+    interpolates the full-resolution rows the same way (the response factors
+    do not depend on the pixel)."""
+    lm, p, act, ctx, orc = env
+    ev = orc.sample_events(act, 10, seed=23)
+    u = np.random.default_rng(23).uniform(0.0, 1.0, 10)
+    pos = (-p.R + (np.asarray(ev["bin"]) + u) * (p.fov / p.nb)).astype(np.float32)
+    d = lm.events_to_device({"position": pos, "angle": ev["angle"],
+                             "energy": np.asarray(ev["energy"], np.float32)})
+    full = ctx.rows(d, part=1).cpu().numpy().astype(np.float64)
+    ctx.set_scatter_pixel_grid(2)
+    try:
+        sc = ctx.rows(d, part=1).cpu().numpy().astype(np.float64)
+    finally:
+        ctx.set_scatter_pixel_grid(1)
+    sup = orc.support.astype(bool)
+    want = _interp(full, _stencil(sup, p.n, 2))
+    got = sc[:, np.flatnonzero(sup)]
+    assert np.abs(got - want).max() <= 1e-6 * want.max()
+
+
 def test_rejections(env):
+    import torch
+
     lm, p, act, ctx, orc = env
     for g in (0, 9, -2):
         with pytest.raises(lm.LmmewError):
             ctx.set_scatter_pixel_grid(g)
     assert ctx.scatter_pixel_grid_nodes() == ctx.support_size
+    w3 = synth.CONFIGS["16x16x8_600"]
+    mu3 = synth.phantom(w3)[0].astype(np.float32)
+    ctx3 = lm.Context(w3.params, torch.from_numpy(mu3))
+    with pytest.raises(lm.LmmewError):
+        ctx3.set_scatter_pixel_grid(2)
+    ctx3.set_scatter_pixel_grid(1)
