@@ -543,11 +543,11 @@ int lmmew_scatter_scale_fit_windows(lmmew_ctx *ctx, lmmew_mlp *mlp, const lmmew_
 int lmmew_set_scatter_model(lmmew_ctx *ctx, lmmew_mlp *mlp);
 
 /* Where OSEM, lmmew_forward, lmmew_backproject, lmmew_rows and the scale
- * fits evaluate this network (an extension of the surrogate: the paper
- * evaluates its scatter model on a grid coarser than the object's, Sec. 5 and
- * the appendix on 3-D requirements, and the scatter density varies slowly
- * over a pixel).  grid = 1 (the default): at every support pixel.  grid =
- * g in 2..8: at nodes placed on the centres of the pixels (g u, g v) for
+ * fits evaluate this network (an extension of the surrogate; the appendix on
+ * the computational requirements in 3-D, to which the Discussion (Sec. 5)
+ * refers, names modelling scatter at a lower resolution as a way to cut the
+ * cost, and the network's density varies slowly over a pixel).  grid = 1
+ * (the default): at every support pixel.  grid = g in 2..8: at nodes placed on the centres of the pixels (g u, g v) for
  * every node any support pixel needs; a support pixel (ix, iy) takes the
  * bilinear interpolation of the four nodes around it, (ix / g, iy / g) and
  * the next ones in x and y (integer division), with weights from
@@ -565,10 +565,10 @@ int lmmew_mlp_set_grid(lmmew_mlp *mlp, int grid);
  * node count with a coarse grid, else the support size.  EINVAL for NULL. */
 int lmmew_mlp_grid_nodes(const lmmew_mlp *mlp);
 
-/* Scatter at a coarser pixel resolution for the exact model (the paper's
- * conclusion and its appendix on 3-D requirements name scatter at a coarser
- * resolution as the way to cut the once-scattered term's cost; Eq. (5)).
- * grid = 1 (the default): the scattered part of every row a_jq (Eq. (3)-(5))
+/* Scatter at a coarser pixel resolution for the exact model (the appendix on
+ * the computational requirements in 3-D, to which the Discussion (Sec. 5)
+ * refers, names modelling scatter at a lower resolution as a way to cut the
+ * cost of the once-scattered term of Eq. (5)).  grid = 1 (the default): the scattered part of every row a_jq (Eq. (3)-(5))
  * at every support pixel.  grid = g in 2..8 (planar model): the scattered
  * part is evaluated only at node pixels and interpolated; the unscattered
  * part stays at every support pixel, and the sensitivity is unchanged.

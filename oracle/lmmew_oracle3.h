@@ -1,7 +1,7 @@
 /*
  * FP64 CPU oracle, 3-D single-scatter model (the extension the paper's
- * conclusion and its appendix on 3-D computational requirements name as the
- * next step, with the scatter modelled on a coarser grid than the image).
+ * Discussion, Sec. 5, and its appendix on 3-D computational requirements name
+ * as the next step, with the scatter modelled at a lower resolution).
  *
  * TEST INFRASTRUCTURE ONLY, like the planar oracle (lmmew_oracle.h).
  *
