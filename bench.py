@@ -400,8 +400,7 @@ def headline(args, sections, out):
                 "roofline": {
                     "bound": "mfma",
                     "kernel": "k_mlp_rows (surrogate inference, all patients' launches of a "
-                              "subset" + (")" if grid == 1 else
-                                         "; with the node interpolation k_coarse_interp)"),
+                              "subset" + (")" if grid == 1 else ", at the nodes)"),
                     "achieved": flops / 1e12, "peak": PEAK_BF16_FLOPS / 1e12,
                     "unit": "TFLOP/s", "frac": flops / PEAK_BF16_FLOPS,
                     "traffic": (mm["fetch"] + mm["write"]) if (mm and grid == 1) else None,
@@ -410,6 +409,9 @@ def headline(args, sections, out):
                     "pairs_per_s": pairs * K / (mlp_ms * 1e-3),
                     "avg_ms_per_subset": mlp_ms / mlp_n, "subsets_timed": mlp_n},
                 "unscattered_kernel_ms_per_iteration": prim_ms / K,
+                "unscattered_kernel": "k_row, unscattered part" if grid == 1 else
+                                      "k_prim_interp: unscattered part and the interpolated "
+                                      "node values in one pass",
                 "calibration": {"events_per_patient": args.calib_events, "seconds": calib_s,
                                 "scales_per_window": [[float(v) for v in k] for k in kappa],
                                 "what": "exact / network scattered density summed over the "

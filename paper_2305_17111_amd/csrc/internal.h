@@ -272,6 +272,24 @@ struct MlpRowArgs {
 // A[e][q] += sum_k w[q].k * C[e][idx[q].k] for the Qm support pixels of rows rows.
 hipError_t launch_coarse_interp(const DevSys &S, const float *C, int ldc, const int4 *idx,
                                 const float4 *w, int rows, float *A, hipStream_t st);
+// The same rows in one pass with their unscattered part (planar, binned
+// events, with the unscattered bin-probability table): A[e][i] = the
+// unscattered part of row e at support pixel i, as the per-event kernel forms
+// it from the table, plus the interpolated node values; 0 on padding pixels.
+struct PrimInterpArgs {
+    const float *psft;                 // [na][nb][Qp] unscattered bin probabilities
+    const float *g_qa;                 // [na][Qp] pixel -> detector integrals (one map), or
+    const MapTab *maps;                // per-case tables (then ev_case names the case), or NULL
+    const int *ev_bin, *ev_ang, *ev_case;
+    const float *ev_E;
+    int rows;
+    const float *C;                    // [rows][ldc] node values
+    int ldc;
+    const int4 *idx;                   // [Qp] a support pixel's four nodes
+    const float4 *w;                   // [Qp] their weights
+    float *A;                          // [rows][Qp] written
+};
+hipError_t launch_prim_interp(const DevSys &S, const PrimInterpArgs &a, hipStream_t st);
 hipError_t mlp_forward_batch(const MlpWork &w, const float *P, const float *feats, const int *idx,
                              int M, const float *tgt, hipStream_t st);
 hipError_t mlp_backward_batch(const MlpWork &w, const float *P, int M, float *G, hipStream_t st);

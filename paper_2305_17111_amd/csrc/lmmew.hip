@@ -1136,10 +1136,13 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
         }
         r.pvt = p->d_pvt;
         const bool prof = p->prof && sub.ntiles > 0;
+        // full rows of binned events with the unscattered table: the
+        // unscattered part and the interpolation in one pass after the nodes
+        const bool fuse = r.mode == 0 && ctx->d_psft && !p->cont;
         if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
         if (r.mode == 1) {
             HIPCHK(ctx, hipMemsetAsync(out, 0, (size_t)sub.rows * ctx->S.Qp * sizeof(float), st));
-        } else {
+        } else if (!fuse) {
             RowArgs u = r;
             u.mode = 2;
             u.case_tiles = nullptr;
@@ -1158,8 +1161,26 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
         Sx.Qm = ctx->xncn;
         Sx.Qp = ctx->xldc;
         HIPCHK(ctx, launch_row(Sx, x, p->JT, st));
-        HIPCHK(ctx, launch_coarse_interp(ctx->S, p->d_C, ctx->xldc, ctx->d_xidx, ctx->d_xw,
-                                         sub.rows, out, st));
+        if (fuse) {
+            PrimInterpArgs pa{};
+            pa.psft = ctx->d_psft;
+            pa.g_qa = ctx->d_gqa;
+            pa.maps = p->maps.empty() ? nullptr : p->d_maps;
+            pa.ev_bin = p->d_bin + sub.row0;
+            pa.ev_ang = p->d_ang + sub.row0;
+            pa.ev_case = p->d_case + sub.row0;
+            pa.ev_E = p->d_E + sub.row0;
+            pa.rows = sub.rows;
+            pa.C = p->d_C;
+            pa.ldc = ctx->xldc;
+            pa.idx = ctx->d_xidx;
+            pa.w = ctx->d_xw;
+            pa.A = out;
+            HIPCHK(ctx, launch_prim_interp(ctx->S, pa, st));
+        } else {
+            HIPCHK(ctx, launch_coarse_interp(ctx->S, p->d_C, ctx->xldc, ctx->d_xidx, ctx->d_xw,
+                                             sub.rows, out, st));
+        }
         if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
         return LMMEW_OK;
     }
@@ -1169,13 +1190,23 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
     if (r.mode == 2) r.case_tiles = nullptr;
     r.pvt = p->d_pvt;
     const bool prof = p->prof && sub.ntiles > 0;
-    if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
-    HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
-    if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
+    // Every case's network on a coarse grid, with the unscattered table: per
+    // run of cases, the network at its nodes, then the unscattered part and
+    // the interpolation in one pass (no separate unscattered launch).
+    bool fuse = surrogate && ctx->d_psft != nullptr;
+    for (int c = 0; fuse && c < p->ncases; ++c) {
+        const lmmew_mlp *m = case_model(ctx, p, c);
+        fuse = m && m->grid > 1;
+    }
+    if (!fuse) {
+        if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
+        HIPCHK(ctx, launch_row(ctx->S, r, p->JT, st));
+        if (prof) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
+    }
     if (surrogate) {
         // one launch per run of consecutive cases that share a network (the
         // whole subset when every case uses the plan context's)
-        const bool profm = p->prof && sub.rows > 0;
+        const bool profm = p->prof && sub.rows > 0 && !fuse;
         if (profm) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
         const int *cr = p->case_rows.data() + (size_t)s * (p->ncases + 1);
         {
@@ -1201,7 +1232,36 @@ int run_rows(lmmew_ctx *ctx, lmmew_plan *p, int s, hipStream_t st, int part = 0,
                 a.case_scale = p->d_cscale;
                 // runs follow each other on the stream: each reuses the
                 // node-value scratch from its start
-                HIPCHK(ctx, net_rows(ctx, m, a, out + (size_t)r0 * ctx->S.Qp, p->d_C, st));
+                if (fuse) {
+                    const bool pr = p->prof;
+                    a.pix_xy = m->d_cnode;
+                    a.npix = m->ncn;
+                    a.ld = m->ldc;
+                    a.assign = 1;
+                    a.A = p->d_C;
+                    if (pr) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
+                    HIPCHK(ctx, mlp_rows(ctx->S, a, st));
+                    if (pr) HIPCHK(ctx, prof_mark(ctx, p, 1, st));
+                    PrimInterpArgs pa{};
+                    pa.psft = ctx->d_psft;
+                    pa.g_qa = ctx->d_gqa;
+                    pa.maps = p->maps.empty() ? nullptr : p->d_maps;
+                    pa.ev_bin = a.ev_bin;
+                    pa.ev_ang = a.ev_ang;
+                    pa.ev_case = p->d_case + sub.row0 + r0;
+                    pa.ev_E = a.ev_E;
+                    pa.rows = a.rows;
+                    pa.C = p->d_C;
+                    pa.ldc = m->ldc;
+                    pa.idx = m->d_cidx;
+                    pa.w = m->d_cw;
+                    pa.A = out + (size_t)r0 * ctx->S.Qp;
+                    if (pr) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
+                    HIPCHK(ctx, launch_prim_interp(ctx->S, pa, st));
+                    if (pr) HIPCHK(ctx, prof_mark(ctx, p, 0, st));
+                } else {
+                    HIPCHK(ctx, net_rows(ctx, m, a, out + (size_t)r0 * ctx->S.Qp, p->d_C, st));
+                }
             }
             c0 = c1;
         }

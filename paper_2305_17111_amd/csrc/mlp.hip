@@ -1015,6 +1015,86 @@ hipError_t launch_coarse_interp(const DevSys &S, const float *C, int ldc, const 
     return hipSuccess;
 }
 
+// Rows of the coarse evaluation grids in one pass: the unscattered part of
+// every (row, support pixel), formed as the per-event kernel forms it from the
+// unscattered bin-probability table (the same operations in the same order:
+// the path weight of each line from the pixel's attenuation integral to the
+// detector, times the energy factor of the event's energy, summed over the
+// lines, times the bin probability), plus the bilinear interpolation of the
+// row's node values.  Each row element is written once, with no read of the
+// row.  A workgroup takes kInterpRows rows: it stages their energy factors
+// (one per row and line) in LDS, and a thread keeps its pixel's stencil, and
+// its path weights while consecutive rows share the angle and the case (the
+// plan sorts its events that way).
+__global__ __launch_bounds__(256) void k_prim_interp(const DevSys S, const PrimInterpArgs a)
+{
+    __shared__ float sgq[kInterpRows * LMMEW_MAX_LINES];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int e0 = blockIdx.y * kInterpRows, e1 = min(e0 + kInterpRows, a.rows);
+    for (int t = threadIdx.x; t < (e1 - e0) * S.nw; t += 256) {
+        const int w = t % S.nw;
+        const float d = a.ev_E[e0 + t / S.nw] - S.E[w];
+        sgq[t] = S.gnorm[w] * __expf(-d * d / (2.f * S.eres_k * S.E[w]));
+    }
+    __syncthreads();
+    if (i >= S.Qp) return;
+    const bool valid = i < S.Qm;
+    const int4 n = valid ? a.idx[i] : make_int4(0, 0, 0, 0);
+    const float4 f = valid ? a.w[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float Pp[LMMEW_MAX_LINES];
+    int key_a = -1, key_c = -1;
+    for (int e = e0; e < e1; ++e) {
+        float out = 0.f;
+        const int an = a.ev_ang[e], cs = a.maps ? a.ev_case[e] : 0;
+        if (valid) {
+            if (an != key_a || cs != key_c) {
+                const float *gq_a = a.maps ? a.maps[cs].g_qa : a.g_qa;
+                const float gqa = gq_a[(size_t)an * S.Qp + i];
+#pragma unroll
+                for (int w = 0; w < LMMEW_MAX_LINES; ++w)
+                    if (w < S.nw) Pp[w] = S.pp[w] * __builtin_amdgcn_exp2f(-S.f[w] * gqa * kLog2e);
+                key_a = an;
+                key_c = cs;
+            }
+            const float ps = a.psft[((size_t)an * S.nb + a.ev_bin[e]) * S.Qp + i];
+            const float *gq = sgq + (e - e0) * S.nw;
+            float g = 0.f;
+#pragma unroll
+            for (int w = 0; w < LMMEW_MAX_LINES; ++w)
+                if (w < S.nw) g = fmaf(Pp[w], gq[w], g);
+            const float *c = a.C + (size_t)e * a.ldc;
+            float v = f.x * c[n.x];
+            v = fmaf(f.y, c[n.y], v);
+            v = fmaf(f.z, c[n.z], v);
+            v = fmaf(f.w, c[n.w], v);
+            out = __fmul_rn(ps, g) + v;
+        }
+        a.A[(size_t)e * S.Qp + i] = out;
+    }
+}
+
+hipError_t launch_prim_interp(const DevSys &S, const PrimInterpArgs &a, hipStream_t st)
+{
+    if (!a.psft || (!a.g_qa && !a.maps) || (a.maps && !a.ev_case)) return hipErrorInvalidValue;
+    // grid.y is limited to 65535 workgroups: launch in slices of rows
+    constexpr int kSlice = 32768 * kInterpRows;
+    for (int r0 = 0; r0 < a.rows; r0 += kSlice) {
+        PrimInterpArgs b = a;
+        b.rows = a.rows - r0 < kSlice ? a.rows - r0 : kSlice;
+        b.ev_bin += r0;
+        b.ev_ang += r0;
+        b.ev_E += r0;
+        if (b.ev_case) b.ev_case += r0;
+        b.C += (size_t)r0 * a.ldc;
+        b.A += (size_t)r0 * S.Qp;
+        hipLaunchKernelGGL(k_prim_interp, dim3(nblk(S.Qp, 256), nblk(b.rows, kInterpRows)), dim3(256),
+                           0, st, S, b);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t mlp_rows(const DevSys &S, const MlpRowArgs &a, hipStream_t st)
 {
     if (a.npix < 1 || a.ld < a.npix) return hipErrorInvalidValue;
