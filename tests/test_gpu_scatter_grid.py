@@ -147,6 +147,28 @@ def test_iterations_graph_cached_and_maps(env):
         ctx.set_scatter_pixel_grid(1)
 
 
+def test_fused_and_two_pass_rows_agree(env):
+    """With the unscattered table the node modes write each row in one pass
+    (unscattered part plus interpolation); without it the per-event kernel's
+    unscattered pass and a separate interpolation.  Both give the same rows
+    (the unscattered arithmetic is the same; the table holds what the kernel
+    otherwise forms with erfc, so within float rounding)."""
+    lm, p, act, ctx, orc = env
+    ev = orc.sample_events(act, 20, seed=24)
+    d = _dev(lm, ev)
+    ctx.set_scatter_pixel_grid(2)
+    try:
+        fused = ctx.rows(d, part=3).cpu().numpy().astype(np.float64)
+        ctx.lmmew_psf_table(False)
+        two = ctx.rows(d, part=3).cpu().numpy().astype(np.float64)
+    finally:
+        ctx.lmmew_psf_table(True)
+        ctx.set_scatter_pixel_grid(1)
+    err = np.abs(fused - two).max() / np.abs(two).max()
+    print(f"fused against two passes: max {err:.2e} of the largest row element")
+    assert err <= 1e-5
+
+
 def test_continuous_positions(env):
     """Events with continuous positions: the scattered part at node pixels
     interpolates the full-resolution rows the same way (the response factors
