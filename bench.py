@@ -383,6 +383,8 @@ def headline(args, sections, out):
             prim_ms, _ = ks["k_row"]
             pairs = float(J) * nodes
             flops = pairs * 2 * MLP_MAC_PER_PAIR * K / (mlp_ms * 1e-3)
+            mt_g, mt_g_src = (mm, mm_src) if grid == 1 else measured_traffic(
+                f"k_mlp_rows_grid{grid}_128x128_16cases_hbm_traffic.md", "mlp.hip")
             entry = {
                 "value": J * K / el_s, "unit": "events*iterations/s",
                 "ms_per_step": 1e3 * el_s / K, "s_per_iteration": el_s / K,
@@ -403,8 +405,8 @@ def headline(args, sections, out):
                               "subset" + (")" if grid == 1 else ", at the nodes)"),
                     "achieved": flops / 1e12, "peak": PEAK_BF16_FLOPS / 1e12,
                     "unit": "TFLOP/s", "frac": flops / PEAK_BF16_FLOPS,
-                    "traffic": (mm["fetch"] + mm["write"]) if (mm and grid == 1) else None,
-                    "traffic_source": mm_src if grid == 1 else "not measured for this grid",
+                    "traffic": (mt_g["fetch"] + mt_g["write"]) if mt_g else None,
+                    "traffic_source": mt_g_src,
                     "flop_per_pair": 2 * MLP_MAC_PER_PAIR, "gelu_per_pair": MLP_GELU_PER_PAIR,
                     "pairs_per_s": pairs * K / (mlp_ms * 1e-3),
                     "avg_ms_per_subset": mlp_ms / mlp_n, "subsets_timed": mlp_n},
